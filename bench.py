@@ -1,0 +1,190 @@
+#!/usr/bin/env python3
+"""Forward-render benchmark on one MI355X.
+
+Workload: a 1.5M-Gaussian SH-degree-3 clustered scene (200 anisotropic blobs
+plus 10% uniform background in a 20-unit box) rendered at 1600x1040 with 16x16
+tiles from 8 orbit cameras (radius 12, 10 degrees elevation), all synthetic and
+seeded.  One step is one forward render of one frame: preprocess, scan, pair
+count read-back, key emission, radix sort, tile ranges and blend.  Each of the
+three tile assignments (3-sigma, SnugBox, AccuTile) is timed over the same
+steps on the same scene; `value` is the AccuTile frame rate.
+
+Per-stage kernel times come from hipEvents the library records on its stream
+inside every timed frame.  The blend (the dominant kernel) is reported against
+the FP32 VALU roofline; the HBM-bound stages against 8 TB/s.  The CPU baseline
+is the test oracle (plain C, one thread) rendering one frame of the same
+workload.
+
+    python bench.py [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "render FPS (AccuTile vs 3-sigma) at 1.5M Gaussians 1600px; p50/p99 serve ms"
+MODES = ("3sigma", "snugbox", "accutile")
+
+# Roofline constants (MI355X: 256 CUs x 4 SIMD x 16 lanes at 2.4 GHz; packed
+# FP32 is not used, so one FP32 VALU op per lane per clock).
+PEAK_VALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12      # 39.3 T ops/s
+PEAK_HBM_GBS = 8000.0
+# FP32 operations per evaluated (pixel, Gaussian) pair of the blend: dx, dy,
+# (a dx) dx, (c dy) dy, ((2b) dx) dy, two adds and the q <= t test.
+OPS_PER_EVAL = 11
+# Algorithmic HBM bytes: preprocess reads 236 B (SH-3 inputs) and writes a 52 B
+# record per Gaussian; the sort moves 8 B (histogram read) + 24 B (key/value
+# read and write) per pair per 8-bit pass.
+PRE_BYTES_PER_G = 236 + 52
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor()
+
+
+def cpu_baseline(scene, cam, runs=3):
+    """The oracle (plain C, single thread) rendering one AccuTile frame."""
+    import oracle
+    oracle.lib()
+    times = []
+    for _ in range(runs):
+        t0 = time.perf_counter()
+        oracle.render(scene, cam, "accutile")
+        times.append(time.perf_counter() - t0)
+        log(f"  cpu oracle frame: {times[-1]:.2f} s")
+    ms = statistics.median(times) * 1e3
+    return {"value": round(1000.0 / ms, 4), "unit": "FPS", "cores": 1, "kind": "oracle",
+            "sample": f"one full 1600x1040 AccuTile frame of the 1.5M-Gaussian scene "
+                      f"(camera 0), median of {runs} runs, {ms:.0f} ms/frame, "
+                      f"on {cpu_model()} ({os.cpu_count()} visible cores)"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=60)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--n", type=int, default=1_500_000)
+    ap.add_argument("--modes", default=",".join(MODES))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2412_00578_amd as ss
+    import scenegen
+
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    scene = scenegen.scene_c1(n=args.n)
+    cams = scenegen.cameras_c1(8)
+    g = ss.Gaussians.from_scene(scene, dev)
+    log(f"scene: {scene.n} Gaussians, generated and uploaded in {time.perf_counter() - t0:.1f} s")
+    r = ss.Renderer(dev)
+    modes = [m for m in args.modes.split(",") if m]
+
+    # Work counters per camera (untimed): pairs and evaluated pixel-Gaussian pairs.
+    work = {}
+    for mode in modes:
+        P, E = [], []
+        for cam in cams:
+            out = r.render(g, cam, mode, full=True)
+            torch.cuda.synchronize()
+            P.append(out.n_pairs)
+            E.append(int(out.frame.n_eval.to(torch.int64).sum().item()))
+        work[mode] = (P, E)
+        log(f"{mode}: pairs/frame {np.mean(P):.0f}, evaluated pairs/frame {np.mean(E):.3e}")
+
+    results = {}
+    for mode in modes:
+        for w in range(args.warmup):
+            r.render(g, cams[w % len(cams)], mode)
+        evs = [ss.StageEvents(dev) for _ in range(args.steps)]
+        start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        start.record()
+        for k in range(args.steps):
+            r.render(g, cams[k % len(cams)], mode, events=evs[k])
+        stop.record()
+        torch.cuda.synchronize()
+        total_ms = start.elapsed_time(stop)
+        ms = total_ms / args.steps
+        stages = {s: statistics.mean(e.stage_ms()[s] for e in evs) for s in ss.STAGES}
+        P, E = work[mode]
+        steps_cam = [k % len(cams) for k in range(args.steps)]
+        p_mean = statistics.mean(P[c] for c in steps_cam)
+        e_mean = statistics.mean(E[c] for c in steps_cam)
+        passes = (32 + int(np.ceil(np.log2(cams[0].tiles_x * cams[0].tiles_y))) + 7) // 8
+        results[mode] = {
+            "fps": round(1000.0 / ms, 2), "ms_per_frame": round(ms, 4),
+            "stage_ms": {k: round(v, 4) for k, v in stages.items()},
+            "pairs_per_frame": int(p_mean), "evaluated_pairs_per_frame": int(e_mean),
+            "blend_tflops": round(e_mean * OPS_PER_EVAL / (stages["blend"] * 1e-3) / 1e12, 3),
+            "preprocess_gbs": round(args.n * PRE_BYTES_PER_G / (stages["preprocess"] * 1e-3) / 1e9,
+                                    1),
+            "sort_gbs": round(p_mean * 32 * passes / (stages["sort"] * 1e-3) / 1e9, 1),
+        }
+        log(f"{mode}: {ms:.3f} ms/frame ({1000 / ms:.1f} FPS) stages "
+            + " ".join(f"{k}={v:.3f}" for k, v in stages.items()))
+
+    acc = results.get("accutile") or results[modes[-1]]
+    base = results.get("3sigma")
+    blend_ms = acc["stage_ms"]["blend"]
+    achieved = acc["evaluated_pairs_per_frame"] * OPS_PER_EVAL / (blend_ms * 1e-3) / 1e12
+    line = {
+        "metric": METRIC,
+        "value": acc["fps"],
+        "unit": "FPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": acc["ms_per_frame"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "1.5M-Gaussian SH-3 clustered scene, 1600x1040, 16x16 tiles, "
+                               "8 orbit cameras, AccuTile forward render",
+                   "n_gaussians": args.n, "width": 1600, "height": 1040, "tile_mode": "accutile"},
+        "speedup_vs_3sigma": round(base["ms_per_frame"] / acc["ms_per_frame"], 3) if base else None,
+        "modes": results,
+        "roofline": {"bound": "alu", "kernel": "blend (k_blend)",
+                     "achieved": round(achieved, 3), "peak": round(PEAK_VALU_TOPS, 1),
+                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_VALU_TOPS, 4),
+                     "traffic": None,
+                     "work": f"{acc['evaluated_pairs_per_frame']} evaluated pixel-Gaussian pairs "
+                             f"x {OPS_PER_EVAL} FP32 ops per launch",
+                     "avg_launch_ms": round(blend_ms, 4)},
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        line["cpu_baseline"] = cpu_baseline(scene, cams[0])
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

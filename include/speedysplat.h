@@ -1,0 +1,240 @@
+/*
+ * speedysplat.h - C ABI of the MI355X (gfx950) Speedy-Splat rasterizer.
+ *
+ * The library renders a set of 3D Gaussians G_i = {mu_i, s_i, r_i, h_i,
+ * sigma_i} for a camera pose (Speedy-Splat, arXiv 2412.00578, Sec. 3) with the
+ * tile-based pipeline of Sec. 3.1-3.3 and one of three tile assignments:
+ *   SS_TILE_3SIGMA    the square of radius ceil(3 sqrt(lambda_max)) (Eq. radius)
+ *   SS_TILE_SNUGBOX   the opacity-aware tight bounding box (Sec. 4.1.1)
+ *   SS_TILE_ACCUTILE  the exact tiles touched by the ellipse (Sec. 4.1.2, Alg. 1)
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Every array argument is DEVICE memory owned by the caller, C-contiguous,
+ *   at least 16-byte aligned (torch allocations are).  The library never
+ *   allocates, frees or keeps device memory and keeps no state between calls
+ *   other than its loaded kernels.
+ * - `stream` is a hipStream_t (NULL = the null stream).  Every call only
+ *   enqueues work on it and returns; outputs are valid once the stream has
+ *   been synchronised.  The exceptions, which synchronise `stream` to read the
+ *   pair count, are named "SYNC" below.
+ * - Status: SS_OK (0) or a positive SS_ERR_* code.  Arguments are checked on
+ *   the host before anything is enqueued; on an error nothing is enqueued and
+ *   ss_last_error() holds a message (thread-local).  A launch failure reported
+ *   by the HIP runtime returns SS_ERR_HIP.
+ * - Data-dependent degeneracies are not errors: a Gaussian that is not finite,
+ *   lies at or before the near plane, has a non-positive-definite screen
+ *   covariance, or (SnugBox/AccuTile) an opacity <= 1/255 is culled: its record
+ *   is all zeros and its tile count 0.
+ *
+ * Geometry conventions
+ * --------------------
+ * Camera: x_cam = R x_world + t, +z forward, +x right, +y down; pinhole
+ * u = fx x/z + cx, v = fy y/z + cy.  Pixel (px, py) is sampled at its centre
+ * (px + 0.5, py + 0.5); tile (tx, ty) covers [16 tx, 16 tx + 16) x
+ * [16 ty, 16 ty + 16); tiles_x = ceil(W/16), tiles_y = ceil(H/16),
+ * tile id = ty * tiles_x + tx.
+ *
+ * Per-Gaussian record (written by the preprocess stage, read by the rest):
+ *   geom  [n,4] f32 = (u, v, depth, t)      t = 2 ln(255 sigma)  (Sec. 4.1)
+ *   conic [n,4] f32 = (a, b, c, sigma)      Sigma_2D^{-1} = [[a, b], [b, c]]
+ *   rgb   [n,4] f32 = (r, g, b, 0)          view-dependent SH colour
+ * The geometry is evaluated in FP64 from the FP32 inputs and rounded once into
+ * the record; every tile decision is then made in FP64 on the stored record, so
+ * the tile counts of the preprocess stage equal the pairs the emit stage writes.
+ *
+ * Pair keys (Sec. 3.2): key = (uint64 tile_id << 32) | bits(depth as f32),
+ * value = Gaussian index.  The sorted order is by key, ties by index.
+ */
+#ifndef SPEEDYSPLAT_H
+#define SPEEDYSPLAT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SS_ABI_VERSION 1
+
+enum ss_status {
+    SS_OK = 0,
+    SS_ERR_INVALID_ARG = 1, /* null pointer, bad size, degree or mode */
+    SS_ERR_WORKSPACE = 2,   /* pair workspace smaller than the pair count */
+    SS_ERR_OVERFLOW = 3,    /* more than 2^32 - 1 pairs, or too many tiles */
+    SS_ERR_HIP = 4          /* the HIP runtime reported an error */
+};
+
+enum ss_tile_mode { SS_TILE_3SIGMA = 0, SS_TILE_SNUGBOX = 1, SS_TILE_ACCUTILE = 2 };
+
+/* Constants the kernels use, exported so tests can compare them with their
+ * own independently typed copies. */
+typedef struct ss_constants {
+    int32_t abi_version;
+    int32_t tile;          /* 16 (Sec. 3.1: 16 x 16 pixel tiles) */
+    float alpha_min;       /* 1/255: inclusion cutoff (Sec. 3.3) */
+    float alpha_max;       /* 0.99: upper clamp of alpha */
+    float t_min;           /* 1e-4: transmittance stop */
+    float dilation;        /* 0.3 added to the diagonal of Sigma_2D */
+    float fov_clamp;       /* 1.3: x/z, y/z clamp in the EWA Jacobian, in half-FOV units */
+    float disc_floor;      /* 0.1: floor of the eigenvalue discriminant (3-sigma) */
+} ss_constants;
+
+typedef struct ss_camera {
+    int32_t width, height;  /* pixels, 1 .. 16384 */
+    float fx, fy, cx, cy;   /* pinhole intrinsics, pixels */
+    float R[9];             /* world -> camera rotation, row-major */
+    float t[3];             /* world -> camera translation */
+    float near_z;           /* cull depth (z <= near_z is culled) */
+    float bg[3];            /* background colour added with the final T */
+} ss_camera;
+
+typedef struct ss_gaussians {
+    int64_t n;              /* number of Gaussians, 0 .. 2^31 - 1 */
+    int32_t sh_degree;      /* 0 .. 3 */
+    int32_t sh_stride;      /* coefficients stored per Gaussian, >= (deg+1)^2 */
+    const float *means;     /* [n,3] world positions mu_i */
+    const float *scales;    /* [n,3] linear scales s_i (the activation is the caller's) */
+    const float *quats;     /* [n,4] rotations r_i as (w, x, y, z), any non-zero norm */
+    const float *opacity;   /* [n]   sigma_i in (0, 1] */
+    const float *sh;        /* [n, sh_stride, 3] SH coefficients h_i */
+} ss_gaussians;
+
+/* Per-frame buffers, sized by ss_frame_sizes(). */
+typedef struct ss_frame {
+    float *geom;            /* [n,4] */
+    float *conic;           /* [n,4] */
+    float *rgb;             /* [n,4] */
+    uint32_t *counts;       /* [n]   tiles per Gaussian */
+    uint32_t *offsets;      /* [n]   inclusive prefix sum of counts */
+    uint64_t *scan_tmp;     /* [scan_tmp_words]; word 0 receives the pair count P */
+    uint32_t *ranges;       /* [n_tiles, 2] per-tile [start, end) into the sorted pairs */
+    float *t_final;         /* [H, W] final transmittance per pixel */
+    uint32_t *n_last;       /* [H, W] 1 + position (within its tile) of the last
+                               Gaussian blended into the pixel, 0 if none */
+    uint32_t *n_eval;       /* optional [H, W] (NULL: not written): Gaussians of the
+                               tile's list the pixel evaluated before it stopped */
+} ss_frame;
+
+typedef struct ss_frame_info {
+    int32_t tiles_x, tiles_y, n_tiles;
+    int32_t sort_bits;      /* significant key bits: 32 + ceil(log2(n_tiles)) */
+    int64_t scan_tmp_words; /* uint64 words for ss_frame.scan_tmp */
+} ss_frame_info;
+
+/* Pair workspace: two ping-pong key/value buffers plus sort scratch. */
+typedef struct ss_pairs {
+    uint64_t capacity;      /* pairs each buffer holds */
+    uint64_t *keys[2];      /* [capacity] each */
+    uint32_t *values[2];    /* [capacity] each */
+    uint32_t *sort_tmp;     /* [sort_tmp_words] */
+} ss_pairs;
+
+/* Optional stage timing for the composite calls: caller-created hipEvent_t
+ * handles (NULL entries are skipped) recorded on the stream at
+ *   [0] before preprocess  [1] after preprocess  [2] after the scan
+ *   [3] before emit (after the pair count was read back)  [4] after emit
+ *   [5] after the sort  [6] after the ranges  [7] after the blend. */
+typedef struct ss_stage_events {
+    void *ev[8];
+} ss_stage_events;
+
+/* Fills *out.  Returns SS_ERR_INVALID_ARG for a null pointer. */
+int ss_get_constants(ss_constants *out);
+
+/* Static message for a status code (never NULL). */
+const char *ss_status_string(int status);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char *ss_last_error(void);
+
+/* Buffer sizes for a frame of n Gaussians at width x height. */
+int ss_frame_sizes(int64_t n, int32_t width, int32_t height, ss_frame_info *out);
+
+/* uint32 words of ss_pairs.sort_tmp for `capacity` pairs. */
+int ss_sort_tmp_words(uint64_t capacity, int64_t *out_words);
+
+/*
+ * Stage 1, preprocess (Sec. 3.1 and Sec. 4.1): for every Gaussian, the record
+ * (projection, Sigma_3D = R S S^T R^T, EWA Sigma_2D + 0.3 I, conic, t, SH
+ * colour) and its tile count under `mode`.  Writes frame->geom, conic, rgb,
+ * counts.
+ */
+int ss_preprocess(const ss_camera *cam, const ss_gaussians *g, int32_t mode,
+                  const ss_frame *frame, void *stream);
+
+/*
+ * Stage 2, inclusive prefix sum of the tile counts (Sec. 3.2 "InclusiveSum"):
+ * frame->offsets[i] = sum_{j <= i} counts[j]; the total P goes to
+ * frame->scan_tmp[0] (uint64).
+ */
+int ss_scan(int64_t n, const ss_frame *frame, void *stream);
+
+/*
+ * Stage 3, key emission (Sec. 3.2 "duplicateWithKeys", Alg. 1 "Process"):
+ * Gaussian i writes its tiles, in its tile-enumeration order, at
+ * [offsets[i] - counts[i], offsets[i]) of pairs->keys[buf] / values[buf].
+ * n_pairs must be the P the scan produced and <= pairs->capacity.
+ */
+int ss_emit(const ss_camera *cam, int64_t n, int32_t mode, const ss_frame *frame,
+            const ss_pairs *pairs, int32_t buf, uint64_t n_pairs, void *stream);
+
+/*
+ * Stage 4, LSD radix sort of the pairs in buffer `buf` on the low
+ * ss_frame_info.sort_bits bits of the key (Sec. 3.2 "RadixSort"); stable, so
+ * equal keys keep index order.  *out_buf receives the buffer holding the result.
+ */
+int ss_sort(const ss_camera *cam, const ss_pairs *pairs, int32_t buf, uint64_t n_pairs,
+            int32_t *out_buf, void *stream);
+
+/*
+ * Stage 5, per-tile ranges of the sorted keys (Sec. 3.2 "identifyTileRanges"):
+ * frame->ranges[tile] = [first, last + 1) of the tile's run; an empty tile gets
+ * start = end = the position where its run would begin.
+ */
+int ss_ranges(const ss_camera *cam, const ss_frame *frame, const ss_pairs *pairs, int32_t buf,
+              uint64_t n_pairs, void *stream);
+
+/*
+ * Stage 6, blend (Sec. 3.3, Eqs. render_alpha, 2d_gaussian_scalar,
+ * contribution): front to back over each tile's sorted Gaussians, a Gaussian
+ * is included at a pixel when q <= t (alpha >= 1/255), alpha = min(0.99,
+ * sigma exp(-q/2)); the walk stops before a Gaussian that would take the
+ * transmittance below 1e-4.  out_rgb is planar [3, H, W] f32; also writes
+ * frame->t_final and frame->n_last.
+ */
+int ss_blend(const ss_camera *cam, const ss_frame *frame, const ss_pairs *pairs, int32_t buf,
+             float *out_rgb, void *stream);
+
+/*
+ * SYNC.  Stages 1-2, then reads P back to the host (*n_pairs_out).
+ * Returns SS_ERR_OVERFLOW if P >= 2^32.  `events` may be NULL.
+ */
+int ss_forward_begin(const ss_camera *cam, const ss_gaussians *g, int32_t mode,
+                     const ss_frame *frame, uint64_t *n_pairs_out,
+                     const ss_stage_events *events, void *stream);
+
+/*
+ * Stages 3-6 for the P returned by ss_forward_begin.  Returns
+ * SS_ERR_WORKSPACE if pairs->capacity < n_pairs.  *out_buf (may be NULL)
+ * receives the pair buffer holding the sorted pairs.  `events` may be NULL.
+ */
+int ss_forward_finish(const ss_camera *cam, int64_t n, int32_t mode, const ss_frame *frame,
+                      const ss_pairs *pairs, uint64_t n_pairs, float *out_rgb,
+                      int32_t *out_buf, const ss_stage_events *events, void *stream);
+
+/*
+ * SYNC.  The whole forward render (stages 1-6).  *n_pairs_out receives P.  If
+ * pairs->capacity < P, returns SS_ERR_WORKSPACE after stage 2 without touching
+ * the pair buffers; the caller grows them to P and calls again.  `events`
+ * may be NULL.
+ */
+int ss_render(const ss_camera *cam, const ss_gaussians *g, int32_t mode, const ss_frame *frame,
+              const ss_pairs *pairs, float *out_rgb, uint64_t *n_pairs_out, int32_t *out_buf,
+              const ss_stage_events *events, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SPEEDYSPLAT_H */

@@ -1,0 +1,204 @@
+// Stage 1: per-Gaussian preprocess (Speedy-Splat Sec. 3.1 "Preprocessing",
+// with the opacity-aware threshold of Sec. 4.1).
+//
+// One lane per Gaussian.  The screen-space geometry is FP64 over the FP32
+// inputs and is rounded once into the FP32 record; the tile count is then an
+// FP64 function of the stored record (the same function the emit stage runs),
+// so counts and emitted pairs agree by construction.  The colour is FP32.
+#include "ss_internal.h"
+
+namespace ss {
+namespace {
+
+// Real SH basis constants, degrees 0..3, ordered (l, m = -l..l) with the
+// Condon-Shortley phase.
+constexpr float kSH0 = 0.28209479177387814f;
+constexpr float kSH1 = 0.4886025119029199f;
+constexpr float kSH2a = 1.0925484305920792f, kSH2b = 0.31539156525252005f,
+                kSH2c = 0.5462742152960396f;
+constexpr float kSH3a = 0.5900435899266435f, kSH3b = 2.890611442640554f,
+                kSH3c = 0.4570457994644658f, kSH3d = 0.3731763325901154f,
+                kSH3e = 1.445305721320277f;
+
+__device__ __forceinline__ bool finite_f(float x) { return __builtin_isfinite(x); }
+
+struct Inputs {
+    const float* means;
+    const float* scales;
+    const float* quats;
+    const float* opacity;
+    const float* sh;
+    int sh_degree, sh_stride;
+};
+
+__global__ __launch_bounds__(256) void k_preprocess(ss_camera cam, Inputs in, int64_t n, int mode,
+                                                    int tx_n, int ty_n, float4* __restrict__ geom,
+                                                    float4* __restrict__ conic,
+                                                    float4* __restrict__ rgb_out,
+                                                    uint32_t* __restrict__ counts) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
+
+    const float m0 = in.means[3 * i], m1 = in.means[3 * i + 1], m2 = in.means[3 * i + 2];
+    const float s0 = in.scales[3 * i], s1 = in.scales[3 * i + 1], s2 = in.scales[3 * i + 2];
+    const float4 qr = *reinterpret_cast<const float4*>(in.quats + 4 * i);
+    const float op = in.opacity[i];
+
+    bool ok = finite_f(m0) && finite_f(m1) && finite_f(m2) && finite_f(s0) && finite_f(s1) &&
+              finite_f(s2) && finite_f(qr.x) && finite_f(qr.y) && finite_f(qr.z) &&
+              finite_f(qr.w) && finite_f(op) && (op > 0.0f);
+
+    // camera space p_c = R mu + t
+    const double R0 = cam.R[0], R1 = cam.R[1], R2 = cam.R[2], R3 = cam.R[3], R4 = cam.R[4],
+                 R5 = cam.R[5], R6 = cam.R[6], R7 = cam.R[7], R8 = cam.R[8];
+    const double mx = m0, my = m1, mz = m2;
+    const double x = ((R0 * mx + R1 * my) + R2 * mz) + (double)cam.t[0];
+    const double y = ((R3 * mx + R4 * my) + R5 * mz) + (double)cam.t[1];
+    const double z = ((R6 * mx + R7 * my) + R8 * mz) + (double)cam.t[2];
+    ok = ok && (z > (double)cam.near_z);
+
+    // quaternion (w, x, y, z) normalised in FP64
+    double qw = qr.x, qx = qr.y, qy = qr.z, qz = qr.w;
+    const double nn = ((qw * qw + qx * qx) + qy * qy) + qz * qz;
+    ok = ok && (nn > 0.0);
+    if (!ok) {
+        geom[i] = zero; conic[i] = zero; rgb_out[i] = zero; counts[i] = 0u;
+        return;
+    }
+    const double fx = cam.fx, fy = cam.fy;
+    const double u = (fx * x) / z + (double)cam.cx;
+    const double v = (fy * y) / z + (double)cam.cy;
+
+    const double qn = sqrt(nn);
+    qw = qw / qn; qx = qx / qn; qy = qy / qn; qz = qz / qn;
+    double Rq[9];
+    Rq[0] = 1.0 - 2.0 * (qy * qy + qz * qz);
+    Rq[1] = 2.0 * (qx * qy - qw * qz);
+    Rq[2] = 2.0 * (qx * qz + qw * qy);
+    Rq[3] = 2.0 * (qx * qy + qw * qz);
+    Rq[4] = 1.0 - 2.0 * (qx * qx + qz * qz);
+    Rq[5] = 2.0 * (qy * qz - qw * qx);
+    Rq[6] = 2.0 * (qx * qz - qw * qy);
+    Rq[7] = 2.0 * (qy * qz + qw * qx);
+    Rq[8] = 1.0 - 2.0 * (qx * qx + qy * qy);
+
+    // Sigma_3D = (R S)(R S)^T
+    const double sc[3] = {(double)s0, (double)s1, (double)s2};
+    double M[9];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) M[3 * r + c] = Rq[3 * r + c] * sc[c];
+    double S3[9];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            S3[3 * r + c] = (M[3 * r] * M[3 * c] + M[3 * r + 1] * M[3 * c + 1]) +
+                            M[3 * r + 2] * M[3 * c + 2];
+
+    // EWA projection with the Jacobian at the FOV-clamped mean
+    const double limx = kFovClamp * ((0.5 * (double)cam.width) / fx);
+    const double limy = kFovClamp * ((0.5 * (double)cam.height) / fy);
+    double txz = x / z, tyz = y / z;
+    txz = txz < -limx ? -limx : txz;
+    txz = txz > limx ? limx : txz;
+    tyz = tyz < -limy ? -limy : tyz;
+    tyz = tyz > limy ? limy : tyz;
+    const double J00 = fx / z, J02 = -(fx * txz) / z;
+    const double J11 = fy / z, J12 = -(fy * tyz) / z;
+    const double Rc[9] = {R0, R1, R2, R3, R4, R5, R6, R7, R8};
+    double T[6];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        T[j] = J00 * Rc[j] + J02 * Rc[6 + j];
+        T[3 + j] = J11 * Rc[3 + j] + J12 * Rc[6 + j];
+    }
+    double V[6];
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            V[3 * r + c] = (T[3 * r] * S3[c] + T[3 * r + 1] * S3[3 + c]) + T[3 * r + 2] * S3[6 + c];
+    const double s00 = (V[0] * T[0] + V[1] * T[1]) + V[2] * T[2];
+    const double s01 = (V[0] * T[3] + V[1] * T[4]) + V[2] * T[5];
+    const double s11 = (V[3] * T[3] + V[4] * T[4]) + V[5] * T[5];
+    const double A = s00 + kDilation, B = s01, C = s11 + kDilation;
+    const double D = A * C - B * B;
+    const float ca = (float)(C / D), cb = (float)(-B / D), cc = (float)(A / D);
+    const float tt = (float)(2.0 * log(255.0 * (double)op));
+    if (!(D > 0.0) || (mode != SS_TILE_3SIGMA && !(tt > 0.0f))) {
+        geom[i] = zero; conic[i] = zero; rgb_out[i] = zero; counts[i] = 0u;
+        return;
+    }
+
+    // view-dependent colour from SH (FP32)
+    const float cpx = -((cam.R[0] * cam.t[0] + cam.R[3] * cam.t[1]) + cam.R[6] * cam.t[2]);
+    const float cpy = -((cam.R[1] * cam.t[0] + cam.R[4] * cam.t[1]) + cam.R[7] * cam.t[2]);
+    const float cpz = -((cam.R[2] * cam.t[0] + cam.R[5] * cam.t[1]) + cam.R[8] * cam.t[2]);
+    float dx = m0 - cpx, dy = m1 - cpy, dz = m2 - cpz;
+    const float inv = 1.0f / sqrtf(dx * dx + dy * dy + dz * dz);
+    dx *= inv; dy *= inv; dz *= inv;
+    const float* h = in.sh + (int64_t)3 * in.sh_stride * i;
+    float Y[16];
+    Y[0] = kSH0;
+    int nb = 1;
+    if (in.sh_degree >= 1) {
+        Y[1] = -kSH1 * dy; Y[2] = kSH1 * dz; Y[3] = -kSH1 * dx;
+        nb = 4;
+    }
+    if (in.sh_degree >= 2) {
+        const float xx = dx * dx, yy = dy * dy, zz = dz * dz;
+        Y[4] = kSH2a * (dx * dy);
+        Y[5] = -kSH2a * (dy * dz);
+        Y[6] = kSH2b * (2.0f * zz - xx - yy);
+        Y[7] = -kSH2a * (dx * dz);
+        Y[8] = kSH2c * (xx - yy);
+        nb = 9;
+        if (in.sh_degree >= 3) {
+            Y[9] = -kSH3a * dy * (3.0f * xx - yy);
+            Y[10] = kSH3b * (dx * dy * dz);
+            Y[11] = -kSH3c * dy * (4.0f * zz - xx - yy);
+            Y[12] = kSH3d * dz * (2.0f * zz - 3.0f * xx - 3.0f * yy);
+            Y[13] = -kSH3c * dx * (4.0f * zz - xx - yy);
+            Y[14] = kSH3e * dz * (xx - yy);
+            Y[15] = -kSH3a * dx * (xx - 3.0f * yy);
+            nb = 16;
+        }
+    }
+    float cr = 0.f, cg = 0.f, cbl = 0.f;
+    for (int k = 0; k < nb; ++k) {
+        cr = fmaf(Y[k], h[3 * k], cr);
+        cg = fmaf(Y[k], h[3 * k + 1], cg);
+        cbl = fmaf(Y[k], h[3 * k + 2], cbl);
+    }
+    cr = fmaxf(cr + 0.5f, 0.0f);
+    cg = fmaxf(cg + 0.5f, 0.0f);
+    cbl = fmaxf(cbl + 0.5f, 0.0f);
+
+    const float4 g4 = make_float4((float)u, (float)v, (float)z, tt);
+    const float4 q4 = make_float4(ca, cb, cc, op);
+    geom[i] = g4;
+    conic[i] = q4;
+    rgb_out[i] = make_float4(cr, cg, cbl, 0.0f);
+    counts[i] = count_tiles(g4, q4, mode, tx_n, ty_n);
+}
+
+}  // namespace
+
+hipError_t launch_preprocess(const ss_camera& cam, const ss_gaussians& g, int mode,
+                             const ss_frame& f, hipStream_t s) {
+    if (g.n == 0) return hipSuccess;
+    const int tx_n = (cam.width + kTile - 1) / kTile, ty_n = (cam.height + kTile - 1) / kTile;
+    Inputs in{g.means, g.scales, g.quats, g.opacity, g.sh, g.sh_degree, g.sh_stride};
+    const int block = 256;
+    const int64_t grid = (g.n + block - 1) / block;
+    hipLaunchKernelGGL(k_preprocess, dim3((unsigned)grid), dim3(block), 0, s, cam, in, g.n, mode,
+                       tx_n, ty_n, reinterpret_cast<float4*>(f.geom),
+                       reinterpret_cast<float4*>(f.conic), reinterpret_cast<float4*>(f.rgb),
+                       f.counts);
+    return hipGetLastError();
+}
+
+}  // namespace ss

@@ -1,0 +1,203 @@
+// Internal declarations of the gfx950 Speedy-Splat library.
+//
+// Build flags (see build.py): -O3 --offload-arch=gfx950 -ffp-contract=off and
+// packed FP32 disabled.  With contraction off every + - * / sqrt below is one
+// IEEE operation rounded once, in the written order; FP64 division and square
+// root are correctly rounded on gfx950, so the FP64 geometry is reproducible.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/speedysplat.h"
+
+namespace ss {
+
+constexpr int kTile = 16;                 // Sec. 3.1: 16 x 16 pixel tiles
+constexpr double kDilation = 0.3;         // added to the diagonal of Sigma_2D
+constexpr double kFovClamp = 1.3;         // J evaluated with x/z, y/z clamped to 1.3x half-FOV
+constexpr double kDiscFloor = 0.1;        // floor of the eigenvalue discriminant (3-sigma)
+constexpr float kAlphaMax = 0.99f;        // upper clamp of alpha
+constexpr float kTMin = 1e-4f;            // transmittance stop
+constexpr float kAlphaMin = 1.0f / 255.0f;  // inclusion cutoff, used as q <= t
+
+// ---------------------------------------------------------------- tile geometry
+//
+// All tile decisions are FP64 functions of the stored FP32 record
+// (u, v, t) = geom.xyw and (a, b, c) = conic.xyz.
+
+struct Ellipse {
+    double u, v, a, b, c, t, det, hx, hy;
+    int x0, x1, y0, y1;  // inclusive tile rectangle
+};
+
+// Edge -> tile index: divide by the tile size, round down, clip to the grid.
+__device__ __forceinline__ int tile_lo(double x, int n) {
+    double f = floor(x / 16.0);
+    f = f < 0.0 ? 0.0 : f;
+    f = f > (double)n ? (double)n : f;
+    return (int)f;
+}
+__device__ __forceinline__ int tile_hi(double x, int n) {
+    double f = floor(x / 16.0);
+    f = f < -1.0 ? -1.0 : f;
+    f = f > (double)(n - 1) ? (double)(n - 1) : f;
+    return (int)f;
+}
+
+// Sets up the record ellipse and the mode's tile rectangle.  False when the
+// record cannot touch a tile (culled record or rectangle outside the image).
+__device__ __forceinline__ bool ellipse_setup(float4 g, float4 q, int mode, int tx_n, int ty_n,
+                                              Ellipse& e) {
+    e.u = g.x; e.v = g.y; e.t = g.w;
+    e.a = q.x; e.b = q.y; e.c = q.z;
+    e.det = e.a * e.c - e.b * e.b;
+    e.hx = 0.0; e.hy = 0.0;
+    if (!(e.det > 0.0)) return false;
+    double xl, xh, yl, yh;
+    if (mode == SS_TILE_3SIGMA) {
+        // Eq. radius: r = ceil(3 sqrt(lambda_max)) of the record covariance.
+        double sxx = e.c / e.det, syy = e.a / e.det;
+        double mid = 0.5 * (sxx + syy);
+        double disc = mid * mid - 1.0 / e.det;
+        disc = disc < kDiscFloor ? kDiscFloor : disc;
+        double lam = mid + sqrt(disc);
+        double r = ceil(3.0 * sqrt(lam));
+        xl = e.u - r; xh = e.u + r; yl = e.v - r; yh = e.v + r;
+    } else {
+        if (!(e.t > 0.0)) return false;
+        // SnugBox (Sec. 4.1.1): extremes of a x^2 + 2bxy + c y^2 = t.
+        e.hx = sqrt((e.t * e.c) / e.det);
+        e.hy = sqrt((e.t * e.a) / e.det);
+        xl = e.u - e.hx; xh = e.u + e.hx; yl = e.v - e.hy; yh = e.v + e.hy;
+    }
+    e.x0 = tile_lo(xl, tx_n); e.x1 = tile_hi(xh, tx_n);
+    e.y0 = tile_lo(yl, ty_n); e.y1 = tile_hi(yh, ty_n);
+    return e.x0 <= e.x1 && e.y0 <= e.y1;
+}
+
+// Intersections of the ellipse with the horizontal line y = Y (x roots).
+__device__ __forceinline__ void row_roots(const Ellipse& e, double Y, double& xl, double& xr) {
+    double dy = Y - e.v;
+    double rad = e.t * e.a - (e.det * dy) * dy;
+    double s = sqrt(rad > 0.0 ? rad : 0.0);
+    double bd = e.b * dy;
+    xl = e.u + (-bd - s) / e.a;
+    xr = e.u + (-bd + s) / e.a;
+}
+
+// Intersections with the vertical line x = X (Eq. ellipse_intersect, y roots).
+__device__ __forceinline__ void col_roots(const Ellipse& e, double X, double& yt, double& yb) {
+    double dx = X - e.u;
+    double rad = e.t * e.c - (e.det * dx) * dx;
+    double s = sqrt(rad > 0.0 ? rad : 0.0);
+    double bd = e.b * dx;
+    yt = e.v + (-bd - s) / e.c;
+    yb = e.v + (-bd + s) / e.c;
+}
+
+// Walks the tile spans of a record in enumeration order and calls
+// span(major, lo, hi) for every non-empty span: for 3-sigma / SnugBox and for
+// AccuTile-by-rows, major = ty and [lo, hi] is a tx interval; for
+// AccuTile-by-columns (more rows than columns), major = tx and [lo, hi] is a
+// ty interval.  Returns true when the spans are column spans.
+//
+// AccuTile (Alg. 1): a band's extent along the other axis is the SnugBox
+// extremal point when it lies inside the band, else the extreme of the two
+// band-boundary intersections; consecutive bands share their boundary, so one
+// new intersection is computed per band.
+template <class Span>
+__device__ __forceinline__ bool for_each_span(const Ellipse& e, int mode, int tx_n, int ty_n,
+                                              Span&& span) {
+    if (mode != SS_TILE_ACCUTILE) {
+        for (int ty = e.y0; ty <= e.y1; ++ty) span(ty, e.x0, e.x1);
+        return false;
+    }
+    const int nrows = e.y1 - e.y0 + 1, ncols = e.x1 - e.x0 + 1;
+    if (nrows <= ncols) {
+        const double k = (e.b / e.c) * e.hx;
+        const double y_left = e.v + k, y_right = e.v - k;
+        const double box_b = e.v - e.hy, box_t = e.v + e.hy;
+        const double x_min = e.u - e.hx, x_max = e.u + e.hx;
+        double ylo = 16.0 * e.y0;
+        ylo = ylo < box_b ? box_b : ylo;
+        double l0, r0;
+        row_roots(e, ylo, l0, r0);
+        for (int ty = e.y0; ty <= e.y1; ++ty) {
+            double yhi = 16.0 * ty + 16.0;
+            yhi = yhi > box_t ? box_t : yhi;
+            double l1, r1;
+            row_roots(e, yhi, l1, r1);
+            double left = (ylo <= y_left && y_left <= yhi) ? x_min : (l0 < l1 ? l0 : l1);
+            double right = (ylo <= y_right && y_right <= yhi) ? x_max : (r0 > r1 ? r0 : r1);
+            int lo = tile_lo(left, tx_n), hi = tile_hi(right, tx_n);
+            lo = lo < e.x0 ? e.x0 : lo;
+            hi = hi > e.x1 ? e.x1 : hi;
+            if (lo <= hi) span(ty, lo, hi);
+            ylo = yhi; l0 = l1; r0 = r1;
+        }
+        return false;
+    }
+    const double m = (e.b / e.a) * e.hy;
+    const double x_top = e.u + m, x_bot = e.u - m;
+    const double box_l = e.u - e.hx, box_r = e.u + e.hx;
+    const double y_min = e.v - e.hy, y_max = e.v + e.hy;
+    double xlo = 16.0 * e.x0;
+    xlo = xlo < box_l ? box_l : xlo;
+    double t0, b0;
+    col_roots(e, xlo, t0, b0);
+    for (int tx = e.x0; tx <= e.x1; ++tx) {
+        double xhi = 16.0 * tx + 16.0;
+        xhi = xhi > box_r ? box_r : xhi;
+        double t1, b1;
+        col_roots(e, xhi, t1, b1);
+        double top = (xlo <= x_top && x_top <= xhi) ? y_min : (t0 < t1 ? t0 : t1);
+        double bot = (xlo <= x_bot && x_bot <= xhi) ? y_max : (b0 > b1 ? b0 : b1);
+        int lo = tile_lo(top, ty_n), hi = tile_hi(bot, ty_n);
+        lo = lo < e.y0 ? e.y0 : lo;
+        hi = hi > e.y1 ? e.y1 : hi;
+        if (lo <= hi) span(tx, lo, hi);
+        xlo = xhi; t0 = t1; b0 = b1;
+    }
+    return true;
+}
+
+__device__ __forceinline__ uint32_t count_tiles(float4 g, float4 q, int mode, int tx_n, int ty_n) {
+    Ellipse e;
+    if (!ellipse_setup(g, q, mode, tx_n, ty_n, e)) return 0u;
+    uint32_t n = 0;
+    for_each_span(e, mode, tx_n, ty_n, [&](int, int lo, int hi) { n += (uint32_t)(hi - lo + 1); });
+    return n;
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs of MI355X.  This maps
+// launch index b (grid = 8 * ceil(n/8)) to item b % 8 * ceil(n/8) + b / 8, so
+// every XCD walks a contiguous run of items and keeps their shared data in its
+// own L2.  Returns -1 for the padding indices.
+__device__ __forceinline__ int xcd_contiguous(int b, int n) {
+    int per = (n + 7) >> 3;
+    int t = (b & 7) * per + (b >> 3);
+    return t < n ? t : -1;
+}
+
+__device__ __forceinline__ unsigned lane_id() { return __lane_id(); }
+
+// ---------------------------------------------------------------- launchers
+// (each returns hipSuccess or the launch error)
+
+hipError_t launch_preprocess(const ss_camera& cam, const ss_gaussians& g, int mode,
+                             const ss_frame& f, hipStream_t s);
+hipError_t launch_scan(int64_t n, const ss_frame& f, hipStream_t s);
+int64_t scan_tmp_words(int64_t n);
+hipError_t launch_emit(int tx_n, int ty_n, int64_t n, int mode, const ss_frame& f,
+                       uint64_t* keys, uint32_t* values, uint64_t n_pairs, hipStream_t s);
+int64_t sort_tmp_words(uint64_t capacity);
+int sort_passes(int bits);
+hipError_t launch_sort(const ss_pairs& p, int buf, uint64_t n_pairs, int bits, int* out_buf,
+                       hipStream_t s);
+hipError_t launch_ranges(const uint64_t* keys, uint64_t n_pairs, int n_tiles, uint32_t* ranges,
+                         hipStream_t s);
+hipError_t launch_blend(const ss_camera& cam, const ss_frame& f, const uint32_t* values,
+                        float* out_rgb, hipStream_t s);
+
+}  // namespace ss

@@ -1,0 +1,260 @@
+"""Python face of the rasterizer: device buffers from torch, work in the library.
+
+    import paper_2412_00578_amd as ss
+    g = ss.Gaussians.from_arrays(means, scales, quats, opacity, sh, sh_degree, device="cuda")
+    r = ss.Renderer()
+    image = r.render(g, camera, "accutile")          # [3, H, W] float32 on the device
+
+torch allocates every buffer (the library allocates nothing) and supplies the
+stream; each call below is one or more C-ABI calls on the current stream.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import check, lib, make_camera, mode_id
+
+
+def _ptr(t: torch.Tensor | None):
+    return ctypes.c_void_p(t.data_ptr() if t is not None else 0)
+
+
+def _stream(device) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+class Gaussians:
+    """Device-resident Gaussian parameters (the C ABI's ss_gaussians)."""
+
+    def __init__(self, means, scales, quats, opacity, sh, sh_degree: int):
+        self.means = means.contiguous()
+        self.scales = scales.contiguous()
+        self.quats = quats.contiguous()
+        self.opacity = opacity.contiguous().reshape(-1)
+        self.sh = sh.contiguous()
+        self.sh_degree = int(sh_degree)
+        for t in (self.means, self.scales, self.quats, self.opacity, self.sh):
+            if t.dtype != torch.float32:
+                raise TypeError("Gaussian parameters must be float32")
+
+    @classmethod
+    def from_arrays(cls, means, scales, quats, opacity, sh, sh_degree, device="cuda"):
+        f = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.float32), device=device)
+        return cls(f(means), f(scales), f(quats), f(opacity), f(sh), sh_degree)
+
+    @classmethod
+    def from_scene(cls, scene, device="cuda"):
+        return cls.from_arrays(scene.means, scene.scales, scene.quats, scene.opacity, scene.sh,
+                               scene.sh_degree, device)
+
+    @property
+    def n(self) -> int:
+        return int(self.means.shape[0])
+
+    @property
+    def device(self):
+        return self.means.device
+
+    @property
+    def nbytes(self) -> int:
+        return sum(t.numel() * 4 for t in (self.means, self.scales, self.quats, self.opacity,
+                                           self.sh))
+
+    def struct(self) -> _lib.SSGaussians:
+        s = _lib.SSGaussians()
+        s.n = self.n
+        s.sh_degree = self.sh_degree
+        s.sh_stride = int(self.sh.shape[1]) if self.sh.dim() == 3 else 1
+        s.means, s.scales, s.quats = (self.means.data_ptr(), self.scales.data_ptr(),
+                                      self.quats.data_ptr())
+        s.opacity, s.sh = self.opacity.data_ptr(), self.sh.data_ptr()
+        return s
+
+
+class Frame:
+    """Per-frame buffers (ss_frame) for n Gaussians at width x height."""
+
+    def __init__(self, n: int, width: int, height: int, device):
+        info = _lib.SSFrameInfo()
+        check(lib().ss_frame_sizes(n, width, height, ctypes.byref(info)), "ss_frame_sizes")
+        self.info = info
+        self.n, self.width, self.height = n, width, height
+        dev = torch.device(device)
+        self.geom = torch.empty((n, 4), dtype=torch.float32, device=dev)
+        self.conic = torch.empty((n, 4), dtype=torch.float32, device=dev)
+        self.rgb = torch.empty((n, 4), dtype=torch.float32, device=dev)
+        self.counts = torch.empty(n, dtype=torch.int32, device=dev)
+        self.offsets = torch.empty(n, dtype=torch.int32, device=dev)
+        self.scan_tmp = torch.zeros(int(info.scan_tmp_words), dtype=torch.int64, device=dev)
+        self.ranges = torch.empty((info.n_tiles, 2), dtype=torch.int32, device=dev)
+        self.t_final = torch.empty((height, width), dtype=torch.float32, device=dev)
+        self.n_last = torch.empty((height, width), dtype=torch.int32, device=dev)
+        self.n_eval = torch.empty((height, width), dtype=torch.int32, device=dev)
+
+    def struct(self) -> _lib.SSFrame:
+        f = _lib.SSFrame()
+        for name in ("geom", "conic", "rgb", "counts", "offsets", "scan_tmp", "ranges",
+                     "t_final", "n_last", "n_eval"):
+            setattr(f, name, getattr(self, name).data_ptr())
+        return f
+
+    def fits(self, n, width, height) -> bool:
+        return self.n == n and self.width == width and self.height == height
+
+
+class Pairs:
+    """Pair workspace (ss_pairs): two key/value buffers and sort scratch."""
+
+    def __init__(self, capacity: int, device):
+        dev = torch.device(device)
+        cap = max(int(capacity), 1)
+        self.capacity = cap
+        self.keys = [torch.empty(cap, dtype=torch.int64, device=dev) for _ in range(2)]
+        self.values = [torch.empty(cap, dtype=torch.int32, device=dev) for _ in range(2)]
+        w = ctypes.c_int64()
+        check(lib().ss_sort_tmp_words(cap, ctypes.byref(w)), "ss_sort_tmp_words")
+        self.sort_tmp = torch.empty(int(w.value), dtype=torch.int32, device=dev)
+
+    def struct(self) -> _lib.SSPairs:
+        p = _lib.SSPairs()
+        p.capacity = self.capacity
+        p.keys[0], p.keys[1] = self.keys[0].data_ptr(), self.keys[1].data_ptr()
+        p.values[0], p.values[1] = self.values[0].data_ptr(), self.values[1].data_ptr()
+        p.sort_tmp = self.sort_tmp.data_ptr()
+        return p
+
+
+STAGES = ("preprocess", "scan", "readback", "emit", "sort", "ranges", "blend")
+
+
+class StageEvents:
+    """Eight timing events recorded by the library at stage boundaries."""
+
+    def __init__(self, device):
+        self.events = [torch.cuda.Event(enable_timing=True) for _ in range(8)]
+        s = torch.cuda.current_stream(device)
+        for e in self.events:  # creates the underlying hipEvent_t
+            e.record(s)
+        s.synchronize()
+
+    def struct(self) -> _lib.SSStageEvents:
+        st = _lib.SSStageEvents()
+        for k, e in enumerate(self.events):
+            st.ev[k] = e.cuda_event
+        return st
+
+    def stage_ms(self) -> dict:
+        """Per-stage milliseconds of the last recorded frame (after a sync)."""
+        ev = self.events
+        return {name: ev[k].elapsed_time(ev[k + 1]) for k, name in enumerate(STAGES)}
+
+    def frame_ms(self) -> float:
+        return self.events[0].elapsed_time(self.events[7])
+
+
+@dataclass
+class RenderOutput:
+    image: torch.Tensor      # [3, H, W]
+    n_pairs: int
+    frame: Frame
+    pairs: Pairs
+    buf: int                 # pair buffer holding the sorted pairs
+
+
+class Renderer:
+    """Owns reusable frame and pair buffers; grows them on demand."""
+
+    def __init__(self, device="cuda", growth: float = 1.25):
+        self.device = torch.device(device)
+        self.growth = growth
+        self._frame: Frame | None = None
+        self._pairs: Pairs | None = None
+
+    def frame_for(self, n, width, height) -> Frame:
+        if self._frame is None or not self._frame.fits(n, width, height):
+            self._frame = Frame(n, width, height, self.device)
+        return self._frame
+
+    def pairs_for(self, n_pairs) -> Pairs:
+        if self._pairs is None or self._pairs.capacity < n_pairs:
+            self._pairs = None
+            self._pairs = Pairs(int(max(n_pairs, 1) * self.growth) + 1024, self.device)
+        return self._pairs
+
+    # ---- whole forward -------------------------------------------------------
+    def render(self, g: Gaussians, cam, mode="accutile", out: torch.Tensor | None = None,
+               full: bool = False, events: "StageEvents | None" = None):
+        """Forward render.  Returns the image [3,H,W] (or a RenderOutput if full).
+        ``events`` (a StageEvents) records per-stage timing on the stream."""
+        m = mode_id(mode)
+        c = make_camera(cam)
+        frame = self.frame_for(g.n, c.width, c.height)
+        if out is None:
+            out = torch.empty((3, c.height, c.width), dtype=torch.float32, device=self.device)
+        gs, fs = g.struct(), frame.struct()
+        stream = _stream(self.device)
+        n_pairs = ctypes.c_uint64()
+        ev = events.struct() if events is not None else None
+        evp = ctypes.byref(ev) if ev is not None else None
+        check(lib().ss_forward_begin(ctypes.byref(c), ctypes.byref(gs), m, ctypes.byref(fs),
+                                     ctypes.byref(n_pairs), evp, stream), "ss_forward_begin")
+        pairs = self.pairs_for(n_pairs.value)
+        ps = pairs.struct()
+        buf = ctypes.c_int32()
+        check(lib().ss_forward_finish(ctypes.byref(c), g.n, m, ctypes.byref(fs), ctypes.byref(ps),
+                                      n_pairs.value, _ptr(out), ctypes.byref(buf), evp, stream),
+              "ss_forward_finish")
+        if full:
+            return RenderOutput(out, int(n_pairs.value), frame, pairs, int(buf.value))
+        return out
+
+    # ---- single stages (for tests and profiling) ---------------------------
+    def preprocess(self, g: Gaussians, cam, mode) -> Frame:
+        c = make_camera(cam)
+        frame = self.frame_for(g.n, c.width, c.height)
+        gs, fs = g.struct(), frame.struct()
+        check(lib().ss_preprocess(ctypes.byref(c), ctypes.byref(gs), mode_id(mode),
+                                  ctypes.byref(fs), _stream(self.device)), "ss_preprocess")
+        return frame
+
+    def scan(self, frame: Frame) -> int:
+        fs = frame.struct()
+        check(lib().ss_scan(frame.n, ctypes.byref(fs), _stream(self.device)), "ss_scan")
+        torch.cuda.current_stream(self.device).synchronize()
+        return int(frame.scan_tmp[0].item())
+
+    def emit(self, cam, frame: Frame, mode, n_pairs: int, buf: int = 0) -> Pairs:
+        c = make_camera(cam)
+        pairs = self.pairs_for(n_pairs)
+        fs, ps = frame.struct(), pairs.struct()
+        check(lib().ss_emit(ctypes.byref(c), frame.n, mode_id(mode), ctypes.byref(fs),
+                            ctypes.byref(ps), buf, n_pairs, _stream(self.device)), "ss_emit")
+        return pairs
+
+    def sort(self, cam, pairs: Pairs, n_pairs: int, buf: int = 0) -> int:
+        c = make_camera(cam)
+        ps = pairs.struct()
+        ob = ctypes.c_int32()
+        check(lib().ss_sort(ctypes.byref(c), ctypes.byref(ps), buf, n_pairs, ctypes.byref(ob),
+                            _stream(self.device)), "ss_sort")
+        return int(ob.value)
+
+    def ranges(self, cam, frame: Frame, pairs: Pairs, n_pairs: int, buf: int):
+        c = make_camera(cam)
+        fs, ps = frame.struct(), pairs.struct()
+        check(lib().ss_ranges(ctypes.byref(c), ctypes.byref(fs), ctypes.byref(ps), buf, n_pairs,
+                              _stream(self.device)), "ss_ranges")
+
+    def blend(self, cam, frame: Frame, pairs: Pairs, buf: int, out=None) -> torch.Tensor:
+        c = make_camera(cam)
+        if out is None:
+            out = torch.empty((3, c.height, c.width), dtype=torch.float32, device=self.device)
+        fs, ps = frame.struct(), pairs.struct()
+        check(lib().ss_blend(ctypes.byref(c), ctypes.byref(fs), ctypes.byref(ps), buf, _ptr(out),
+                             _stream(self.device)), "ss_blend")
+        return out

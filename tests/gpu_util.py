@@ -1,0 +1,87 @@
+"""Helpers shared by the GPU tests: run the HIP pipeline stage by stage and
+compare every intermediate with the oracle."""
+import numpy as np
+import torch
+
+import oracle
+
+
+def u32(t: torch.Tensor) -> np.ndarray:
+    return t.detach().cpu().numpy().view(np.uint32)
+
+
+def u64(t: torch.Tensor) -> np.ndarray:
+    return t.detach().cpu().numpy().view(np.uint64)
+
+
+def gpu_stages(renderer, g, cam, mode):
+    """Runs the six stages one call at a time; returns every intermediate."""
+    frame = renderer.preprocess(g, cam, mode)
+    torch.cuda.synchronize()
+    out = {
+        "geom": frame.geom.cpu().numpy().copy(),
+        "conic": frame.conic.cpu().numpy().copy(),
+        "rgb": frame.rgb.cpu().numpy().copy(),
+        "counts": u32(frame.counts).copy(),
+    }
+    p = renderer.scan(frame)
+    out["n_pairs"] = p
+    out["offsets"] = u32(frame.offsets).copy()
+    pairs = renderer.emit(cam, frame, mode, p, buf=0)
+    torch.cuda.synchronize()
+    out["keys"] = u64(pairs.keys[0][:p]).copy()
+    out["values"] = u32(pairs.values[0][:p]).copy()
+    ob = renderer.sort(cam, pairs, p, 0)
+    renderer.ranges(cam, frame, pairs, p, ob)
+    img = renderer.blend(cam, frame, pairs, ob)
+    torch.cuda.synchronize()
+    out["sorted_keys"] = u64(pairs.keys[ob][:p]).copy()
+    out["sorted_values"] = u32(pairs.values[ob][:p]).copy()
+    out["ranges"] = u32(frame.ranges).copy()
+    out["image"] = img.cpu().numpy()
+    out["t_final"] = frame.t_final.cpu().numpy().copy()
+    out["n_last"] = u32(frame.n_last).copy()
+    out["n_eval"] = u32(frame.n_eval).copy()
+    return out
+
+
+def first_diffs(a, b, k=5):
+    idx = np.nonzero(a != b)[0][:k]
+    return [(int(i), a[i], b[i]) for i in idx]
+
+
+def assert_records_equal(gpu, ref: "oracle.Records"):
+    g32, r32 = gpu["geom"].view(np.uint32), ref.geom.view(np.uint32)
+    bad = np.nonzero((g32 != r32).any(axis=1))[0]
+    assert len(bad) == 0, f"{len(bad)} geom mismatches, e.g. " + str(
+        [(int(i), gpu["geom"][i].tolist(), ref.geom[i].tolist()) for i in bad[:3]])
+    c32, q32 = gpu["conic"].view(np.uint32), ref.conic.view(np.uint32)
+    bad = np.nonzero((c32 != q32).any(axis=1))[0]
+    assert len(bad) == 0, f"{len(bad)} conic mismatches, e.g. " + str(
+        [(int(i), gpu["conic"][i].tolist(), ref.conic[i].tolist()) for i in bad[:3]])
+    np.testing.assert_allclose(gpu["rgb"], ref.rgb, rtol=1e-6, atol=2e-6)
+    bad = np.nonzero(gpu["counts"] != ref.counts)[0]
+    assert len(bad) == 0, f"{len(bad)} count mismatches " + str(first_diffs(gpu["counts"],
+                                                                            ref.counts))
+
+
+def assert_pipeline_equal(gpu, fr, image_tol=1e-4):
+    """Bit-exact integer intermediates; image within image_tol except where the
+    oracle flags a stop decision that exp rounding may flip."""
+    assert_records_equal(gpu, fr.records)
+    assert gpu["n_pairs"] == fr.n_pairs
+    assert np.array_equal(gpu["offsets"], fr.offsets.astype(np.uint32))
+    assert np.array_equal(gpu["keys"], fr.keys), first_diffs(gpu["keys"], fr.keys)
+    assert np.array_equal(gpu["values"], fr.values)
+    assert np.array_equal(gpu["sorted_keys"], fr.sorted_keys), \
+        first_diffs(gpu["sorted_keys"], fr.sorted_keys)
+    assert np.array_equal(gpu["sorted_values"], fr.sorted_values)
+    assert np.array_equal(gpu["ranges"], fr.ranges)
+    if fr.image is not None:
+        ok = ~fr.ambiguous
+        d = np.abs(gpu["image"] - fr.image)[:, ok]
+        assert d.max(initial=0.0) <= image_tol, f"image max diff {d.max()}"
+        assert np.abs(gpu["t_final"] - fr.t_final)[ok].max(initial=0.0) <= 1e-5
+        assert np.array_equal(gpu["n_last"][ok], fr.n_last[ok])
+        assert np.array_equal(gpu["n_eval"][ok], fr.n_eval[ok])
+        assert ok.mean() > 0.999

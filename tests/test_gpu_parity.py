@@ -1,0 +1,197 @@
+"""GPU parity: every stage of the HIP pipeline against the CPU oracle.
+
+Integers (counts, offsets, pair count, keys, values, ranges) and the FP32
+records (u, v, depth, t, a, b, c) must match bit for bit; colours within
+1e-6 relative; images within 1e-4 per channel except at pixels where the oracle
+flags a stop decision that a different (faithful) exp could flip.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import scenegen
+from gpu_util import assert_pipeline_equal, gpu_stages, u32, u64
+
+pytestmark = pytest.mark.gpu
+MODES = ["3sigma", "snugbox", "accutile"]
+
+
+@pytest.fixture(scope="module")
+def ss():
+    import paper_2412_00578_amd as ss
+    ss.lib()
+    return ss
+
+
+def _run(ss, dev, scene, cam, mode):
+    print(f"[case] n={scene.n} {cam.width}x{cam.height} mode={mode}", flush=True)
+    r = ss.Renderer(dev)
+    g = ss.Gaussians.from_scene(scene, dev)
+    return gpu_stages(r, g, cam, mode)
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_c0_all_stages(ss, gpu_device, mode):
+    sc, cam = scenegen.scene_c0(), scenegen.camera_c0()
+    gpu = _run(ss, gpu_device, sc, cam, mode)
+    assert_pipeline_equal(gpu, oracle.render(sc, cam, mode))
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_c1_full_size(ss, gpu_device, mode):
+    # 1.5M Gaussians, SH degree 3, 1600x1040: the benchmark workload.
+    sc, cam = scenegen.scene_c1(), scenegen.camera_c1()
+    gpu = _run(ss, gpu_device, sc, cam, mode)
+    assert_pipeline_equal(gpu, oracle.render(sc, cam, mode))
+
+
+def test_c2_shape_other_camera(ss, gpu_device):
+    sc = scenegen.scene_c2()
+    cam = scenegen.cameras_c2(4)[3]
+    gpu = _run(ss, gpu_device, sc, cam, "accutile")
+    assert_pipeline_equal(gpu, oracle.render(sc, cam, "accutile"))
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_partial_edge_tiles(ss, gpu_device, mode):
+    # 1920x1080 has a half-filled last tile row; the camera sits inside the scene.
+    sc = scenegen.scene_blobs(60_000, 21, log_s=(-3.0, 1.0))
+    cam = scenegen.cameras_c1(8)[1].with_size(1920, 1080)
+    gpu = _run(ss, gpu_device, sc, cam, mode)
+    assert_pipeline_equal(gpu, oracle.render(sc, cam, mode))
+
+
+def test_odd_sizes_and_sh_degrees(ss, gpu_device):
+    # Ragged Gaussian count, tiny odd image, SH degree 1 and 2 stored with stride 16.
+    cam = scenegen.Camera(200, 70, 180.0, 180.0, 100.0, 35.0, np.eye(3), np.zeros(3))
+    for deg in (1, 2, 3):
+        sc = scenegen.scene_c0(n=4097, seed=30 + deg, sh_degree=3, log_s=(-3.0, 0.8))
+        sc.sh_degree = deg
+        for mode in MODES:
+            gpu = _run(ss, gpu_device, sc, cam, mode)
+            assert_pipeline_equal(gpu, oracle.render(sc, cam, mode))
+
+
+def test_degenerate_fixtures(ss, gpu_device):
+    # near plane, behind the camera, non-finite, zero quaternion, sigma < 1/255,
+    # a huge screen-filling Gaussian, Gaussians straddling the image edges.
+    cam = scenegen.Camera(96, 80, 90.0, 90.0, 48.0, 40.0, np.eye(3), np.zeros(3))
+    means = [(0, 0, 0.1), (0, 0, -3), (np.nan, 0, 3), (0, 0, 3), (0.1, 0, 3), (0, 0, 0.5),
+             (-0.55, 0.2, 1.0), (0.5, -0.45, 1.0), (0.05, 0.05, 2.0), (1.9, 0, 1.0)]
+    scales = [(0.05,) * 3, (0.05,) * 3, (0.05,) * 3, (0.05,) * 3, (0.05,) * 3, (2.0, 1.5, 1.0),
+              (0.1, 0.02, 0.05), (0.03, 0.2, 0.05), (0.0, 0.0, 0.0), (0.5, 0.5, 0.5)]
+    quats = [(1, 0, 0, 0)] * 3 + [(0, 0, 0, 0)] + [(1, 0, 0, 0)] * 2 + \
+        [(0.9, 0.1, 0.2, 0.3), (0.5, -0.5, 0.5, 0.5), (1, 0, 0, 0), (1, 0, 0, 0)]
+    opac = [0.5, 0.5, 0.5, 0.5, 1.0 / 300.0, 0.9, 0.8, 0.99, 0.6, 0.7]
+    cols = [(0.3, 0.6, 0.9)] * 10
+    sc = scenegen.fixture_scene(means, scales, quats, opac, cols)
+    for mode in MODES:
+        gpu = _run(ss, gpu_device, sc, cam, mode)
+        assert_pipeline_equal(gpu, oracle.render(sc, cam, mode))
+
+
+def test_empty_scene_gives_background(ss, gpu_device):
+    cam = scenegen.Camera(40, 24, 40.0, 40.0, 20.0, 12.0, np.eye(3), np.zeros(3),
+                          bg=(0.25, 0.5, 1.0))
+    sc = scenegen.fixture_scene(np.zeros((0, 3)), np.zeros((0, 3)), np.zeros((0, 4)),
+                                np.zeros(0), np.zeros((0, 3)))
+    r = ss.Renderer(gpu_device)
+    g = ss.Gaussians.from_scene(sc, gpu_device)
+    out = r.render(g, cam, "accutile", full=True)
+    torch.cuda.synchronize()
+    assert out.n_pairs == 0
+    img = out.image.cpu().numpy()
+    for ch, b in enumerate(cam.bg):
+        assert np.all(img[ch] == np.float32(b))
+    assert np.all(u32(out.frame.ranges) == 0)
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_composite_render_equals_stages(ss, gpu_device, mode):
+    sc, cam = scenegen.scene_c0(seed=3), scenegen.camera_c0()
+    r = ss.Renderer(gpu_device)
+    g = ss.Gaussians.from_scene(sc, gpu_device)
+    stages = gpu_stages(r, g, cam, mode)
+    out = r.render(g, cam, mode, full=True)
+    torch.cuda.synchronize()
+    assert out.buf == 0
+    p = out.n_pairs
+    assert p == stages["n_pairs"]
+    assert np.array_equal(u64(out.pairs.keys[0][:p]), stages["sorted_keys"])
+    assert np.array_equal(u32(out.pairs.values[0][:p]), stages["sorted_values"])
+    assert np.array_equal(out.image.cpu().numpy(), stages["image"])
+
+
+def test_forward_is_deterministic(ss, gpu_device):
+    sc, cam = scenegen.scene_c2(n=100_000), scenegen.cameras_c2(2)[1]
+    r = ss.Renderer(gpu_device)
+    g = ss.Gaussians.from_scene(sc, gpu_device)
+    a = r.render(g, cam, "accutile").clone()
+    b = r.render(g, cam, "accutile").clone()
+    assert torch.equal(a, b)
+
+
+def test_snugbox_and_accutile_images_identical(ss, gpu_device):
+    # The extra SnugBox pairs never pass q <= t, so the blends are bitwise equal.
+    sc, cam = scenegen.scene_c1(n=300_000, seed=5), scenegen.cameras_c1(8)[2]
+    r = ss.Renderer(gpu_device)
+    g = ss.Gaussians.from_scene(sc, gpu_device)
+    a = r.render(g, cam, "snugbox", full=True)
+    ia, pa = a.image.clone(), a.n_pairs
+    b = r.render(g, cam, "accutile", full=True)
+    assert b.n_pairs < pa
+    assert torch.equal(ia, b.image)
+
+
+def test_three_modes_identical_when_t_le_9(ss, gpu_device):
+    sc, cam = scenegen.scene_c0_lowsigma(), scenegen.camera_c0()
+    r = ss.Renderer(gpu_device)
+    g = ss.Gaussians.from_scene(sc, gpu_device)
+    imgs = [r.render(g, cam, m).clone() for m in MODES]
+    assert torch.equal(imgs[0], imgs[1]) and torch.equal(imgs[1], imgs[2])
+
+
+# ------------------------------------------------------------ primitives alone
+
+@pytest.mark.parametrize("n", [0, 1, 4095, 4096, 4097, 1_000_003, 6_000_000])
+def test_scan_matches_cumsum(ss, gpu_device, n):
+    print(f"[case] scan n={n}", flush=True)
+    rng = np.random.default_rng(n + 1)
+    counts = rng.integers(0, 12, size=n).astype(np.uint32)
+    f = ss.Frame(n, 16, 16, gpu_device)
+    f.counts.copy_(torch.from_numpy(counts.view(np.int32)))
+    r = ss.Renderer(gpu_device)
+    total = r.scan(f)
+    assert total == int(counts.astype(np.uint64).sum())
+    if n:
+        assert np.array_equal(u32(f.offsets), np.cumsum(counts, dtype=np.uint64).astype(np.uint32))
+
+
+@pytest.mark.parametrize("n", [0, 1, 2, 4095, 4097, 70_001, 5_000_003])
+def test_sort_and_ranges_random_keys(ss, gpu_device, n):
+    print(f"[case] sort n={n}", flush=True)
+    rng = np.random.default_rng(n + 7)
+    cam = scenegen.Camera(1600, 1040, 1000.0, 1000.0, 800.0, 520.0, np.eye(3), np.zeros(3))
+    n_tiles = cam.tiles_x * cam.tiles_y
+    tiles = rng.integers(0, n_tiles, size=n).astype(np.uint64)
+    # depth-like low words with many exact ties
+    low = rng.integers(0x3e000000, 0x3e000000 + 5000, size=n).astype(np.uint64)
+    keys = (tiles << np.uint64(32)) | low
+    vals = np.arange(n, dtype=np.uint32)
+    r = ss.Renderer(gpu_device)
+    pairs = r.pairs_for(n)
+    if n:
+        pairs.keys[0][:n].copy_(torch.from_numpy(keys.view(np.int64)))
+        pairs.values[0][:n].copy_(torch.from_numpy(vals.view(np.int32)))
+    ob = r.sort(cam, pairs, n, 0)
+    f = ss.Frame(1, cam.width, cam.height, gpu_device)
+    r.ranges(cam, f, pairs, n, ob)
+    torch.cuda.synchronize()
+    order = np.lexsort((vals, keys))
+    assert np.array_equal(u64(pairs.keys[ob][:n]), keys[order])
+    assert np.array_equal(u32(pairs.values[ob][:n]), vals[order])
+    st = (keys[order] >> np.uint64(32)).astype(np.int64)
+    rg = u32(f.ranges).reshape(-1, 2)
+    assert np.array_equal(rg[:, 0], np.searchsorted(st, np.arange(n_tiles), "left"))
+    assert np.array_equal(rg[:, 1], np.searchsorted(st, np.arange(n_tiles), "right"))
