@@ -85,6 +85,9 @@ def main():
     ap.add_argument("--n", type=int, default=1_500_000)
     ap.add_argument("--modes", default=",".join(MODES))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a 1 GiB device-to-device copy 5 times (the reference "
+                         "kernel for scaling HBM traffic counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -98,6 +101,14 @@ def main():
     import scenegen
 
     dev = torch.device("cuda:0")
+    if args.copy_calibration:
+        a = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_each_way": a.numel() * 4, "copies": 5}), flush=True)
+        return
     t0 = time.perf_counter()
     scene = scenegen.scene_c1(n=args.n)
     cams = scenegen.cameras_c1(8)
