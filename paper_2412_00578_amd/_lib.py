@@ -45,7 +45,7 @@ class SSGaussians(ctypes.Structure):
 class SSFrame(ctypes.Structure):
     _fields_ = [("geom", _vp), ("conic", _vp), ("rgb", _vp), ("counts", _vp), ("offsets", _vp),
                 ("scan_tmp", _vp), ("ranges", _vp), ("t_final", _vp), ("n_last", _vp),
-                ("n_eval", _vp)]
+                ("n_eval", _vp), ("emit_tmp", _vp)]
 
 
 class SSFrameInfo(ctypes.Structure):

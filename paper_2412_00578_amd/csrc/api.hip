@@ -57,8 +57,8 @@ int check_gaussians(const ss_gaussians* g) {
         return fail(SS_ERR_INVALID_ARG, "sh_stride %d < (deg+1)^2", g->sh_stride);
     if (g->n > 0 && (!g->means || !g->scales || !g->quats || !g->opacity || !g->sh))
         return fail(SS_ERR_INVALID_ARG, "a Gaussian parameter pointer is NULL");
-    if (g->n > 0 && !aligned16(g->quats))
-        return fail(SS_ERR_INVALID_ARG, "quats must be 16-byte aligned");
+    if (g->n > 0 && (!aligned16(g->quats) || !aligned16(g->sh)))
+        return fail(SS_ERR_INVALID_ARG, "quats and sh must be 16-byte aligned");
     return SS_OK;
 }
 
@@ -70,7 +70,7 @@ int check_mode(int32_t mode) {
 
 int check_frame_records(const ss_frame* f, int64_t n) {
     if (!f) return fail(SS_ERR_INVALID_ARG, "frame is NULL");
-    if (n > 0 && (!f->geom || !f->conic || !f->rgb || !f->counts || !f->offsets))
+    if (n > 0 && (!f->geom || !f->conic || !f->rgb || !f->counts || !f->offsets || !f->emit_tmp))
         return fail(SS_ERR_INVALID_ARG, "a per-Gaussian frame buffer is NULL");
     if (!aligned16(f->geom) || !aligned16(f->conic) || !aligned16(f->rgb))
         return fail(SS_ERR_INVALID_ARG, "frame records must be 16-byte aligned");

@@ -4,10 +4,30 @@
 // Gaussian i re-walks its tile spans with the same FP64 function the
 // preprocess stage counted with and writes key = tile_id << 32 | bits(depth),
 // value = i, at [offsets[i] - counts[i], offsets[i]).
+//
+// Tile counts are heavy-tailed (most Gaussians touch a few tiles, a Gaussian
+// near the camera thousands), so the work is split in two launches:
+//   k_emit      one lane per Gaussian writes Gaussians with <= 32 tiles and
+//               queues the others (one atomic per wave);
+//   k_emit_big  one wave per queued Gaussian: lanes compute up to 64 spans
+//               (rows, or columns for AccuTile on tall extents) at once, a wave
+//               prefix sum places them, and the wave writes the keys with
+//               consecutive lanes on consecutive addresses.
+// The emission order within a Gaussian is the same in both paths.
 #include "ss_internal.h"
 
 namespace ss {
 namespace {
+
+constexpr uint32_t kSmall = 32;
+constexpr int kBigBlock = 256;
+constexpr int kBigGrid = 1024;
+
+__device__ __forceinline__ bool span_columns(const Ellipse& e, int mode) {
+    return mode == SS_TILE_ACCUTILE && (e.y1 - e.y0 > e.x1 - e.x0);
+}
+
+__global__ void k_zero(uint32_t* p) { *p = 0u; }
 
 __global__ __launch_bounds__(256) void k_emit(int tx_n, int ty_n, int64_t n, int mode,
                                               uint32_t limit,
@@ -16,18 +36,30 @@ __global__ __launch_bounds__(256) void k_emit(int tx_n, int ty_n, int64_t n, int
                                               const uint32_t* __restrict__ counts,
                                               const uint32_t* __restrict__ offsets,
                                               uint64_t* __restrict__ keys,
-                                              uint32_t* __restrict__ values) {
+                                              uint32_t* __restrict__ values,
+                                              uint32_t* __restrict__ queue) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const uint32_t cnt = counts[i];
-    if (cnt == 0u) return;
+    const uint32_t cnt = i < n ? counts[i] : 0u;
+    const bool big = cnt > kSmall;
+    const uint64_t mask = __ballot(big);
+    if (mask) {
+        const int leader = __builtin_ctzll(mask);
+        uint32_t base = 0;
+        if ((int)__lane_id() == leader) base = atomicAdd(queue, (uint32_t)__popcll(mask));
+        base = __shfl(base, leader, 64);
+        const uint32_t slot = base + __builtin_amdgcn_mbcnt_hi(
+                                         (uint32_t)(mask >> 32),
+                                         __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+        if (big && slot < (uint32_t)n) queue[1 + slot] = (uint32_t)i;
+    }
+    if (cnt == 0u || big) return;
     const uint32_t end = offsets[i] < limit ? offsets[i] : limit;
     uint32_t pos = end - cnt;
     const float4 g = geom[i], q = conic[i];
     Ellipse e;
     if (!ellipse_setup(g, q, mode, tx_n, ty_n, e)) return;
     const uint64_t dbits = (uint64_t)__float_as_uint(g.z);
-    const bool cols = (mode == SS_TILE_ACCUTILE) && (e.y1 - e.y0 > e.x1 - e.x0);
+    const bool cols = span_columns(e, mode);
     const uint32_t vi = (uint32_t)i;
     for_each_span(e, mode, tx_n, ty_n, [&](int major, int lo, int hi) {
         for (int k = lo; k <= hi; ++k) {
@@ -41,18 +73,139 @@ __global__ __launch_bounds__(256) void k_emit(int tx_n, int ty_n, int64_t n, int
     });
 }
 
+// Span of one row (or column) of the record's tile rectangle; the same
+// arithmetic as one step of for_each_span (the band ends are clipped to the
+// SnugBox box, so an interior band boundary is the shared tile edge).
+__device__ __forceinline__ void one_span(const Ellipse& e, int mode, int tx_n, int ty_n, bool cols,
+                                         int major, int& lo, int& hi) {
+    if (mode != SS_TILE_ACCUTILE) {
+        lo = e.x0;
+        hi = e.x1;
+        return;
+    }
+    if (!cols) {
+        const double k = (e.b / e.c) * e.hx;
+        const double y_left = e.v + k, y_right = e.v - k;
+        const double box_b = e.v - e.hy, box_t = e.v + e.hy;
+        double ylo = 16.0 * major, yhi = 16.0 * major + 16.0;
+        ylo = ylo < box_b ? box_b : ylo;
+        yhi = yhi > box_t ? box_t : yhi;
+        double l0, r0, l1, r1;
+        row_roots(e, ylo, l0, r0);
+        row_roots(e, yhi, l1, r1);
+        const double left = (ylo <= y_left && y_left <= yhi) ? e.u - e.hx : (l0 < l1 ? l0 : l1);
+        const double right = (ylo <= y_right && y_right <= yhi) ? e.u + e.hx : (r0 > r1 ? r0 : r1);
+        lo = tile_lo(left, tx_n);
+        hi = tile_hi(right, tx_n);
+        lo = lo < e.x0 ? e.x0 : lo;
+        hi = hi > e.x1 ? e.x1 : hi;
+    } else {
+        const double m = (e.b / e.a) * e.hy;
+        const double x_top = e.u + m, x_bot = e.u - m;
+        const double box_l = e.u - e.hx, box_r = e.u + e.hx;
+        double xlo = 16.0 * major, xhi = 16.0 * major + 16.0;
+        xlo = xlo < box_l ? box_l : xlo;
+        xhi = xhi > box_r ? box_r : xhi;
+        double t0, b0, t1, b1;
+        col_roots(e, xlo, t0, b0);
+        col_roots(e, xhi, t1, b1);
+        const double top = (xlo <= x_top && x_top <= xhi) ? e.v - e.hy : (t0 < t1 ? t0 : t1);
+        const double bot = (xlo <= x_bot && x_bot <= xhi) ? e.v + e.hy : (b0 > b1 ? b0 : b1);
+        lo = tile_lo(top, ty_n);
+        hi = tile_hi(bot, ty_n);
+        lo = lo < e.y0 ? e.y0 : lo;
+        hi = hi > e.y1 ? e.y1 : hi;
+    }
+}
+
+__device__ __forceinline__ uint32_t wave_incl_scan_u32(uint32_t x) {
+    const int lane = (int)__lane_id();
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t y = __shfl_up(x, d, 64);
+        if (lane >= d) x += y;
+    }
+    return x;
+}
+
+__global__ __launch_bounds__(kBigBlock) void k_emit_big(int tx_n, int ty_n, int mode,
+                                                        uint32_t limit, uint32_t qcap,
+                                                        const float4* __restrict__ geom,
+                                                        const float4* __restrict__ conic,
+                                                        const uint32_t* __restrict__ counts,
+                                                        const uint32_t* __restrict__ offsets,
+                                                        uint64_t* __restrict__ keys,
+                                                        uint32_t* __restrict__ values,
+                                                        const uint32_t* __restrict__ queue) {
+    __shared__ uint32_t s_excl[kBigBlock / 64][64];
+    __shared__ int s_lo[kBigBlock / 64][64];
+    const int w = threadIdx.x >> 6;
+    const int lane = (int)__lane_id();
+    const uint32_t nq = queue[0] < qcap ? queue[0] : qcap;
+    const uint32_t wave0 = blockIdx.x * (kBigBlock / 64) + w;
+    const uint32_t waves = gridDim.x * (kBigBlock / 64);
+    for (uint32_t b = wave0; b < nq; b += waves) {
+        const uint32_t i = queue[1 + b];
+        const uint32_t cnt = counts[i];
+        const uint32_t end = offsets[i] < limit ? offsets[i] : limit;
+        const uint32_t pos0 = end - cnt;
+        const float4 g = geom[i], q = conic[i];
+        Ellipse e;
+        if (!ellipse_setup(g, q, mode, tx_n, ty_n, e)) continue;
+        const uint64_t dbits = (uint64_t)__float_as_uint(g.z);
+        const bool cols = span_columns(e, mode);
+        const int maj0 = cols ? e.x0 : e.y0;
+        const int nmaj = cols ? e.x1 - e.x0 + 1 : e.y1 - e.y0 + 1;
+        uint32_t done = 0;
+        for (int c0 = 0; c0 < nmaj; c0 += 64) {
+            int lo = 0, hi = -1;
+            if (c0 + lane < nmaj) one_span(e, mode, tx_n, ty_n, cols, maj0 + c0 + lane, lo, hi);
+            const uint32_t len = hi >= lo ? (uint32_t)(hi - lo + 1) : 0u;
+            const uint32_t incl = wave_incl_scan_u32(len);
+            const uint32_t total = __shfl(incl, 63, 64);
+            s_excl[w][lane] = incl - len;
+            s_lo[w][lane] = lo;
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            for (uint32_t idx = lane; idx < total; idx += 64) {
+                // the last span whose exclusive start is <= idx
+                int a = 0, z = 63;
+                while (a < z) {
+                    const int mid = (a + z + 1) >> 1;
+                    if (s_excl[w][mid] <= idx) a = mid; else z = mid - 1;
+                }
+                const int major = maj0 + c0 + a;
+                const int minor = s_lo[w][a] + (int)(idx - s_excl[w][a]);
+                const uint32_t tile = cols ? (uint32_t)(minor * tx_n + major)
+                                           : (uint32_t)(major * tx_n + minor);
+                const uint32_t pos = pos0 + done + idx;
+                if (pos < end) {
+                    keys[pos] = ((uint64_t)tile << 32) | dbits;
+                    values[pos] = i;
+                }
+            }
+            done += total;
+            __builtin_amdgcn_wave_barrier();
+        }
+    }
+}
+
 }  // namespace
 
 hipError_t launch_emit(int tx_n, int ty_n, int64_t n, int mode, const ss_frame& f, uint64_t* keys,
                        uint32_t* values, uint64_t n_pairs, hipStream_t s) {
     if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero, dim3(1), dim3(1), 0, s, f.emit_tmp);
     const int block = 256;
     const int64_t grid = (n + block - 1) / block;
     hipLaunchKernelGGL(k_emit, dim3((unsigned)grid), dim3(block), 0, s, tx_n, ty_n, n, mode,
-                       (uint32_t)n_pairs,
-                       reinterpret_cast<const float4*>(f.geom),
+                       (uint32_t)n_pairs, reinterpret_cast<const float4*>(f.geom),
                        reinterpret_cast<const float4*>(f.conic), f.counts, f.offsets, keys,
-                       values);
+                       values, f.emit_tmp);
+    hipLaunchKernelGGL(k_emit_big, dim3(kBigGrid), dim3(kBigBlock), 0, s, tx_n, ty_n, mode,
+                       (uint32_t)n_pairs, (uint32_t)n, reinterpret_cast<const float4*>(f.geom),
+                       reinterpret_cast<const float4*>(f.conic), f.counts, f.offsets, keys,
+                       values, f.emit_tmp);
     return hipGetLastError();
 }
 

@@ -31,12 +31,54 @@ struct Inputs {
     int sh_degree, sh_stride;
 };
 
-__global__ __launch_bounds__(256) void k_preprocess(ss_camera cam, Inputs in, int64_t n, int mode,
-                                                    int tx_n, int ty_n, float4* __restrict__ geom,
-                                                    float4* __restrict__ conic,
-                                                    float4* __restrict__ rgb_out,
-                                                    uint32_t* __restrict__ counts) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+constexpr int kBlock = 256;
+constexpr int kShMax = 48;                 // SH floats per Gaussian staged (degree 3)
+constexpr int kShPitch = kShMax + 1;       // odd LDS pitch: lanes hit distinct banks
+
+// Copies the SH coefficients of this workgroup's Gaussians into LDS with
+// coalesced 16-byte loads (the [n, stride, 3] rows of consecutive Gaussians are
+// contiguous), so each lane then reads its own coefficients from LDS instead of
+// issuing strided per-lane loads.  Only the first `need` floats of each
+// Gaussian are kept.
+__device__ __forceinline__ void stage_sh(const float* __restrict__ sh, int64_t first, int64_t n,
+                                         int row, int need, float* s_sh) {
+    const int cnt = (n - first) < kBlock ? (int)(n - first) : kBlock;
+    const unsigned total = (unsigned)(cnt * row);        // floats of this block
+    const unsigned urow = (unsigned)row;
+    const float* src = sh + first * row;
+    if (((uintptr_t)src & 15u) == 0 && (row & 3) == 0) {
+        const float4* src4 = reinterpret_cast<const float4*>(src);
+        for (unsigned e = threadIdx.x; e < (total >> 2); e += kBlock) {
+            const float4 v = src4[e];
+            const unsigned f = e << 2, g = f / urow, c = f - g * urow;
+            if ((int)c < need) {  // row % 4 == 0: the four floats stay in one Gaussian
+                float* d = s_sh + g * kShPitch + c;
+                d[0] = v.x;
+                if ((int)c + 1 < need) d[1] = v.y;
+                if ((int)c + 2 < need) d[2] = v.z;
+                if ((int)c + 3 < need) d[3] = v.w;
+            }
+        }
+    } else {
+        for (unsigned f = threadIdx.x; f < total; f += kBlock) {
+            const unsigned g = f / urow, c = f - g * urow;
+            if ((int)c < need) s_sh[g * kShPitch + c] = src[f];
+        }
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_preprocess(ss_camera cam, Inputs in, int64_t n,
+                                                       int mode, int tx_n, int ty_n,
+                                                       float4* __restrict__ geom,
+                                                       float4* __restrict__ conic,
+                                                       float4* __restrict__ rgb_out,
+                                                       uint32_t* __restrict__ counts) {
+    __shared__ float s_sh[kBlock * kShPitch];
+    const int64_t first = (int64_t)blockIdx.x * kBlock;
+    const int nb_coef = (in.sh_degree + 1) * (in.sh_degree + 1);
+    stage_sh(in.sh, first, n, 3 * in.sh_stride, 3 * nb_coef, s_sh);
+    __syncthreads();
+    const int64_t i = first + threadIdx.x;
     if (i >= n) return;
     const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
 
@@ -140,7 +182,7 @@ __global__ __launch_bounds__(256) void k_preprocess(ss_camera cam, Inputs in, in
     float dx = m0 - cpx, dy = m1 - cpy, dz = m2 - cpz;
     const float inv = 1.0f / sqrtf(dx * dx + dy * dy + dz * dz);
     dx *= inv; dy *= inv; dz *= inv;
-    const float* h = in.sh + (int64_t)3 * in.sh_stride * i;
+    const float* h = s_sh + threadIdx.x * kShPitch;
     float Y[16];
     Y[0] = kSH0;
     int nb = 1;
@@ -192,9 +234,8 @@ hipError_t launch_preprocess(const ss_camera& cam, const ss_gaussians& g, int mo
     if (g.n == 0) return hipSuccess;
     const int tx_n = (cam.width + kTile - 1) / kTile, ty_n = (cam.height + kTile - 1) / kTile;
     Inputs in{g.means, g.scales, g.quats, g.opacity, g.sh, g.sh_degree, g.sh_stride};
-    const int block = 256;
-    const int64_t grid = (g.n + block - 1) / block;
-    hipLaunchKernelGGL(k_preprocess, dim3((unsigned)grid), dim3(block), 0, s, cam, in, g.n, mode,
+    const int64_t grid = (g.n + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(k_preprocess, dim3((unsigned)grid), dim3(kBlock), 0, s, cam, in, g.n, mode,
                        tx_n, ty_n, reinterpret_cast<float4*>(f.geom),
                        reinterpret_cast<float4*>(f.conic), reinterpret_cast<float4*>(f.rgb),
                        f.counts);

@@ -3,16 +3,17 @@
 // ("identifyTileRanges").
 //
 // Only the low 32 + ceil(log2(n_tiles)) key bits can be non-zero, so the sort
-// runs ceil(bits / 8) passes of 8-bit digits.  Each pass is reduce-then-scan:
+// runs ceil(bits / 8) passes of 8-bit digits.  Each pass is reduce-then-scan,
+// so no workgroup ever waits on another:
 //   hist     workgroup b counts the digits of its contiguous key chunk
-//   scan     one workgroup turns the (digit, workgroup) counts, digit-major,
-//            into exclusive output offsets
-//   scatter  workgroup b re-reads its chunk in 4096-key sub-tiles; each wave
-//            ranks 64 keys at a time by matching digits with 8 ballots
-//            (stable: lane order), keeps per-wave running digit counts in LDS,
-//            and writes each key at offset(digit, b) + keys of that digit
-//            before it in the chunk.
-// No workgroup waits on another, so there is no forward-progress assumption.
+//   dscan    256 workgroups, one per digit: exclusive scan of that digit's
+//            per-workgroup counts, and the digit's total
+//   scatter  workgroup b turns the digit totals into digit starts, re-reads its
+//            chunk in 4096-key sub-tiles, ranks each key stably (each wave
+//            matches 64 digits at a time with 8 ballots; per-wave running
+//            counts live in LDS), reorders the sub-tile by digit in LDS and
+//            writes every digit run to its global offset with consecutive
+//            lanes on consecutive addresses.
 #include "ss_internal.h"
 
 namespace ss {
@@ -39,8 +40,14 @@ Plan make_plan(uint64_t n) {
     return Plan{(uint32_t)(grid ? grid : 1), (per ? per : 1) * kSub};
 }
 
-__global__ __launch_bounds__(kBlock) void k_hist(const uint64_t* __restrict__ keys, uint64_t n,
-                                                 int shift, uint64_t chunk, uint32_t grid,
+template <class K>
+__device__ __forceinline__ uint32_t digit_of(K key, int shift) {
+    return (uint32_t)(key >> shift) & (kRadix - 1);
+}
+
+template <class K>
+__global__ __launch_bounds__(kBlock) void k_hist(const K* __restrict__ keys, uint64_t n, int shift,
+                                                 uint64_t chunk, uint32_t grid,
                                                  uint32_t* __restrict__ hist) {
     __shared__ uint32_t h[kWaves][kRadix];
     for (int k = threadIdx.x; k < kWaves * kRadix; k += kBlock) (&h[0][0])[k] = 0u;
@@ -48,10 +55,8 @@ __global__ __launch_bounds__(kBlock) void k_hist(const uint64_t* __restrict__ ke
     const uint64_t lo = (uint64_t)blockIdx.x * chunk;
     const uint64_t hi = lo + chunk < n ? lo + chunk : n;
     const int w = threadIdx.x >> 6;
-    for (uint64_t i = lo + threadIdx.x; i < hi; i += kBlock) {
-        const uint32_t d = (uint32_t)(keys[i] >> shift) & (kRadix - 1);
-        atomicAdd(&h[w][d], 1u);
-    }
+    for (uint64_t i = lo + threadIdx.x; i < hi; i += kBlock)
+        atomicAdd(&h[w][digit_of(keys[i], shift)], 1u);
     __syncthreads();
     for (int d = threadIdx.x; d < kRadix; d += kBlock) {
         uint32_t s = 0;
@@ -71,66 +76,92 @@ __device__ __forceinline__ uint32_t wave_incl_scan32(uint32_t x) {
     return x;
 }
 
-// Exclusive scan of m = 256 * grid counts in place; one workgroup of 1024.
-__global__ __launch_bounds__(1024) void k_hist_scan(uint32_t* __restrict__ hist, uint32_t m) {
-    __shared__ uint32_t wsum[16];
-    __shared__ uint32_t carry;
-    if (threadIdx.x == 0) carry = 0;
+// Exclusive scan of 256 values held one per lane of a 256-lane workgroup.
+// `wsum` is 4 words of LDS.  Returns the exclusive prefix; *total gets the sum.
+__device__ __forceinline__ uint32_t block_excl_scan256(uint32_t x, uint32_t* wsum,
+                                                       uint32_t* total) {
+    const uint32_t inc = wave_incl_scan32(x);
+    const int w = threadIdx.x >> 6;
+    if (__lane_id() == 63) wsum[w] = inc;
     __syncthreads();
-    constexpr int kPer = 4;
-    for (uint32_t base = 0; base < m; base += 1024 * kPer) {
-        const uint32_t first = base + threadIdx.x * kPer;
-        uint32_t c[kPer];
-        uint32_t s = 0;
+    uint32_t before = 0, all = 0;
 #pragma unroll
-        for (int k = 0; k < kPer; ++k) {
-            c[k] = first + k < m ? hist[first + k] : 0u;
-            s += c[k];
-        }
-        const uint32_t inc = wave_incl_scan32(s);
-        const int w = threadIdx.x >> 6;
-        if (__lane_id() == 63) wsum[w] = inc;
-        __syncthreads();
-        uint32_t run = carry + inc - s;
-        for (int k = 0; k < w; ++k) run += wsum[k];
-#pragma unroll
-        for (int k = 0; k < kPer; ++k) {
-            if (first + k < m) hist[first + k] = run;
-            run += c[k];
-        }
-        __syncthreads();
-        if (threadIdx.x == 1023) carry = run;
-        __syncthreads();
+    for (int k = 0; k < kWaves; ++k) {
+        before += k < w ? wsum[k] : 0u;
+        all += wsum[k];
     }
+    __syncthreads();
+    *total = all;
+    return before + inc - x;
 }
 
-__global__ __launch_bounds__(kBlock) void k_scatter(const uint64_t* __restrict__ keys_in,
+// Workgroup d: exclusive scan over the grid counts of digit d, in place, and
+// the digit total in hist[256 * grid + d].  grid <= 1024 = 256 lanes x 4.
+__global__ __launch_bounds__(kBlock) void k_dscan(uint32_t* __restrict__ hist, uint32_t grid) {
+    __shared__ uint32_t wsum[kWaves];
+    uint32_t* row = hist + (uint64_t)blockIdx.x * grid;
+    const uint32_t first = threadIdx.x * 4;
+    uint32_t c[4], s = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        c[k] = first + k < grid ? row[first + k] : 0u;
+        s += c[k];
+    }
+    uint32_t total;
+    uint32_t run = block_excl_scan256(s, wsum, &total);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        if (first + k < grid) row[first + k] = run;
+        run += c[k];
+    }
+    if (threadIdx.x == 0) hist[(uint64_t)kRadix * grid + blockIdx.x] = total;
+}
+
+template <class K>
+__global__ __launch_bounds__(kBlock) void k_scatter(const K* __restrict__ keys_in,
                                                     const uint32_t* __restrict__ vals_in,
-                                                    uint64_t* __restrict__ keys_out,
+                                                    K* __restrict__ keys_out,
                                                     uint32_t* __restrict__ vals_out, uint64_t n,
                                                     int shift, uint64_t chunk, uint32_t grid,
                                                     const uint32_t* __restrict__ hist) {
-    __shared__ uint32_t base[kRadix];
+    __shared__ K s_key[kSub];
+    __shared__ uint32_t s_val[kSub];
+    __shared__ uint32_t base[kRadix];     // global position of this chunk's next key per digit
+    __shared__ uint32_t lstart[kRadix];   // digit start within the current sub-tile
+    __shared__ uint32_t tot[kRadix];      // digit count within the current sub-tile
     __shared__ uint32_t wcnt[kWaves][kRadix];
-    __shared__ uint32_t tot[kRadix];
-    for (int d = threadIdx.x; d < kRadix; d += kBlock) base[d] = hist[(uint64_t)d * grid + blockIdx.x];
+    __shared__ uint32_t wsum[kWaves];
+
+    const int t = threadIdx.x;            // one digit per lane in the per-digit steps
+    {
+        uint32_t dummy;
+        const uint32_t dstart =
+            block_excl_scan256(hist[(uint64_t)kRadix * grid + t], wsum, &dummy);
+        base[t] = dstart + hist[(uint64_t)t * grid + blockIdx.x];
+    }
     const uint64_t lo = (uint64_t)blockIdx.x * chunk;
     const uint64_t hi = lo + chunk < n ? lo + chunk : n;
-    const int w = threadIdx.x >> 6;
+    const int w = t >> 6;
     const unsigned lane = __lane_id();
     for (uint64_t sub = lo; sub < hi; sub += kSub) {
-        for (int k = threadIdx.x; k < kWaves * kRadix; k += kBlock) (&wcnt[0][0])[k] = 0u;
+#pragma unroll
+        for (int ww = 0; ww < kWaves; ++ww) wcnt[ww][t] = 0u;
         __syncthreads();
-        uint64_t key[kItems];
+        K key[kItems];
         uint32_t val[kItems];
         uint32_t rank[kItems];
 #pragma unroll
         for (int k = 0; k < kItems; ++k) {
             const uint64_t idx = sub + (uint64_t)w * (64 * kItems) + (uint64_t)k * 64 + lane;
             const bool valid = idx < hi;
-            key[k] = valid ? keys_in[idx] : 0ull;
+            key[k] = valid ? keys_in[idx] : (K)0;
             val[k] = valid ? vals_in[idx] : 0u;
-            const uint32_t d = (uint32_t)(key[k] >> shift) & (kRadix - 1);
+        }
+#pragma unroll
+        for (int k = 0; k < kItems; ++k) {
+            const uint64_t idx = sub + (uint64_t)w * (64 * kItems) + (uint64_t)k * 64 + lane;
+            const bool valid = idx < hi;
+            const uint32_t d = digit_of(key[k], shift);
             uint64_t m = __ballot(valid);
 #pragma unroll
             for (int bit = 0; bit < 8; ++bit) {
@@ -145,31 +176,44 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const uint64_t* __restrict__
             if (valid && below == 0u) wcnt[w][d] = pre + (uint32_t)__popcll(m);
         }
         __syncthreads();
-        for (int d = threadIdx.x; d < kRadix; d += kBlock) {
+        {   // per digit: prefix over waves, sub-tile total, sub-tile digit start
             uint32_t s = 0;
 #pragma unroll
             for (int ww = 0; ww < kWaves; ++ww) {
-                const uint32_t c = wcnt[ww][d];
-                wcnt[ww][d] = s;
+                const uint32_t c = wcnt[ww][t];
+                wcnt[ww][t] = s;
                 s += c;
             }
-            tot[d] = s;
+            tot[t] = s;
+            uint32_t dummy;
+            lstart[t] = block_excl_scan256(s, wsum, &dummy);
         }
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < kItems; ++k) {
             const uint64_t idx = sub + (uint64_t)w * (64 * kItems) + (uint64_t)k * 64 + lane;
             if (idx < hi) {
-                const uint32_t d = (uint32_t)(key[k] >> shift) & (kRadix - 1);
-                const uint32_t pos = base[d] + wcnt[w][d] + rank[k];
-                if (pos < n) {
-                    keys_out[pos] = key[k];
-                    vals_out[pos] = val[k];
+                const uint32_t d = digit_of(key[k], shift);
+                const uint32_t lp = lstart[d] + wcnt[w][d] + rank[k];
+                if (lp < (uint32_t)kSub) {
+                    s_key[lp] = key[k];
+                    s_val[lp] = val[k];
                 }
             }
         }
         __syncthreads();
-        for (int d = threadIdx.x; d < kRadix; d += kBlock) base[d] += tot[d];
+        const uint32_t n_sub = (uint32_t)(hi - sub < (uint64_t)kSub ? hi - sub : (uint64_t)kSub);
+        for (uint32_t i = t; i < n_sub; i += kBlock) {
+            const K kk = s_key[i];
+            const uint32_t d = digit_of(kk, shift);
+            const uint32_t pos = base[d] + (i - lstart[d]);
+            if (pos < n) {
+                keys_out[pos] = kk;
+                vals_out[pos] = s_val[i];
+            }
+        }
+        __syncthreads();
+        base[t] += tot[t];
         __syncthreads();
     }
 }
@@ -187,32 +231,38 @@ __global__ __launch_bounds__(256) void k_ranges(const uint64_t* __restrict__ key
     for (int t = prev < 0 ? 0 : prev; t < cur && t < n_tiles; ++t) ranges[2 * t + 1] = (uint32_t)i;
 }
 
-}  // namespace
-
-int sort_passes(int bits) { return (bits + 7) / 8; }
-
-int64_t sort_tmp_words(uint64_t) { return (int64_t)kRadix * kMaxGrid; }
-
-hipError_t launch_sort(const ss_pairs& p, int buf, uint64_t n, int bits, int* out_buf,
-                       hipStream_t s) {
-    int cur = buf;
+template <class K>
+hipError_t radix_sort(K* keys[2], uint32_t* vals[2], int cur, uint64_t n, int bits,
+                      uint32_t* tmp, int* out_buf, hipStream_t s) {
     if (n > 1) {
         const Plan plan = make_plan(n);
-        const int passes = sort_passes(bits);
+        const int passes = (bits + 7) / 8;
         for (int pass = 0; pass < passes; ++pass) {
             const int shift = pass * 8;
-            hipLaunchKernelGGL(k_hist, dim3(plan.grid), dim3(kBlock), 0, s, p.keys[cur], n, shift,
-                               plan.chunk, plan.grid, p.sort_tmp);
-            hipLaunchKernelGGL(k_hist_scan, dim3(1), dim3(1024), 0, s, p.sort_tmp,
-                               (uint32_t)(kRadix * plan.grid));
-            hipLaunchKernelGGL(k_scatter, dim3(plan.grid), dim3(kBlock), 0, s, p.keys[cur],
-                               p.values[cur], p.keys[1 - cur], p.values[1 - cur], n, shift,
-                               plan.chunk, plan.grid, p.sort_tmp);
+            hipLaunchKernelGGL(k_hist<K>, dim3(plan.grid), dim3(kBlock), 0, s, keys[cur], n,
+                               shift, plan.chunk, plan.grid, tmp);
+            hipLaunchKernelGGL(k_dscan, dim3(kRadix), dim3(kBlock), 0, s, tmp, plan.grid);
+            hipLaunchKernelGGL(k_scatter<K>, dim3(plan.grid), dim3(kBlock), 0, s, keys[cur],
+                               vals[cur], keys[1 - cur], vals[1 - cur], n, shift, plan.chunk,
+                               plan.grid, tmp);
             cur = 1 - cur;
         }
     }
     *out_buf = cur;
     return hipGetLastError();
+}
+
+}  // namespace
+
+int sort_passes(int bits) { return (bits + 7) / 8; }
+
+int64_t sort_tmp_words(uint64_t) { return (int64_t)kRadix * kMaxGrid + kRadix; }
+
+hipError_t launch_sort(const ss_pairs& p, int buf, uint64_t n, int bits, int* out_buf,
+                       hipStream_t s) {
+    uint64_t* keys[2] = {p.keys[0], p.keys[1]};
+    uint32_t* vals[2] = {p.values[0], p.values[1]};
+    return radix_sort<uint64_t>(keys, vals, buf, n, bits, p.sort_tmp, out_buf, s);
 }
 
 hipError_t launch_ranges(const uint64_t* keys, uint64_t n, int n_tiles, uint32_t* ranges,

@@ -95,11 +95,12 @@ class Frame:
         self.t_final = torch.empty((height, width), dtype=torch.float32, device=dev)
         self.n_last = torch.empty((height, width), dtype=torch.int32, device=dev)
         self.n_eval = torch.empty((height, width), dtype=torch.int32, device=dev)
+        self.emit_tmp = torch.empty(n + 1, dtype=torch.int32, device=dev)
 
     def struct(self) -> _lib.SSFrame:
         f = _lib.SSFrame()
         for name in ("geom", "conic", "rgb", "counts", "offsets", "scan_tmp", "ranges",
-                     "t_final", "n_last", "n_eval"):
+                     "t_final", "n_last", "n_eval", "emit_tmp"):
             setattr(f, name, getattr(self, name).data_ptr())
         return f
 
