@@ -115,6 +115,7 @@ def main():
     g = ss.Gaussians.from_scene(scene, dev)
     log(f"scene: {scene.n} Gaussians, generated and uploaded in {time.perf_counter() - t0:.1f} s")
     r = ss.Renderer(dev)
+    r_stats = ss.Renderer(dev, stats=True)
     modes = [m for m in args.modes.split(",") if m]
 
     # Work counters per camera (untimed): pairs and evaluated pixel-Gaussian pairs.
@@ -122,12 +123,13 @@ def main():
     for mode in modes:
         P, E = [], []
         for cam in cams:
-            out = r.render(g, cam, mode, full=True)
+            out = r_stats.render(g, cam, mode, full=True)
             torch.cuda.synchronize()
             P.append(out.n_pairs)
             E.append(int(out.frame.n_eval.to(torch.int64).sum().item()))
         work[mode] = (P, E)
         log(f"{mode}: pairs/frame {np.mean(P):.0f}, evaluated pairs/frame {np.mean(E):.3e}")
+    del r_stats
 
     results = {}
     for mode in modes:

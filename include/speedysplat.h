@@ -133,6 +133,19 @@ typedef struct ss_pairs {
     uint32_t *sort_tmp;     /* [sort_tmp_words] */
 } ss_pairs;
 
+/* Gradients written by ss_render_backward (device memory, caller-owned). */
+typedef struct ss_grads {
+    float *means;           /* [n,3]  dL/dmu (overwritten) */
+    float *scales;          /* [n,3]  dL/ds for the linear scales (overwritten) */
+    float *quats;           /* [n,4]  dL/dr for the quaternions as given (overwritten) */
+    float *opacity;         /* [n]    dL/dsigma (overwritten) */
+    float *sh;              /* [n, sh_stride, 3] dL/dh (overwritten; unused degrees 0) */
+    float *g2d;             /* [n,12] screen-space gradients, also scratch: per Gaussian
+                               (du, dv, 0, 0, da, db, dc, dsigma, dr, dg, db, 0) */
+    float *score;           /* optional [n] (NULL: skipped): sum over pixels and channels
+                               of (dC/dg_i)^2, g_i the 2D Gaussian's value at the pixel */
+} ss_grads;
+
 /* Optional stage timing for the composite calls: caller-created hipEvent_t
  * handles (NULL entries are skipped) recorded on the stream at
  *   [0] before preprocess  [1] after preprocess  [2] after the scan
@@ -235,6 +248,22 @@ int ss_forward_finish(const ss_camera *cam, int64_t n, int32_t mode, const ss_fr
 int ss_render(const ss_camera *cam, const ss_gaussians *g, int32_t mode, const ss_frame *frame,
               const ss_pairs *pairs, float *out_rgb, uint64_t *n_pairs_out, int32_t *out_buf,
               const ss_stage_events *events, void *stream);
+
+/*
+ * Adjoint of the forward render (the gradient flow of Sec. 4.2: per-pixel
+ * gradients aggregated to the 2D parameters, then per Gaussian to the 3D
+ * ones).  Inputs: the same camera and Gaussians as the forward call, its
+ * frame (records, ranges, t_final, n_last) and pair workspace (`buf` holds
+ * the sorted pairs), and dl_drgb [3, H, W], the loss gradient of the image.
+ * The blend is walked back to front per tile, recomputing alpha and the
+ * transmittance from the stored final T.  out->g2d and out->score are
+ * zeroed and accumulated with FP32 atomics (their summation order varies
+ * between runs); the parameter gradients are then written per Gaussian.
+ * Culled Gaussians get zero gradients.
+ */
+int ss_render_backward(const ss_camera *cam, const ss_gaussians *g, const ss_frame *frame,
+                       const ss_pairs *pairs, int32_t buf, const float *dl_drgb,
+                       const ss_grads *out, void *stream);
 
 #ifdef __cplusplus
 }

@@ -59,6 +59,11 @@ class SSPairs(ctypes.Structure):
                 ("sort_tmp", _vp)]
 
 
+class SSGrads(ctypes.Structure):
+    _fields_ = [("means", _vp), ("scales", _vp), ("quats", _vp), ("opacity", _vp), ("sh", _vp),
+                ("g2d", _vp), ("score", _vp)]
+
+
 class SSStageEvents(ctypes.Structure):
     _fields_ = [("ev", _vp * 8)]
 
@@ -86,6 +91,8 @@ PROTOTYPES = {
                           _P(SSStageEvents), _vp],
     "ss_render": [_P(SSCamera), _P(SSGaussians), ctypes.c_int32, _P(SSFrame), _P(SSPairs), _vp,
                   _P(ctypes.c_uint64), _P(ctypes.c_int32), _P(SSStageEvents), _vp],
+    "ss_render_backward": [_P(SSCamera), _P(SSGaussians), _P(SSFrame), _P(SSPairs),
+                           ctypes.c_int32, _vp, _P(SSGrads), _vp],
 }
 RESTYPES = {"ss_status_string": ctypes.c_char_p, "ss_last_error": ctypes.c_char_p}
 

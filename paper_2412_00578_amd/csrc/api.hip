@@ -289,4 +289,22 @@ int ss_render(const ss_camera* cam, const ss_gaussians* g, int32_t mode, const s
     return ss_forward_finish(cam, g->n, mode, f, p, n_pairs, out_rgb, out_buf, ev, stream);
 }
 
+int ss_render_backward(const ss_camera* cam, const ss_gaussians* g, const ss_frame* f,
+                       const ss_pairs* p, int32_t buf, const float* dl_drgb, const ss_grads* out,
+                       void* stream) {
+    SS_TRY(check_camera(cam));
+    SS_TRY(check_gaussians(g));
+    SS_TRY(check_frame_records(f, g->n));
+    SS_TRY(check_frame_pixels(f));
+    if (!p || (buf != 0 && buf != 1)) return fail(SS_ERR_INVALID_ARG, "bad pair workspace");
+    if (!dl_drgb) return fail(SS_ERR_INVALID_ARG, "dl_drgb is NULL");
+    if (!out) return fail(SS_ERR_INVALID_ARG, "grads is NULL");
+    if (g->n > 0 && (!out->means || !out->scales || !out->quats || !out->opacity || !out->sh ||
+                     !out->g2d))
+        return fail(SS_ERR_INVALID_ARG, "a gradient buffer is NULL");
+    return hip_status(
+        ss::launch_backward(*cam, *g, *f, p->values[buf], dl_drgb, *out, (hipStream_t)stream),
+        "backward");
+}
+
 }  // extern "C"

@@ -20,7 +20,7 @@ PKG = os.path.dirname(HERE)
 ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "libspeedysplat.so")
 SOURCES = ["api.hip", "k_preprocess.hip", "k_scan.hip", "k_emit.hip", "k_sort.hip",
-           "k_blend.hip"]
+           "k_blend.hip", "k_backward.hip"]
 ARCH = os.environ.get("SS_OFFLOAD_ARCH", "gfx950")
 
 
@@ -33,6 +33,7 @@ def hipcc() -> str:
 
 def common_flags():
     return ["-O3", f"--offload-arch={ARCH}", "-std=c++17", "-fPIC", "-ffp-contract=off",
+            "-munsafe-fp-atomics",
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
             "-Wall", "-Wno-unused-function", "-I", os.path.join(ROOT, "include")]
 

@@ -1,0 +1,487 @@
+// Adjoint of the forward render: the gradient flow of Speedy-Splat Sec. 4.2
+// (per-pixel gradients aggregated to the 2D parameters, then per Gaussian to
+// the 3D parameters).
+//
+// Stage 7, blend backward.  Same tile / strip / wave layout as the forward
+// blend.  Each wave walks its tile's list back to front from the last
+// Gaussian any of its pixels blended (n_last), recomputing alpha and the
+// transmittance before each Gaussian as T_before = T_after / (1 - alpha) from
+// the stored final T (no per-pixel, per-Gaussian state is kept from the
+// forward pass).  With R the colour of everything behind the Gaussian
+// (starting at the background),
+//   dC/dc_i     = alpha_i T_i
+//   dC/dalpha_i = T_i (c_i - R),   R <- alpha_i c_i + (1 - alpha_i) R.
+// The per-pixel gradients with respect to (u, v, a, b, c, sigma, r, g, b) are
+// summed over the wave and added with one set of atomics per wave and
+// Gaussian.  An optional per-Gaussian score accumulates sum over pixels and
+// channels of (dC/dg_i)^2, g_i the 2D Gaussian's value at the pixel (the
+// efficient pruning score of Sec. 4.2).
+//
+// Stage 8, preprocess backward.  One lane per Gaussian: the chain rule from
+// (u, v, conic, sigma, colour) back to means, scales, quaternions, opacity and
+// SH coefficients, with the forward geometry recomputed in FP64.
+#include "ss_internal.h"
+
+namespace ss {
+namespace {
+
+constexpr int kBatch = 64;
+
+__device__ __forceinline__ float wave_sum(float x) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) x += __shfl_xor(x, m, 64);
+    return x;
+}
+
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t x) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+        const uint32_t y = __shfl_xor(x, m, 64);
+        x = y > x ? y : x;
+    }
+    return x;
+}
+
+// Same strip mask as the forward blend (pixel centres outside a 1% widened
+// ellipse box never pass q <= t).
+__device__ __forceinline__ uint32_t strip_mask_b(float4 g, float4 q, int tx, int ty) {
+    const double a = q.x, b = q.y, c = q.z, t = g.w;
+    const double det = a * c - b * b;
+    if (!(t > 0.0)) return t == 0.0 ? 0xFu : 0u;
+    if (!(det > 0.0) || (a + c) * (a + c) > 1.0e3 * det) return 0xFu;
+    const double hx = 1.01 * sqrt((t * c) / det) + 1e-3;
+    const double hy = 1.01 * sqrt((t * a) / det) + 1e-3;
+    const double u = g.x, v = g.y;
+    const double x0 = 16.0 * tx + 0.5, x1 = 16.0 * tx + 15.5;
+    if (x1 < u - hx || x0 > u + hx) return 0u;
+    uint32_t m = 0u;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const double y0 = 16.0 * ty + 4.0 * s + 0.5, y1 = y0 + 3.0;
+        if (!(y1 < v - hy || y0 > v + hy)) m |= 1u << s;
+    }
+    return m;
+}
+
+template <int SPW>
+__global__ __launch_bounds__(64 * (4 / SPW)) void k_blend_bwd(
+    int tx_n, int n_tiles, int W, int H, float bg0, float bg1, float bg2,
+    const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ values,
+    const float4* __restrict__ geom, const float4* __restrict__ conic,
+    const float4* __restrict__ rgb, const float* __restrict__ t_final,
+    const uint32_t* __restrict__ n_last, const float* __restrict__ dl_drgb,
+    float* __restrict__ g2d, float* __restrict__ score) {
+    constexpr int kWaves = 4 / SPW;
+    __shared__ float4 s_geo[kWaves][kBatch];   // (u, v, strip mask bits, t)
+    __shared__ float4 s_con[kWaves][kBatch];   // (a, 2b, c, sigma)
+    __shared__ float4 s_col[kWaves][kBatch];   // (r, g, b, -)
+    __shared__ uint32_t s_idx[kWaves][kBatch];
+    const int tile = xcd_contiguous((int)blockIdx.x, n_tiles);
+    if (tile < 0) return;
+    const int w = (int)(threadIdx.x >> 6);
+    const int lane = (int)(threadIdx.x & 63);
+    const int strip0 = w * SPW;
+    const int tx = tile % tx_n, ty = tile / tx_n;
+    const int px = tx * kTile + (lane & 15);
+    const int py0 = ty * kTile + 4 * strip0 + (lane >> 4);
+    const float fx = (float)px + 0.5f;
+    const size_t hw = (size_t)W * (size_t)H;
+    float fy[SPW], T[SPW], R[SPW][3], dC[SPW][3];
+    uint32_t nl[SPW];
+    uint32_t jmax = 0u;
+#pragma unroll
+    for (int s = 0; s < SPW; ++s) {
+        const int py = py0 + 4 * s;
+        fy[s] = (float)py + 0.5f;
+        const bool in = px < W && py < H;
+        const size_t p = in ? (size_t)py * W + px : 0;
+        nl[s] = in ? n_last[p] : 0u;
+        T[s] = in ? t_final[p] : 1.0f;
+        R[s][0] = bg0; R[s][1] = bg1; R[s][2] = bg2;
+        dC[s][0] = in ? dl_drgb[p] : 0.0f;
+        dC[s][1] = in ? dl_drgb[hw + p] : 0.0f;
+        dC[s][2] = in ? dl_drgb[2 * hw + p] : 0.0f;
+        jmax = nl[s] > jmax ? nl[s] : jmax;
+    }
+    jmax = wave_max_u32(jmax);
+    const uint32_t start = ranges[2 * tile];
+    for (uint32_t hi = jmax; hi > 0u;) {
+        const uint32_t lo = hi > (uint32_t)kBatch ? hi - kBatch : 0u;
+        const uint32_t cnt = hi - lo;
+        if ((uint32_t)lane < cnt) {
+            const uint32_t gi = values[start + lo + lane];
+            const float4 g = geom[gi], q = conic[gi];
+            s_geo[w][lane] = make_float4(g.x, g.y, __uint_as_float(strip_mask_b(g, q, tx, ty)), g.w);
+            s_con[w][lane] = make_float4(q.x, 2.0f * q.y, q.z, q.w);
+            s_col[w][lane] = rgb[gi];
+            s_idx[w][lane] = gi;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        for (int k = (int)cnt - 1; k >= 0; --k) {
+            const uint32_t j = lo + (uint32_t)k;
+            const float4 g = s_geo[w][k];
+            uint32_t m = __builtin_amdgcn_readfirstlane(__float_as_uint(g.z));
+            if (!(m & (((1u << SPW) - 1u) << strip0))) continue;
+            const float4 q = s_con[w][k];
+            const float4 c = s_col[w][k];
+            const float dx = fx - g.x;
+            const float adx2 = (q.x * dx) * dx;
+            const float b2dx = q.y * dx;
+            float gu = 0.f, gv = 0.f, ga = 0.f, gb = 0.f, gc = 0.f, gs = 0.f;
+            float gr = 0.f, gg = 0.f, gbl = 0.f, sc = 0.f;
+            bool any = false;
+#pragma unroll
+            for (int s = 0; s < SPW; ++s) {
+                if (!(m & (1u << (strip0 + s)))) continue;
+                const float dy = fy[s] - g.y;
+                const float qq = (adx2 + (q.z * dy) * dy) + b2dx * dy;
+                if (j < nl[s] && qq <= g.w) {
+                    any = true;
+                    const float gval = __expf(-0.5f * qq);
+                    const float araw = q.w * gval;
+                    const float al = fminf(kAlphaMax, araw);
+                    const float tb = T[s] / (1.0f - al);
+                    const float wgt = al * tb;
+                    gr = fmaf(wgt, dC[s][0], gr);
+                    gg = fmaf(wgt, dC[s][1], gg);
+                    gbl = fmaf(wgt, dC[s][2], gbl);
+                    const float e0 = c.x - R[s][0], e1 = c.y - R[s][1], e2 = c.z - R[s][2];
+                    const float dal = tb * (dC[s][0] * e0 + dC[s][1] * e1 + dC[s][2] * e2);
+                    R[s][0] = fmaf(al, c.x, (1.0f - al) * R[s][0]);
+                    R[s][1] = fmaf(al, c.y, (1.0f - al) * R[s][1]);
+                    R[s][2] = fmaf(al, c.z, (1.0f - al) * R[s][2]);
+                    T[s] = tb;
+                    if (araw < kAlphaMax) {
+                        gs = fmaf(dal, gval, gs);
+                        const float dq = -0.5f * al * dal;
+                        // q = a dx^2 + 2b dx dy + c dy^2 with dx = px - u, dy = py - v
+                        gu += dq * -(2.0f * q.x * dx + q.y * dy);
+                        gv += dq * -(q.y * dx + 2.0f * q.z * dy);
+                        ga = fmaf(dq, dx * dx, ga);
+                        gb = fmaf(dq, 2.0f * dx * dy, gb);
+                        gc = fmaf(dq, dy * dy, gc);
+                        if (score) {
+                            const float k0 = q.w * tb;
+                            sc += k0 * k0 * (e0 * e0 + e1 * e1 + e2 * e2);
+                        }
+                    }
+                }
+            }
+            if (__ballot(any) == 0ull) continue;
+            gu = wave_sum(gu); gv = wave_sum(gv); ga = wave_sum(ga); gb = wave_sum(gb);
+            gc = wave_sum(gc); gs = wave_sum(gs); gr = wave_sum(gr); gg = wave_sum(gg);
+            gbl = wave_sum(gbl);
+            if (score) sc = wave_sum(sc);
+            if (lane == 0) {
+                float* o = g2d + (size_t)s_idx[w][k] * 12;
+                atomicAdd(o + 0, gu);
+                atomicAdd(o + 1, gv);
+                atomicAdd(o + 4, ga);
+                atomicAdd(o + 5, gb);
+                atomicAdd(o + 6, gc);
+                atomicAdd(o + 7, gs);
+                atomicAdd(o + 8, gr);
+                atomicAdd(o + 9, gg);
+                atomicAdd(o + 10, gbl);
+                if (score) atomicAdd(score + s_idx[w][k], sc);
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+        hi = lo;
+    }
+}
+
+__global__ void k_fill_zero(float* __restrict__ p, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0.0f;
+}
+
+// ------------------------------------------------------------ preprocess backward
+
+constexpr double kC0 = 0.28209479177387814;
+constexpr double kC1 = 0.4886025119029199;
+constexpr double kC2a = 1.0925484305920792, kC2b = 0.31539156525252005, kC2c = 0.5462742152960396;
+constexpr double kC3a = 0.5900435899266435, kC3b = 2.890611442640554, kC3c = 0.4570457994644658,
+                 kC3d = 0.3731763325901154, kC3e = 1.445305721320277;
+
+// SH basis Y[16] and its partial derivatives dY[16][3] with respect to the
+// (unnormalised) direction components, evaluated at a unit direction.
+__device__ void sh_basis_grad(double x, double y, double z, int nb, double* Y, double (*dY)[3]) {
+    const double xx = x * x, yy = y * y, zz = z * z;
+    for (int k = 0; k < 16; ++k) { Y[k] = 0.0; dY[k][0] = dY[k][1] = dY[k][2] = 0.0; }
+    Y[0] = kC0;
+    if (nb > 1) {
+        Y[1] = -kC1 * y; dY[1][1] = -kC1;
+        Y[2] = kC1 * z;  dY[2][2] = kC1;
+        Y[3] = -kC1 * x; dY[3][0] = -kC1;
+    }
+    if (nb > 4) {
+        Y[4] = kC2a * x * y;  dY[4][0] = kC2a * y;  dY[4][1] = kC2a * x;
+        Y[5] = -kC2a * y * z; dY[5][1] = -kC2a * z; dY[5][2] = -kC2a * y;
+        Y[6] = kC2b * (2 * zz - xx - yy);
+        dY[6][0] = -2 * kC2b * x; dY[6][1] = -2 * kC2b * y; dY[6][2] = 4 * kC2b * z;
+        Y[7] = -kC2a * x * z; dY[7][0] = -kC2a * z; dY[7][2] = -kC2a * x;
+        Y[8] = kC2c * (xx - yy); dY[8][0] = 2 * kC2c * x; dY[8][1] = -2 * kC2c * y;
+    }
+    if (nb > 9) {
+        Y[9] = -kC3a * y * (3 * xx - yy);
+        dY[9][0] = -6 * kC3a * x * y; dY[9][1] = -kC3a * (3 * xx - 3 * yy);
+        Y[10] = kC3b * x * y * z;
+        dY[10][0] = kC3b * y * z; dY[10][1] = kC3b * x * z; dY[10][2] = kC3b * x * y;
+        Y[11] = -kC3c * y * (4 * zz - xx - yy);
+        dY[11][0] = 2 * kC3c * x * y; dY[11][1] = -kC3c * (4 * zz - xx - 3 * yy);
+        dY[11][2] = -8 * kC3c * y * z;
+        Y[12] = kC3d * z * (2 * zz - 3 * xx - 3 * yy);
+        dY[12][0] = -6 * kC3d * x * z; dY[12][1] = -6 * kC3d * y * z;
+        dY[12][2] = kC3d * (6 * zz - 3 * xx - 3 * yy);
+        Y[13] = -kC3c * x * (4 * zz - xx - yy);
+        dY[13][0] = -kC3c * (4 * zz - 3 * xx - yy); dY[13][1] = 2 * kC3c * x * y;
+        dY[13][2] = -8 * kC3c * x * z;
+        Y[14] = kC3e * z * (xx - yy);
+        dY[14][0] = 2 * kC3e * x * z; dY[14][1] = -2 * kC3e * y * z; dY[14][2] = kC3e * (xx - yy);
+        Y[15] = -kC3a * x * (xx - 3 * yy);
+        dY[15][0] = -kC3a * (3 * xx - 3 * yy); dY[15][1] = 6 * kC3a * x * y;
+    }
+}
+
+struct BwdIn {
+    const float* means;
+    const float* scales;
+    const float* quats;
+    const float* opacity;
+    const float* sh;
+    int sh_degree, sh_stride;
+};
+
+struct BwdOut {
+    float* means;
+    float* scales;
+    float* quats;
+    float* opacity;
+    float* sh;
+};
+
+__global__ __launch_bounds__(256) void k_preprocess_bwd(ss_camera cam, BwdIn in, int64_t n,
+                                                        const float4* __restrict__ conic_rec,
+                                                        const float4* __restrict__ rgb_rec,
+                                                        const float* __restrict__ g2d,
+                                                        BwdOut out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int nb = (in.sh_degree + 1) * (in.sh_degree + 1);
+    float* osh = out.sh + (int64_t)3 * in.sh_stride * i;
+    const float4 rec = conic_rec[i];
+    const bool alive = rec.x != 0.0f || rec.y != 0.0f || rec.z != 0.0f;
+    if (!alive) {
+        for (int k = 0; k < 3; ++k) { out.means[3 * i + k] = 0.f; out.scales[3 * i + k] = 0.f; }
+        for (int k = 0; k < 4; ++k) out.quats[4 * i + k] = 0.f;
+        out.opacity[i] = 0.f;
+        for (int k = 0; k < 3 * in.sh_stride; ++k) osh[k] = 0.f;
+        return;
+    }
+    const float* G = g2d + (size_t)i * 12;
+    const double gu = G[0], gv = G[1], ga = G[4], gb = G[5], gc = G[6];
+    const double grgb[3] = {G[8], G[9], G[10]};
+    out.opacity[i] = G[7];
+
+    const double Rc[9] = {cam.R[0], cam.R[1], cam.R[2], cam.R[3], cam.R[4],
+                          cam.R[5], cam.R[6], cam.R[7], cam.R[8]};
+    const double mx = in.means[3 * i], my = in.means[3 * i + 1], mz = in.means[3 * i + 2];
+    const double x = ((Rc[0] * mx + Rc[1] * my) + Rc[2] * mz) + (double)cam.t[0];
+    const double y = ((Rc[3] * mx + Rc[4] * my) + Rc[5] * mz) + (double)cam.t[1];
+    const double z = ((Rc[6] * mx + Rc[7] * my) + Rc[8] * mz) + (double)cam.t[2];
+    const double fx = cam.fx, fy = cam.fy;
+
+    // ---- colour -> SH and view direction (a channel the forward clamped to 0,
+    // as its stored colour shows, passes no gradient)
+    double gpos[3] = {0.0, 0.0, 0.0};   // gradient w.r.t. the camera-space point
+    double gmean[3] = {0.0, 0.0, 0.0};  // gradient w.r.t. the world mean
+    {
+        const float cpx = -((cam.R[0] * cam.t[0] + cam.R[3] * cam.t[1]) + cam.R[6] * cam.t[2]);
+        const float cpy = -((cam.R[1] * cam.t[0] + cam.R[4] * cam.t[1]) + cam.R[7] * cam.t[2]);
+        const float cpz = -((cam.R[2] * cam.t[0] + cam.R[5] * cam.t[1]) + cam.R[8] * cam.t[2]);
+        const float m0 = in.means[3 * i], m1 = in.means[3 * i + 1], m2 = in.means[3 * i + 2];
+        const double dvx = (double)m0 - cpx, dvy = (double)m1 - cpy, dvz = (double)m2 - cpz;
+        const double len = sqrt(dvx * dvx + dvy * dvy + dvz * dvz);
+        const double dx = dvx / len, dy = dvy / len, dz = dvz / len;
+        double Y[16], dY[16][3];
+        sh_basis_grad(dx, dy, dz, nb, Y, dY);
+        const float* h = in.sh + (int64_t)3 * in.sh_stride * i;
+        const float4 col = rgb_rec[i];
+        const double gsum[3] = {col.x > 0.0f ? grgb[0] : 0.0, col.y > 0.0f ? grgb[1] : 0.0,
+                                col.z > 0.0f ? grgb[2] : 0.0};
+        double gd[3] = {0.0, 0.0, 0.0};
+        for (int k = 0; k < nb; ++k) {
+            const double gy = (double)h[3 * k] * gsum[0] + (double)h[3 * k + 1] * gsum[1] +
+                              (double)h[3 * k + 2] * gsum[2];
+            for (int a = 0; a < 3; ++a) gd[a] += gy * dY[k][a];
+            for (int ch = 0; ch < 3; ++ch) osh[3 * k + ch] = (float)(Y[k] * gsum[ch]);
+        }
+        for (int k = 3 * nb; k < 3 * in.sh_stride; ++k) osh[k] = 0.f;
+        const double dd = gd[0] * dx + gd[1] * dy + gd[2] * dz;
+        gmean[0] += (gd[0] - dx * dd) / len;
+        gmean[1] += (gd[1] - dy * dd) / len;
+        gmean[2] += (gd[2] - dz * dd) / len;
+    }
+
+    // ---- projection of the mean
+    gpos[0] += gu * fx / z;
+    gpos[1] += gv * fy / z;
+    gpos[2] += -gu * fx * x / (z * z) - gv * fy * y / (z * z);
+
+    // ---- forward geometry (FP64) for the covariance chain
+    const float4 qr = *reinterpret_cast<const float4*>(in.quats + 4 * i);
+    const double q0 = qr.x, q1 = qr.y, q2 = qr.z, q3 = qr.w;
+    const double qnorm = sqrt(((q0 * q0 + q1 * q1) + q2 * q2) + q3 * q3);
+    const double w_ = q0 / qnorm, x_ = q1 / qnorm, y_ = q2 / qnorm, z_ = q3 / qnorm;
+    double Rq[9];
+    Rq[0] = 1.0 - 2.0 * (y_ * y_ + z_ * z_);
+    Rq[1] = 2.0 * (x_ * y_ - w_ * z_);
+    Rq[2] = 2.0 * (x_ * z_ + w_ * y_);
+    Rq[3] = 2.0 * (x_ * y_ + w_ * z_);
+    Rq[4] = 1.0 - 2.0 * (x_ * x_ + z_ * z_);
+    Rq[5] = 2.0 * (y_ * z_ - w_ * x_);
+    Rq[6] = 2.0 * (x_ * z_ - w_ * y_);
+    Rq[7] = 2.0 * (y_ * z_ + w_ * x_);
+    Rq[8] = 1.0 - 2.0 * (x_ * x_ + y_ * y_);
+    const double sc[3] = {in.scales[3 * i], in.scales[3 * i + 1], in.scales[3 * i + 2]};
+    double M[9], S3[9];
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) M[3 * r + c] = Rq[3 * r + c] * sc[c];
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c)
+            S3[3 * r + c] = M[3 * r] * M[3 * c] + M[3 * r + 1] * M[3 * c + 1] + M[3 * r + 2] * M[3 * c + 2];
+    const double limx = kFovClamp * ((0.5 * (double)cam.width) / fx);
+    const double limy = kFovClamp * ((0.5 * (double)cam.height) / fy);
+    const double rx = x / z, ry = y / z;
+    const bool clx = rx < -limx || rx > limx, cly = ry < -limy || ry > limy;
+    const double txz = rx < -limx ? -limx : (rx > limx ? limx : rx);
+    const double tyz = ry < -limy ? -limy : (ry > limy ? limy : ry);
+    const double J00 = fx / z, J02 = -(fx * txz) / z, J11 = fy / z, J12 = -(fy * tyz) / z;
+    double T[6];
+    for (int j = 0; j < 3; ++j) {
+        T[j] = J00 * Rc[j] + J02 * Rc[6 + j];
+        T[3 + j] = J11 * Rc[3 + j] + J12 * Rc[6 + j];
+    }
+    double V[6];
+    for (int r = 0; r < 2; ++r)
+        for (int c = 0; c < 3; ++c)
+            V[3 * r + c] = T[3 * r] * S3[c] + T[3 * r + 1] * S3[3 + c] + T[3 * r + 2] * S3[6 + c];
+    const double A = V[0] * T[0] + V[1] * T[1] + V[2] * T[2] + kDilation;
+    const double B = V[0] * T[3] + V[1] * T[4] + V[2] * T[5];
+    const double C = V[3] * T[3] + V[4] * T[4] + V[5] * T[5] + kDilation;
+    const double D = A * C - B * B;
+    const double D2 = D * D;
+
+    // ---- conic (a, b, c) = (C, -B, A) / D  ->  (A, B, C)
+    const double gA = (-ga * C * C + gb * B * C - gc * B * B) / D2;
+    const double gB = (2.0 * ga * B * C - gb * (A * C + B * B) + 2.0 * gc * A * B) / D2;
+    const double gC = (-ga * B * B + gb * A * B - gc * A * A) / D2;
+    // symmetric upstream gradient of Sigma_2D (B sits in both off-diagonal entries)
+    const double G00 = gA, G01 = 0.5 * gB, G11 = gC;
+
+    // ---- Sigma_2D = T Sigma_3D T^T:  gS3 = T^T G T,  gT = 2 G T Sigma_3D
+    double GT[6];   // G T (2x3)
+    for (int c = 0; c < 3; ++c) {
+        GT[c] = G00 * T[c] + G01 * T[3 + c];
+        GT[3 + c] = G01 * T[c] + G11 * T[3 + c];
+    }
+    double gS3[9];
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) gS3[3 * r + c] = T[r] * GT[c] + T[3 + r] * GT[3 + c];
+    double gT[6];
+    for (int r = 0; r < 2; ++r)
+        for (int c = 0; c < 3; ++c)
+            gT[3 * r + c] = 2.0 * (GT[3 * r] * S3[c] + GT[3 * r + 1] * S3[3 + c] +
+                                   GT[3 * r + 2] * S3[6 + c]);
+    // T = J Rc:  gJ = gT Rc^T (only J00, J02, J11, J12 vary)
+    const double gJ00 = gT[0] * Rc[0] + gT[1] * Rc[1] + gT[2] * Rc[2];
+    const double gJ02 = gT[0] * Rc[6] + gT[1] * Rc[7] + gT[2] * Rc[8];
+    const double gJ11 = gT[3] * Rc[3] + gT[4] * Rc[4] + gT[5] * Rc[5];
+    const double gJ12 = gT[3] * Rc[6] + gT[4] * Rc[7] + gT[5] * Rc[8];
+    const double z2 = z * z, z3 = z2 * z;
+    gpos[2] += -gJ00 * fx / z2 - gJ11 * fy / z2;
+    if (!clx) {
+        gpos[0] += -gJ02 * fx / z2;
+        gpos[2] += gJ02 * 2.0 * fx * x / z3;
+    } else {
+        gpos[2] += gJ02 * fx * txz / z2;
+    }
+    if (!cly) {
+        gpos[1] += -gJ12 * fy / z2;
+        gpos[2] += gJ12 * 2.0 * fy * y / z3;
+    } else {
+        gpos[2] += gJ12 * fy * tyz / z2;
+    }
+    // camera space -> world
+    for (int a = 0; a < 3; ++a)
+        gmean[a] += Rc[a] * gpos[0] + Rc[3 + a] * gpos[1] + Rc[6 + a] * gpos[2];
+    for (int a = 0; a < 3; ++a) out.means[3 * i + a] = (float)gmean[a];
+
+    // ---- Sigma_3D = M M^T, M = Rq diag(s)
+    double gM[9];
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c)
+            gM[3 * r + c] = 2.0 * (gS3[3 * r] * M[c] + gS3[3 * r + 1] * M[3 + c] +
+                                   gS3[3 * r + 2] * M[6 + c]);
+    double gRq[9];
+    for (int c = 0; c < 3; ++c) {
+        double gsc = 0.0;
+        for (int r = 0; r < 3; ++r) {
+            gsc += gM[3 * r + c] * Rq[3 * r + c];
+            gRq[3 * r + c] = gM[3 * r + c] * sc[c];
+        }
+        out.scales[3 * i + c] = (float)gsc;
+    }
+    // rotation of the unit quaternion (w, x, y, z)
+    double gw = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
+    gx += -4.0 * x_ * (gRq[4] + gRq[8]);
+    gy += -4.0 * y_ * (gRq[0] + gRq[8]);
+    gz += -4.0 * z_ * (gRq[0] + gRq[4]);
+    gw += 2.0 * (-z_ * gRq[1] + y_ * gRq[2] + z_ * gRq[3] - x_ * gRq[5] - y_ * gRq[6] + x_ * gRq[7]);
+    gx += 2.0 * (y_ * gRq[1] + z_ * gRq[2] + y_ * gRq[3] - w_ * gRq[5] + z_ * gRq[6] + w_ * gRq[7]);
+    gy += 2.0 * (x_ * gRq[1] + w_ * gRq[2] + x_ * gRq[3] + z_ * gRq[5] - w_ * gRq[6] + z_ * gRq[7]);
+    gz += 2.0 * (-w_ * gRq[1] + x_ * gRq[2] + w_ * gRq[3] + y_ * gRq[5] + x_ * gRq[6] + y_ * gRq[7]);
+    // through the normalisation q / |q|
+    const double dot = gw * w_ + gx * x_ + gy * y_ + gz * z_;
+    out.quats[4 * i + 0] = (float)((gw - w_ * dot) / qnorm);
+    out.quats[4 * i + 1] = (float)((gx - x_ * dot) / qnorm);
+    out.quats[4 * i + 2] = (float)((gy - y_ * dot) / qnorm);
+    out.quats[4 * i + 3] = (float)((gz - z_ * dot) / qnorm);
+}
+
+}  // namespace
+
+hipError_t launch_backward(const ss_camera& cam, const ss_gaussians& g, const ss_frame& f,
+                           const uint32_t* values, const float* dl_drgb, const ss_grads& out,
+                           hipStream_t s) {
+    const int tx_n = (cam.width + kTile - 1) / kTile, ty_n = (cam.height + kTile - 1) / kTile;
+    const int n_tiles = tx_n * ty_n;
+    if (g.n > 0) {
+        const int64_t m = g.n * 12;
+        hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s,
+                           out.g2d, m);
+        if (out.score)
+            hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)((g.n + 255) / 256)), dim3(256), 0, s,
+                               out.score, g.n);
+    }
+    const int grid = 8 * ((n_tiles + 7) / 8);
+    hipLaunchKernelGGL(k_blend_bwd<1>, dim3(grid), dim3(256), 0, s, tx_n, n_tiles, cam.width,
+                       cam.height, cam.bg[0], cam.bg[1], cam.bg[2], f.ranges, values,
+                       reinterpret_cast<const float4*>(f.geom),
+                       reinterpret_cast<const float4*>(f.conic),
+                       reinterpret_cast<const float4*>(f.rgb), f.t_final, f.n_last, dl_drgb,
+                       out.g2d, out.score);
+    if (g.n > 0) {
+        BwdIn in{g.means, g.scales, g.quats, g.opacity, g.sh, g.sh_degree, g.sh_stride};
+        BwdOut o{out.means, out.scales, out.quats, out.opacity, out.sh};
+        hipLaunchKernelGGL(k_preprocess_bwd, dim3((unsigned)((g.n + 255) / 256)), dim3(256), 0, s,
+                           cam, in, g.n, reinterpret_cast<const float4*>(f.conic),
+                           reinterpret_cast<const float4*>(f.rgb), out.g2d, o);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace ss

@@ -4,21 +4,51 @@
 // One wave (64 lanes) per 16x16 tile.  Lane l owns column l % 16 and rows
 // l / 16 + 4s of the four 16x4 strips s = 0..3, so the dx-dependent terms of
 // q are computed once per lane and Gaussian and shared by its four pixels, and
-// each strip skips a Gaussian as a unit when none of its 64 pixels lies inside
-// the ellipse.  The tile's sorted Gaussians are staged through LDS 64 at a
-// time (one record per lane, gathered by index), and the walk ends as soon as
-// a ballot finds every pixel of the tile finished.  The quadratic form is
-// evaluated as ((a dx) dx + (c dy) dy) + ((2b) dx) dy without contraction and
-// compared with the record's t, so the inclusion test (alpha >= 1/255) is
-// exact and reproducible.  Nothing on this path is a dense contraction, so it
-// runs on the FP32 VALU.
+// a strip's included-pixel work is skipped as a unit when none of its 64
+// pixels lies inside the ellipse.  The tile's sorted Gaussians are staged
+// through LDS 64 at a time (one gathered record per lane); the next batch's
+// records are loaded into registers while the current batch is blended.
+//
+// A pixel that has finished (the next Gaussian would take its transmittance
+// below 1e-4) moves its sample row to y = 1e30, so its q <= t test fails from
+// then on with no extra instructions; the wave stops once a ballot finds every
+// pixel finished.  The quadratic form is evaluated as
+// ((a dx) dx + (c dy) dy) + ((2b) dx) dy without contraction and compared
+// with the record's t, so the inclusion test (alpha >= 1/255) is exact and
+// reproducible.  Nothing on this path is a dense contraction, so it runs on
+// the FP32 VALU.
 #include "ss_internal.h"
 
 namespace ss {
 namespace {
 
 constexpr int kBatch = 64;
+constexpr float kDone = 1e30f;                    // sample row of a finished pixel
+constexpr float kNegHalfLog2e = -0.72134752044448170368f;  // -log2(e) / 2
 
+struct Rec {
+    float4 g;   // (u, v, -, t)
+    float4 q;   // (a, 2b, c, sigma)
+    float4 c;   // (r, g, b, -)
+};
+
+__device__ __forceinline__ Rec load_rec(const uint32_t* __restrict__ values,
+                                        const float4* __restrict__ geom,
+                                        const float4* __restrict__ conic,
+                                        const float4* __restrict__ rgb, uint32_t j, uint32_t end) {
+    Rec r;
+    if (j < end) {
+        const uint32_t gi = values[j];
+        r.g = geom[gi];
+        r.q = conic[gi];
+        r.c = rgb[gi];
+    } else {
+        r.g = r.q = r.c = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    return r;
+}
+
+template <bool STATS>
 __global__ __launch_bounds__(64) void k_blend(int tx_n, int n_tiles, int W, int H, float bg0,
                                               float bg1, float bg2,
                                               const uint32_t* __restrict__ ranges,
@@ -30,9 +60,9 @@ __global__ __launch_bounds__(64) void k_blend(int tx_n, int n_tiles, int W, int 
                                               float* __restrict__ t_final,
                                               uint32_t* __restrict__ n_last,
                                               uint32_t* __restrict__ n_eval) {
-    __shared__ float4 s_geo[kBatch];   // (u, v, -, t)
-    __shared__ float4 s_con[kBatch];   // (a, 2b, c, sigma)
-    __shared__ float4 s_col[kBatch];   // (r, g, b, -)
+    __shared__ float4 s_geo[kBatch];
+    __shared__ float4 s_con[kBatch];
+    __shared__ float4 s_col[kBatch];
     const int tile = xcd_contiguous((int)blockIdx.x, n_tiles);
     if (tile < 0) return;
     const int lane = (int)threadIdx.x;
@@ -42,58 +72,54 @@ __global__ __launch_bounds__(64) void k_blend(int tx_n, int n_tiles, int W, int 
     const float fx = (float)px + 0.5f;
     float fy[4], T[4], C[4][3];
     uint32_t last[4], stop[4];
-    bool alive[4];
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
-        fy[s] = (float)(py0 + 4 * s) + 0.5f;
+        const bool in = px < W && (py0 + 4 * s) < H;
+        fy[s] = in ? (float)(py0 + 4 * s) + 0.5f : kDone;
         T[s] = 1.0f;
         C[s][0] = C[s][1] = C[s][2] = 0.0f;
         last[s] = 0u;
         stop[s] = 0u;
-        alive[s] = px < W && (py0 + 4 * s) < H;
     }
     const uint32_t start = ranges[2 * tile], end = ranges[2 * tile + 1];
-    bool any = __ballot(alive[0] | alive[1] | alive[2] | alive[3]) != 0ull;
-    for (uint32_t base = start; base < end && any; base += kBatch) {
-        const uint32_t j = base + lane;
-        if (j < end) {
-            const uint32_t gi = values[j];
-            const float4 g = geom[gi], q = conic[gi];
-            s_geo[lane] = g;
-            s_con[lane] = make_float4(q.x, 2.0f * q.y, q.z, q.w);
-            s_col[lane] = rgb[gi];
-        }
+    bool live = __ballot(fy[0] < kDone || fy[1] < kDone || fy[2] < kDone || fy[3] < kDone) != 0ull;
+    Rec nxt = load_rec(values, geom, conic, rgb, start + lane, end);
+    for (uint32_t base = start; base < end && live; base += kBatch) {
+        s_geo[lane] = nxt.g;
+        s_con[lane] = make_float4(nxt.q.x, 2.0f * nxt.q.y, nxt.q.z, nxt.q.w);
+        s_col[lane] = nxt.c;
         __syncthreads();
+        if (base + kBatch < end) nxt = load_rec(values, geom, conic, rgb, base + kBatch + lane, end);
         const uint32_t nb = end - base < (uint32_t)kBatch ? end - base : (uint32_t)kBatch;
         for (uint32_t k = 0; k < nb; ++k) {
             const float4 g = s_geo[k];
             const float4 q = s_con[k];
+            const float4 c = s_col[k];
             const float dx = fx - g.x;
             const float adx2 = (q.x * dx) * dx;
             const float b2dx = q.y * dx;
+            const uint32_t pos = base + k - start + 1u;
 #pragma unroll
             for (int s = 0; s < 4; ++s) {
                 const float dy = fy[s] - g.y;
                 const float qq = (adx2 + (q.z * dy) * dy) + b2dx * dy;
-                if (alive[s] && qq <= g.w) {
-                    const float al = fminf(kAlphaMax, q.w * __expf(-0.5f * qq));
+                if (qq <= g.w) {
+                    const float al = fminf(kAlphaMax, q.w * __builtin_amdgcn_exp2f(qq * kNegHalfLog2e));
                     const float tn = T[s] * (1.0f - al);
-                    if (tn < kTMin) {
-                        alive[s] = false;
-                        stop[s] = base + k - start + 1u;
-                    } else {
-                        const float4 c = s_col[k];
-                        const float w = al * T[s];
-                        C[s][0] = fmaf(c.x, w, C[s][0]);
-                        C[s][1] = fmaf(c.y, w, C[s][1]);
-                        C[s][2] = fmaf(c.z, w, C[s][2]);
-                        T[s] = tn;
-                        last[s] = base + k - start + 1u;
-                    }
+                    const bool ok = tn >= kTMin;
+                    const float wgt = ok ? al * T[s] : 0.0f;
+                    C[s][0] = fmaf(c.x, wgt, C[s][0]);
+                    C[s][1] = fmaf(c.y, wgt, C[s][1]);
+                    C[s][2] = fmaf(c.z, wgt, C[s][2]);
+                    T[s] = ok ? tn : T[s];
+                    last[s] = ok ? pos : last[s];
+                    fy[s] = ok ? fy[s] : kDone;
+                    if (STATS) stop[s] = ok ? stop[s] : pos;
                 }
             }
-            if (__ballot(alive[0] | alive[1] | alive[2] | alive[3]) == 0ull) {
-                any = false;
+            if ((k & 7u) == 7u &&
+                !__ballot(fy[0] < kDone || fy[1] < kDone || fy[2] < kDone || fy[3] < kDone)) {
+                live = false;
                 break;
             }
         }
@@ -110,7 +136,7 @@ __global__ __launch_bounds__(64) void k_blend(int tx_n, int n_tiles, int W, int 
             out[2 * hw + p] = C[s][2] + T[s] * bg2;
             t_final[p] = T[s];
             n_last[p] = last[s];
-            if (n_eval) n_eval[p] = alive[s] ? end - start : stop[s];
+            if (STATS) n_eval[p] = stop[s] ? stop[s] : end - start;
         }
     }
 }
@@ -122,12 +148,16 @@ hipError_t launch_blend(const ss_camera& cam, const ss_frame& f, const uint32_t*
     const int tx_n = (cam.width + kTile - 1) / kTile, ty_n = (cam.height + kTile - 1) / kTile;
     const int n_tiles = tx_n * ty_n;
     const int grid = 8 * ((n_tiles + 7) / 8);
-    hipLaunchKernelGGL(k_blend, dim3(grid), dim3(64), 0, s, tx_n, n_tiles, cam.width, cam.height,
-                       cam.bg[0], cam.bg[1], cam.bg[2], f.ranges, values,
-                       reinterpret_cast<const float4*>(f.geom),
-                       reinterpret_cast<const float4*>(f.conic),
-                       reinterpret_cast<const float4*>(f.rgb), out_rgb, f.t_final, f.n_last,
-                       f.n_eval);
+    auto go = [&](auto kernel) {
+        hipLaunchKernelGGL(kernel, dim3(grid), dim3(64), 0, s, tx_n, n_tiles, cam.width,
+                           cam.height, cam.bg[0], cam.bg[1], cam.bg[2], f.ranges, values,
+                           reinterpret_cast<const float4*>(f.geom),
+                           reinterpret_cast<const float4*>(f.conic),
+                           reinterpret_cast<const float4*>(f.rgb), out_rgb, f.t_final, f.n_last,
+                           f.n_eval);
+    };
+    if (f.n_eval) go(k_blend<true>);
+    else go(k_blend<false>);
     return hipGetLastError();
 }
 

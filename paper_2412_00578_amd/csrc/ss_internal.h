@@ -199,5 +199,8 @@ hipError_t launch_ranges(const uint64_t* keys, uint64_t n_pairs, int n_tiles, ui
                          hipStream_t s);
 hipError_t launch_blend(const ss_camera& cam, const ss_frame& f, const uint32_t* values,
                         float* out_rgb, hipStream_t s);
+hipError_t launch_backward(const ss_camera& cam, const ss_gaussians& g, const ss_frame& f,
+                           const uint32_t* values, const float* dl_drgb, const ss_grads& out,
+                           hipStream_t s);
 
 }  // namespace ss

@@ -79,7 +79,7 @@ class Gaussians:
 class Frame:
     """Per-frame buffers (ss_frame) for n Gaussians at width x height."""
 
-    def __init__(self, n: int, width: int, height: int, device):
+    def __init__(self, n: int, width: int, height: int, device, stats: bool = True):
         info = _lib.SSFrameInfo()
         check(lib().ss_frame_sizes(n, width, height, ctypes.byref(info)), "ss_frame_sizes")
         self.info = info
@@ -94,18 +94,21 @@ class Frame:
         self.ranges = torch.empty((info.n_tiles, 2), dtype=torch.int32, device=dev)
         self.t_final = torch.empty((height, width), dtype=torch.float32, device=dev)
         self.n_last = torch.empty((height, width), dtype=torch.int32, device=dev)
-        self.n_eval = torch.empty((height, width), dtype=torch.int32, device=dev)
+        # per-pixel count of evaluated list entries (a statistic; NULL skips it)
+        self.n_eval = torch.empty((height, width), dtype=torch.int32, device=dev) if stats else None
         self.emit_tmp = torch.empty(n + 1, dtype=torch.int32, device=dev)
 
     def struct(self) -> _lib.SSFrame:
         f = _lib.SSFrame()
         for name in ("geom", "conic", "rgb", "counts", "offsets", "scan_tmp", "ranges",
                      "t_final", "n_last", "n_eval", "emit_tmp"):
-            setattr(f, name, getattr(self, name).data_ptr())
+            t = getattr(self, name)
+            setattr(f, name, t.data_ptr() if t is not None else None)
         return f
 
-    def fits(self, n, width, height) -> bool:
-        return self.n == n and self.width == width and self.height == height
+    def fits(self, n, width, height, stats=True) -> bool:
+        return (self.n == n and self.width == width and self.height == height
+                and (self.n_eval is not None) == stats)
 
 
 class Pairs:
@@ -170,15 +173,19 @@ class RenderOutput:
 class Renderer:
     """Owns reusable frame and pair buffers; grows them on demand."""
 
-    def __init__(self, device="cuda", growth: float = 1.25):
+    def __init__(self, device="cuda", growth: float = 1.25, stats: bool = False):
+        """stats=True also records, per pixel, how many list entries it evaluated
+        (Frame.n_eval)."""
         self.device = torch.device(device)
         self.growth = growth
+        self.stats = stats
         self._frame: Frame | None = None
         self._pairs: Pairs | None = None
 
     def frame_for(self, n, width, height) -> Frame:
-        if self._frame is None or not self._frame.fits(n, width, height):
-            self._frame = Frame(n, width, height, self.device)
+        if self._frame is None or not self._frame.fits(n, width, height, self.stats):
+            self._frame = None
+            self._frame = Frame(n, width, height, self.device, self.stats)
         return self._frame
 
     def pairs_for(self, n_pairs) -> Pairs:
@@ -259,3 +266,80 @@ class Renderer:
         check(lib().ss_blend(ctypes.byref(c), ctypes.byref(fs), ctypes.byref(ps), buf, _ptr(out),
                              _stream(self.device)), "ss_blend")
         return out
+
+
+# ---------------------------------------------------------------- gradients
+
+@dataclass
+class Grads:
+    means: torch.Tensor
+    scales: torch.Tensor
+    quats: torch.Tensor
+    opacity: torch.Tensor
+    sh: torch.Tensor
+    g2d: torch.Tensor        # [n, 12] screen-space gradients (u, v, -, -, a, b, c, sigma, r, g, b, -)
+    score: torch.Tensor | None
+
+
+def backward(g: Gaussians, cam, out: RenderOutput, dl_drgb: torch.Tensor,
+             want_score: bool = False) -> Grads:
+    """Adjoint of a forward render `out` (from Renderer.render(..., full=True))."""
+    c = make_camera(cam)
+    dev = g.device
+    dl = dl_drgb.contiguous().to(torch.float32)
+    if tuple(dl.shape) != (3, c.height, c.width):
+        raise ValueError(f"dl_drgb must be [3, {c.height}, {c.width}]")
+    n = g.n
+    gr = Grads(torch.empty_like(g.means), torch.empty_like(g.scales), torch.empty_like(g.quats),
+               torch.empty_like(g.opacity), torch.empty_like(g.sh),
+               torch.empty((n, 12), dtype=torch.float32, device=dev),
+               torch.empty(n, dtype=torch.float32, device=dev) if want_score else None)
+    st = _lib.SSGrads()
+    st.means, st.scales, st.quats = gr.means.data_ptr(), gr.scales.data_ptr(), gr.quats.data_ptr()
+    st.opacity, st.sh, st.g2d = gr.opacity.data_ptr(), gr.sh.data_ptr(), gr.g2d.data_ptr()
+    st.score = gr.score.data_ptr() if want_score else None
+    gs, fs, ps = g.struct(), out.frame.struct(), out.pairs.struct()
+    check(lib().ss_render_backward(ctypes.byref(c), ctypes.byref(gs), ctypes.byref(fs),
+                                   ctypes.byref(ps), out.buf, _ptr(dl), ctypes.byref(st),
+                                   _stream(dev)), "ss_render_backward")
+    return gr
+
+
+class _Rasterize(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, means, scales, quats, opacity, sh, cam, mode, sh_degree):
+        g = Gaussians(means.detach(), scales.detach(), quats.detach(), opacity.detach(),
+                      sh.detach(), sh_degree)
+        r = Renderer(means.device)   # buffers owned by this call, kept for its backward
+        out = r.render(g, cam, mode, full=True)
+        ctx.state = (g, cam, out)
+        return out.image
+
+    @staticmethod
+    def backward(ctx, grad_img):
+        g, cam, out = ctx.state
+        gr = backward(g, cam, out, grad_img)
+        ctx.state = None
+        return gr.means, gr.scales, gr.quats, gr.opacity, gr.sh, None, None, None
+
+
+def render(means, scales, quats, opacity, sh, camera, mode="accutile", sh_degree=None):
+    """Differentiable forward render (a torch.autograd.Function).
+
+    means [N,3], scales [N,3] (linear, > 0), quats [N,4] (w, x, y, z),
+    opacity [N] in (0, 1], sh [N, K, 3]; all float32 on the GPU.  Apply the
+    activations (e.g. exp of log-scales, sigmoid of logits) in torch before the
+    call.  Returns the image [3, H, W]."""
+    deg = int(round(sh.shape[1] ** 0.5)) - 1 if sh_degree is None else int(sh_degree)
+    return _Rasterize.apply(means, scales, quats, opacity.reshape(-1), sh, camera, mode, deg)
+
+
+def pruning_score(g: Gaussians, cam, mode="accutile") -> torch.Tensor:
+    """Per-Gaussian efficient pruning score: sum over pixels and colour channels
+    of (dC/dg_i)^2, where g_i is the value of Gaussian i's projected 2D
+    Gaussian at the pixel.  One forward and one adjoint pass."""
+    r = Renderer(g.device)
+    out = r.render(g, cam, mode, full=True)
+    dl = torch.zeros((3, out.image.shape[1], out.image.shape[2]), dtype=torch.float32,
+                     device=g.device)
+    return backward(g, cam, out, dl, want_score=True).score

@@ -26,7 +26,7 @@ def ss():
 
 def _run(ss, dev, scene, cam, mode):
     print(f"[case] n={scene.n} {cam.width}x{cam.height} mode={mode}", flush=True)
-    r = ss.Renderer(dev)
+    r = ss.Renderer(dev, stats=True)
     g = ss.Gaussians.from_scene(scene, dev)
     return gpu_stages(r, g, cam, mode)
 
@@ -110,12 +110,14 @@ def test_empty_scene_gives_background(ss, gpu_device):
 @pytest.mark.parametrize("mode", MODES)
 def test_composite_render_equals_stages(ss, gpu_device, mode):
     sc, cam = scenegen.scene_c0(seed=3), scenegen.camera_c0()
-    r = ss.Renderer(gpu_device)
+    r = ss.Renderer(gpu_device, stats=True)
     g = ss.Gaussians.from_scene(sc, gpu_device)
     stages = gpu_stages(r, g, cam, mode)
-    out = r.render(g, cam, mode, full=True)
+    # the composite call without per-pixel statistics renders the same bits
+    out = ss.Renderer(gpu_device).render(g, cam, mode, full=True)
     torch.cuda.synchronize()
     assert out.buf == 0
+    assert np.array_equal(u32(out.frame.n_last), stages["n_last"])
     p = out.n_pairs
     assert p == stages["n_pairs"]
     assert np.array_equal(u64(out.pairs.keys[0][:p]), stages["sorted_keys"])
@@ -159,7 +161,7 @@ def test_scan_matches_cumsum(ss, gpu_device, n):
     print(f"[case] scan n={n}", flush=True)
     rng = np.random.default_rng(n + 1)
     counts = rng.integers(0, 12, size=n).astype(np.uint32)
-    f = ss.Frame(n, 16, 16, gpu_device)
+    f = ss.Frame(n, 16, 16, gpu_device, stats=False)
     f.counts.copy_(torch.from_numpy(counts.view(np.int32)))
     r = ss.Renderer(gpu_device)
     total = r.scan(f)
@@ -185,7 +187,7 @@ def test_sort_and_ranges_random_keys(ss, gpu_device, n):
         pairs.keys[0][:n].copy_(torch.from_numpy(keys.view(np.int64)))
         pairs.values[0][:n].copy_(torch.from_numpy(vals.view(np.int32)))
     ob = r.sort(cam, pairs, n, 0)
-    f = ss.Frame(1, cam.width, cam.height, gpu_device)
+    f = ss.Frame(1, cam.width, cam.height, gpu_device, stats=False)
     r.ranges(cam, f, pairs, n, ob)
     torch.cuda.synchronize()
     order = np.lexsort((vals, keys))
