@@ -2,8 +2,8 @@
  * speedysplat.h - C ABI of the MI355X (gfx950) Speedy-Splat rasterizer.
  *
  * The library renders a set of 3D Gaussians G_i = {mu_i, s_i, r_i, h_i,
- * sigma_i} for a camera pose (Speedy-Splat, arXiv 2412.00578, Sec. 3) with the
- * tile-based pipeline of Sec. 3.1-3.3 and one of three tile assignments:
+ * sigma_i} for a camera pose (Speedy-Splat, arXiv 2412.00578, Sec. 3.1) with the
+ * tile-based pipeline of Sec. 3.2.1-3.2.3 and one of three tile assignments:
  *   SS_TILE_3SIGMA    the square of radius ceil(3 sqrt(lambda_max)) (Eq. radius)
  *   SS_TILE_SNUGBOX   the opacity-aware tight bounding box (Sec. 4.1.1)
  *   SS_TILE_ACCUTILE  the exact tiles touched by the ellipse (Sec. 4.1.2, Alg. 1)
@@ -43,7 +43,7 @@
  * the record; every tile decision is then made in FP64 on the stored record, so
  * the tile counts of the preprocess stage equal the pairs the emit stage writes.
  *
- * Pair keys (Sec. 3.2): key = (uint64 tile_id << 32) | bits(depth as f32),
+ * Pair keys (Sec. 3.2.2): key = (uint64 tile_id << 32) | bits(depth as f32),
  * value = Gaussian index.  The sorted order is by key, ties by index.
  */
 #ifndef SPEEDYSPLAT_H
@@ -72,8 +72,8 @@ enum ss_tile_mode { SS_TILE_3SIGMA = 0, SS_TILE_SNUGBOX = 1, SS_TILE_ACCUTILE = 
  * own independently typed copies. */
 typedef struct ss_constants {
     int32_t abi_version;
-    int32_t tile;          /* 16 (Sec. 3.1: 16 x 16 pixel tiles) */
-    float alpha_min;       /* 1/255: inclusion cutoff (Sec. 3.3) */
+    int32_t tile;          /* 16 (Sec. 3.2: 16 x 16 pixel tiles) */
+    float alpha_min;       /* 1/255: inclusion cutoff (Sec. 3.2.3) */
     float alpha_max;       /* 0.99: upper clamp of alpha */
     float t_min;           /* 1e-4: transmittance stop */
     float dilation;        /* 0.3 added to the diagonal of Sigma_2D */
@@ -171,7 +171,7 @@ int ss_frame_sizes(int64_t n, int32_t width, int32_t height, ss_frame_info *out)
 int ss_sort_tmp_words(uint64_t capacity, int64_t *out_words);
 
 /*
- * Stage 1, preprocess (Sec. 3.1 and Sec. 4.1): for every Gaussian, the record
+ * Stage 1, preprocess (Sec. 3.2.1 and Sec. 4.1): for every Gaussian, the record
  * (projection, Sigma_3D = R S S^T R^T, EWA Sigma_2D + 0.3 I, conic, t, SH
  * colour) and its tile count under `mode`.  Writes frame->geom, conic, rgb,
  * counts.
@@ -180,14 +180,14 @@ int ss_preprocess(const ss_camera *cam, const ss_gaussians *g, int32_t mode,
                   const ss_frame *frame, void *stream);
 
 /*
- * Stage 2, inclusive prefix sum of the tile counts (Sec. 3.2 "InclusiveSum"):
+ * Stage 2, inclusive prefix sum of the tile counts (Sec. 3.2.2, "InclusiveSum"):
  * frame->offsets[i] = sum_{j <= i} counts[j]; the total P goes to
  * frame->scan_tmp[0] (uint64).
  */
 int ss_scan(int64_t n, const ss_frame *frame, void *stream);
 
 /*
- * Stage 3, key emission (Sec. 3.2 "duplicateWithKeys", Alg. 1 "Process"):
+ * Stage 3, key emission (Sec. 3.2.2, "duplicateWithKeys"; Alg. 1 "Process"):
  * Gaussian i writes its tiles, in its tile-enumeration order, at
  * [offsets[i] - counts[i], offsets[i]) of pairs->keys[buf] / values[buf].
  * n_pairs must be the P the scan produced and <= pairs->capacity.
@@ -197,14 +197,14 @@ int ss_emit(const ss_camera *cam, int64_t n, int32_t mode, const ss_frame *frame
 
 /*
  * Stage 4, LSD radix sort of the pairs in buffer `buf` on the low
- * ss_frame_info.sort_bits bits of the key (Sec. 3.2 "RadixSort"); stable, so
+ * ss_frame_info.sort_bits bits of the key (Sec. 3.2.2, "RadixSort"); stable, so
  * equal keys keep index order.  *out_buf receives the buffer holding the result.
  */
 int ss_sort(const ss_camera *cam, const ss_pairs *pairs, int32_t buf, uint64_t n_pairs,
             int32_t *out_buf, void *stream);
 
 /*
- * Stage 5, per-tile ranges of the sorted keys (Sec. 3.2 "identifyTileRanges"):
+ * Stage 5, per-tile ranges of the sorted keys (Sec. 3.2.2, "identifyTileRanges"):
  * frame->ranges[tile] = [first, last + 1) of the tile's run; an empty tile gets
  * start = end = the position where its run would begin.
  */
@@ -212,7 +212,7 @@ int ss_ranges(const ss_camera *cam, const ss_frame *frame, const ss_pairs *pairs
               uint64_t n_pairs, void *stream);
 
 /*
- * Stage 6, blend (Sec. 3.3, Eqs. render_alpha, 2d_gaussian_scalar,
+ * Stage 6, blend (Sec. 3.2.3, Eqs. render_alpha, 2d_gaussian_scalar,
  * contribution): front to back over each tile's sorted Gaussians, a Gaussian
  * is included at a pixel when q <= t (alpha >= 1/255), alpha = min(0.99,
  * sigma exp(-q/2)); the walk stops before a Gaussian that would take the

@@ -3,7 +3,7 @@
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 
 The renderer recomputes the per-Gaussian records in FP64 from the parameters
-(the chain of Sec. 3.1: camera space, projection, Sigma_3D = R S S^T R^T, EWA
+(the chain of Sec. 3.2.1: camera space, projection, Sigma_3D = R S S^T R^T, EWA
 with the FOV-clamped Jacobian and +0.3 dilation, conic, SH colour) and blends
 every pixel against all Gaussians in depth order (Eqs. render_alpha,
 2d_gaussian_scalar, contribution).  The discrete parts of the forward pass

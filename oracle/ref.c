@@ -11,7 +11,7 @@
  * evaluated in the written order (no contraction into FMA).
  *
  * Stages and where the paper defines them (Speedy-Splat, arXiv 2412.00578):
- *   preprocess   Sec. 3.1 "Preprocessing": projection of the mean, the 3D
+ *   preprocess   Sec. 3.2.1 "Preprocessing": projection of the mean, the 3D
  *                covariance R S S^T R^T (Eq. for Sigma_3D), the EWA projection
  *                J W Sigma W^T J^T with the last row/column dropped, its
  *                inverse (the conic), and the view-dependent colour from SH.
@@ -25,9 +25,9 @@
  *                side of the SnugBox tile extent is shorter) the ellipse's
  *                extent is the SnugBox extremal point when it lies in the band,
  *                otherwise the extreme of the two band-boundary intersections.
- *   keys/sort    Sec. 3.2 "Sorting": key = tile index | depth, stable sort,
+ *   keys/sort    Sec. 3.2.2 "Sorting": key = tile index | depth, stable sort,
  *                per-tile ranges.
- *   blend        Sec. 3.3, Eqs. render_alpha, 2d_gaussian_scalar and
+ *   blend        Sec. 3.2.3, Eqs. render_alpha, 2d_gaussian_scalar and
  *                contribution: alpha = sigma exp(-q/2), included when
  *                alpha >= 1/255 (tested as q <= t), front-to-back compositing.
  *

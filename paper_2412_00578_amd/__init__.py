@@ -1,7 +1,7 @@
 """MI355X-native Speedy-Splat rasterizer (gfx950 HIP kernels behind a C ABI).
 
 The forward path renders 3D Gaussians with the tile pipeline of Speedy-Splat
-(arXiv 2412.00578, Sec. 3) and one of three tile assignments: the 3-sigma
+(arXiv 2412.00578, Sec. 3.2) and one of three tile assignments: the 3-sigma
 square (Eq. radius), SnugBox (Sec. 4.1.1) or AccuTile (Sec. 4.1.2, Alg. 1).
 """
 from ._lib import MODES, SplatError, constants, lib  # noqa: F401

@@ -1,4 +1,4 @@
-// Stage 6: per-tile front-to-back alpha blending (Speedy-Splat Sec. 3.3,
+// Stage 6: per-tile front-to-back alpha blending (Speedy-Splat Sec. 3.2.3,
 // Eqs. render_alpha, 2d_gaussian_scalar and contribution).
 //
 // One wave (64 lanes) per 16x16 tile.  Lane l owns column l % 16 and rows

@@ -1,4 +1,4 @@
-// Stage 3: key emission (Speedy-Splat Sec. 3.2 "duplicateWithKeys"; the
+// Stage 3: key emission (Speedy-Splat Sec. 3.2.2, "duplicateWithKeys"; the
 // "Process" step of Alg. 1).
 //
 // Gaussian i re-walks its tile spans with the same FP64 function the

@@ -1,4 +1,4 @@
-// Stage 1: per-Gaussian preprocess (Speedy-Splat Sec. 3.1 "Preprocessing",
+// Stage 1: per-Gaussian preprocess (Speedy-Splat Sec. 3.2.1, "Preprocessing",
 // with the opacity-aware threshold of Sec. 4.1).
 //
 // One lane per Gaussian.  The screen-space geometry is FP64 over the FP32

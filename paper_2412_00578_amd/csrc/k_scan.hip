@@ -1,5 +1,5 @@
 // Stage 2: inclusive prefix sum of the per-Gaussian tile counts
-// (Speedy-Splat Sec. 3.2, "InclusiveSum").
+// (Speedy-Splat Sec. 3.2.2, "InclusiveSum").
 //
 // Reduce-then-scan in three launches, so no workgroup ever waits on another:
 //   1. each workgroup sums its 4096 counts into a 64-bit partial;

@@ -1,5 +1,5 @@
 // Stage 4: LSD radix sort of the (tile | depth) keys with their Gaussian
-// indices (Speedy-Splat Sec. 3.2 "RadixSort"), and stage 5: per-tile ranges
+// indices (Speedy-Splat Sec. 3.2.2, "RadixSort"), and stage 5: per-tile ranges
 // ("identifyTileRanges").
 //
 // Only the low 32 + ceil(log2(n_tiles)) key bits can be non-zero, so the sort

@@ -13,7 +13,7 @@
 
 namespace ss {
 
-constexpr int kTile = 16;                 // Sec. 3.1: 16 x 16 pixel tiles
+constexpr int kTile = 16;                 // Sec. 3.2: 16 x 16 pixel tiles
 constexpr double kDilation = 0.3;         // added to the diagonal of Sigma_2D
 constexpr double kFovClamp = 1.3;         // J evaluated with x/z, y/z clamped to 1.3x half-FOV
 constexpr double kDiscFloor = 0.1;        // floor of the eigenvalue discriminant (3-sigma)

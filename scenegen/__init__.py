@@ -5,7 +5,7 @@ rendering arithmetic, so both the CPU oracle and the GPU path can take their
 inputs from it without sharing any code of the method itself.
 
 Scene parameters follow the Gaussian parameterisation of Speedy-Splat
-(Sec. 3, the set G_i = {mu_i, s_i, r_i, h_i, sigma_i}): means [N,3],
+(Sec. 3.1, the set G_i = {mu_i, s_i, r_i, h_i, sigma_i}): means [N,3],
 scales [N,3] (linear, > 0), rotations [N,4] as unit quaternions (w, x, y, z),
 opacities [N] in (0, 1) and spherical-harmonic coefficients [N, (d+1)^2, 3].
 The pre-activation values (log-scales and opacity logits) are returned as well,
