@@ -4,8 +4,9 @@
 Workload: a 1.5M-Gaussian SH-degree-3 clustered scene (200 anisotropic blobs
 plus 10% uniform background in a 20-unit box) rendered at 1600x1040 with 16x16
 tiles from 8 orbit cameras (radius 12, 10 degrees elevation), all synthetic and
-seeded.  One step is one forward render of one frame: preprocess, scan, pair
-count read-back, key emission, radix sort, tile ranges and blend.  Each of the
+seeded.  One step is one forward render of one frame: preprocess, depth
+order, scan, pair count read-back, key emission, tile sort, tile ranges and
+blend.  Each of the
 three tile assignments (3-sigma, SnugBox, AccuTile) is timed over the same
 steps on the same scene; `value` is the AccuTile frame rate.
 
@@ -15,7 +16,10 @@ the FP32 VALU roofline; the HBM-bound stages against 8 TB/s.  The CPU baseline
 is the test oracle (plain C, one thread) rendering one frame of the same
 workload.
 
-    python bench.py [--steps K] [--warmup W] [--no-cpu-baseline]
+A serving measurement follows (see serving_bench): p50/p99 request latency
+at 0.5 and 0.8 of the saturation request rate over four resident scenes.
+
+    python bench.py [--steps K] [--warmup W] [--no-cpu-baseline] [--no-serve]
 """
 from __future__ import annotations
 
@@ -40,10 +44,15 @@ PEAK_HBM_GBS = 8000.0
 # FP32 operations per evaluated (pixel, Gaussian) pair of the blend: dx, dy,
 # (a dx) dx, (c dy) dy, ((2b) dx) dy, two adds and the q <= t test.
 OPS_PER_EVAL = 11
-# Algorithmic HBM bytes: preprocess reads 236 B (SH-3 inputs) and writes a 52 B
-# record per Gaussian; the sort moves 8 B (histogram read) + 24 B (key/value
-# read and write) per pair per 8-bit pass.
-PRE_BYTES_PER_G = 236 + 52
+# Algorithmic HBM bytes: preprocess reads 236 B (SH-3 inputs) and writes a 56 B
+# record (geom, conic, rgb, count, depth key) per Gaussian; the depth order
+# moves 72 B per Gaussian over its four passes (histogram read 4 B, key and
+# value read and write 4 B each, less the identity values the first pass does
+# not read and the keys the last pass does not write); the tile sort moves
+# 20 B per pair per 8-bit pass.
+PRE_BYTES_PER_G = 236 + 56
+DEPTH_ORDER_BYTES_PER_G = 72
+SORT_BYTES_PER_PAIR_PASS = 20
 
 
 def log(*a):
@@ -77,6 +86,47 @@ def cpu_baseline(scene, cam, runs=3):
                       f"on {cpu_model()} ({os.cpu_count()} visible cores)"}
 
 
+def serving_bench(ss, dev, scale=1.0, n_sat=400, n_req=1000, max_batch=8, pool_gib=16):
+    """Continuous-batching serving over 4 resident scenes (0.3M / 1M / 3M / 6M
+    Gaussians, SH-3, clustered) with random orbit cameras at 640x480,
+    1280x720, 1600x1040 or 1920x1080: the saturation rate X (every request
+    waiting from the start), then p50/p99 latency at Poisson arrivals of 0.5X
+    and 0.8X."""
+    import scenegen
+    from paper_2412_00578_amd.serve import Request, serve
+    t0 = time.perf_counter()
+    gs = []
+    for k in range(4):
+        sc = scenegen.scene_c4(k, scale=scale)
+        gs.append(ss.Gaussians.from_scene(sc, dev))
+        del sc
+    n_res = sum(g.n for g in gs)
+    log(f"serving: {n_res} resident Gaussians ({sum(g.nbytes for g in gs) / 2**30:.2f} GiB) "
+        f"in {time.perf_counter() - t0:.1f} s")
+
+    def stream(n, qps, seed):
+        return [Request(k, s, cam, t) for k, (t, s, cam) in
+                enumerate(scenegen.request_stream(n, qps, 4, seed))]
+
+    kw = dict(device=dev, pool_bytes=int(pool_gib * 2**30), max_batch=max_batch)
+    serve(gs, stream(60, 1e9, 45), mode="accutile", **kw)          # warm-up
+    sat = serve(gs, stream(n_sat, 1e9, 46), mode="accutile", **kw)
+    X = sat.fps
+    out = {"workload": "4 resident scenes 0.3M/1M/3M/6M Gaussians SH-3; cameras on a radius-12 "
+                       "orbit; resolutions 640x480/1280x720/1600x1040/1920x1080 uniform; "
+                       f"pool {pool_gib} GiB, batches <= {max_batch}, 2 launch slots",
+           "resident_gaussians": n_res, "saturation": sat.summary()}
+    log(f"serving saturation: {X:.1f} requests/s, {sat.summary()}")
+    for frac in (0.5, 0.8):
+        st = serve(gs, stream(n_req, frac * X, 44), mode="accutile", **kw)
+        out[f"poisson_{frac}X"] = dict(st.summary(), qps=round(frac * X, 2))
+        log(f"serving at {frac}X = {frac * X:.1f} qps: {st.summary()}")
+    s3 = serve(gs, stream(n_sat, 1e9, 46), mode="3sigma", **kw)
+    out["saturation_3sigma"] = s3.summary()
+    log(f"serving saturation, 3-sigma: {s3.summary()}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -85,6 +135,9 @@ def main():
     ap.add_argument("--n", type=int, default=1_500_000)
     ap.add_argument("--modes", default=",".join(MODES))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--serve-scale", type=float, default=1.0,
+                    help="scale of the resident scenes of the serving measurement")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device-to-device copy 5 times (the reference "
                          "kernel for scaling HBM traffic counters)")
@@ -150,7 +203,7 @@ def main():
         steps_cam = [k % len(cams) for k in range(args.steps)]
         p_mean = statistics.mean(P[c] for c in steps_cam)
         e_mean = statistics.mean(E[c] for c in steps_cam)
-        passes = (32 + int(np.ceil(np.log2(cams[0].tiles_x * cams[0].tiles_y))) + 7) // 8
+        passes = (int(np.ceil(np.log2(cams[0].tiles_x * cams[0].tiles_y))) + 7) // 8
         results[mode] = {
             "fps": round(1000.0 / ms, 2), "ms_per_frame": round(ms, 4),
             "stage_ms": {k: round(v, 4) for k, v in stages.items()},
@@ -158,7 +211,10 @@ def main():
             "blend_tflops": round(e_mean * OPS_PER_EVAL / (stages["blend"] * 1e-3) / 1e12, 3),
             "preprocess_gbs": round(args.n * PRE_BYTES_PER_G / (stages["preprocess"] * 1e-3) / 1e9,
                                     1),
-            "sort_gbs": round(p_mean * 32 * passes / (stages["sort"] * 1e-3) / 1e9, 1),
+            "depth_order_gbs": round(args.n * DEPTH_ORDER_BYTES_PER_G /
+                                     (stages["depth_order"] * 1e-3) / 1e9, 1),
+            "sort_gbs": round(p_mean * SORT_BYTES_PER_PAIR_PASS * passes /
+                              (stages["sort"] * 1e-3) / 1e9, 1),
         }
         log(f"{mode}: {ms:.3f} ms/frame ({1000 / ms:.1f} FPS) stages "
             + " ".join(f"{k}={v:.3f}" for k, v in stages.items()))
@@ -193,6 +249,10 @@ def main():
                              f"x {OPS_PER_EVAL} FP32 ops per launch",
                      "avg_launch_ms": round(blend_ms, 4)},
     }
+    if not args.no_serve:
+        line["serving"] = serving_bench(ss, dev, args.serve_scale)
+        line["serving_p50_ms"] = line["serving"]["poisson_0.8X"]["p50_ms"]
+        line["serving_p99_ms"] = line["serving"]["poisson_0.8X"]["p99_ms"]
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         line["cpu_baseline"] = cpu_baseline(scene, cams[0])

@@ -43,8 +43,12 @@
  * the record; every tile decision is then made in FP64 on the stored record, so
  * the tile counts of the preprocess stage equal the pairs the emit stage writes.
  *
- * Pair keys (Sec. 3.2.2): key = (uint64 tile_id << 32) | bits(depth as f32),
- * value = Gaussian index.  The sorted order is by key, ties by index.
+ * Pair order (Sec. 3.2.2).  The paper sorts (key, value) pairs with key =
+ * (uint64 tile_id << 32) | bits(depth as f32) and value = Gaussian index; the
+ * sorted order is by tile, then depth, then index.  This library reaches the
+ * same order in two stable sorts: ss_depth_order sorts the Gaussians by
+ * bits(depth) (ties by index), ss_emit writes the pairs in that order with
+ * key = tile id (uint32), and ss_sort sorts them stably on the tile id.
  */
 #ifndef SPEEDYSPLAT_H
 #define SPEEDYSPLAT_H
@@ -56,7 +60,7 @@
 extern "C" {
 #endif
 
-#define SS_ABI_VERSION 1
+#define SS_ABI_VERSION 2
 
 enum ss_status {
     SS_OK = 0,
@@ -107,7 +111,13 @@ typedef struct ss_frame {
     float *conic;           /* [n,4] */
     float *rgb;             /* [n,4] */
     uint32_t *counts;       /* [n]   tiles per Gaussian */
-    uint32_t *offsets;      /* [n]   inclusive prefix sum of counts */
+    uint32_t *depth_keys;   /* [2n]  depth-order sort keys: the preprocess stage writes
+                               [0, n) (bits(depth), or 0xffffffff for a Gaussian with no
+                               tiles); [n, 2n) is scratch of ss_depth_order */
+    uint32_t *order;        /* [2n]  after ss_depth_order, [0, n) holds the Gaussians
+                               sorted by (depth key, index); [n, 2n) is scratch */
+    uint32_t *order_tmp;    /* [order_tmp_words] scratch of ss_depth_order */
+    uint32_t *offsets;      /* [n]   inclusive prefix sum of counts in depth order */
     uint64_t *scan_tmp;     /* [scan_tmp_words]; word 0 receives the pair count P */
     uint32_t *ranges;       /* [n_tiles, 2] per-tile [start, end) into the sorted pairs */
     float *t_final;         /* [H, W] final transmittance per pixel */
@@ -117,18 +127,45 @@ typedef struct ss_frame {
                                tile's list the pixel evaluated before it stopped */
     uint32_t *emit_tmp;     /* [n + 1] scratch of the emit stage (queue of Gaussians
                                with many tiles); contents are not an output */
+    void *table;            /* [table_bytes] 16-byte aligned: the frame's item table
+                               (camera, scene pointers, offsets), written by
+                               ss_preprocess / ss_forward_begin / ss_batch_begin and
+                               read by the later stages of the same frame */
 } ss_frame;
 
 typedef struct ss_frame_info {
     int32_t tiles_x, tiles_y, n_tiles;
-    int32_t sort_bits;      /* significant key bits: 32 + ceil(log2(n_tiles)) */
+    int32_t sort_bits;      /* significant tile-key bits: ceil(log2(n_tiles)) */
     int64_t scan_tmp_words; /* uint64 words for ss_frame.scan_tmp */
+    int64_t order_tmp_words; /* uint32 words for ss_frame.order_tmp */
+    int64_t table_bytes;    /* bytes for ss_frame.table */
 } ss_frame_info;
+
+/* One render request of a batch: a camera, a resident scene, an output image. */
+typedef struct ss_batch_item {
+    ss_camera cam;
+    ss_gaussians g;         /* device pointers of a scene (shared between items freely) */
+    float *out_rgb;         /* [3, H, W] f32 device image this item's blend writes */
+} ss_batch_item;
+
+/* Buffer sizes of a batch (ss_batch_sizes).  The frame of a batch holds all
+ * items: per-Gaussian buffers have n_slots entries (each item's records start
+ * at a multiple of 256), per-pixel buffers n_pixels (items' pixels packed in
+ * order), ranges n_tiles rows (items' tiles packed in order). */
+typedef struct ss_batch_info {
+    int64_t n_slots;
+    int64_t n_pixels;
+    int32_t n_tiles;
+    int32_t sort_bits;      /* ceil(log2(n_tiles)) */
+    int64_t scan_tmp_words;
+    int64_t order_tmp_words;
+    int64_t table_bytes;
+} ss_batch_info;
 
 /* Pair workspace: two ping-pong key/value buffers plus sort scratch. */
 typedef struct ss_pairs {
     uint64_t capacity;      /* pairs each buffer holds */
-    uint64_t *keys[2];      /* [capacity] each */
+    uint32_t *keys[2];      /* [capacity] each: tile ids */
     uint32_t *values[2];    /* [capacity] each */
     uint32_t *sort_tmp;     /* [sort_tmp_words] */
 } ss_pairs;
@@ -148,11 +185,11 @@ typedef struct ss_grads {
 
 /* Optional stage timing for the composite calls: caller-created hipEvent_t
  * handles (NULL entries are skipped) recorded on the stream at
- *   [0] before preprocess  [1] after preprocess  [2] after the scan
- *   [3] before emit (after the pair count was read back)  [4] after emit
- *   [5] after the sort  [6] after the ranges  [7] after the blend. */
+ *   [0] before preprocess  [1] after preprocess  [2] after the depth order
+ *   [3] after the scan  [4] before emit (after the pair count was read back)
+ *   [5] after emit  [6] after the sort  [7] after the ranges  [8] after the blend. */
 typedef struct ss_stage_events {
-    void *ev[8];
+    void *ev[9];
 } ss_stage_events;
 
 /* Fills *out.  Returns SS_ERR_INVALID_ARG for a null pointer. */
@@ -174,31 +211,41 @@ int ss_sort_tmp_words(uint64_t capacity, int64_t *out_words);
  * Stage 1, preprocess (Sec. 3.2.1 and Sec. 4.1): for every Gaussian, the record
  * (projection, Sigma_3D = R S S^T R^T, EWA Sigma_2D + 0.3 I, conic, t, SH
  * colour) and its tile count under `mode`.  Writes frame->geom, conic, rgb,
- * counts.
+ * counts and depth_keys[0, n).
  */
 int ss_preprocess(const ss_camera *cam, const ss_gaussians *g, int32_t mode,
                   const ss_frame *frame, void *stream);
 
 /*
- * Stage 2, inclusive prefix sum of the tile counts (Sec. 3.2.2, "InclusiveSum"):
- * frame->offsets[i] = sum_{j <= i} counts[j]; the total P goes to
- * frame->scan_tmp[0] (uint64).
+ * Stage 2a, depth order (the depth half of the Sec. 3.2.2 sort key): stable LSD
+ * radix sort of the n Gaussians on frame->depth_keys; frame->order[0, n)
+ * receives the Gaussian indices by (bits(depth), index), Gaussians without
+ * tiles last.  Uses depth_keys[n, 2n), order[n, 2n) and order_tmp as scratch.
+ */
+int ss_depth_order(int64_t n, const ss_frame *frame, void *stream);
+
+/*
+ * Stage 2b, inclusive prefix sum of the tile counts in depth order (Sec. 3.2.2,
+ * "InclusiveSum"): frame->offsets[j] = sum_{k <= j} counts[order[k]]; the
+ * total P goes to frame->scan_tmp[0] (uint64).
  */
 int ss_scan(int64_t n, const ss_frame *frame, void *stream);
 
 /*
  * Stage 3, key emission (Sec. 3.2.2, "duplicateWithKeys"; Alg. 1 "Process"):
- * Gaussian i writes its tiles, in its tile-enumeration order, at
- * [offsets[i] - counts[i], offsets[i]) of pairs->keys[buf] / values[buf].
- * n_pairs must be the P the scan produced and <= pairs->capacity.
+ * for each depth-order entry j, Gaussian i = order[j] writes its tiles, in its
+ * tile-enumeration order, at [offsets[j] - counts[i], offsets[j]) of
+ * pairs->keys[buf] (tile id) / values[buf] (i).  n_pairs must be the P the
+ * scan produced and <= pairs->capacity.
  */
 int ss_emit(const ss_camera *cam, int64_t n, int32_t mode, const ss_frame *frame,
             const ss_pairs *pairs, int32_t buf, uint64_t n_pairs, void *stream);
 
 /*
  * Stage 4, LSD radix sort of the pairs in buffer `buf` on the low
- * ss_frame_info.sort_bits bits of the key (Sec. 3.2.2, "RadixSort"); stable, so
- * equal keys keep index order.  *out_buf receives the buffer holding the result.
+ * ss_frame_info.sort_bits bits of the tile key (Sec. 3.2.2, "RadixSort"); stable,
+ * so a tile's pairs keep their depth order.  *out_buf receives the buffer
+ * holding the result.
  */
 int ss_sort(const ss_camera *cam, const ss_pairs *pairs, int32_t buf, uint64_t n_pairs,
             int32_t *out_buf, void *stream);
@@ -223,7 +270,7 @@ int ss_blend(const ss_camera *cam, const ss_frame *frame, const ss_pairs *pairs,
              float *out_rgb, void *stream);
 
 /*
- * SYNC.  Stages 1-2, then reads P back to the host (*n_pairs_out).
+ * SYNC.  Stages 1, 2a and 2b, then reads P back to the host (*n_pairs_out).
  * Returns SS_ERR_OVERFLOW if P >= 2^32.  `events` may be NULL.
  */
 int ss_forward_begin(const ss_camera *cam, const ss_gaussians *g, int32_t mode,
@@ -248,6 +295,31 @@ int ss_forward_finish(const ss_camera *cam, int64_t n, int32_t mode, const ss_fr
 int ss_render(const ss_camera *cam, const ss_gaussians *g, int32_t mode, const ss_frame *frame,
               const ss_pairs *pairs, float *out_rgb, uint64_t *n_pairs_out, int32_t *out_buf,
               const ss_stage_events *events, void *stream);
+
+/* Sizes for a batch of n_items (1 .. 4096) items. */
+int ss_batch_sizes(const ss_batch_item *items, int32_t n_items, ss_batch_info *out);
+
+/*
+ * SYNC.  Batched stages 1-2b for n_items render requests (different scenes and
+ * resolutions) in one launch per stage: the item table is written to
+ * frame->table, records go to the items' slots, and the pair count P of the
+ * whole batch is read back.  Pair keys carry a batch-global tile id (the
+ * item's first tile + its tile), so one depth order and one tile sort order
+ * every item's tiles, and an item's pairs, sorted and blended, are those it
+ * would have alone.
+ */
+int ss_batch_begin(const ss_batch_item *items, int32_t n_items, int32_t mode,
+                   const ss_frame *frame, uint64_t *n_pairs_out,
+                   const ss_stage_events *events, void *stream);
+
+/*
+ * Batched stages 3-6 for the P returned by ss_batch_begin (same items, mode
+ * and frame); each item's image goes to its out_rgb.  Returns
+ * SS_ERR_WORKSPACE if pairs->capacity < n_pairs.
+ */
+int ss_batch_finish(const ss_batch_item *items, int32_t n_items, int32_t mode,
+                    const ss_frame *frame, const ss_pairs *pairs, uint64_t n_pairs,
+                    int32_t *out_buf, const ss_stage_events *events, void *stream);
 
 /*
  * Adjoint of the forward render (the gradient flow of Sec. 4.2: per-pixel

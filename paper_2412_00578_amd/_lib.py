@@ -43,15 +43,28 @@ class SSGaussians(ctypes.Structure):
 
 
 class SSFrame(ctypes.Structure):
-    _fields_ = [("geom", _vp), ("conic", _vp), ("rgb", _vp), ("counts", _vp), ("offsets", _vp),
+    _fields_ = [("geom", _vp), ("conic", _vp), ("rgb", _vp), ("counts", _vp),
+                ("depth_keys", _vp), ("order", _vp), ("order_tmp", _vp), ("offsets", _vp),
                 ("scan_tmp", _vp), ("ranges", _vp), ("t_final", _vp), ("n_last", _vp),
-                ("n_eval", _vp), ("emit_tmp", _vp)]
+                ("n_eval", _vp), ("emit_tmp", _vp), ("table", _vp)]
 
 
 class SSFrameInfo(ctypes.Structure):
     _fields_ = [("tiles_x", ctypes.c_int32), ("tiles_y", ctypes.c_int32),
                 ("n_tiles", ctypes.c_int32), ("sort_bits", ctypes.c_int32),
-                ("scan_tmp_words", ctypes.c_int64)]
+                ("scan_tmp_words", ctypes.c_int64), ("order_tmp_words", ctypes.c_int64),
+                ("table_bytes", ctypes.c_int64)]
+
+
+class SSBatchItem(ctypes.Structure):
+    _fields_ = [("cam", SSCamera), ("g", SSGaussians), ("out_rgb", _vp)]
+
+
+class SSBatchInfo(ctypes.Structure):
+    _fields_ = [("n_slots", ctypes.c_int64), ("n_pixels", ctypes.c_int64),
+                ("n_tiles", ctypes.c_int32), ("sort_bits", ctypes.c_int32),
+                ("scan_tmp_words", ctypes.c_int64), ("order_tmp_words", ctypes.c_int64),
+                ("table_bytes", ctypes.c_int64)]
 
 
 class SSPairs(ctypes.Structure):
@@ -65,7 +78,7 @@ class SSGrads(ctypes.Structure):
 
 
 class SSStageEvents(ctypes.Structure):
-    _fields_ = [("ev", _vp * 8)]
+    _fields_ = [("ev", _vp * 9)]
 
 
 # Exported symbols and their prototypes (restype c_int unless noted).
@@ -77,6 +90,7 @@ PROTOTYPES = {
     "ss_frame_sizes": [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _P(SSFrameInfo)],
     "ss_sort_tmp_words": [ctypes.c_uint64, _P(ctypes.c_int64)],
     "ss_preprocess": [_P(SSCamera), _P(SSGaussians), ctypes.c_int32, _P(SSFrame), _vp],
+    "ss_depth_order": [ctypes.c_int64, _P(SSFrame), _vp],
     "ss_scan": [ctypes.c_int64, _P(SSFrame), _vp],
     "ss_emit": [_P(SSCamera), ctypes.c_int64, ctypes.c_int32, _P(SSFrame), _P(SSPairs),
                 ctypes.c_int32, ctypes.c_uint64, _vp],
@@ -91,6 +105,11 @@ PROTOTYPES = {
                           _P(SSStageEvents), _vp],
     "ss_render": [_P(SSCamera), _P(SSGaussians), ctypes.c_int32, _P(SSFrame), _P(SSPairs), _vp,
                   _P(ctypes.c_uint64), _P(ctypes.c_int32), _P(SSStageEvents), _vp],
+    "ss_batch_sizes": [_P(SSBatchItem), ctypes.c_int32, _P(SSBatchInfo)],
+    "ss_batch_begin": [_P(SSBatchItem), ctypes.c_int32, ctypes.c_int32, _P(SSFrame),
+                       _P(ctypes.c_uint64), _P(SSStageEvents), _vp],
+    "ss_batch_finish": [_P(SSBatchItem), ctypes.c_int32, ctypes.c_int32, _P(SSFrame),
+                        _P(SSPairs), ctypes.c_uint64, _P(ctypes.c_int32), _P(SSStageEvents), _vp],
     "ss_render_backward": [_P(SSCamera), _P(SSGaussians), _P(SSFrame), _P(SSPairs),
                            ctypes.c_int32, _vp, _P(SSGrads), _vp],
 }

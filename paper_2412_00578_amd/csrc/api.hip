@@ -4,6 +4,8 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <vector>
+
 #include "ss_internal.h"
 
 namespace {
@@ -31,10 +33,12 @@ int tiles_of(const ss_camera* cam, int* tx, int* ty) {
     return *tx * *ty;
 }
 
+// Bits of the tile sort: ceil(log2(n_tiles)) (the depth half of the paper's
+// key is ordered by the depth-order stage).
 int sort_bits_for(int n_tiles) {
     int b = 0;
     while ((1ll << b) < (long long)n_tiles) ++b;
-    return 32 + b;
+    return b;
 }
 
 int check_camera(const ss_camera* cam) {
@@ -70,7 +74,8 @@ int check_mode(int32_t mode) {
 
 int check_frame_records(const ss_frame* f, int64_t n) {
     if (!f) return fail(SS_ERR_INVALID_ARG, "frame is NULL");
-    if (n > 0 && (!f->geom || !f->conic || !f->rgb || !f->counts || !f->offsets || !f->emit_tmp))
+    if (n > 0 && (!f->geom || !f->conic || !f->rgb || !f->counts || !f->offsets || !f->emit_tmp ||
+                  !f->depth_keys || !f->order || !f->order_tmp))
         return fail(SS_ERR_INVALID_ARG, "a per-Gaussian frame buffer is NULL");
     if (!aligned16(f->geom) || !aligned16(f->conic) || !aligned16(f->rgb))
         return fail(SS_ERR_INVALID_ARG, "frame records must be 16-byte aligned");
@@ -108,6 +113,140 @@ void record(const ss_stage_events* ev, int k, hipStream_t s) {
         int _st = (x);                 \
         if (_st != SS_OK) return _st;  \
     } while (0)
+
+constexpr int kMaxItems = 4096;
+
+int64_t pad_slots(int64_t n) { return (n + ss::kSlotAlign - 1) / ss::kSlotAlign * ss::kSlotAlign; }
+
+// Host copy of a batch's item table and its totals.
+struct Layout {
+    std::vector<ss::Item> items;
+    ss::BatchDims d{};
+};
+
+ss::Item make_item(const ss_camera& cam, const ss_gaussians& g, float* out) {
+    ss::Item it{};
+    it.cam = cam;
+    it.means = g.means; it.scales = g.scales; it.quats = g.quats;
+    it.opacity = g.opacity; it.sh = g.sh; it.out_rgb = out;
+    it.n = g.n;
+    it.sh_degree = g.sh_degree; it.sh_stride = g.sh_stride;
+    it.tx_n = (cam.width + ss::kTile - 1) / ss::kTile;
+    it.ty_n = (cam.height + ss::kTile - 1) / ss::kTile;
+    return it;
+}
+
+// Places the items one after another: record slots padded to 256, tiles and
+// pixels packed.
+int lay_out(const ss_batch_item* items, int n_items, Layout& L) {
+    if (!items || n_items < 1 || n_items > kMaxItems)
+        return fail(SS_ERR_INVALID_ARG, "a batch holds 1..%d items", kMaxItems);
+    L.items.resize((size_t)n_items);
+    int64_t slots = 0, pixels = 0, tiles = 0;
+    for (int k = 0; k < n_items; ++k) {
+        SS_TRY(check_camera(&items[k].cam));
+        SS_TRY(check_gaussians(&items[k].g));
+        ss::Item it = make_item(items[k].cam, items[k].g, items[k].out_rgb);
+        it.g_off = slots;
+        it.tile_off = (int32_t)tiles;
+        it.pix_off = pixels;
+        slots += pad_slots(it.n);
+        tiles += (int64_t)it.tx_n * it.ty_n;
+        pixels += (int64_t)it.cam.width * it.cam.height;
+        L.items[(size_t)k] = it;
+    }
+    if (tiles >= (1ll << 31) || slots >= (1ll << 32) - 1)
+        return fail(SS_ERR_OVERFLOW, "batch too large (%lld tiles, %lld slots)",
+                    (long long)tiles, (long long)slots);
+    L.d.n_items = n_items;
+    L.d.n_tiles = (int32_t)tiles;
+    L.d.n_slots = slots;
+    L.d.n_pixels = pixels;
+    return SS_OK;
+}
+
+Layout single_layout(const ss_camera& cam, const ss_gaussians& g) {
+    Layout L;
+    L.items.push_back(make_item(cam, g, nullptr));
+    L.d.n_items = 1;
+    L.d.n_tiles = L.items[0].tx_n * L.items[0].ty_n;
+    L.d.n_slots = g.n;
+    L.d.n_pixels = (int64_t)cam.width * cam.height;
+    return L;
+}
+
+// Dims of a single frame when only the camera and n are at hand.
+ss::BatchDims single_dims(const ss_camera& cam, int64_t n) {
+    ss::BatchDims d{};
+    int tx, ty;
+    d.n_items = 1;
+    d.n_tiles = tiles_of(&cam, &tx, &ty);
+    d.n_slots = n;
+    d.n_pixels = (int64_t)cam.width * cam.height;
+    return d;
+}
+
+int check_table(const ss_frame* f) {
+    if (!f || !f->table) return fail(SS_ERR_INVALID_ARG, "frame table is NULL");
+    if (((uintptr_t)f->table & 15u) != 0)
+        return fail(SS_ERR_INVALID_ARG, "frame table must be 16-byte aligned");
+    return SS_OK;
+}
+
+int begin_impl(const Layout& L, int32_t mode, const ss_frame* f, uint64_t* n_pairs_out,
+               const ss_stage_events* ev, hipStream_t s) {
+    SS_TRY(check_mode(mode));
+    SS_TRY(check_frame_records(f, L.d.n_slots));
+    SS_TRY(check_table(f));
+    if (!n_pairs_out) return fail(SS_ERR_INVALID_ARG, "n_pairs_out is NULL");
+    ss::Item* table = reinterpret_cast<ss::Item*>(f->table);
+    record(ev, 0, s);
+    SS_TRY(hip_status(ss::write_items(table, L.items.data(), L.d.n_items, s), "item table"));
+    SS_TRY(hip_status(ss::launch_preprocess(table, L.d, mode, *f, s), "preprocess"));
+    record(ev, 1, s);
+    SS_TRY(hip_status(ss::launch_depth_order(L.d.n_slots, *f, s), "depth order"));
+    record(ev, 2, s);
+    SS_TRY(hip_status(ss::launch_scan(L.d.n_slots, *f, s), "scan"));
+    record(ev, 3, s);
+    uint64_t p = 0;
+    SS_TRY(hip_status(hipMemcpyAsync(&p, f->scan_tmp, sizeof(p), hipMemcpyDeviceToHost, s),
+                      "read pair count"));
+    SS_TRY(hip_status(hipStreamSynchronize(s), "synchronise"));
+    *n_pairs_out = p;
+    if (p >= 0xffffffffull)
+        return fail(SS_ERR_OVERFLOW, "%llu pairs do not fit 32-bit offsets", (unsigned long long)p);
+    return SS_OK;
+}
+
+int finish_impl(const ss::BatchDims& d, int32_t mode, const ss_frame* f, const ss_pairs* p,
+                uint64_t n_pairs, float* out_single, int32_t* out_buf, const ss_stage_events* ev,
+                hipStream_t s) {
+    SS_TRY(check_mode(mode));
+    SS_TRY(check_frame_records(f, d.n_slots));
+    SS_TRY(check_frame_pixels(f));
+    SS_TRY(check_table(f));
+    SS_TRY(check_pairs(p, 0, n_pairs));
+    const ss::Item* table = reinterpret_cast<const ss::Item*>(f->table);
+    const int bits = sort_bits_for(d.n_tiles);
+    // Emit into the buffer that makes the sorted result land in buffer 0.
+    const int passes = n_pairs > 1 ? ss::sort_passes(bits) : 0;
+    const int first = passes & 1;
+    record(ev, 4, s);
+    SS_TRY(hip_status(ss::launch_emit(table, d, mode, *f, p->keys[first], p->values[first],
+                                      n_pairs, s),
+                      "emit"));
+    record(ev, 5, s);
+    int cur = first;
+    SS_TRY(hip_status(ss::launch_sort(*p, first, n_pairs, bits, &cur, s), "sort"));
+    record(ev, 6, s);
+    SS_TRY(hip_status(ss::launch_ranges(p->keys[cur], n_pairs, d.n_tiles, f->ranges, s),
+                      "ranges"));
+    record(ev, 7, s);
+    SS_TRY(hip_status(ss::launch_blend(table, d, *f, p->values[cur], out_single, s), "blend"));
+    record(ev, 8, s);
+    if (out_buf) *out_buf = cur;
+    return SS_OK;
+}
 
 }  // namespace
 
@@ -148,6 +287,8 @@ int ss_frame_sizes(int64_t n, int32_t width, int32_t height, ss_frame_info* out)
     out->n_tiles = out->tiles_x * out->tiles_y;
     out->sort_bits = sort_bits_for(out->n_tiles);
     out->scan_tmp_words = ss::scan_tmp_words(n);
+    out->order_tmp_words = ss::sort_tmp_words((uint64_t)n);
+    out->table_bytes = (int64_t)((sizeof(ss::Item) + 255) / 256 * 256);
     return SS_OK;
 }
 
@@ -163,8 +304,18 @@ int ss_preprocess(const ss_camera* cam, const ss_gaussians* g, int32_t mode, con
     SS_TRY(check_gaussians(g));
     SS_TRY(check_mode(mode));
     SS_TRY(check_frame_records(f, g->n));
-    return hip_status(ss::launch_preprocess(*cam, *g, mode, *f, (hipStream_t)stream),
-                      "preprocess");
+    SS_TRY(check_table(f));
+    const Layout L = single_layout(*cam, *g);
+    hipStream_t s = (hipStream_t)stream;
+    ss::Item* table = reinterpret_cast<ss::Item*>(f->table);
+    SS_TRY(hip_status(ss::write_items(table, L.items.data(), 1, s), "item table"));
+    return hip_status(ss::launch_preprocess(table, L.d, mode, *f, s), "preprocess");
+}
+
+int ss_depth_order(int64_t n, const ss_frame* f, void* stream) {
+    if (n < 0) return fail(SS_ERR_INVALID_ARG, "n < 0");
+    SS_TRY(check_frame_records(f, n));
+    return hip_status(ss::launch_depth_order(n, *f, (hipStream_t)stream), "depth order");
 }
 
 int ss_scan(int64_t n, const ss_frame* f, void* stream) {
@@ -179,11 +330,11 @@ int ss_emit(const ss_camera* cam, int64_t n, int32_t mode, const ss_frame* f, co
     SS_TRY(check_mode(mode));
     if (n < 0) return fail(SS_ERR_INVALID_ARG, "n < 0");
     SS_TRY(check_frame_records(f, n));
+    SS_TRY(check_table(f));
     SS_TRY(check_pairs(p, buf, n_pairs));
-    int tx, ty;
-    tiles_of(cam, &tx, &ty);
-    return hip_status(ss::launch_emit(tx, ty, n, mode, *f, p->keys[buf], p->values[buf], n_pairs,
-                                      (hipStream_t)stream),
+    return hip_status(ss::launch_emit(reinterpret_cast<const ss::Item*>(f->table),
+                                      single_dims(*cam, n), mode, *f, p->keys[buf],
+                                      p->values[buf], n_pairs, (hipStream_t)stream),
                       "emit");
 }
 
@@ -218,62 +369,32 @@ int ss_blend(const ss_camera* cam, const ss_frame* f, const ss_pairs* p, int32_t
     SS_TRY(check_camera(cam));
     if (!f) return fail(SS_ERR_INVALID_ARG, "frame is NULL");
     SS_TRY(check_frame_pixels(f));
+    SS_TRY(check_table(f));
     if (!p || (buf != 0 && buf != 1)) return fail(SS_ERR_INVALID_ARG, "bad pair workspace");
     if (!out_rgb) return fail(SS_ERR_INVALID_ARG, "out_rgb is NULL");
     if (!aligned16(f->geom) || !aligned16(f->conic) || !aligned16(f->rgb))
         return fail(SS_ERR_INVALID_ARG, "frame records must be 16-byte aligned");
-    return hip_status(ss::launch_blend(*cam, *f, p->values[buf], out_rgb, (hipStream_t)stream),
+    return hip_status(ss::launch_blend(reinterpret_cast<const ss::Item*>(f->table),
+                                       single_dims(*cam, 0), *f, p->values[buf], out_rgb,
+                                       (hipStream_t)stream),
                       "blend");
 }
 
 int ss_forward_begin(const ss_camera* cam, const ss_gaussians* g, int32_t mode, const ss_frame* f,
                      uint64_t* n_pairs_out, const ss_stage_events* ev, void* stream) {
-    if (!n_pairs_out) return fail(SS_ERR_INVALID_ARG, "n_pairs_out is NULL");
-    hipStream_t s = (hipStream_t)stream;
-    record(ev, 0, s);
-    SS_TRY(ss_preprocess(cam, g, mode, f, stream));
-    record(ev, 1, s);
-    SS_TRY(ss_scan(g->n, f, stream));
-    record(ev, 2, s);
-    uint64_t p = 0;
-    SS_TRY(hip_status(hipMemcpyAsync(&p, f->scan_tmp, sizeof(p), hipMemcpyDeviceToHost, s),
-                      "read pair count"));
-    SS_TRY(hip_status(hipStreamSynchronize(s), "synchronise"));
-    *n_pairs_out = p;
-    if (p >= 0xffffffffull)
-        return fail(SS_ERR_OVERFLOW, "%llu pairs do not fit 32-bit offsets", (unsigned long long)p);
-    return SS_OK;
+    SS_TRY(check_camera(cam));
+    SS_TRY(check_gaussians(g));
+    return begin_impl(single_layout(*cam, *g), mode, f, n_pairs_out, ev, (hipStream_t)stream);
 }
 
 int ss_forward_finish(const ss_camera* cam, int64_t n, int32_t mode, const ss_frame* f,
                       const ss_pairs* p, uint64_t n_pairs, float* out_rgb, int32_t* out_buf,
                       const ss_stage_events* ev, void* stream) {
     SS_TRY(check_camera(cam));
-    SS_TRY(check_mode(mode));
-    SS_TRY(check_frame_records(f, n));
-    SS_TRY(check_frame_pixels(f));
-    SS_TRY(check_pairs(p, 0, n_pairs));
+    if (n < 0) return fail(SS_ERR_INVALID_ARG, "n < 0");
     if (!out_rgb) return fail(SS_ERR_INVALID_ARG, "out_rgb is NULL");
-    int tx, ty;
-    const int n_tiles = tiles_of(cam, &tx, &ty);
-    const int bits = sort_bits_for(n_tiles);
-    hipStream_t s = (hipStream_t)stream;
-    // Emit into the buffer that makes the sorted result land in buffer 0.
-    const int passes = n_pairs > 1 ? ss::sort_passes(bits) : 0;
-    const int first = passes & 1;
-    record(ev, 3, s);
-    SS_TRY(hip_status(
-        ss::launch_emit(tx, ty, n, mode, *f, p->keys[first], p->values[first], n_pairs, s), "emit"));
-    record(ev, 4, s);
-    int cur = first;
-    SS_TRY(hip_status(ss::launch_sort(*p, first, n_pairs, bits, &cur, s), "sort"));
-    record(ev, 5, s);
-    SS_TRY(hip_status(ss::launch_ranges(p->keys[cur], n_pairs, n_tiles, f->ranges, s), "ranges"));
-    record(ev, 6, s);
-    SS_TRY(hip_status(ss::launch_blend(*cam, *f, p->values[cur], out_rgb, s), "blend"));
-    record(ev, 7, s);
-    if (out_buf) *out_buf = cur;
-    return SS_OK;
+    return finish_impl(single_dims(*cam, n), mode, f, p, n_pairs, out_rgb, out_buf, ev,
+                       (hipStream_t)stream);
 }
 
 int ss_render(const ss_camera* cam, const ss_gaussians* g, int32_t mode, const ss_frame* f,
@@ -287,6 +408,37 @@ int ss_render(const ss_camera* cam, const ss_gaussians* g, int32_t mode, const s
         return fail(SS_ERR_WORKSPACE, "%llu pairs exceed the workspace capacity %llu",
                     (unsigned long long)n_pairs, (unsigned long long)p->capacity);
     return ss_forward_finish(cam, g->n, mode, f, p, n_pairs, out_rgb, out_buf, ev, stream);
+}
+
+int ss_batch_sizes(const ss_batch_item* items, int32_t n_items, ss_batch_info* out) {
+    if (!out) return fail(SS_ERR_INVALID_ARG, "out is NULL");
+    Layout L;
+    SS_TRY(lay_out(items, n_items, L));
+    out->n_slots = L.d.n_slots;
+    out->n_pixels = L.d.n_pixels;
+    out->n_tiles = L.d.n_tiles;
+    out->sort_bits = sort_bits_for(L.d.n_tiles);
+    out->scan_tmp_words = ss::scan_tmp_words(L.d.n_slots);
+    out->order_tmp_words = ss::sort_tmp_words((uint64_t)L.d.n_slots);
+    out->table_bytes = (int64_t)((sizeof(ss::Item) * (size_t)n_items + 255) / 256 * 256);
+    return SS_OK;
+}
+
+int ss_batch_begin(const ss_batch_item* items, int32_t n_items, int32_t mode, const ss_frame* f,
+                   uint64_t* n_pairs_out, const ss_stage_events* ev, void* stream) {
+    Layout L;
+    SS_TRY(lay_out(items, n_items, L));
+    for (int k = 0; k < n_items; ++k)
+        if (!items[k].out_rgb) return fail(SS_ERR_INVALID_ARG, "item %d has no out_rgb", k);
+    return begin_impl(L, mode, f, n_pairs_out, ev, (hipStream_t)stream);
+}
+
+int ss_batch_finish(const ss_batch_item* items, int32_t n_items, int32_t mode, const ss_frame* f,
+                    const ss_pairs* p, uint64_t n_pairs, int32_t* out_buf,
+                    const ss_stage_events* ev, void* stream) {
+    Layout L;
+    SS_TRY(lay_out(items, n_items, L));
+    return finish_impl(L.d, mode, f, p, n_pairs, nullptr, out_buf, ev, (hipStream_t)stream);
 }
 
 int ss_render_backward(const ss_camera* cam, const ss_gaussians* g, const ss_frame* f,

@@ -49,24 +49,31 @@ __device__ __forceinline__ Rec load_rec(const uint32_t* __restrict__ values,
 }
 
 template <bool STATS>
-__global__ __launch_bounds__(64) void k_blend(int tx_n, int n_tiles, int W, int H, float bg0,
-                                              float bg1, float bg2,
+__global__ __launch_bounds__(64) void k_blend(const Item* __restrict__ items, BatchDims dims,
                                               const uint32_t* __restrict__ ranges,
                                               const uint32_t* __restrict__ values,
                                               const float4* __restrict__ geom,
                                               const float4* __restrict__ conic,
                                               const float4* __restrict__ rgb,
-                                              float* __restrict__ out,
-                                              float* __restrict__ t_final,
-                                              uint32_t* __restrict__ n_last,
-                                              uint32_t* __restrict__ n_eval) {
+                                              float* __restrict__ out_single,
+                                              float* __restrict__ t_final_all,
+                                              uint32_t* __restrict__ n_last_all,
+                                              uint32_t* __restrict__ n_eval_all) {
     __shared__ float4 s_geo[kBatch];
     __shared__ float4 s_con[kBatch];
     __shared__ float4 s_col[kBatch];
-    const int tile = xcd_contiguous((int)blockIdx.x, n_tiles);
+    const int tile = xcd_contiguous((int)blockIdx.x, dims.n_tiles);
     if (tile < 0) return;
+    const Item& it = items[dims.n_items == 1 ? 0 : item_of_tile(items, dims.n_items, tile)];
+    const int W = it.cam.width, H = it.cam.height, tx_n = it.tx_n;
+    const float bg0 = it.cam.bg[0], bg1 = it.cam.bg[1], bg2 = it.cam.bg[2];
+    float* __restrict__ out = out_single ? out_single : it.out_rgb;
+    float* __restrict__ t_final = t_final_all + it.pix_off;
+    uint32_t* __restrict__ n_last = n_last_all + it.pix_off;
+    uint32_t* __restrict__ n_eval = STATS ? n_eval_all + it.pix_off : nullptr;
+    const int lt = tile - it.tile_off;      // tile within the item's image
     const int lane = (int)threadIdx.x;
-    const int tx = tile % tx_n, ty = tile / tx_n;
+    const int tx = lt % tx_n, ty = lt / tx_n;
     const int px = tx * kTile + (lane & 15);
     const int py0 = ty * kTile + (lane >> 4);
     const float fx = (float)px + 0.5f;
@@ -143,18 +150,16 @@ __global__ __launch_bounds__(64) void k_blend(int tx_n, int n_tiles, int W, int 
 
 }  // namespace
 
-hipError_t launch_blend(const ss_camera& cam, const ss_frame& f, const uint32_t* values,
-                        float* out_rgb, hipStream_t s) {
-    const int tx_n = (cam.width + kTile - 1) / kTile, ty_n = (cam.height + kTile - 1) / kTile;
-    const int n_tiles = tx_n * ty_n;
-    const int grid = 8 * ((n_tiles + 7) / 8);
+hipError_t launch_blend(const Item* items, const BatchDims& d, const ss_frame& f,
+                        const uint32_t* values, float* out_rgb_single, hipStream_t s) {
+    const int grid = 8 * ((d.n_tiles + 7) / 8);
+    if (grid == 0) return hipSuccess;
     auto go = [&](auto kernel) {
-        hipLaunchKernelGGL(kernel, dim3(grid), dim3(64), 0, s, tx_n, n_tiles, cam.width,
-                           cam.height, cam.bg[0], cam.bg[1], cam.bg[2], f.ranges, values,
+        hipLaunchKernelGGL(kernel, dim3(grid), dim3(64), 0, s, items, d, f.ranges, values,
                            reinterpret_cast<const float4*>(f.geom),
                            reinterpret_cast<const float4*>(f.conic),
-                           reinterpret_cast<const float4*>(f.rgb), out_rgb, f.t_final, f.n_last,
-                           f.n_eval);
+                           reinterpret_cast<const float4*>(f.rgb), out_rgb_single, f.t_final,
+                           f.n_last, f.n_eval);
     };
     if (f.n_eval) go(k_blend<true>);
     else go(k_blend<false>);

@@ -1,15 +1,20 @@
 // Stage 3: key emission (Speedy-Splat Sec. 3.2.2, "duplicateWithKeys"; the
 // "Process" step of Alg. 1).
 //
-// Gaussian i re-walks its tile spans with the same FP64 function the
-// preprocess stage counted with and writes key = tile_id << 32 | bits(depth),
-// value = i, at [offsets[i] - counts[i], offsets[i]).
+// Entries are taken in depth order: entry j is Gaussian i = order[j], whose
+// tiles, re-walked with the same FP64 function the preprocess stage counted
+// with, go to [offsets[j] - counts[i], offsets[j]) as key = tile id, value = i.
+// The emitted pairs are therefore sorted by (depth, index), and a stable sort
+// on the tile id alone yields the paper's (tile | depth) order.
 //
 // Tile counts are heavy-tailed (most Gaussians touch a few tiles, a Gaussian
 // near the camera thousands), so the work is split in two launches:
-//   k_emit      one lane per Gaussian writes Gaussians with <= 32 tiles and
-//               queues the others (one atomic per wave);
-//   k_emit_big  one wave per queued Gaussian: lanes compute up to 64 spans
+//   k_emit      one lane per entry with <= 32 tiles: each lane writes its tile
+//               ids to the wave's LDS stage, then the wave copies the stage to
+//               the pair buffers with consecutive lanes on consecutive
+//               addresses; entries with more tiles are queued (one atomic per
+//               wave);
+//   k_emit_big  one wave per queued entry: lanes compute up to 64 spans
 //               (rows, or columns for AccuTile on tall extents) at once, a wave
 //               prefix sum places them, and the wave writes the keys with
 //               consecutive lanes on consecutive addresses.
@@ -29,48 +34,102 @@ __device__ __forceinline__ bool span_columns(const Ellipse& e, int mode) {
 
 __global__ void k_zero(uint32_t* p) { *p = 0u; }
 
-__global__ __launch_bounds__(256) void k_emit(int tx_n, int ty_n, int64_t n, int mode,
-                                              uint32_t limit,
-                                              const float4* __restrict__ geom,
-                                              const float4* __restrict__ conic,
-                                              const uint32_t* __restrict__ counts,
-                                              const uint32_t* __restrict__ offsets,
-                                              uint64_t* __restrict__ keys,
-                                              uint32_t* __restrict__ values,
-                                              uint32_t* __restrict__ queue) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const uint32_t cnt = i < n ? counts[i] : 0u;
+__device__ __forceinline__ uint32_t wave_incl_scan_u32(uint32_t x) {
+    const int lane = (int)__lane_id();
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t y = __shfl_up(x, d, 64);
+        if (lane >= d) x += y;
+    }
+    return x;
+}
+
+// Orders the wave's LDS writes before its LDS reads by other lanes.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+constexpr int kEmitBlock = 256;
+constexpr int kEmitWaves = kEmitBlock / 64;
+constexpr int kStage = 64 * (int)kSmall;     // tile ids one wave can stage
+
+__global__ __launch_bounds__(kEmitBlock) void k_emit(const Item* __restrict__ items,
+                                                     BatchDims dims, int mode, uint32_t limit,
+                                                     const float4* __restrict__ geom,
+                                                     const float4* __restrict__ conic,
+                                                     const uint32_t* __restrict__ order,
+                                                     const uint32_t* __restrict__ offsets,
+                                                     uint32_t* __restrict__ keys,
+                                                     uint32_t* __restrict__ values,
+                                                     uint32_t* __restrict__ queue) {
+    __shared__ uint32_t s_tile[kEmitWaves][kStage];
+    __shared__ uint32_t s_pre[kEmitWaves][64];    // exclusive prefix of the staged counts
+    __shared__ uint32_t s_pos[kEmitWaves][64];    // first pair position of each lane's entry
+    __shared__ uint32_t s_gid[kEmitWaves][64];
+    const int w = threadIdx.x >> 6;
+    const int lane = (int)__lane_id();
+    const int64_t j = (int64_t)blockIdx.x * kEmitBlock + threadIdx.x;   // depth-order entry
+    const bool valid = j < dims.n_slots;
+    const uint32_t end = valid ? offsets[j] : 0u;
+    uint32_t prev = __shfl_up(end, 1, 64);
+    if (lane == 0) prev = (valid && j > 0) ? offsets[j - 1] : 0u;
+    const uint32_t cnt = valid ? end - prev : 0u;
     const bool big = cnt > kSmall;
     const uint64_t mask = __ballot(big);
     if (mask) {
         const int leader = __builtin_ctzll(mask);
         uint32_t base = 0;
-        if ((int)__lane_id() == leader) base = atomicAdd(queue, (uint32_t)__popcll(mask));
+        if (lane == leader) base = atomicAdd(queue, (uint32_t)__popcll(mask));
         base = __shfl(base, leader, 64);
         const uint32_t slot = base + __builtin_amdgcn_mbcnt_hi(
                                          (uint32_t)(mask >> 32),
                                          __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
-        if (big && slot < (uint32_t)n) queue[1 + slot] = (uint32_t)i;
+        if (big && slot < (uint32_t)dims.n_slots) queue[1 + slot] = (uint32_t)j;
     }
-    if (cnt == 0u || big) return;
-    const uint32_t end = offsets[i] < limit ? offsets[i] : limit;
-    uint32_t pos = end - cnt;
-    const float4 g = geom[i], q = conic[i];
-    Ellipse e;
-    if (!ellipse_setup(g, q, mode, tx_n, ty_n, e)) return;
-    const uint64_t dbits = (uint64_t)__float_as_uint(g.z);
-    const bool cols = span_columns(e, mode);
-    const uint32_t vi = (uint32_t)i;
-    for_each_span(e, mode, tx_n, ty_n, [&](int major, int lo, int hi) {
-        for (int k = lo; k <= hi; ++k) {
-            const uint32_t tile = cols ? (uint32_t)(k * tx_n + major) : (uint32_t)(major * tx_n + k);
-            if (pos < end) {
-                keys[pos] = ((uint64_t)tile << 32) | dbits;
-                values[pos] = vi;
-            }
-            ++pos;
+    const uint32_t small = big ? 0u : cnt;
+    const uint32_t incl = wave_incl_scan_u32(small);
+    const uint32_t total = __shfl(incl, 63, 64);
+    if (total == 0u) return;                      // wave-uniform; no workgroup barrier follows
+    const uint32_t pre = incl - small;
+    const uint32_t gid = small ? order[j] : 0u;
+    s_pre[w][lane] = pre;
+    s_pos[w][lane] = prev;
+    s_gid[w][lane] = gid;
+    if (small) {
+        const Item& it = items[dims.n_items == 1 ? 0 : item_of_slot(items, dims.n_items, gid)];
+        const int tx_n = it.tx_n, ty_n = it.ty_n;
+        const uint32_t tile_off = (uint32_t)it.tile_off;
+        Ellipse e;
+        if (ellipse_setup(geom[gid], conic[gid], mode, tx_n, ty_n, e)) {
+            const bool cols = span_columns(e, mode);
+            uint32_t p = pre;
+            const uint32_t stop = pre + small;    // never past the lane's own share
+            for_each_span(e, mode, tx_n, ty_n, [&](int major, int lo, int hi) {
+                for (int k = lo; k <= hi; ++k) {
+                    if (p < stop)
+                        s_tile[w][p] = tile_off + (cols ? (uint32_t)(k * tx_n + major)
+                                                        : (uint32_t)(major * tx_n + k));
+                    ++p;
+                }
+            });
         }
-    });
+    }
+    wave_lds_sync();
+    for (uint32_t idx = (uint32_t)lane; idx < total; idx += 64) {
+        // the last lane whose staged run starts at or before idx
+        int a = 0, z = 63;
+        while (a < z) {
+            const int mid = (a + z + 1) >> 1;
+            if (s_pre[w][mid] <= idx) a = mid; else z = mid - 1;
+        }
+        const uint32_t pos = s_pos[w][a] + (idx - s_pre[w][a]);
+        if (pos < limit) {
+            keys[pos] = s_tile[w][idx];
+            values[pos] = s_gid[w][a];
+        }
+    }
 }
 
 // Span of one row (or column) of the record's tile rectangle; the same
@@ -118,23 +177,14 @@ __device__ __forceinline__ void one_span(const Ellipse& e, int mode, int tx_n, i
     }
 }
 
-__device__ __forceinline__ uint32_t wave_incl_scan_u32(uint32_t x) {
-    const int lane = (int)__lane_id();
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const uint32_t y = __shfl_up(x, d, 64);
-        if (lane >= d) x += y;
-    }
-    return x;
-}
-
-__global__ __launch_bounds__(kBigBlock) void k_emit_big(int tx_n, int ty_n, int mode,
-                                                        uint32_t limit, uint32_t qcap,
+__global__ __launch_bounds__(kBigBlock) void k_emit_big(const Item* __restrict__ items,
+                                                        BatchDims dims, int mode, uint32_t limit,
+                                                        uint32_t qcap,
                                                         const float4* __restrict__ geom,
                                                         const float4* __restrict__ conic,
-                                                        const uint32_t* __restrict__ counts,
+                                                        const uint32_t* __restrict__ order,
                                                         const uint32_t* __restrict__ offsets,
-                                                        uint64_t* __restrict__ keys,
+                                                        uint32_t* __restrict__ keys,
                                                         uint32_t* __restrict__ values,
                                                         const uint32_t* __restrict__ queue) {
     __shared__ uint32_t s_excl[kBigBlock / 64][64];
@@ -145,14 +195,15 @@ __global__ __launch_bounds__(kBigBlock) void k_emit_big(int tx_n, int ty_n, int 
     const uint32_t wave0 = blockIdx.x * (kBigBlock / 64) + w;
     const uint32_t waves = gridDim.x * (kBigBlock / 64);
     for (uint32_t b = wave0; b < nq; b += waves) {
-        const uint32_t i = queue[1 + b];
-        const uint32_t cnt = counts[i];
-        const uint32_t end = offsets[i] < limit ? offsets[i] : limit;
-        const uint32_t pos0 = end - cnt;
-        const float4 g = geom[i], q = conic[i];
+        const uint32_t j = queue[1 + b];          // depth-order entry
+        const uint32_t i = order[j];
+        const Item& it = items[dims.n_items == 1 ? 0 : item_of_slot(items, dims.n_items, i)];
+        const int tx_n = it.tx_n, ty_n = it.ty_n;
+        const uint32_t tile_off = (uint32_t)it.tile_off;
+        const uint32_t pos0 = j > 0 ? offsets[j - 1] : 0u;
+        const uint32_t end = offsets[j];
         Ellipse e;
-        if (!ellipse_setup(g, q, mode, tx_n, ty_n, e)) continue;
-        const uint64_t dbits = (uint64_t)__float_as_uint(g.z);
+        if (!ellipse_setup(geom[i], conic[i], mode, tx_n, ty_n, e)) continue;
         const bool cols = span_columns(e, mode);
         const int maj0 = cols ? e.x0 : e.y0;
         const int nmaj = cols ? e.x1 - e.x0 + 1 : e.y1 - e.y0 + 1;
@@ -165,8 +216,7 @@ __global__ __launch_bounds__(kBigBlock) void k_emit_big(int tx_n, int ty_n, int 
             const uint32_t total = __shfl(incl, 63, 64);
             s_excl[w][lane] = incl - len;
             s_lo[w][lane] = lo;
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            wave_lds_sync();
             for (uint32_t idx = lane; idx < total; idx += 64) {
                 // the last span whose exclusive start is <= idx
                 int a = 0, z = 63;
@@ -176,35 +226,35 @@ __global__ __launch_bounds__(kBigBlock) void k_emit_big(int tx_n, int ty_n, int 
                 }
                 const int major = maj0 + c0 + a;
                 const int minor = s_lo[w][a] + (int)(idx - s_excl[w][a]);
-                const uint32_t tile = cols ? (uint32_t)(minor * tx_n + major)
-                                           : (uint32_t)(major * tx_n + minor);
+                const uint32_t tile = tile_off + (cols ? (uint32_t)(minor * tx_n + major)
+                                                       : (uint32_t)(major * tx_n + minor));
                 const uint32_t pos = pos0 + done + idx;
-                if (pos < end) {
-                    keys[pos] = ((uint64_t)tile << 32) | dbits;
+                if (pos < end && pos < limit) {
+                    keys[pos] = tile;
                     values[pos] = i;
                 }
             }
             done += total;
-            __builtin_amdgcn_wave_barrier();
+            wave_lds_sync();
         }
     }
 }
 
 }  // namespace
 
-hipError_t launch_emit(int tx_n, int ty_n, int64_t n, int mode, const ss_frame& f, uint64_t* keys,
-                       uint32_t* values, uint64_t n_pairs, hipStream_t s) {
-    if (n == 0) return hipSuccess;
+hipError_t launch_emit(const Item* items, const BatchDims& d, int mode, const ss_frame& f,
+                       uint32_t* keys, uint32_t* values, uint64_t n_pairs, hipStream_t s) {
+    if (d.n_slots == 0) return hipSuccess;
     hipLaunchKernelGGL(k_zero, dim3(1), dim3(1), 0, s, f.emit_tmp);
-    const int block = 256;
-    const int64_t grid = (n + block - 1) / block;
-    hipLaunchKernelGGL(k_emit, dim3((unsigned)grid), dim3(block), 0, s, tx_n, ty_n, n, mode,
+    const int64_t grid = (d.n_slots + kEmitBlock - 1) / kEmitBlock;
+    hipLaunchKernelGGL(k_emit, dim3((unsigned)grid), dim3(kEmitBlock), 0, s, items, d, mode,
                        (uint32_t)n_pairs, reinterpret_cast<const float4*>(f.geom),
-                       reinterpret_cast<const float4*>(f.conic), f.counts, f.offsets, keys,
+                       reinterpret_cast<const float4*>(f.conic), f.order, f.offsets, keys,
                        values, f.emit_tmp);
-    hipLaunchKernelGGL(k_emit_big, dim3(kBigGrid), dim3(kBigBlock), 0, s, tx_n, ty_n, mode,
-                       (uint32_t)n_pairs, (uint32_t)n, reinterpret_cast<const float4*>(f.geom),
-                       reinterpret_cast<const float4*>(f.conic), f.counts, f.offsets, keys,
+    hipLaunchKernelGGL(k_emit_big, dim3(kBigGrid), dim3(kBigBlock), 0, s, items, d, mode,
+                       (uint32_t)n_pairs, (uint32_t)d.n_slots,
+                       reinterpret_cast<const float4*>(f.geom),
+                       reinterpret_cast<const float4*>(f.conic), f.order, f.offsets, keys,
                        values, f.emit_tmp);
     return hipGetLastError();
 }

@@ -32,6 +32,11 @@ struct Inputs {
 };
 
 constexpr int kBlock = 256;
+static_assert(kBlock == kSlotAlign, "a preprocess workgroup must not span two items");
+constexpr int kPack = 16;                  // items per table-writing launch (kernel-argument bytes)
+struct ItemPack {
+    Item it[kPack];
+};
 constexpr int kShMax = 48;                 // SH floats per Gaussian staged (degree 3)
 constexpr int kShPitch = kShMax + 1;       // odd LDS pitch: lanes hit distinct banks
 
@@ -67,20 +72,33 @@ __device__ __forceinline__ void stage_sh(const float* __restrict__ sh, int64_t f
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_preprocess(ss_camera cam, Inputs in, int64_t n,
-                                                       int mode, int tx_n, int ty_n,
+__global__ __launch_bounds__(kBlock) void k_preprocess(const Item* __restrict__ items,
+                                                       BatchDims dims, int mode,
                                                        float4* __restrict__ geom,
                                                        float4* __restrict__ conic,
                                                        float4* __restrict__ rgb_out,
-                                                       uint32_t* __restrict__ counts) {
+                                                       uint32_t* __restrict__ counts,
+                                                       uint32_t* __restrict__ dkeys) {
     __shared__ float s_sh[kBlock * kShPitch];
-    const int64_t first = (int64_t)blockIdx.x * kBlock;
+    const int64_t slot0 = (int64_t)blockIdx.x * kBlock;
+    const Item& it = items[dims.n_items == 1 ? 0 : item_of_slot(items, dims.n_items, slot0)];
+    const ss_camera cam = it.cam;
+    const Inputs in{it.means, it.scales, it.quats, it.opacity, it.sh, it.sh_degree, it.sh_stride};
+    const int64_t n = it.n;
+    const int tx_n = it.tx_n, ty_n = it.ty_n;
+    const int64_t first = slot0 - it.g_off;       // local index of this block's first lane
     const int nb_coef = (in.sh_degree + 1) * (in.sh_degree + 1);
-    stage_sh(in.sh, first, n, 3 * in.sh_stride, 3 * nb_coef, s_sh);
+    if (first < n) stage_sh(in.sh, first, n, 3 * in.sh_stride, 3 * nb_coef, s_sh);
     __syncthreads();
-    const int64_t i = first + threadIdx.x;
-    if (i >= n) return;
+    const int64_t i = first + threadIdx.x;        // Gaussian of the item
+    const int64_t o = slot0 + threadIdx.x;        // its record slot
+    if (o >= dims.n_slots) return;
     const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (i >= n) {  // padding slot between items
+        geom[o] = zero; conic[o] = zero; rgb_out[o] = zero; counts[o] = 0u;
+        dkeys[o] = kCulledKey;
+        return;
+    }
 
     const float m0 = in.means[3 * i], m1 = in.means[3 * i + 1], m2 = in.means[3 * i + 2];
     const float s0 = in.scales[3 * i], s1 = in.scales[3 * i + 1], s2 = in.scales[3 * i + 2];
@@ -105,7 +123,8 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(ss_camera cam, Inputs in,
     const double nn = ((qw * qw + qx * qx) + qy * qy) + qz * qz;
     ok = ok && (nn > 0.0);
     if (!ok) {
-        geom[i] = zero; conic[i] = zero; rgb_out[i] = zero; counts[i] = 0u;
+        geom[o] = zero; conic[o] = zero; rgb_out[o] = zero; counts[o] = 0u;
+        dkeys[o] = kCulledKey;
         return;
     }
     const double fx = cam.fx, fy = cam.fy;
@@ -171,7 +190,8 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(ss_camera cam, Inputs in,
     const float ca = (float)(C / D), cb = (float)(-B / D), cc = (float)(A / D);
     const float tt = (float)(2.0 * log(255.0 * (double)op));
     if (!(D > 0.0) || (mode != SS_TILE_3SIGMA && !(tt > 0.0f))) {
-        geom[i] = zero; conic[i] = zero; rgb_out[i] = zero; counts[i] = 0u;
+        geom[o] = zero; conic[o] = zero; rgb_out[o] = zero; counts[o] = 0u;
+        dkeys[o] = kCulledKey;
         return;
     }
 
@@ -221,24 +241,38 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(ss_camera cam, Inputs in,
 
     const float4 g4 = make_float4((float)u, (float)v, (float)z, tt);
     const float4 q4 = make_float4(ca, cb, cc, op);
-    geom[i] = g4;
-    conic[i] = q4;
-    rgb_out[i] = make_float4(cr, cg, cbl, 0.0f);
-    counts[i] = count_tiles(g4, q4, mode, tx_n, ty_n);
+    geom[o] = g4;
+    conic[o] = q4;
+    rgb_out[o] = make_float4(cr, cg, cbl, 0.0f);
+    const uint32_t cnt = count_tiles(g4, q4, mode, tx_n, ty_n);
+    counts[o] = cnt;
+    dkeys[o] = cnt ? __float_as_uint(g4.z) : kCulledKey;
 }
 
 }  // namespace
 
-hipError_t launch_preprocess(const ss_camera& cam, const ss_gaussians& g, int mode,
-                             const ss_frame& f, hipStream_t s) {
-    if (g.n == 0) return hipSuccess;
-    const int tx_n = (cam.width + kTile - 1) / kTile, ty_n = (cam.height + kTile - 1) / kTile;
-    Inputs in{g.means, g.scales, g.quats, g.opacity, g.sh, g.sh_degree, g.sh_stride};
-    const int64_t grid = (g.n + kBlock - 1) / kBlock;
-    hipLaunchKernelGGL(k_preprocess, dim3((unsigned)grid), dim3(kBlock), 0, s, cam, in, g.n, mode,
-                       tx_n, ty_n, reinterpret_cast<float4*>(f.geom),
-                       reinterpret_cast<float4*>(f.conic), reinterpret_cast<float4*>(f.rgb),
-                       f.counts);
+hipError_t launch_preprocess(const Item* items, const BatchDims& d, int mode, const ss_frame& f,
+                             hipStream_t s) {
+    if (d.n_slots == 0) return hipSuccess;
+    const int64_t grid = (d.n_slots + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(k_preprocess, dim3((unsigned)grid), dim3(kBlock), 0, s, items, d, mode,
+                       reinterpret_cast<float4*>(f.geom), reinterpret_cast<float4*>(f.conic),
+                       reinterpret_cast<float4*>(f.rgb), f.counts, f.depth_keys);
+    return hipGetLastError();
+}
+
+__global__ void k_write_items(Item* __restrict__ table, ItemPack pack, int first, int count) {
+    const int k = threadIdx.x;
+    if (k < count) table[first + k] = pack.it[k];
+}
+
+hipError_t write_items(Item* table, const Item* host_items, int n_items, hipStream_t s) {
+    for (int first = 0; first < n_items; first += kPack) {
+        ItemPack pack;
+        const int count = n_items - first < kPack ? n_items - first : kPack;
+        for (int k = 0; k < count; ++k) pack.it[k] = host_items[first + k];
+        hipLaunchKernelGGL(k_write_items, dim3(1), dim3(kPack), 0, s, table, pack, first, count);
+    }
     return hipGetLastError();
 }
 

@@ -1,9 +1,16 @@
-// Stage 4: LSD radix sort of the (tile | depth) keys with their Gaussian
-// indices (Speedy-Splat Sec. 3.2.2, "RadixSort"), and stage 5: per-tile ranges
-// ("identifyTileRanges").
+// The sorts of the pipeline (Speedy-Splat Sec. 3.2.2, "RadixSort") and stage 5,
+// per-tile ranges ("identifyTileRanges").
 //
-// Only the low 32 + ceil(log2(n_tiles)) key bits can be non-zero, so the sort
-// runs ceil(bits / 8) passes of 8-bit digits.  Each pass is reduce-then-scan,
+// The paper sorts the pairs once on the 64-bit key tile << 32 | bits(depth).
+// The same order (tile, then depth, then Gaussian index) comes from two
+// shorter stable sorts:
+//   depth order  the record slots by bits(depth) (culled slots last), 4 passes
+//                over n slots;
+//   tile sort    the pairs, emitted in depth order, by tile id alone:
+//                ceil(log2(n_tiles)) bits, 2 passes at 1600x1040,
+// which moves about a third of the bytes of six passes over 12-byte pairs.
+//
+// Both are LSD radix sorts with 8-bit digits.  Each pass is reduce-then-scan,
 // so no workgroup ever waits on another:
 //   hist     workgroup b counts the digits of its contiguous key chunk
 //   dscan    256 workgroups, one per digit: exclusive scan of that digit's
@@ -117,6 +124,8 @@ __global__ __launch_bounds__(kBlock) void k_dscan(uint32_t* __restrict__ hist, u
     if (threadIdx.x == 0) hist[(uint64_t)kRadix * grid + blockIdx.x] = total;
 }
 
+// vals_in == nullptr stands for the identity (value = input position);
+// keys_out == nullptr skips the key writes (a last pass whose keys are unused).
 template <class K>
 __global__ __launch_bounds__(kBlock) void k_scatter(const K* __restrict__ keys_in,
                                                     const uint32_t* __restrict__ vals_in,
@@ -155,7 +164,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const K* __restrict__ keys_i
             const uint64_t idx = sub + (uint64_t)w * (64 * kItems) + (uint64_t)k * 64 + lane;
             const bool valid = idx < hi;
             key[k] = valid ? keys_in[idx] : (K)0;
-            val[k] = valid ? vals_in[idx] : 0u;
+            val[k] = valid ? (vals_in ? vals_in[idx] : (uint32_t)idx) : 0u;
         }
 #pragma unroll
         for (int k = 0; k < kItems; ++k) {
@@ -208,7 +217,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const K* __restrict__ keys_i
             const uint32_t d = digit_of(kk, shift);
             const uint32_t pos = base[d] + (i - lstart[d]);
             if (pos < n) {
-                keys_out[pos] = kk;
+                if (keys_out) keys_out[pos] = kk;
                 vals_out[pos] = s_val[i];
             }
         }
@@ -220,31 +229,37 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const K* __restrict__ keys_i
 
 // One lane per boundary position i in [0, n]: every tile whose run starts at i
 // gets start = i, every tile whose run ends at i gets end = i.
-__global__ __launch_bounds__(256) void k_ranges(const uint64_t* __restrict__ keys, uint64_t n,
+__global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ keys, uint64_t n,
                                                 int n_tiles, uint32_t* __restrict__ ranges) {
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i > n) return;
-    const int prev = i == 0 ? -1 : (int)(keys[i - 1] >> 32);
-    const int cur = i == n ? n_tiles : (int)(keys[i] >> 32);
+    const int prev = i == 0 ? -1 : (int)keys[i - 1];
+    const int cur = i == n ? n_tiles : (int)keys[i];
     if (prev == cur) return;
     for (int t = prev + 1; t <= cur && t < n_tiles; ++t) ranges[2 * t] = (uint32_t)i;
     for (int t = prev < 0 ? 0 : prev; t < cur && t < n_tiles; ++t) ranges[2 * t + 1] = (uint32_t)i;
 }
 
+// Sorts n (key, value) pairs on the low `bits` key bits, ping-ponging between
+// buffers 0 and 1 from buffer `cur`; *out_buf receives the buffer holding the
+// result.  identity: the input values are 0..n-1 and are not read.  With
+// last_keys false the final pass writes values only.
 template <class K>
 hipError_t radix_sort(K* keys[2], uint32_t* vals[2], int cur, uint64_t n, int bits,
-                      uint32_t* tmp, int* out_buf, hipStream_t s) {
+                      uint32_t* tmp, bool identity, bool last_keys, int* out_buf,
+                      hipStream_t s) {
     if (n > 1) {
         const Plan plan = make_plan(n);
         const int passes = (bits + 7) / 8;
         for (int pass = 0; pass < passes; ++pass) {
             const int shift = pass * 8;
+            K* kout = (pass + 1 == passes && !last_keys) ? nullptr : keys[1 - cur];
+            const uint32_t* vin = (pass == 0 && identity) ? nullptr : vals[cur];
             hipLaunchKernelGGL(k_hist<K>, dim3(plan.grid), dim3(kBlock), 0, s, keys[cur], n,
                                shift, plan.chunk, plan.grid, tmp);
             hipLaunchKernelGGL(k_dscan, dim3(kRadix), dim3(kBlock), 0, s, tmp, plan.grid);
             hipLaunchKernelGGL(k_scatter<K>, dim3(plan.grid), dim3(kBlock), 0, s, keys[cur],
-                               vals[cur], keys[1 - cur], vals[1 - cur], n, shift, plan.chunk,
-                               plan.grid, tmp);
+                               vin, kout, vals[1 - cur], n, shift, plan.chunk, plan.grid, tmp);
             cur = 1 - cur;
         }
     }
@@ -252,20 +267,36 @@ hipError_t radix_sort(K* keys[2], uint32_t* vals[2], int cur, uint64_t n, int bi
     return hipGetLastError();
 }
 
+__global__ void k_identity1(uint32_t* v) { v[0] = 0u; }
+
 }  // namespace
 
 int sort_passes(int bits) { return (bits + 7) / 8; }
 
 int64_t sort_tmp_words(uint64_t) { return (int64_t)kRadix * kMaxGrid + kRadix; }
 
-hipError_t launch_sort(const ss_pairs& p, int buf, uint64_t n, int bits, int* out_buf,
-                       hipStream_t s) {
-    uint64_t* keys[2] = {p.keys[0], p.keys[1]};
-    uint32_t* vals[2] = {p.values[0], p.values[1]};
-    return radix_sort<uint64_t>(keys, vals, buf, n, bits, p.sort_tmp, out_buf, s);
+hipError_t launch_depth_order(int64_t n, const ss_frame& f, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    if (n == 1) {   // a single slot is its own order
+        hipLaunchKernelGGL(k_identity1, dim3(1), dim3(1), 0, s, f.order);
+        return hipGetLastError();
+    }
+    uint32_t* keys[2] = {f.depth_keys, f.depth_keys + n};
+    uint32_t* vals[2] = {f.order, f.order + n};
+    int out = 0;
+    // 4 passes from buffer 0 end in buffer 0: the order lands in f.order[0, n).
+    return radix_sort<uint32_t>(keys, vals, 0, (uint64_t)n, 32, f.order_tmp, true, false, &out,
+                                s);
 }
 
-hipError_t launch_ranges(const uint64_t* keys, uint64_t n, int n_tiles, uint32_t* ranges,
+hipError_t launch_sort(const ss_pairs& p, int buf, uint64_t n, int bits, int* out_buf,
+                       hipStream_t s) {
+    uint32_t* keys[2] = {p.keys[0], p.keys[1]};
+    uint32_t* vals[2] = {p.values[0], p.values[1]};
+    return radix_sort<uint32_t>(keys, vals, buf, n, bits, p.sort_tmp, false, true, out_buf, s);
+}
+
+hipError_t launch_ranges(const uint32_t* keys, uint64_t n, int n_tiles, uint32_t* ranges,
                          hipStream_t s) {
     const uint64_t items = n + 1;
     const uint64_t grid = (items + 255) / 256;

@@ -20,6 +20,7 @@ constexpr double kDiscFloor = 0.1;        // floor of the eigenvalue discriminan
 constexpr float kAlphaMax = 0.99f;        // upper clamp of alpha
 constexpr float kTMin = 1e-4f;            // transmittance stop
 constexpr float kAlphaMin = 1.0f / 255.0f;  // inclusion cutoff, used as q <= t
+constexpr uint32_t kCulledKey = 0xffffffffu;  // depth-order key of a slot with no tiles
 
 // ---------------------------------------------------------------- tile geometry
 //
@@ -182,23 +183,80 @@ __device__ __forceinline__ int xcd_contiguous(int b, int n) {
 
 __device__ __forceinline__ unsigned lane_id() { return __lane_id(); }
 
+// ---------------------------------------------------------------- render items
+//
+// Every launch renders a batch of one or more items (a camera, a resident
+// scene and an output image).  Per-Gaussian buffers hold each item's records
+// in a run of "slots" starting at g_off (a multiple of 256, so a 256-lane
+// workgroup never spans two items); tiles carry a global id tile_off + local
+// id; per-pixel buffers hold each item's pixels from pix_off.  A single frame
+// is the batch of one item with g_off = tile_off = pix_off = 0.  The item
+// table lives in device memory (written by write_items).
+
+constexpr int kSlotAlign = 256;
+
+struct Item {
+    ss_camera cam;
+    const float* means;
+    const float* scales;
+    const float* quats;
+    const float* opacity;
+    const float* sh;
+    float* out_rgb;       // [3, H, W]
+    int64_t n;            // Gaussians of the scene
+    int64_t g_off;        // first record slot
+    int64_t pix_off;      // first pixel in the per-pixel buffers
+    int32_t sh_degree, sh_stride;
+    int32_t tx_n, ty_n;   // tile grid of the item's image
+    int32_t tile_off;     // first global tile id
+    int32_t pad_;
+};
+
+struct BatchDims {
+    int32_t n_items;
+    int32_t n_tiles;      // total tiles
+    int64_t n_slots;      // total record slots
+    int64_t n_pixels;     // total pixels
+};
+
+// Item owning record slot `slot` / global tile `tile` (tables are ordered by
+// g_off and tile_off).  Uniform when the argument is.
+__device__ __forceinline__ int item_of_slot(const Item* items, int n_items, int64_t slot) {
+    int lo = 0, hi = n_items - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (items[mid].g_off <= slot) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+__device__ __forceinline__ int item_of_tile(const Item* items, int n_items, int tile) {
+    int lo = 0, hi = n_items - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (items[mid].tile_off <= tile) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
 // ---------------------------------------------------------------- launchers
 // (each returns hipSuccess or the launch error)
 
-hipError_t launch_preprocess(const ss_camera& cam, const ss_gaussians& g, int mode,
-                             const ss_frame& f, hipStream_t s);
+hipError_t write_items(Item* table, const Item* host_items, int n_items, hipStream_t s);
+hipError_t launch_preprocess(const Item* items, const BatchDims& d, int mode, const ss_frame& f,
+                             hipStream_t s);
+hipError_t launch_depth_order(int64_t n, const ss_frame& f, hipStream_t s);
 hipError_t launch_scan(int64_t n, const ss_frame& f, hipStream_t s);
 int64_t scan_tmp_words(int64_t n);
-hipError_t launch_emit(int tx_n, int ty_n, int64_t n, int mode, const ss_frame& f,
-                       uint64_t* keys, uint32_t* values, uint64_t n_pairs, hipStream_t s);
+hipError_t launch_emit(const Item* items, const BatchDims& d, int mode, const ss_frame& f,
+                       uint32_t* keys, uint32_t* values, uint64_t n_pairs, hipStream_t s);
 int64_t sort_tmp_words(uint64_t capacity);
 int sort_passes(int bits);
 hipError_t launch_sort(const ss_pairs& p, int buf, uint64_t n_pairs, int bits, int* out_buf,
                        hipStream_t s);
-hipError_t launch_ranges(const uint64_t* keys, uint64_t n_pairs, int n_tiles, uint32_t* ranges,
+hipError_t launch_ranges(const uint32_t* keys, uint64_t n_pairs, int n_tiles, uint32_t* ranges,
                          hipStream_t s);
-hipError_t launch_blend(const ss_camera& cam, const ss_frame& f, const uint32_t* values,
-                        float* out_rgb, hipStream_t s);
+hipError_t launch_blend(const Item* items, const BatchDims& d, const ss_frame& f,
+                        const uint32_t* values, float* out_rgb_single, hipStream_t s);
 hipError_t launch_backward(const ss_camera& cam, const ss_gaussians& g, const ss_frame& f,
                            const uint32_t* values, const float* dl_drgb, const ss_grads& out,
                            hipStream_t s);

@@ -89,6 +89,9 @@ class Frame:
         self.conic = torch.empty((n, 4), dtype=torch.float32, device=dev)
         self.rgb = torch.empty((n, 4), dtype=torch.float32, device=dev)
         self.counts = torch.empty(n, dtype=torch.int32, device=dev)
+        self.depth_keys = torch.empty(2 * n, dtype=torch.int32, device=dev)
+        self.order = torch.empty(2 * n, dtype=torch.int32, device=dev)
+        self.order_tmp = torch.empty(int(info.order_tmp_words), dtype=torch.int32, device=dev)
         self.offsets = torch.empty(n, dtype=torch.int32, device=dev)
         self.scan_tmp = torch.zeros(int(info.scan_tmp_words), dtype=torch.int64, device=dev)
         self.ranges = torch.empty((info.n_tiles, 2), dtype=torch.int32, device=dev)
@@ -97,11 +100,13 @@ class Frame:
         # per-pixel count of evaluated list entries (a statistic; NULL skips it)
         self.n_eval = torch.empty((height, width), dtype=torch.int32, device=dev) if stats else None
         self.emit_tmp = torch.empty(n + 1, dtype=torch.int32, device=dev)
+        self.table = torch.empty(int(info.table_bytes), dtype=torch.uint8, device=dev)
 
     def struct(self) -> _lib.SSFrame:
         f = _lib.SSFrame()
-        for name in ("geom", "conic", "rgb", "counts", "offsets", "scan_tmp", "ranges",
-                     "t_final", "n_last", "n_eval", "emit_tmp"):
+        for name in ("geom", "conic", "rgb", "counts", "depth_keys", "order", "order_tmp",
+                     "offsets", "scan_tmp", "ranges", "t_final", "n_last", "n_eval", "emit_tmp",
+                     "table"):
             t = getattr(self, name)
             setattr(f, name, t.data_ptr() if t is not None else None)
         return f
@@ -112,13 +117,13 @@ class Frame:
 
 
 class Pairs:
-    """Pair workspace (ss_pairs): two key/value buffers and sort scratch."""
+    """Pair workspace (ss_pairs): two tile-key/value buffers and sort scratch."""
 
     def __init__(self, capacity: int, device):
         dev = torch.device(device)
         cap = max(int(capacity), 1)
         self.capacity = cap
-        self.keys = [torch.empty(cap, dtype=torch.int64, device=dev) for _ in range(2)]
+        self.keys = [torch.empty(cap, dtype=torch.int32, device=dev) for _ in range(2)]
         self.values = [torch.empty(cap, dtype=torch.int32, device=dev) for _ in range(2)]
         w = ctypes.c_int64()
         check(lib().ss_sort_tmp_words(cap, ctypes.byref(w)), "ss_sort_tmp_words")
@@ -133,14 +138,14 @@ class Pairs:
         return p
 
 
-STAGES = ("preprocess", "scan", "readback", "emit", "sort", "ranges", "blend")
+STAGES = ("preprocess", "depth_order", "scan", "readback", "emit", "sort", "ranges", "blend")
 
 
 class StageEvents:
-    """Eight timing events recorded by the library at stage boundaries."""
+    """Nine timing events recorded by the library at stage boundaries."""
 
     def __init__(self, device):
-        self.events = [torch.cuda.Event(enable_timing=True) for _ in range(8)]
+        self.events = [torch.cuda.Event(enable_timing=True) for _ in range(len(STAGES) + 1)]
         s = torch.cuda.current_stream(device)
         for e in self.events:  # creates the underlying hipEvent_t
             e.record(s)
@@ -158,7 +163,7 @@ class StageEvents:
         return {name: ev[k].elapsed_time(ev[k + 1]) for k, name in enumerate(STAGES)}
 
     def frame_ms(self) -> float:
-        return self.events[0].elapsed_time(self.events[7])
+        return self.events[0].elapsed_time(self.events[len(STAGES)])
 
 
 @dataclass
@@ -229,6 +234,13 @@ class Renderer:
         check(lib().ss_preprocess(ctypes.byref(c), ctypes.byref(gs), mode_id(mode),
                                   ctypes.byref(fs), _stream(self.device)), "ss_preprocess")
         return frame
+
+    def depth_order(self, frame: Frame) -> torch.Tensor:
+        """Stage 2a; returns frame.order[:n] (Gaussians by depth, then index)."""
+        fs = frame.struct()
+        check(lib().ss_depth_order(frame.n, ctypes.byref(fs), _stream(self.device)),
+              "ss_depth_order")
+        return frame.order[:frame.n]
 
     def scan(self, frame: Frame) -> int:
         fs = frame.struct()
@@ -343,3 +355,113 @@ def pruning_score(g: Gaussians, cam, mode="accutile") -> torch.Tensor:
     dl = torch.zeros((3, out.image.shape[1], out.image.shape[2]), dtype=torch.float32,
                      device=g.device)
     return backward(g, cam, out, dl, want_score=True).score
+
+
+# ---------------------------------------------------------------- batches
+
+class BatchFrame:
+    """Frame buffers (ss_frame) of a batch: all items' records, tiles and pixels."""
+
+    def __init__(self, info: _lib.SSBatchInfo, n_items: int, device, stats: bool = False):
+        dev = torch.device(device)
+        ns, npx = int(info.n_slots), int(info.n_pixels)
+        self.info = info
+        self.geom = torch.empty((ns, 4), dtype=torch.float32, device=dev)
+        self.conic = torch.empty((ns, 4), dtype=torch.float32, device=dev)
+        self.rgb = torch.empty((ns, 4), dtype=torch.float32, device=dev)
+        self.counts = torch.empty(ns, dtype=torch.int32, device=dev)
+        self.depth_keys = torch.empty(2 * ns, dtype=torch.int32, device=dev)
+        self.order = torch.empty(2 * ns, dtype=torch.int32, device=dev)
+        self.order_tmp = torch.empty(int(info.order_tmp_words), dtype=torch.int32, device=dev)
+        self.offsets = torch.empty(ns, dtype=torch.int32, device=dev)
+        self.scan_tmp = torch.zeros(int(info.scan_tmp_words), dtype=torch.int64, device=dev)
+        self.ranges = torch.empty((max(int(info.n_tiles), 1), 2), dtype=torch.int32, device=dev)
+        self.t_final = torch.empty(max(npx, 1), dtype=torch.float32, device=dev)
+        self.n_last = torch.empty(max(npx, 1), dtype=torch.int32, device=dev)
+        self.n_eval = torch.empty(max(npx, 1), dtype=torch.int32, device=dev) if stats else None
+        self.emit_tmp = torch.empty(ns + 1, dtype=torch.int32, device=dev)
+        self.table = torch.empty(int(info.table_bytes), dtype=torch.uint8, device=dev)
+
+    struct = Frame.struct
+
+    @property
+    def nbytes(self) -> int:
+        return sum(t.numel() * t.element_size() for t in
+                   (self.geom, self.conic, self.rgb, self.counts, self.depth_keys, self.order,
+                    self.order_tmp, self.offsets, self.scan_tmp, self.ranges, self.t_final,
+                    self.n_last, self.emit_tmp, self.table))
+
+
+def batch_items(requests, outs) -> "ctypes.Array":
+    """ss_batch_item array for [(Gaussians, camera), ...] and output images."""
+    arr = (_lib.SSBatchItem * len(requests))()
+    for k, ((g, cam), out) in enumerate(zip(requests, outs)):
+        arr[k].cam = make_camera(cam)
+        arr[k].g = g.struct()
+        arr[k].out_rgb = out.data_ptr()
+    return arr
+
+
+def batch_sizes(items, n) -> _lib.SSBatchInfo:
+    info = _lib.SSBatchInfo()
+    check(lib().ss_batch_sizes(items, n, ctypes.byref(info)), "ss_batch_sizes")
+    return info
+
+
+class BatchRenderer:
+    """Renders several requests (scenes and resolutions may differ) with one
+    launch per stage.  Buffers are allocated per batch through torch."""
+
+    def __init__(self, device="cuda", growth: float = 1.25):
+        self.device = torch.device(device)
+        self.growth = growth
+
+    def begin(self, requests, mode="accutile", outs=None, stream=None):
+        """Stages 1-2b for [(Gaussians, camera), ...]; returns a handle with the
+        pair count (synchronises `stream`)."""
+        n = len(requests)
+        if outs is None:
+            outs = [torch.empty((3, int(c.height), int(c.width)), dtype=torch.float32,
+                                device=self.device) for _, c in requests]
+        items = batch_items(requests, outs)
+        info = batch_sizes(items, n)
+        frame = BatchFrame(info, n, self.device)
+        fs = frame.struct()
+        st = ctypes.c_void_p(stream.cuda_stream if stream is not None else
+                             torch.cuda.current_stream(self.device).cuda_stream)
+        n_pairs = ctypes.c_uint64()
+        check(lib().ss_batch_begin(items, n, mode_id(mode), ctypes.byref(fs),
+                                   ctypes.byref(n_pairs), None, st), "ss_batch_begin")
+        return _BatchHandle(items, n, mode_id(mode), frame, int(n_pairs.value), outs, st)
+
+    def finish(self, h: "_BatchHandle"):
+        """Stages 3-6; returns the output images (valid after the stream syncs)."""
+        h.pairs = Pairs(int(max(h.n_pairs, 1) * self.growth) + 1024, self.device)
+        fs, ps = h.frame.struct(), h.pairs.struct()
+        buf = ctypes.c_int32()
+        check(lib().ss_batch_finish(h.items, h.n, h.mode, ctypes.byref(fs), ctypes.byref(ps),
+                                    h.n_pairs, ctypes.byref(buf), None, h.stream),
+              "ss_batch_finish")
+        return h.outs
+
+    def render(self, requests, mode="accutile", outs=None, stream=None):
+        return self.finish(self.begin(requests, mode, outs, stream))
+
+
+@dataclass
+class _BatchHandle:
+    items: object
+    n: int
+    mode: int
+    frame: BatchFrame
+    n_pairs: int
+    outs: list
+    stream: ctypes.c_void_p
+    pairs: Pairs | None = None
+
+    @property
+    def nbytes(self) -> int:
+        b = self.frame.nbytes + sum(o.numel() * 4 for o in self.outs)
+        if self.pairs is not None:
+            b += self.pairs.capacity * 16 + self.pairs.sort_tmp.numel() * 4
+        return b

@@ -15,7 +15,7 @@ def u64(t: torch.Tensor) -> np.ndarray:
 
 
 def gpu_stages(renderer, g, cam, mode):
-    """Runs the six stages one call at a time; returns every intermediate."""
+    """Runs the stages one call at a time; returns every intermediate."""
     frame = renderer.preprocess(g, cam, mode)
     torch.cuda.synchronize()
     out = {
@@ -24,18 +24,20 @@ def gpu_stages(renderer, g, cam, mode):
         "rgb": frame.rgb.cpu().numpy().copy(),
         "counts": u32(frame.counts).copy(),
     }
+    out["depth_keys"] = u32(frame.depth_keys[:frame.n]).copy()
+    out["order"] = u32(renderer.depth_order(frame)).copy()
     p = renderer.scan(frame)
     out["n_pairs"] = p
     out["offsets"] = u32(frame.offsets).copy()
     pairs = renderer.emit(cam, frame, mode, p, buf=0)
     torch.cuda.synchronize()
-    out["keys"] = u64(pairs.keys[0][:p]).copy()
+    out["keys"] = u32(pairs.keys[0][:p]).copy()
     out["values"] = u32(pairs.values[0][:p]).copy()
     ob = renderer.sort(cam, pairs, p, 0)
     renderer.ranges(cam, frame, pairs, p, ob)
     img = renderer.blend(cam, frame, pairs, ob)
     torch.cuda.synchronize()
-    out["sorted_keys"] = u64(pairs.keys[ob][:p]).copy()
+    out["sorted_keys"] = u32(pairs.keys[ob][:p]).copy()
     out["sorted_values"] = u32(pairs.values[ob][:p]).copy()
     out["ranges"] = u32(frame.ranges).copy()
     out["image"] = img.cpu().numpy()
@@ -65,16 +67,54 @@ def assert_records_equal(gpu, ref: "oracle.Records"):
                                                                             ref.counts))
 
 
+CULLED_KEY = np.uint32(0xFFFFFFFF)
+
+
+def expected_depth_keys(rec: "oracle.Records") -> np.ndarray:
+    """Depth-order key of every record: bits(depth), or all ones without tiles."""
+    bits = np.ascontiguousarray(rec.geom[:, 2]).view(np.uint32)
+    return np.where(rec.counts > 0, bits, CULLED_KEY).astype(np.uint32)
+
+
+def expected_order(dkeys: np.ndarray) -> np.ndarray:
+    """Indices sorted by (key, index)."""
+    return np.lexsort((np.arange(len(dkeys)), dkeys)).astype(np.uint32)
+
+
+def depth_ordered_pairs(fr, order):
+    """The oracle's pairs (emitted in index order, each Gaussian's tiles in its
+    enumeration order) regrouped Gaussian by Gaussian in `order`: the pairs the
+    depth-ordered emission writes, with key = tile id."""
+    counts = fr.records.counts.astype(np.int64)
+    start = np.cumsum(counts) - counts
+    c = counts[order]
+    seg0 = np.repeat(start[order], c)
+    within = np.arange(int(c.sum())) - np.repeat(np.cumsum(c) - c, c)
+    idx = seg0 + within
+    return (fr.keys[idx] >> np.uint64(32)).astype(np.uint32), fr.values[idx].astype(np.uint32)
+
+
 def assert_pipeline_equal(gpu, fr, image_tol=1e-4):
     """Bit-exact integer intermediates; image within image_tol except where the
-    oracle flags a stop decision that exp rounding may flip."""
+    oracle flags a stop decision that exp rounding may flip.
+
+    The oracle sorts (tile << 32 | depth, index) pairs once; the GPU path orders
+    the Gaussians by depth first, emits tile-id keys in that order and sorts
+    them stably by tile.  The expected GPU intermediates are derived from the
+    oracle's: the final sorted values and ranges must be identical."""
     assert_records_equal(gpu, fr.records)
+    dk = expected_depth_keys(fr.records)
+    assert np.array_equal(gpu["depth_keys"], dk), first_diffs(gpu["depth_keys"], dk)
+    order = expected_order(dk)
+    assert np.array_equal(gpu["order"], order), first_diffs(gpu["order"], order)
     assert gpu["n_pairs"] == fr.n_pairs
-    assert np.array_equal(gpu["offsets"], fr.offsets.astype(np.uint32))
-    assert np.array_equal(gpu["keys"], fr.keys), first_diffs(gpu["keys"], fr.keys)
-    assert np.array_equal(gpu["values"], fr.values)
-    assert np.array_equal(gpu["sorted_keys"], fr.sorted_keys), \
-        first_diffs(gpu["sorted_keys"], fr.sorted_keys)
+    counts = fr.records.counts.astype(np.uint64)
+    assert np.array_equal(gpu["offsets"], np.cumsum(counts[order]).astype(np.uint32))
+    ek, ev = depth_ordered_pairs(fr, order)
+    assert np.array_equal(gpu["keys"], ek), first_diffs(gpu["keys"], ek)
+    assert np.array_equal(gpu["values"], ev), first_diffs(gpu["values"], ev)
+    st = (fr.sorted_keys >> np.uint64(32)).astype(np.uint32)
+    assert np.array_equal(gpu["sorted_keys"], st), first_diffs(gpu["sorted_keys"], st)
     assert np.array_equal(gpu["sorted_values"], fr.sorted_values)
     assert np.array_equal(gpu["ranges"], fr.ranges)
     if fr.image is not None:

@@ -24,8 +24,9 @@ def L():
 
 def test_header_declares_the_stages():
     names = declared_functions()
-    for n in ("ss_preprocess", "ss_scan", "ss_emit", "ss_sort", "ss_ranges", "ss_blend",
-              "ss_render", "ss_forward_begin", "ss_forward_finish", "ss_get_constants"):
+    for n in ("ss_preprocess", "ss_depth_order", "ss_scan", "ss_emit", "ss_sort", "ss_ranges",
+              "ss_blend", "ss_render", "ss_forward_begin", "ss_forward_finish",
+              "ss_get_constants"):
         assert n in names
 
 
@@ -39,7 +40,7 @@ def test_every_declared_symbol_is_exported_and_bound(L):
 def test_constants_match_independent_values(L):
     from paper_2412_00578_amd import _lib
     c = _lib.constants()
-    assert c.abi_version == 1 and c.tile == 16
+    assert c.abi_version == 2 and c.tile == 16
     assert c.alpha_min == pytest.approx(1 / 255, rel=1e-7)
     assert c.alpha_max == pytest.approx(0.99, rel=1e-7)
     assert c.t_min == pytest.approx(1e-4, rel=1e-7)
@@ -59,11 +60,11 @@ def test_frame_sizes(L):
     info = _lib.SSFrameInfo()
     assert L.ss_frame_sizes(1_500_000, 1600, 1040, ctypes.byref(info)) == 0
     assert (info.tiles_x, info.tiles_y, info.n_tiles) == (100, 65, 6500)
-    assert info.sort_bits == 32 + 13
+    assert info.sort_bits == 13
     assert info.scan_tmp_words == 1 + (1_500_000 + 4095) // 4096
     assert L.ss_frame_sizes(10, 1920, 1080, ctypes.byref(info)) == 0
     assert (info.tiles_x, info.tiles_y) == (120, 68)
-    assert L.ss_frame_sizes(10, 256, 256, ctypes.byref(info)) == 0 and info.sort_bits == 40
+    assert L.ss_frame_sizes(10, 256, 256, ctypes.byref(info)) == 0 and info.sort_bits == 8
     assert L.ss_frame_sizes(-1, 16, 16, ctypes.byref(info)) == _lib.SS_ERR_INVALID_ARG
     assert L.ss_frame_sizes(1, 0, 16, ctypes.byref(info)) == _lib.SS_ERR_INVALID_ARG
 
@@ -117,3 +118,36 @@ def test_workspace_and_overflow_checks(L):
                      None) == _lib.SS_ERR_INVALID_ARG
     assert L.ss_blend(ctypes.byref(cam), ctypes.byref(f), ctypes.byref(p), 0, None,
                       None) == _lib.SS_ERR_INVALID_ARG
+
+
+def test_ctypes_layouts_match_the_header(tmp_path):
+    """Every ctypes struct has the size and field offsets gcc gives the header's."""
+    import shutil
+    import subprocess
+
+    from paper_2412_00578_amd import _lib
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    structs = {"ss_constants": _lib.SSConstants, "ss_camera": _lib.SSCamera,
+               "ss_gaussians": _lib.SSGaussians, "ss_frame": _lib.SSFrame,
+               "ss_frame_info": _lib.SSFrameInfo, "ss_batch_item": _lib.SSBatchItem,
+               "ss_batch_info": _lib.SSBatchInfo, "ss_pairs": _lib.SSPairs,
+               "ss_grads": _lib.SSGrads, "ss_stage_events": _lib.SSStageEvents}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "speedysplat.h"',
+             "int main(void) {"]
+    want = []
+    for cname, cls in structs.items():
+        lines.append(f'printf("%zu\\n", sizeof({cname}));')
+        want.append(ctypes.sizeof(cls))
+        for fname, _ in cls._fields_:
+            lines.append(f'printf("%zu\\n", offsetof({cname}, {fname}));')
+            want.append(getattr(cls, fname).offset)
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], check=True, capture_output=True,
+                                          text=True).stdout.split()]
+    assert got == want

@@ -120,7 +120,7 @@ def test_composite_render_equals_stages(ss, gpu_device, mode):
     assert np.array_equal(u32(out.frame.n_last), stages["n_last"])
     p = out.n_pairs
     assert p == stages["n_pairs"]
-    assert np.array_equal(u64(out.pairs.keys[0][:p]), stages["sorted_keys"])
+    assert np.array_equal(u32(out.pairs.keys[0][:p]), stages["sorted_keys"])
     assert np.array_equal(u32(out.pairs.values[0][:p]), stages["sorted_values"])
     assert np.array_equal(out.image.cpu().numpy(), stages["image"])
 
@@ -161,13 +161,32 @@ def test_scan_matches_cumsum(ss, gpu_device, n):
     print(f"[case] scan n={n}", flush=True)
     rng = np.random.default_rng(n + 1)
     counts = rng.integers(0, 12, size=n).astype(np.uint32)
+    perm = rng.permutation(n).astype(np.uint32)
     f = ss.Frame(n, 16, 16, gpu_device, stats=False)
     f.counts.copy_(torch.from_numpy(counts.view(np.int32)))
+    f.order[:n].copy_(torch.from_numpy(perm.view(np.int32)))
     r = ss.Renderer(gpu_device)
     total = r.scan(f)
     assert total == int(counts.astype(np.uint64).sum())
     if n:
-        assert np.array_equal(u32(f.offsets), np.cumsum(counts, dtype=np.uint64).astype(np.uint32))
+        want = np.cumsum(counts[perm], dtype=np.uint64).astype(np.uint32)
+        assert np.array_equal(u32(f.offsets), want)
+
+
+@pytest.mark.parametrize("n", [0, 1, 2, 255, 4095, 4097, 70_001, 1_500_000, 6_000_001])
+def test_depth_order_random_keys(ss, gpu_device, n):
+    print(f"[case] depth order n={n}", flush=True)
+    rng = np.random.default_rng(n + 11)
+    # depth bits with many exact ties, and slots without tiles (all-ones key)
+    keys = rng.integers(0x3e4ccccd, 0x3e4ccccd + 20000, size=n).astype(np.uint32)
+    keys[rng.random(n) < 0.2] = np.uint32(0xFFFFFFFF)
+    f = ss.Frame(n, 16, 16, gpu_device, stats=False)
+    if n:
+        f.depth_keys[:n].copy_(torch.from_numpy(keys.view(np.int32)))
+    r = ss.Renderer(gpu_device)
+    got = u32(r.depth_order(f))
+    torch.cuda.synchronize()
+    assert np.array_equal(got, np.argsort(keys, kind="stable").astype(np.uint32))
 
 
 @pytest.mark.parametrize("n", [0, 1, 2, 4095, 4097, 70_001, 5_000_003])
@@ -176,24 +195,21 @@ def test_sort_and_ranges_random_keys(ss, gpu_device, n):
     rng = np.random.default_rng(n + 7)
     cam = scenegen.Camera(1600, 1040, 1000.0, 1000.0, 800.0, 520.0, np.eye(3), np.zeros(3))
     n_tiles = cam.tiles_x * cam.tiles_y
-    tiles = rng.integers(0, n_tiles, size=n).astype(np.uint64)
-    # depth-like low words with many exact ties
-    low = rng.integers(0x3e000000, 0x3e000000 + 5000, size=n).astype(np.uint64)
-    keys = (tiles << np.uint64(32)) | low
-    vals = np.arange(n, dtype=np.uint32)
+    keys = rng.integers(0, n_tiles, size=n).astype(np.uint32)
+    vals = rng.permutation(n).astype(np.uint32)    # arbitrary values: checks stability
     r = ss.Renderer(gpu_device)
     pairs = r.pairs_for(n)
     if n:
-        pairs.keys[0][:n].copy_(torch.from_numpy(keys.view(np.int64)))
+        pairs.keys[0][:n].copy_(torch.from_numpy(keys.view(np.int32)))
         pairs.values[0][:n].copy_(torch.from_numpy(vals.view(np.int32)))
     ob = r.sort(cam, pairs, n, 0)
     f = ss.Frame(1, cam.width, cam.height, gpu_device, stats=False)
     r.ranges(cam, f, pairs, n, ob)
     torch.cuda.synchronize()
-    order = np.lexsort((vals, keys))
-    assert np.array_equal(u64(pairs.keys[ob][:n]), keys[order])
+    order = np.argsort(keys, kind="stable")
+    assert np.array_equal(u32(pairs.keys[ob][:n]), keys[order])
     assert np.array_equal(u32(pairs.values[ob][:n]), vals[order])
-    st = (keys[order] >> np.uint64(32)).astype(np.int64)
+    st = keys[order].astype(np.int64)
     rg = u32(f.ranges).reshape(-1, 2)
     assert np.array_equal(rg[:, 0], np.searchsorted(st, np.arange(n_tiles), "left"))
     assert np.array_equal(rg[:, 1], np.searchsorted(st, np.arange(n_tiles), "right"))

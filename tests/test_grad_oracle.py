@@ -82,7 +82,7 @@ def test_autograd_equals_finite_differences():
         pix_i = og.gaussian_pixels(rec, i, cam)
         w_i = weights[pix_i[:, 1] * cam.width + pix_i[:, 0]]
         base_L, base_sig = og.loss_fd(p, cam, pix_i, w_i, order)
-        theta = float(leaf[idx])
+        theta = float(leaf.detach()[idx])
         h = 1e-6 * max(1.0, abs(theta))
         vals = []
         sigs = []
