@@ -41,9 +41,10 @@ MODES = ("3sigma", "snugbox", "accutile")
 # FP32 is not used, so one FP32 VALU op per lane per clock).
 PEAK_VALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12      # 39.3 T ops/s
 PEAK_HBM_GBS = 8000.0
-# FP32 operations per evaluated (pixel, Gaussian) pair of the blend: dx, dy,
-# (a dx) dx, (c dy) dy, ((2b) dx) dy, two adds and the q <= t test.
-OPS_PER_EVAL = 11
+# FP32 operations per evaluated (pixel, Gaussian) pair of the blend's inclusion
+# test q = fma(dy, fma(c, dy, (2b) dx), (a dx) dx) <= t: dx, dy, a dx,
+# (a dx) dx, (2b) dx, two FMAs and the compare (an FMA counts as one).
+OPS_PER_EVAL = 8
 # Algorithmic HBM bytes: preprocess reads 236 B (SH-3 inputs) and writes a 56 B
 # record (geom, conic, rgb, count, depth key) per Gaussian; the depth order
 # moves 72 B per Gaussian over its four passes (histogram read 4 B, key and

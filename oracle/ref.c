@@ -8,7 +8,8 @@
  *
  * Build: gcc -O2 -std=c99 -ffp-contract=off -fno-fast-math -fPIC -shared.
  * Every floating-point operation below is one IEEE operation rounded once,
- * evaluated in the written order (no contraction into FMA).
+ * evaluated in the written order (no contraction into FMA; the blend's
+ * quadratic form calls fmaf explicitly, a fused multiply-add rounded once).
  *
  * Stages and where the paper defines them (Speedy-Splat, arXiv 2412.00578):
  *   preprocess   Sec. 3.2.1 "Preprocessing": projection of the mean, the 3D
@@ -452,7 +453,7 @@ void orc_ranges(int64_t p, const uint64_t *keys, int64_t n_tiles, uint32_t *rang
 
 /*
  * Blend one tile front to back (FP32).  For each pixel centre
- * (px + 0.5, py + 0.5):  q = ((a dx) dx + (c dy) dy) + ((2b) dx) dy;
+ * (px + 0.5, py + 0.5):  q = fma(dy, fma(c, dy, (2b) dx), (a dx) dx);
  * a Gaussian is included when q <= t (alpha >= 1/255); alpha = min(0.99,
  * sigma exp(-q/2)); the walk stops before a Gaussian that would take the
  * transmittance below 1e-4.  Output planar [3,H,W].
@@ -481,7 +482,7 @@ static void blend_tile(const orc_cam *cam, int tx, int ty, const uint32_t *range
                 uint32_t i = values[j];
                 const float *g = geom + 4 * (int64_t)i, *q = conic + 4 * (int64_t)i;
                 float dx = fx - g[0], dy = fy - g[1];
-                float qq = ((q[0] * dx) * dx + (q[2] * dy) * dy) + ((2.0f * q[1]) * dx) * dy;
+                float qq = fmaf(dy, fmaf(q[2], dy, (2.0f * q[1]) * dx), (q[0] * dx) * dx);
                 if (!(qq <= g[3])) continue;
                 float al = q[3] * expf(-0.5f * qq);
                 if (al > ORC_ALPHA_MAX) al = ORC_ALPHA_MAX;

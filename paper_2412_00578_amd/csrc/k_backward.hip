@@ -136,7 +136,7 @@ __global__ __launch_bounds__(64 * (4 / SPW)) void k_blend_bwd(
             for (int s = 0; s < SPW; ++s) {
                 if (!(m & (1u << (strip0 + s)))) continue;
                 const float dy = fy[s] - g.y;
-                const float qq = (adx2 + (q.z * dy) * dy) + b2dx * dy;
+                const float qq = fmaf(dy, fmaf(q.z, dy, b2dx), adx2);
                 if (j < nl[s] && qq <= g.w) {
                     any = true;
                     const float gval = __expf(-0.5f * qq);

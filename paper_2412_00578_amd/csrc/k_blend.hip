@@ -11,12 +11,15 @@
 //
 // A pixel that has finished (the next Gaussian would take its transmittance
 // below 1e-4) moves its sample row to y = 1e30, so its q <= t test fails from
-// then on with no extra instructions; the wave stops once a ballot finds every
-// pixel finished.  The quadratic form is evaluated as
-// ((a dx) dx + (c dy) dy) + ((2b) dx) dy without contraction and compared
+// then on; every 8 Gaussians a ballot per strip marks strips whose 64 pixels
+// have all finished, which then skip their work, and the wave stops once
+// every pixel has finished.  The quadratic form is evaluated with two fused
+// multiply-adds as q = fma(dy, fma(c, dy, (2b) dx), (a dx) dx) and compared
 // with the record's t, so the inclusion test (alpha >= 1/255) is exact and
-// reproducible.  Nothing on this path is a dense contraction, so it runs on
-// the FP32 VALU.
+// reproducible.  An included strip takes a short path when none of its
+// pixels stops at this Gaussian (wave-uniform test) and the full path, which
+// freezes the stopping pixels, otherwise.  Nothing on this path is a dense
+// contraction, so it runs on the FP32 VALU.
 #include "ss_internal.h"
 
 namespace ss {
@@ -88,10 +91,12 @@ __global__ __launch_bounds__(64) void k_blend(const Item* __restrict__ items, Ba
         last[s] = 0u;
         stop[s] = 0u;
     }
+    uint32_t sl = 0;                              // bit s: strip s has an unfinished pixel
+#pragma unroll
+    for (int s = 0; s < 4; ++s) sl |= (__ballot(fy[s] < kDone) != 0ull ? 1u : 0u) << s;
     const uint32_t start = ranges[2 * tile], end = ranges[2 * tile + 1];
-    bool live = __ballot(fy[0] < kDone || fy[1] < kDone || fy[2] < kDone || fy[3] < kDone) != 0ull;
     Rec nxt = load_rec(values, geom, conic, rgb, start + lane, end);
-    for (uint32_t base = start; base < end && live; base += kBatch) {
+    for (uint32_t base = start; base < end && sl; base += kBatch) {
         s_geo[lane] = nxt.g;
         s_con[lane] = make_float4(nxt.q.x, 2.0f * nxt.q.y, nxt.q.z, nxt.q.w);
         s_col[lane] = nxt.c;
@@ -108,26 +113,35 @@ __global__ __launch_bounds__(64) void k_blend(const Item* __restrict__ items, Ba
             const uint32_t pos = base + k - start + 1u;
 #pragma unroll
             for (int s = 0; s < 4; ++s) {
+                if (!(sl & (1u << s))) continue;      // wave-uniform
                 const float dy = fy[s] - g.y;
-                const float qq = (adx2 + (q.z * dy) * dy) + b2dx * dy;
+                const float qq = fmaf(dy, fmaf(q.z, dy, b2dx), adx2);
                 if (qq <= g.w) {
                     const float al = fminf(kAlphaMax, q.w * __builtin_amdgcn_exp2f(qq * kNegHalfLog2e));
-                    const float tn = T[s] * (1.0f - al);
-                    const bool ok = tn >= kTMin;
-                    const float wgt = ok ? al * T[s] : 0.0f;
+                    float tn = T[s] * (1.0f - al);
+                    float wgt = al * T[s];
+                    uint32_t lp = pos;
+                    if (__ballot(tn < kTMin) != 0ull) {   // some included pixel stops here
+                        const bool ok = tn >= kTMin;
+                        wgt = ok ? wgt : 0.0f;
+                        tn = ok ? tn : T[s];
+                        lp = ok ? pos : last[s];
+                        fy[s] = ok ? fy[s] : kDone;
+                        if (STATS) stop[s] = ok ? stop[s] : pos;
+                    }
                     C[s][0] = fmaf(c.x, wgt, C[s][0]);
                     C[s][1] = fmaf(c.y, wgt, C[s][1]);
                     C[s][2] = fmaf(c.z, wgt, C[s][2]);
-                    T[s] = ok ? tn : T[s];
-                    last[s] = ok ? pos : last[s];
-                    fy[s] = ok ? fy[s] : kDone;
-                    if (STATS) stop[s] = ok ? stop[s] : pos;
+                    T[s] = tn;
+                    last[s] = lp;
                 }
             }
-            if ((k & 7u) == 7u &&
-                !__ballot(fy[0] < kDone || fy[1] < kDone || fy[2] < kDone || fy[3] < kDone)) {
-                live = false;
-                break;
+            if ((k & 7u) == 7u) {
+                uint32_t now = 0;
+#pragma unroll
+                for (int s = 0; s < 4; ++s) now |= (__ballot(fy[s] < kDone) != 0ull ? 1u : 0u) << s;
+                sl &= now;
+                if (!sl) break;
             }
         }
         __syncthreads();

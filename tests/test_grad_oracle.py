@@ -107,3 +107,42 @@ def test_autograd_equals_finite_differences():
         checked += 1
     assert checked >= 120, (checked, skipped)
     print(f"checked {checked}, skipped {skipped}, worst relative error {worst:.2e}")
+
+
+def _fma32_exact(a, b, c):
+    """Correctly rounded (to nearest, ties to even) FP32 value of a*b + c,
+    from exact rational arithmetic."""
+    from fractions import Fraction
+    x = Fraction(float(a)) * Fraction(float(b)) + Fraction(float(c))
+    guess = np.float32(float(x))
+    cands = [np.nextafter(guess, np.float32(-np.inf)), guess,
+             np.nextafter(guess, np.float32(np.inf))]
+    best = min(cands, key=lambda v: (abs(Fraction(float(v)) - x),
+                                     int(np.array(v).view(np.int32)) & 1))
+    return np.float32(best)
+
+
+def test_fma32_is_correctly_rounded():
+    """The FP32 fused multiply-add of the gradient oracle against exact rational
+    rounding and against the C library's fmaf, including near-cancellation and
+    exact-tie inputs."""
+    import ctypes
+    import ctypes.util
+    libm = ctypes.CDLL(ctypes.util.find_library("m"))
+    libm.fmaf.argtypes = [ctypes.c_float] * 3
+    libm.fmaf.restype = ctypes.c_float
+    rng = np.random.default_rng(12)
+    cases = []
+    for _ in range(3000):
+        a, b = rng.standard_normal(2).astype(np.float32) * np.float32(rng.choice([1e-3, 1, 1e3]))
+        c = np.float32(-(np.float64(a) * np.float64(b)) * (1 + rng.standard_normal() * 1e-6))
+        cases.append((a, b, c))                                  # near cancellation
+        cases.append((a, b, np.float32(rng.standard_normal() * 10)))
+    # a*b + c exactly halfway between two FP32 values (ties to even)
+    cases.append((np.float32(1 + 2 ** -12), np.float32(1 + 2 ** -12), np.float32(-1.0)))
+    cases.append((np.float32(1.0), np.float32(2 ** -24), np.float32(1.0)))
+    cases.append((np.float32(1.0), np.float32(3 * 2 ** -24), np.float32(1.0)))
+    for a, b, c in cases:
+        got = og.fma32(a, b, c)
+        assert got == _fma32_exact(a, b, c), (a, b, c)
+        assert got == np.float32(libm.fmaf(float(a), float(b), float(c))), (a, b, c)
