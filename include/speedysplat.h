@@ -117,6 +117,10 @@ typedef struct ss_frame {
     uint32_t *order;        /* [2n]  after ss_depth_order, [0, n) holds the Gaussians
                                sorted by (depth key, index); [n, 2n) is scratch */
     uint32_t *order_tmp;    /* [order_tmp_words] scratch of ss_depth_order */
+    uint32_t *tile_sets;    /* [n,4] per Gaussian, written by the preprocess stage: when
+                               its tile rectangle fits 8 x 8 tiles, the 64-bit mask
+                               (words 0-1, bit r * 8 + c = tile (x0 + c, y0 + r)) and
+                               x0 | y0 << 16 (word 2); mask 0 otherwise */
     uint32_t *offsets;      /* [n]   inclusive prefix sum of counts in depth order */
     uint64_t *scan_tmp;     /* [scan_tmp_words]; word 0 receives the pair count P */
     uint32_t *ranges;       /* [n_tiles, 2] per-tile [start, end) into the sorted pairs */
@@ -211,7 +215,7 @@ int ss_sort_tmp_words(uint64_t capacity, int64_t *out_words);
  * Stage 1, preprocess (Sec. 3.2.1 and Sec. 4.1): for every Gaussian, the record
  * (projection, Sigma_3D = R S S^T R^T, EWA Sigma_2D + 0.3 I, conic, t, SH
  * colour) and its tile count under `mode`.  Writes frame->geom, conic, rgb,
- * counts and depth_keys[0, n).
+ * counts, tile_sets and depth_keys[0, n).
  */
 int ss_preprocess(const ss_camera *cam, const ss_gaussians *g, int32_t mode,
                   const ss_frame *frame, void *stream);
@@ -233,8 +237,8 @@ int ss_scan(int64_t n, const ss_frame *frame, void *stream);
 
 /*
  * Stage 3, key emission (Sec. 3.2.2, "duplicateWithKeys"; Alg. 1 "Process"):
- * for each depth-order entry j, Gaussian i = order[j] writes its tiles, in its
- * tile-enumeration order, at [offsets[j] - counts[i], offsets[j]) of
+ * for each depth-order entry j, Gaussian i = order[j] writes its tiles (in an
+ * unspecified order) at [offsets[j] - counts[i], offsets[j]) of
  * pairs->keys[buf] (tile id) / values[buf] (i).  n_pairs must be the P the
  * scan produced and <= pairs->capacity.
  */
@@ -278,7 +282,21 @@ int ss_forward_begin(const ss_camera *cam, const ss_gaussians *g, int32_t mode,
                      const ss_stage_events *events, void *stream);
 
 /*
- * Stages 3-6 for the P returned by ss_forward_begin.  Returns
+ * Stages 1, 2a and 2b like ss_forward_begin, without waiting: the pair count
+ * P is copied into the HOST word *n_pairs_host by a copy enqueued on `stream`
+ * after the scan, and the call returns at once.  *n_pairs_host is valid once
+ * the stream has passed that copy (synchronise an event recorded after this
+ * call).  Pinned host memory (hipHostMalloc) keeps the copy asynchronous.  The
+ * caller then grows the pair workspace if needed and calls ss_forward_finish;
+ * meanwhile it may enqueue other frames' work, e.g. the next frame's stages
+ * 1-2b into a second ss_frame, so that the GPU never waits for the host.
+ */
+int ss_forward_begin_async(const ss_camera *cam, const ss_gaussians *g, int32_t mode,
+                           const ss_frame *frame, uint64_t *n_pairs_host,
+                           const ss_stage_events *events, void *stream);
+
+/*
+ * Stages 3-6 for the P returned by ss_forward_begin (or ss_forward_begin_async).  Returns
  * SS_ERR_WORKSPACE if pairs->capacity < n_pairs.  *out_buf (may be NULL)
  * receives the pair buffer holding the sorted pairs.  `events` may be NULL.
  */

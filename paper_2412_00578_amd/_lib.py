@@ -44,7 +44,8 @@ class SSGaussians(ctypes.Structure):
 
 class SSFrame(ctypes.Structure):
     _fields_ = [("geom", _vp), ("conic", _vp), ("rgb", _vp), ("counts", _vp),
-                ("depth_keys", _vp), ("order", _vp), ("order_tmp", _vp), ("offsets", _vp),
+                ("depth_keys", _vp), ("order", _vp), ("order_tmp", _vp), ("tile_sets", _vp),
+                ("offsets", _vp),
                 ("scan_tmp", _vp), ("ranges", _vp), ("t_final", _vp), ("n_last", _vp),
                 ("n_eval", _vp), ("emit_tmp", _vp), ("table", _vp)]
 
@@ -100,6 +101,8 @@ PROTOTYPES = {
     "ss_blend": [_P(SSCamera), _P(SSFrame), _P(SSPairs), ctypes.c_int32, _vp, _vp],
     "ss_forward_begin": [_P(SSCamera), _P(SSGaussians), ctypes.c_int32, _P(SSFrame),
                          _P(ctypes.c_uint64), _P(SSStageEvents), _vp],
+    "ss_forward_begin_async": [_P(SSCamera), _P(SSGaussians), ctypes.c_int32, _P(SSFrame),
+                               _vp, _P(SSStageEvents), _vp],
     "ss_forward_finish": [_P(SSCamera), ctypes.c_int64, ctypes.c_int32, _P(SSFrame),
                           _P(SSPairs), ctypes.c_uint64, _vp, _P(ctypes.c_int32),
                           _P(SSStageEvents), _vp],

@@ -75,9 +75,10 @@ int check_mode(int32_t mode) {
 int check_frame_records(const ss_frame* f, int64_t n) {
     if (!f) return fail(SS_ERR_INVALID_ARG, "frame is NULL");
     if (n > 0 && (!f->geom || !f->conic || !f->rgb || !f->counts || !f->offsets || !f->emit_tmp ||
-                  !f->depth_keys || !f->order || !f->order_tmp))
+                  !f->depth_keys || !f->order || !f->order_tmp || !f->tile_sets))
         return fail(SS_ERR_INVALID_ARG, "a per-Gaussian frame buffer is NULL");
-    if (!aligned16(f->geom) || !aligned16(f->conic) || !aligned16(f->rgb))
+    if (!aligned16(f->geom) || !aligned16(f->conic) || !aligned16(f->rgb) ||
+        !aligned16(f->tile_sets))
         return fail(SS_ERR_INVALID_ARG, "frame records must be 16-byte aligned");
     if (!f->scan_tmp) return fail(SS_ERR_INVALID_ARG, "frame scan_tmp is NULL");
     return SS_OK;
@@ -193,8 +194,10 @@ int check_table(const ss_frame* f) {
     return SS_OK;
 }
 
+// Stages 1-2b.  sync: wait for P and store it in *n_pairs_out; otherwise
+// enqueue its copy into the host word *n_pairs_out and return.
 int begin_impl(const Layout& L, int32_t mode, const ss_frame* f, uint64_t* n_pairs_out,
-               const ss_stage_events* ev, hipStream_t s) {
+               const ss_stage_events* ev, bool sync, hipStream_t s) {
     SS_TRY(check_mode(mode));
     SS_TRY(check_frame_records(f, L.d.n_slots));
     SS_TRY(check_table(f));
@@ -208,6 +211,10 @@ int begin_impl(const Layout& L, int32_t mode, const ss_frame* f, uint64_t* n_pai
     record(ev, 2, s);
     SS_TRY(hip_status(ss::launch_scan(L.d.n_slots, *f, s), "scan"));
     record(ev, 3, s);
+    if (!sync)
+        return hip_status(hipMemcpyAsync(n_pairs_out, f->scan_tmp, sizeof(uint64_t),
+                                         hipMemcpyDeviceToHost, s),
+                          "copy pair count");
     uint64_t p = 0;
     SS_TRY(hip_status(hipMemcpyAsync(&p, f->scan_tmp, sizeof(p), hipMemcpyDeviceToHost, s),
                       "read pair count"));
@@ -384,7 +391,17 @@ int ss_forward_begin(const ss_camera* cam, const ss_gaussians* g, int32_t mode, 
                      uint64_t* n_pairs_out, const ss_stage_events* ev, void* stream) {
     SS_TRY(check_camera(cam));
     SS_TRY(check_gaussians(g));
-    return begin_impl(single_layout(*cam, *g), mode, f, n_pairs_out, ev, (hipStream_t)stream);
+    return begin_impl(single_layout(*cam, *g), mode, f, n_pairs_out, ev, true,
+                      (hipStream_t)stream);
+}
+
+int ss_forward_begin_async(const ss_camera* cam, const ss_gaussians* g, int32_t mode,
+                           const ss_frame* f, uint64_t* n_pairs_host, const ss_stage_events* ev,
+                           void* stream) {
+    SS_TRY(check_camera(cam));
+    SS_TRY(check_gaussians(g));
+    return begin_impl(single_layout(*cam, *g), mode, f, n_pairs_host, ev, false,
+                      (hipStream_t)stream);
 }
 
 int ss_forward_finish(const ss_camera* cam, int64_t n, int32_t mode, const ss_frame* f,
@@ -430,7 +447,7 @@ int ss_batch_begin(const ss_batch_item* items, int32_t n_items, int32_t mode, co
     SS_TRY(lay_out(items, n_items, L));
     for (int k = 0; k < n_items; ++k)
         if (!items[k].out_rgb) return fail(SS_ERR_INVALID_ARG, "item %d has no out_rgb", k);
-    return begin_impl(L, mode, f, n_pairs_out, ev, (hipStream_t)stream);
+    return begin_impl(L, mode, f, n_pairs_out, ev, true, (hipStream_t)stream);
 }
 
 int ss_batch_finish(const ss_batch_item* items, int32_t n_items, int32_t mode, const ss_frame* f,

@@ -2,23 +2,24 @@
 // "Process" step of Alg. 1).
 //
 // Entries are taken in depth order: entry j is Gaussian i = order[j], whose
-// tiles, re-walked with the same FP64 function the preprocess stage counted
-// with, go to [offsets[j] - counts[i], offsets[j]) as key = tile id, value = i.
+// tiles go to [offsets[j] - counts[i], offsets[j]) as key = tile id, value = i.
 // The emitted pairs are therefore sorted by (depth, index), and a stable sort
-// on the tile id alone yields the paper's (tile | depth) order.
+// on the tile id alone yields the paper's (tile | depth) order.  The order of
+// one Gaussian's own pairs (distinct tiles) does not matter.
 //
 // Tile counts are heavy-tailed (most Gaussians touch a few tiles, a Gaussian
 // near the camera thousands), so the work is split in two launches:
-//   k_emit      one lane per entry with <= 32 tiles: each lane writes its tile
-//               ids to the wave's LDS stage, then the wave copies the stage to
-//               the pair buffers with consecutive lanes on consecutive
-//               addresses; entries with more tiles are queued (one atomic per
-//               wave);
-//   k_emit_big  one wave per queued entry: lanes compute up to 64 spans
-//               (rows, or columns for AccuTile on tall extents) at once, a wave
-//               prefix sum places them, and the wave writes the keys with
-//               consecutive lanes on consecutive addresses.
-// The emission order within a Gaussian is the same in both paths.
+//   k_emit      one lane per entry whose tile set the preprocess stage stored
+//               as a mask (tile rectangle within 8 x 8) with <= 32 tiles: each
+//               lane expands its mask into its wave's LDS stage, then the wave
+//               copies the stage to the pair buffers with consecutive lanes on
+//               consecutive addresses.  Other entries are queued (one atomic
+//               per wave);
+//   k_emit_big  one wave per queued entry re-walks the FP64 tile spans of the
+//               record: lanes compute up to 64 spans (rows, or columns for
+//               AccuTile on tall extents) at once, a wave prefix sum places
+//               them, and the wave writes the keys with consecutive lanes on
+//               consecutive addresses.
 #include "ss_internal.h"
 
 namespace ss {
@@ -27,10 +28,6 @@ namespace {
 constexpr uint32_t kSmall = 32;
 constexpr int kBigBlock = 256;
 constexpr int kBigGrid = 1024;
-
-__device__ __forceinline__ bool span_columns(const Ellipse& e, int mode) {
-    return mode == SS_TILE_ACCUTILE && (e.y1 - e.y0 > e.x1 - e.x0);
-}
 
 __global__ void k_zero(uint32_t* p) { *p = 0u; }
 
@@ -56,9 +53,8 @@ constexpr int kEmitWaves = kEmitBlock / 64;
 constexpr int kStage = 64 * (int)kSmall;     // tile ids one wave can stage
 
 __global__ __launch_bounds__(kEmitBlock) void k_emit(const Item* __restrict__ items,
-                                                     BatchDims dims, int mode, uint32_t limit,
-                                                     const float4* __restrict__ geom,
-                                                     const float4* __restrict__ conic,
+                                                     BatchDims dims, uint32_t limit,
+                                                     const uint4* __restrict__ tsets,
                                                      const uint32_t* __restrict__ order,
                                                      const uint32_t* __restrict__ offsets,
                                                      uint32_t* __restrict__ keys,
@@ -76,16 +72,20 @@ __global__ __launch_bounds__(kEmitBlock) void k_emit(const Item* __restrict__ it
     uint32_t prev = __shfl_up(end, 1, 64);
     if (lane == 0) prev = (valid && j > 0) ? offsets[j - 1] : 0u;
     const uint32_t cnt = valid ? end - prev : 0u;
-    const bool big = cnt > kSmall;
-    const uint64_t mask = __ballot(big);
-    if (mask) {
-        const int leader = __builtin_ctzll(mask);
+    const uint32_t gid = cnt ? order[j] : 0u;
+    uint4 ts = make_uint4(0u, 0u, 0u, 0u);
+    if (cnt) ts = tsets[gid];
+    const uint64_t mask = (uint64_t)ts.x | ((uint64_t)ts.y << 32);
+    const bool big = cnt > kSmall || (cnt && mask == 0ull);
+    const uint64_t bigs = __ballot(big);
+    if (bigs) {
+        const int leader = __builtin_ctzll(bigs);
         uint32_t base = 0;
-        if (lane == leader) base = atomicAdd(queue, (uint32_t)__popcll(mask));
+        if (lane == leader) base = atomicAdd(queue, (uint32_t)__popcll(bigs));
         base = __shfl(base, leader, 64);
         const uint32_t slot = base + __builtin_amdgcn_mbcnt_hi(
-                                         (uint32_t)(mask >> 32),
-                                         __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+                                         (uint32_t)(bigs >> 32),
+                                         __builtin_amdgcn_mbcnt_lo((uint32_t)bigs, 0u));
         if (big && slot < (uint32_t)dims.n_slots) queue[1 + slot] = (uint32_t)j;
     }
     const uint32_t small = big ? 0u : cnt;
@@ -93,27 +93,20 @@ __global__ __launch_bounds__(kEmitBlock) void k_emit(const Item* __restrict__ it
     const uint32_t total = __shfl(incl, 63, 64);
     if (total == 0u) return;                      // wave-uniform; no workgroup barrier follows
     const uint32_t pre = incl - small;
-    const uint32_t gid = small ? order[j] : 0u;
     s_pre[w][lane] = pre;
     s_pos[w][lane] = prev;
     s_gid[w][lane] = gid;
     if (small) {
         const Item& it = items[dims.n_items == 1 ? 0 : item_of_slot(items, dims.n_items, gid)];
-        const int tx_n = it.tx_n, ty_n = it.ty_n;
-        const uint32_t tile_off = (uint32_t)it.tile_off;
-        Ellipse e;
-        if (ellipse_setup(geom[gid], conic[gid], mode, tx_n, ty_n, e)) {
-            const bool cols = span_columns(e, mode);
-            uint32_t p = pre;
-            const uint32_t stop = pre + small;    // never past the lane's own share
-            for_each_span(e, mode, tx_n, ty_n, [&](int major, int lo, int hi) {
-                for (int k = lo; k <= hi; ++k) {
-                    if (p < stop)
-                        s_tile[w][p] = tile_off + (cols ? (uint32_t)(k * tx_n + major)
-                                                        : (uint32_t)(major * tx_n + k));
-                    ++p;
-                }
-            });
+        const uint32_t tx_n = (uint32_t)it.tx_n, tile_off = (uint32_t)it.tile_off;
+        const uint32_t x0 = ts.z & 0xffffu, y0 = ts.z >> 16;
+        uint64_t m = mask;
+        uint32_t p = pre;
+        const uint32_t stop = pre + small;        // never past the lane's own share
+        while (m && p < stop) {
+            const uint32_t b = (uint32_t)__builtin_ctzll(m);
+            m &= m - 1ull;
+            s_tile[w][p++] = tile_off + (y0 + b / kSetSide) * tx_n + x0 + b % kSetSide;
         }
     }
     wave_lds_sync();
@@ -247,10 +240,9 @@ hipError_t launch_emit(const Item* items, const BatchDims& d, int mode, const ss
     if (d.n_slots == 0) return hipSuccess;
     hipLaunchKernelGGL(k_zero, dim3(1), dim3(1), 0, s, f.emit_tmp);
     const int64_t grid = (d.n_slots + kEmitBlock - 1) / kEmitBlock;
-    hipLaunchKernelGGL(k_emit, dim3((unsigned)grid), dim3(kEmitBlock), 0, s, items, d, mode,
-                       (uint32_t)n_pairs, reinterpret_cast<const float4*>(f.geom),
-                       reinterpret_cast<const float4*>(f.conic), f.order, f.offsets, keys,
-                       values, f.emit_tmp);
+    hipLaunchKernelGGL(k_emit, dim3((unsigned)grid), dim3(kEmitBlock), 0, s, items, d,
+                       (uint32_t)n_pairs, reinterpret_cast<const uint4*>(f.tile_sets), f.order,
+                       f.offsets, keys, values, f.emit_tmp);
     hipLaunchKernelGGL(k_emit_big, dim3(kBigGrid), dim3(kBigBlock), 0, s, items, d, mode,
                        (uint32_t)n_pairs, (uint32_t)d.n_slots,
                        reinterpret_cast<const float4*>(f.geom),

@@ -3,8 +3,10 @@
 //
 // One lane per Gaussian.  The screen-space geometry is FP64 over the FP32
 // inputs and is rounded once into the FP32 record; the tile count is then an
-// FP64 function of the stored record (the same function the emit stage runs),
-// so counts and emitted pairs agree by construction.  The colour is FP32.
+// FP64 function of the stored record.  A record whose tile rectangle fits 8 x 8
+// tiles also stores its tile set as a bit mask, which the emit stage expands;
+// the emit stage re-walks the same FP64 function for the others, so counts and
+// emitted pairs agree by construction.  The colour is FP32.
 #include "ss_internal.h"
 
 namespace ss {
@@ -78,7 +80,8 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(const Item* __restrict__ 
                                                        float4* __restrict__ conic,
                                                        float4* __restrict__ rgb_out,
                                                        uint32_t* __restrict__ counts,
-                                                       uint32_t* __restrict__ dkeys) {
+                                                       uint32_t* __restrict__ dkeys,
+                                                       uint4* __restrict__ tsets) {
     __shared__ float s_sh[kBlock * kShPitch];
     const int64_t slot0 = (int64_t)blockIdx.x * kBlock;
     const Item& it = items[dims.n_items == 1 ? 0 : item_of_slot(items, dims.n_items, slot0)];
@@ -97,6 +100,7 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(const Item* __restrict__ 
     if (i >= n) {  // padding slot between items
         geom[o] = zero; conic[o] = zero; rgb_out[o] = zero; counts[o] = 0u;
         dkeys[o] = kCulledKey;
+        tsets[o] = make_uint4(0u, 0u, 0u, 0u);
         return;
     }
 
@@ -125,6 +129,7 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(const Item* __restrict__ 
     if (!ok) {
         geom[o] = zero; conic[o] = zero; rgb_out[o] = zero; counts[o] = 0u;
         dkeys[o] = kCulledKey;
+        tsets[o] = make_uint4(0u, 0u, 0u, 0u);
         return;
     }
     const double fx = cam.fx, fy = cam.fy;
@@ -192,6 +197,7 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(const Item* __restrict__ 
     if (!(D > 0.0) || (mode != SS_TILE_3SIGMA && !(tt > 0.0f))) {
         geom[o] = zero; conic[o] = zero; rgb_out[o] = zero; counts[o] = 0u;
         dkeys[o] = kCulledKey;
+        tsets[o] = make_uint4(0u, 0u, 0u, 0u);
         return;
     }
 
@@ -244,9 +250,12 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(const Item* __restrict__ 
     geom[o] = g4;
     conic[o] = q4;
     rgb_out[o] = make_float4(cr, cg, cbl, 0.0f);
-    const uint32_t cnt = count_tiles(g4, q4, mode, tx_n, ty_n);
+    uint64_t mask;
+    uint32_t origin;
+    const uint32_t cnt = tile_set(g4, q4, mode, tx_n, ty_n, &mask, &origin);
     counts[o] = cnt;
     dkeys[o] = cnt ? __float_as_uint(g4.z) : kCulledKey;
+    tsets[o] = make_uint4((uint32_t)mask, (uint32_t)(mask >> 32), origin, 0u);
 }
 
 }  // namespace
@@ -257,7 +266,8 @@ hipError_t launch_preprocess(const Item* items, const BatchDims& d, int mode, co
     const int64_t grid = (d.n_slots + kBlock - 1) / kBlock;
     hipLaunchKernelGGL(k_preprocess, dim3((unsigned)grid), dim3(kBlock), 0, s, items, d, mode,
                        reinterpret_cast<float4*>(f.geom), reinterpret_cast<float4*>(f.conic),
-                       reinterpret_cast<float4*>(f.rgb), f.counts, f.depth_keys);
+                       reinterpret_cast<float4*>(f.rgb), f.counts, f.depth_keys,
+                       reinterpret_cast<uint4*>(f.tile_sets));
     return hipGetLastError();
 }
 

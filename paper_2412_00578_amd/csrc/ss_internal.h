@@ -163,11 +163,43 @@ __device__ __forceinline__ bool for_each_span(const Ellipse& e, int mode, int tx
     return true;
 }
 
-__device__ __forceinline__ uint32_t count_tiles(float4 g, float4 q, int mode, int tx_n, int ty_n) {
+// AccuTile walks columns when the tile extent has more rows than columns.
+__device__ __forceinline__ bool span_columns(const Ellipse& e, int mode) {
+    return mode == SS_TILE_ACCUTILE && (e.y1 - e.y0 > e.x1 - e.x0);
+}
+
+// Side of the tile window a tile set records: a record whose tile rectangle
+// fits kSetSide x kSetSide tiles stores its tiles as a bit mask over that
+// window, bit r * kSetSide + c for tile (x0 + c, y0 + r).
+constexpr int kSetSide = 8;
+
+// Counts the record's tiles under `mode` and, when its tile rectangle fits the
+// window, records them: *mask gets the bits, *origin = x0 | y0 << 16.
+// Otherwise *mask = 0 (the emit stage re-walks the spans).
+__device__ __forceinline__ uint32_t tile_set(float4 g, float4 q, int mode, int tx_n, int ty_n,
+                                             uint64_t* mask, uint32_t* origin) {
+    *mask = 0ull;
+    *origin = 0u;
     Ellipse e;
     if (!ellipse_setup(g, q, mode, tx_n, ty_n, e)) return 0u;
+    const bool fits = e.x1 - e.x0 < kSetSide && e.y1 - e.y0 < kSetSide;
+    const bool cols = span_columns(e, mode);
     uint32_t n = 0;
-    for_each_span(e, mode, tx_n, ty_n, [&](int, int lo, int hi) { n += (uint32_t)(hi - lo + 1); });
+    uint64_t m = 0ull;
+    for_each_span(e, mode, tx_n, ty_n, [&](int major, int lo, int hi) {
+        n += (uint32_t)(hi - lo + 1);
+        if (!fits) return;
+        if (!cols) {
+            const uint64_t run = (1ull << (hi - lo + 1)) - 1ull;
+            m |= run << ((major - e.y0) * kSetSide + (lo - e.x0));
+        } else {
+            for (int r = lo; r <= hi; ++r) m |= 1ull << ((r - e.y0) * kSetSide + (major - e.x0));
+        }
+    });
+    if (fits) {
+        *mask = m;
+        *origin = (uint32_t)e.x0 | ((uint32_t)e.y0 << 16);
+    }
     return n;
 }
 

@@ -92,6 +92,7 @@ class Frame:
         self.depth_keys = torch.empty(2 * n, dtype=torch.int32, device=dev)
         self.order = torch.empty(2 * n, dtype=torch.int32, device=dev)
         self.order_tmp = torch.empty(int(info.order_tmp_words), dtype=torch.int32, device=dev)
+        self.tile_sets = torch.empty((n, 4), dtype=torch.int32, device=dev)
         self.offsets = torch.empty(n, dtype=torch.int32, device=dev)
         self.scan_tmp = torch.zeros(int(info.scan_tmp_words), dtype=torch.int64, device=dev)
         self.ranges = torch.empty((info.n_tiles, 2), dtype=torch.int32, device=dev)
@@ -105,8 +106,8 @@ class Frame:
     def struct(self) -> _lib.SSFrame:
         f = _lib.SSFrame()
         for name in ("geom", "conic", "rgb", "counts", "depth_keys", "order", "order_tmp",
-                     "offsets", "scan_tmp", "ranges", "t_final", "n_last", "n_eval", "emit_tmp",
-                     "table"):
+                     "tile_sets", "offsets", "scan_tmp", "ranges", "t_final", "n_last", "n_eval",
+                     "emit_tmp", "table"):
             t = getattr(self, name)
             setattr(f, name, t.data_ptr() if t is not None else None)
         return f
@@ -186,6 +187,8 @@ class Renderer:
         self.stats = stats
         self._frame: Frame | None = None
         self._pairs: Pairs | None = None
+        self._ring: list = [None, None]          # frames of render_many
+        self._host_p: torch.Tensor | None = None
 
     def frame_for(self, n, width, height) -> Frame:
         if self._frame is None or not self._frame.fits(n, width, height, self.stats):
@@ -225,6 +228,59 @@ class Renderer:
         if full:
             return RenderOutput(out, int(n_pairs.value), frame, pairs, int(buf.value))
         return out
+
+    def _ring_frame(self, s, n, width, height) -> Frame:
+        f = self._ring[s]
+        if f is None or not f.fits(n, width, height, self.stats):
+            self._ring[s] = None
+            self._ring[s] = f = Frame(n, width, height, self.device, self.stats)
+        return f
+
+    def render_many(self, g: Gaussians, cams, mode="accutile", outs=None) -> list:
+        """Renders one frame per camera, keeping the host one frame ahead of the
+        GPU: frame k+1's preprocess, depth order and scan are enqueued (into the
+        second of two frame buffers) before frame k's emit, sort, ranges and
+        blend, and each pair count comes back by an asynchronous copy, so the
+        GPU never idles waiting for the host between frames.  Every frame is
+        rendered completely; the images are valid once the stream syncs."""
+        m = mode_id(mode)
+        cs = [make_camera(c) for c in cams]
+        if outs is None:
+            outs = [torch.empty((3, c.height, c.width), dtype=torch.float32, device=self.device)
+                    for c in cs]
+        if not cs:
+            return outs
+        st = torch.cuda.current_stream(self.device)
+        sp = ctypes.c_void_p(st.cuda_stream)
+        gs = g.struct()
+        if self._host_p is None:
+            self._host_p = torch.zeros(2, dtype=torch.int64, pin_memory=True)
+        host = self._host_p
+        ready = [torch.cuda.Event(), torch.cuda.Event()]
+        fss = [None, None]
+
+        def begin(k):
+            s = k % 2
+            fss[s] = self._ring_frame(s, g.n, cs[k].width, cs[k].height).struct()
+            check(lib().ss_forward_begin_async(ctypes.byref(cs[k]), ctypes.byref(gs), m,
+                                               ctypes.byref(fss[s]),
+                                               ctypes.c_void_p(host.data_ptr() + 8 * s), None,
+                                               sp), "ss_forward_begin_async")
+            ready[s].record(st)
+
+        begin(0)
+        buf = ctypes.c_int32()
+        for k in range(len(cs)):
+            if k + 1 < len(cs):
+                begin(k + 1)
+            s = k % 2
+            ready[s].synchronize()
+            n_pairs = int(host[s])
+            ps = self.pairs_for(n_pairs).struct()
+            check(lib().ss_forward_finish(ctypes.byref(cs[k]), g.n, m, ctypes.byref(fss[s]),
+                                          ctypes.byref(ps), n_pairs, _ptr(outs[k]),
+                                          ctypes.byref(buf), None, sp), "ss_forward_finish")
+        return outs
 
     # ---- single stages (for tests and profiling) ---------------------------
     def preprocess(self, g: Gaussians, cam, mode) -> Frame:
@@ -373,6 +429,7 @@ class BatchFrame:
         self.depth_keys = torch.empty(2 * ns, dtype=torch.int32, device=dev)
         self.order = torch.empty(2 * ns, dtype=torch.int32, device=dev)
         self.order_tmp = torch.empty(int(info.order_tmp_words), dtype=torch.int32, device=dev)
+        self.tile_sets = torch.empty((ns, 4), dtype=torch.int32, device=dev)
         self.offsets = torch.empty(ns, dtype=torch.int32, device=dev)
         self.scan_tmp = torch.zeros(int(info.scan_tmp_words), dtype=torch.int64, device=dev)
         self.ranges = torch.empty((max(int(info.n_tiles), 1), 2), dtype=torch.int32, device=dev)
@@ -388,7 +445,7 @@ class BatchFrame:
     def nbytes(self) -> int:
         return sum(t.numel() * t.element_size() for t in
                    (self.geom, self.conic, self.rgb, self.counts, self.depth_keys, self.order,
-                    self.order_tmp, self.offsets, self.scan_tmp, self.ranges, self.t_final,
+                    self.order_tmp, self.tile_sets, self.offsets, self.scan_tmp, self.ranges, self.t_final,
                     self.n_last, self.emit_tmp, self.table))
 
 

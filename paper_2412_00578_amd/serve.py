@@ -219,10 +219,10 @@ class GpuBackend:
         n = self.scenes[r.scene].n
         px = int(r.cam.width) * int(r.cam.height)
         est = self.pairs_per.get(self._key(r), 4 * n)
-        # records, counts, depth keys, order, offsets and queue: 76 B per slot;
-        # image and per-pixel state 20 B per pixel; 16 B per pair (two buffers)
-        # with the 1.25 growth; sort scratch
-        return int(80 * n + 32 * px + 16 * 1.25 * est + (3 << 20))
+        # records, counts, tile sets, depth keys, order, offsets and queue: 92 B
+        # per slot; image and per-pixel state 20 B per pixel; 16 B per pair (two
+        # buffers) with the 1.25 growth; sort scratch
+        return int(96 * n + 32 * px + 16 * 1.25 * est + (3 << 20))
 
     def sync_reference(self, clock):
         """Ties GPU event times to the scheduler clock."""

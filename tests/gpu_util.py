@@ -23,6 +23,8 @@ def gpu_stages(renderer, g, cam, mode):
         "conic": frame.conic.cpu().numpy().copy(),
         "rgb": frame.rgb.cpu().numpy().copy(),
         "counts": u32(frame.counts).copy(),
+        "tile_sets": u32(frame.tile_sets).copy(),
+        "tiles_x": int(cam.tiles_x),
     }
     out["depth_keys"] = u32(frame.depth_keys[:frame.n]).copy()
     out["order"] = u32(renderer.depth_order(frame)).copy()
@@ -81,6 +83,42 @@ def expected_order(dkeys: np.ndarray) -> np.ndarray:
     return np.lexsort((np.arange(len(dkeys)), dkeys)).astype(np.uint32)
 
 
+def segment_sorted(keys, counts_in_order):
+    """Keys with each Gaussian's run (lengths counts_in_order) sorted: the order
+    of a Gaussian's own pairs is unspecified."""
+    c = counts_in_order.astype(np.int64)
+    seg = np.repeat(np.arange(len(c)), c)
+    return keys[np.lexsort((keys, seg))]
+
+
+def assert_tile_sets(tsets, fr, tiles_x):
+    """Every stored tile mask expands to exactly the oracle's tile list, and a
+    Gaussian without a mask has a tile rectangle wider or taller than 8."""
+    counts = fr.records.counts.astype(np.int64)
+    mask = tsets[:, 0].astype(np.uint64) | (tsets[:, 1].astype(np.uint64) << np.uint64(32))
+    x0, y0 = (tsets[:, 2] & 0xFFFF).astype(np.int64), (tsets[:, 2] >> 16).astype(np.int64)
+    has = mask != 0
+    assert not np.any(has & (counts == 0))
+    # oracle tiles, each Gaussian's run ascending
+    tiles = segment_sorted((fr.keys >> np.uint64(32)).astype(np.int64), counts)
+    owner = np.repeat(np.arange(len(counts)), counts)
+    # masked Gaussians: bits in ascending order give ascending tile ids
+    g, b = np.nonzero(((mask[has, None] >> np.arange(64, dtype=np.uint64)) & np.uint64(1)) != 0)
+    gi = np.nonzero(has)[0][g]
+    got = (y0[gi] + b // 8) * tiles_x + x0[gi] + b % 8
+    assert np.array_equal(got, tiles[has[owner]])
+    # unmasked Gaussians with tiles: their tile extent exceeds 8 on a side
+    rest = (~has) & (counts > 0)
+    sel = rest[owner]
+    if sel.any():
+        t, o = tiles[sel], owner[sel]
+        first = np.r_[0, np.nonzero(np.diff(o))[0] + 1]
+        tx, ty = t % tiles_x, t // tiles_x
+        wide = (np.maximum.reduceat(tx, first) - np.minimum.reduceat(tx, first) >= 8) | \
+            (np.maximum.reduceat(ty, first) - np.minimum.reduceat(ty, first) >= 8)
+        assert wide.all()
+
+
 def depth_ordered_pairs(fr, order):
     """The oracle's pairs (emitted in index order, each Gaussian's tiles in its
     enumeration order) regrouped Gaussian by Gaussian in `order`: the pairs the
@@ -103,6 +141,7 @@ def assert_pipeline_equal(gpu, fr, image_tol=1e-4):
     them stably by tile.  The expected GPU intermediates are derived from the
     oracle's: the final sorted values and ranges must be identical."""
     assert_records_equal(gpu, fr.records)
+    assert_tile_sets(gpu["tile_sets"], fr, gpu["tiles_x"])
     dk = expected_depth_keys(fr.records)
     assert np.array_equal(gpu["depth_keys"], dk), first_diffs(gpu["depth_keys"], dk)
     order = expected_order(dk)
@@ -110,8 +149,10 @@ def assert_pipeline_equal(gpu, fr, image_tol=1e-4):
     assert gpu["n_pairs"] == fr.n_pairs
     counts = fr.records.counts.astype(np.uint64)
     assert np.array_equal(gpu["offsets"], np.cumsum(counts[order]).astype(np.uint32))
+    cio = counts[order]
     ek, ev = depth_ordered_pairs(fr, order)
-    assert np.array_equal(gpu["keys"], ek), first_diffs(gpu["keys"], ek)
+    gk, ek = segment_sorted(gpu["keys"], cio), segment_sorted(ek, cio)
+    assert np.array_equal(gk, ek), first_diffs(gk, ek)
     assert np.array_equal(gpu["values"], ev), first_diffs(gpu["values"], ev)
     st = (fr.sorted_keys >> np.uint64(32)).astype(np.uint32)
     assert np.array_equal(gpu["sorted_keys"], st), first_diffs(gpu["sorted_keys"], st)

@@ -125,6 +125,21 @@ def test_composite_render_equals_stages(ss, gpu_device, mode):
     assert np.array_equal(out.image.cpu().numpy(), stages["image"])
 
 
+def test_render_many_equals_frame_by_frame(ss, gpu_device):
+    # pipelined frames (two frame buffers, asynchronous pair counts), with a
+    # resolution change and a pair workspace that has to grow mid-sequence
+    sc = scenegen.scene_c2(n=100_000)
+    cams = list(scenegen.cameras_c2(5))
+    cams.insert(2, cams[1].with_size(640, 480))
+    cams.insert(0, cams[0].with_size(64, 48))
+    g = ss.Gaussians.from_scene(sc, gpu_device)
+    imgs = ss.Renderer(gpu_device).render_many(g, cams, "accutile")
+    torch.cuda.synchronize()
+    for k, (cam, img) in enumerate(zip(cams, imgs)):
+        want = ss.Renderer(gpu_device).render(g, cam, "accutile")
+        assert torch.equal(img, want), k
+
+
 def test_forward_is_deterministic(ss, gpu_device):
     sc, cam = scenegen.scene_c2(n=100_000), scenegen.cameras_c2(2)[1]
     r = ss.Renderer(gpu_device)
