@@ -116,6 +116,7 @@ typedef struct ss_frame {
                                tiles); [n, 2n) is scratch of ss_depth_order */
     uint32_t *order;        /* [2n]  after ss_depth_order, [0, n) holds the Gaussians
                                sorted by (depth key, index); [n, 2n) is scratch */
+    uint32_t *order_counts; /* [n]   after ss_depth_order: counts[order[j]] */
     uint32_t *order_tmp;    /* [order_tmp_words] scratch of ss_depth_order */
     uint32_t *tile_sets;    /* [n,4] per Gaussian, written by the preprocess stage: when
                                its tile rectangle fits 8 x 8 tiles, the 64-bit mask
@@ -224,13 +225,14 @@ int ss_preprocess(const ss_camera *cam, const ss_gaussians *g, int32_t mode,
  * Stage 2a, depth order (the depth half of the Sec. 3.2.2 sort key): stable LSD
  * radix sort of the n Gaussians on frame->depth_keys; frame->order[0, n)
  * receives the Gaussian indices by (bits(depth), index), Gaussians without
- * tiles last.  Uses depth_keys[n, 2n), order[n, 2n) and order_tmp as scratch.
+ * tiles last, and frame->order_counts[j] = counts[order[j]].  Uses
+ * depth_keys[n, 2n), order[n, 2n) and order_tmp as scratch.
  */
 int ss_depth_order(int64_t n, const ss_frame *frame, void *stream);
 
 /*
  * Stage 2b, inclusive prefix sum of the tile counts in depth order (Sec. 3.2.2,
- * "InclusiveSum"): frame->offsets[j] = sum_{k <= j} counts[order[k]]; the
+ * "InclusiveSum"): frame->offsets[j] = sum_{k <= j} order_counts[k]; the
  * total P goes to frame->scan_tmp[0] (uint64).
  */
 int ss_scan(int64_t n, const ss_frame *frame, void *stream);

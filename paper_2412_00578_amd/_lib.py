@@ -44,7 +44,8 @@ class SSGaussians(ctypes.Structure):
 
 class SSFrame(ctypes.Structure):
     _fields_ = [("geom", _vp), ("conic", _vp), ("rgb", _vp), ("counts", _vp),
-                ("depth_keys", _vp), ("order", _vp), ("order_tmp", _vp), ("tile_sets", _vp),
+                ("depth_keys", _vp), ("order", _vp), ("order_counts", _vp), ("order_tmp", _vp),
+                ("tile_sets", _vp),
                 ("offsets", _vp),
                 ("scan_tmp", _vp), ("ranges", _vp), ("t_final", _vp), ("n_last", _vp),
                 ("n_eval", _vp), ("emit_tmp", _vp), ("table", _vp)]

@@ -75,7 +75,8 @@ int check_mode(int32_t mode) {
 int check_frame_records(const ss_frame* f, int64_t n) {
     if (!f) return fail(SS_ERR_INVALID_ARG, "frame is NULL");
     if (n > 0 && (!f->geom || !f->conic || !f->rgb || !f->counts || !f->offsets || !f->emit_tmp ||
-                  !f->depth_keys || !f->order || !f->order_tmp || !f->tile_sets))
+                  !f->depth_keys || !f->order || !f->order_counts || !f->order_tmp ||
+                  !f->tile_sets))
         return fail(SS_ERR_INVALID_ARG, "a per-Gaussian frame buffer is NULL");
     if (!aligned16(f->geom) || !aligned16(f->conic) || !aligned16(f->rgb) ||
         !aligned16(f->tile_sets))

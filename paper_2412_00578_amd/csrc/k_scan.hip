@@ -1,7 +1,8 @@
 // Stage 2: inclusive prefix sum of the per-Gaussian tile counts
-// (Speedy-Splat Sec. 3.2.2, "InclusiveSum"), taken in depth order: entry j
-// sums counts[order[j']] for j' <= j, so Gaussian order[j] writes its pairs at
-// [offsets[j] - counts[order[j]], offsets[j]) and the emitted pairs come out
+// (Speedy-Splat Sec. 3.2.2, "InclusiveSum"), taken in depth order: the depth
+// order stage leaves order_counts[j] = counts[order[j]], entry j of the scan
+// sums order_counts[j'] for j' <= j, so Gaussian order[j] writes its pairs at
+// [offsets[j] - order_counts[j], offsets[j]) and the emitted pairs come out
 // sorted by depth.
 //
 // Reduce-then-scan in three launches, so no workgroup ever waits on another:
@@ -31,14 +32,13 @@ __device__ __forceinline__ uint64_t wave_incl_scan(uint64_t x) {
 }
 
 __global__ __launch_bounds__(kBlock) void k_block_sums(const uint32_t* __restrict__ counts,
-                                                       const uint32_t* __restrict__ order,
                                                        int64_t n, uint64_t* __restrict__ tmp) {
     const int64_t base = (int64_t)blockIdx.x * kPerBlock;
     uint64_t s = 0;
 #pragma unroll
     for (int k = 0; k < kItems; ++k) {
         const int64_t i = base + (int64_t)k * kBlock + threadIdx.x;
-        if (i < n) s += counts[order[i]];
+        if (i < n) s += counts[i];
     }
     s = wave_incl_scan(s);
     __shared__ uint64_t wsum[kBlock / 64];
@@ -75,7 +75,6 @@ __global__ __launch_bounds__(1024) void k_scan_partials(uint64_t* __restrict__ t
 }
 
 __global__ __launch_bounds__(kBlock) void k_block_scan(const uint32_t* __restrict__ counts,
-                                                       const uint32_t* __restrict__ order,
                                                        int64_t n, const uint64_t* __restrict__ tmp,
                                                        uint32_t* __restrict__ offsets) {
     // Lane l of the workgroup owns entries [base + l*16, base + l*16 + 16).
@@ -83,7 +82,7 @@ __global__ __launch_bounds__(kBlock) void k_block_scan(const uint32_t* __restric
     const int64_t first = base + (int64_t)threadIdx.x * kItems;
     uint32_t c[kItems];
 #pragma unroll
-    for (int k = 0; k < kItems; ++k) c[k] = (first + k < n) ? counts[order[first + k]] : 0u;
+    for (int k = 0; k < kItems; ++k) c[k] = (first + k < n) ? counts[first + k] : 0u;
     uint64_t s = 0;
 #pragma unroll
     for (int k = 0; k < kItems; ++k) s += c[k];
@@ -108,13 +107,13 @@ int64_t scan_tmp_words(int64_t n) { return 1 + (n + kPerBlock - 1) / kPerBlock; 
 hipError_t launch_scan(int64_t n, const ss_frame& f, hipStream_t s) {
     const int64_t nb = (n + kPerBlock - 1) / kPerBlock;
     if (nb > 0) {
-        hipLaunchKernelGGL(k_block_sums, dim3((unsigned)nb), dim3(kBlock), 0, s, f.counts,
-                           f.order, n, f.scan_tmp);
+        hipLaunchKernelGGL(k_block_sums, dim3((unsigned)nb), dim3(kBlock), 0, s,
+                           f.order_counts, n, f.scan_tmp);
     }
     hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, s, f.scan_tmp, nb);
     if (nb > 0) {
-        hipLaunchKernelGGL(k_block_scan, dim3((unsigned)nb), dim3(kBlock), 0, s, f.counts,
-                           f.order, n, f.scan_tmp, f.offsets);
+        hipLaunchKernelGGL(k_block_scan, dim3((unsigned)nb), dim3(kBlock), 0, s,
+                           f.order_counts, n, f.scan_tmp, f.offsets);
     }
     return hipGetLastError();
 }

@@ -52,6 +52,27 @@ __device__ __forceinline__ uint32_t digit_of(K key, int shift) {
     return (uint32_t)(key >> shift) & (kRadix - 1);
 }
 
+// Lanes of the wave holding the same digit as this lane (among `valid` lanes),
+// found with one ballot per digit bit.
+__device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid) {
+    uint64_t m = __ballot(valid);
+#pragma unroll
+    for (int bit = 0; bit < 8; ++bit) {
+        const bool set = (d >> bit) & 1u;
+        const uint64_t bb = __ballot(set);
+        m &= set ? bb : ~bb;
+    }
+    return m;
+}
+
+__device__ __forceinline__ uint32_t lanes_below(uint64_t m) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// Each wave counts 64 keys at a time: lanes with equal digits are matched and
+// the lowest of them adds the group's size, so a digit shared by many keys
+// costs one LDS atomic per wave instead of one per key.
 template <class K>
 __global__ __launch_bounds__(kBlock) void k_hist(const K* __restrict__ keys, uint64_t n, int shift,
                                                  uint64_t chunk, uint32_t grid,
@@ -62,8 +83,13 @@ __global__ __launch_bounds__(kBlock) void k_hist(const K* __restrict__ keys, uin
     const uint64_t lo = (uint64_t)blockIdx.x * chunk;
     const uint64_t hi = lo + chunk < n ? lo + chunk : n;
     const int w = threadIdx.x >> 6;
-    for (uint64_t i = lo + threadIdx.x; i < hi; i += kBlock)
-        atomicAdd(&h[w][digit_of(keys[i], shift)], 1u);
+    for (uint64_t base = lo; base < hi; base += kBlock) {   // uniform trip count
+        const uint64_t i = base + threadIdx.x;
+        const bool valid = i < hi;
+        const uint32_t d = valid ? digit_of(keys[i], shift) : 0u;
+        const uint64_t m = match_digit(d, valid);
+        if (valid && lanes_below(m) == 0u) atomicAdd(&h[w][d], (uint32_t)__popcll(m));
+    }
     __syncthreads();
     for (int d = threadIdx.x; d < kRadix; d += kBlock) {
         uint32_t s = 0;
@@ -125,14 +151,17 @@ __global__ __launch_bounds__(kBlock) void k_dscan(uint32_t* __restrict__ hist, u
 }
 
 // vals_in == nullptr stands for the identity (value = input position);
-// keys_out == nullptr skips the key writes (a last pass whose keys are unused).
+// keys_out == nullptr skips the key writes (a last pass whose keys are unused);
+// with gather_out, gather_out[p] = gather[value] for every output position p.
 template <class K>
 __global__ __launch_bounds__(kBlock) void k_scatter(const K* __restrict__ keys_in,
                                                     const uint32_t* __restrict__ vals_in,
                                                     K* __restrict__ keys_out,
                                                     uint32_t* __restrict__ vals_out, uint64_t n,
                                                     int shift, uint64_t chunk, uint32_t grid,
-                                                    const uint32_t* __restrict__ hist) {
+                                                    const uint32_t* __restrict__ hist,
+                                                    const uint32_t* __restrict__ gather,
+                                                    uint32_t* __restrict__ gather_out) {
     __shared__ K s_key[kSub];
     __shared__ uint32_t s_val[kSub];
     __shared__ uint32_t base[kRadix];     // global position of this chunk's next key per digit
@@ -171,15 +200,8 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const K* __restrict__ keys_i
             const uint64_t idx = sub + (uint64_t)w * (64 * kItems) + (uint64_t)k * 64 + lane;
             const bool valid = idx < hi;
             const uint32_t d = digit_of(key[k], shift);
-            uint64_t m = __ballot(valid);
-#pragma unroll
-            for (int bit = 0; bit < 8; ++bit) {
-                const bool set = (d >> bit) & 1u;
-                const uint64_t bb = __ballot(set);
-                m &= set ? bb : ~bb;
-            }
-            const uint32_t below = __builtin_amdgcn_mbcnt_hi(
-                (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+            const uint64_t m = match_digit(d, valid);
+            const uint32_t below = lanes_below(m);
             const uint32_t pre = wcnt[w][d];
             rank[k] = pre + below;
             if (valid && below == 0u) wcnt[w][d] = pre + (uint32_t)__popcll(m);
@@ -218,7 +240,9 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const K* __restrict__ keys_i
             const uint32_t pos = base[d] + (i - lstart[d]);
             if (pos < n) {
                 if (keys_out) keys_out[pos] = kk;
-                vals_out[pos] = s_val[i];
+                const uint32_t v = s_val[i];
+                vals_out[pos] = v;
+                if (gather_out) gather_out[pos] = gather[v];
             }
         }
         __syncthreads();
@@ -243,11 +267,12 @@ __global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ key
 // Sorts n (key, value) pairs on the low `bits` key bits, ping-ponging between
 // buffers 0 and 1 from buffer `cur`; *out_buf receives the buffer holding the
 // result.  identity: the input values are 0..n-1 and are not read.  With
-// last_keys false the final pass writes values only.
+// last_keys false the final pass writes values only; with gather_out it also
+// writes gather[value] in the sorted order.
 template <class K>
 hipError_t radix_sort(K* keys[2], uint32_t* vals[2], int cur, uint64_t n, int bits,
-                      uint32_t* tmp, bool identity, bool last_keys, int* out_buf,
-                      hipStream_t s) {
+                      uint32_t* tmp, bool identity, bool last_keys, const uint32_t* gather,
+                      uint32_t* gather_out, int* out_buf, hipStream_t s) {
     if (n > 1) {
         const Plan plan = make_plan(n);
         const int passes = (bits + 7) / 8;
@@ -258,8 +283,10 @@ hipError_t radix_sort(K* keys[2], uint32_t* vals[2], int cur, uint64_t n, int bi
             hipLaunchKernelGGL(k_hist<K>, dim3(plan.grid), dim3(kBlock), 0, s, keys[cur], n,
                                shift, plan.chunk, plan.grid, tmp);
             hipLaunchKernelGGL(k_dscan, dim3(kRadix), dim3(kBlock), 0, s, tmp, plan.grid);
+            const bool last = pass + 1 == passes;
             hipLaunchKernelGGL(k_scatter<K>, dim3(plan.grid), dim3(kBlock), 0, s, keys[cur],
-                               vin, kout, vals[1 - cur], n, shift, plan.chunk, plan.grid, tmp);
+                               vin, kout, vals[1 - cur], n, shift, plan.chunk, plan.grid, tmp,
+                               gather, last ? gather_out : nullptr);
             cur = 1 - cur;
         }
     }
@@ -267,7 +294,10 @@ hipError_t radix_sort(K* keys[2], uint32_t* vals[2], int cur, uint64_t n, int bi
     return hipGetLastError();
 }
 
-__global__ void k_identity1(uint32_t* v) { v[0] = 0u; }
+__global__ void k_identity1(uint32_t* v, const uint32_t* counts, uint32_t* order_counts) {
+    v[0] = 0u;
+    order_counts[0] = counts[0];
+}
 
 }  // namespace
 
@@ -278,22 +308,25 @@ int64_t sort_tmp_words(uint64_t) { return (int64_t)kRadix * kMaxGrid + kRadix; }
 hipError_t launch_depth_order(int64_t n, const ss_frame& f, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     if (n == 1) {   // a single slot is its own order
-        hipLaunchKernelGGL(k_identity1, dim3(1), dim3(1), 0, s, f.order);
+        hipLaunchKernelGGL(k_identity1, dim3(1), dim3(1), 0, s, f.order, f.counts,
+                           f.order_counts);
         return hipGetLastError();
     }
     uint32_t* keys[2] = {f.depth_keys, f.depth_keys + n};
     uint32_t* vals[2] = {f.order, f.order + n};
     int out = 0;
-    // 4 passes from buffer 0 end in buffer 0: the order lands in f.order[0, n).
-    return radix_sort<uint32_t>(keys, vals, 0, (uint64_t)n, 32, f.order_tmp, true, false, &out,
-                                s);
+    // 4 passes from buffer 0 end in buffer 0: the order lands in f.order[0, n),
+    // and the last pass writes the tile counts in that order.
+    return radix_sort<uint32_t>(keys, vals, 0, (uint64_t)n, 32, f.order_tmp, true, false,
+                                f.counts, f.order_counts, &out, s);
 }
 
 hipError_t launch_sort(const ss_pairs& p, int buf, uint64_t n, int bits, int* out_buf,
                        hipStream_t s) {
     uint32_t* keys[2] = {p.keys[0], p.keys[1]};
     uint32_t* vals[2] = {p.values[0], p.values[1]};
-    return radix_sort<uint32_t>(keys, vals, buf, n, bits, p.sort_tmp, false, true, out_buf, s);
+    return radix_sort<uint32_t>(keys, vals, buf, n, bits, p.sort_tmp, false, true, nullptr,
+                                nullptr, out_buf, s);
 }
 
 hipError_t launch_ranges(const uint32_t* keys, uint64_t n, int n_tiles, uint32_t* ranges,

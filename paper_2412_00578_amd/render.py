@@ -91,6 +91,7 @@ class Frame:
         self.counts = torch.empty(n, dtype=torch.int32, device=dev)
         self.depth_keys = torch.empty(2 * n, dtype=torch.int32, device=dev)
         self.order = torch.empty(2 * n, dtype=torch.int32, device=dev)
+        self.order_counts = torch.empty(n, dtype=torch.int32, device=dev)
         self.order_tmp = torch.empty(int(info.order_tmp_words), dtype=torch.int32, device=dev)
         self.tile_sets = torch.empty((n, 4), dtype=torch.int32, device=dev)
         self.offsets = torch.empty(n, dtype=torch.int32, device=dev)
@@ -105,8 +106,8 @@ class Frame:
 
     def struct(self) -> _lib.SSFrame:
         f = _lib.SSFrame()
-        for name in ("geom", "conic", "rgb", "counts", "depth_keys", "order", "order_tmp",
-                     "tile_sets", "offsets", "scan_tmp", "ranges", "t_final", "n_last", "n_eval",
+        for name in ("geom", "conic", "rgb", "counts", "depth_keys", "order", "order_counts",
+                     "order_tmp", "tile_sets", "offsets", "scan_tmp", "ranges", "t_final", "n_last", "n_eval",
                      "emit_tmp", "table"):
             t = getattr(self, name)
             setattr(f, name, t.data_ptr() if t is not None else None)
@@ -428,6 +429,7 @@ class BatchFrame:
         self.counts = torch.empty(ns, dtype=torch.int32, device=dev)
         self.depth_keys = torch.empty(2 * ns, dtype=torch.int32, device=dev)
         self.order = torch.empty(2 * ns, dtype=torch.int32, device=dev)
+        self.order_counts = torch.empty(ns, dtype=torch.int32, device=dev)
         self.order_tmp = torch.empty(int(info.order_tmp_words), dtype=torch.int32, device=dev)
         self.tile_sets = torch.empty((ns, 4), dtype=torch.int32, device=dev)
         self.offsets = torch.empty(ns, dtype=torch.int32, device=dev)
@@ -445,7 +447,7 @@ class BatchFrame:
     def nbytes(self) -> int:
         return sum(t.numel() * t.element_size() for t in
                    (self.geom, self.conic, self.rgb, self.counts, self.depth_keys, self.order,
-                    self.order_tmp, self.tile_sets, self.offsets, self.scan_tmp, self.ranges, self.t_final,
+                    self.order_counts, self.order_tmp, self.tile_sets, self.offsets, self.scan_tmp, self.ranges, self.t_final,
                     self.n_last, self.emit_tmp, self.table))
 
 

@@ -28,6 +28,8 @@ def gpu_stages(renderer, g, cam, mode):
     }
     out["depth_keys"] = u32(frame.depth_keys[:frame.n]).copy()
     out["order"] = u32(renderer.depth_order(frame)).copy()
+    torch.cuda.synchronize()
+    out["order_counts"] = u32(frame.order_counts).copy()
     p = renderer.scan(frame)
     out["n_pairs"] = p
     out["offsets"] = u32(frame.offsets).copy()
@@ -146,6 +148,7 @@ def assert_pipeline_equal(gpu, fr, image_tol=1e-4):
     assert np.array_equal(gpu["depth_keys"], dk), first_diffs(gpu["depth_keys"], dk)
     order = expected_order(dk)
     assert np.array_equal(gpu["order"], order), first_diffs(gpu["order"], order)
+    assert np.array_equal(gpu["order_counts"], fr.records.counts[order])
     assert gpu["n_pairs"] == fr.n_pairs
     counts = fr.records.counts.astype(np.uint64)
     assert np.array_equal(gpu["offsets"], np.cumsum(counts[order]).astype(np.uint32))

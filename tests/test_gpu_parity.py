@@ -176,15 +176,13 @@ def test_scan_matches_cumsum(ss, gpu_device, n):
     print(f"[case] scan n={n}", flush=True)
     rng = np.random.default_rng(n + 1)
     counts = rng.integers(0, 12, size=n).astype(np.uint32)
-    perm = rng.permutation(n).astype(np.uint32)
     f = ss.Frame(n, 16, 16, gpu_device, stats=False)
-    f.counts.copy_(torch.from_numpy(counts.view(np.int32)))
-    f.order[:n].copy_(torch.from_numpy(perm.view(np.int32)))
+    f.order_counts.copy_(torch.from_numpy(counts.view(np.int32)))
     r = ss.Renderer(gpu_device)
     total = r.scan(f)
     assert total == int(counts.astype(np.uint64).sum())
     if n:
-        want = np.cumsum(counts[perm], dtype=np.uint64).astype(np.uint32)
+        want = np.cumsum(counts, dtype=np.uint64).astype(np.uint32)
         assert np.array_equal(u32(f.offsets), want)
 
 
@@ -195,13 +193,17 @@ def test_depth_order_random_keys(ss, gpu_device, n):
     # depth bits with many exact ties, and slots without tiles (all-ones key)
     keys = rng.integers(0x3e4ccccd, 0x3e4ccccd + 20000, size=n).astype(np.uint32)
     keys[rng.random(n) < 0.2] = np.uint32(0xFFFFFFFF)
+    counts = rng.integers(0, 50, size=n).astype(np.uint32)
     f = ss.Frame(n, 16, 16, gpu_device, stats=False)
     if n:
         f.depth_keys[:n].copy_(torch.from_numpy(keys.view(np.int32)))
+        f.counts.copy_(torch.from_numpy(counts.view(np.int32)))
     r = ss.Renderer(gpu_device)
     got = u32(r.depth_order(f))
     torch.cuda.synchronize()
-    assert np.array_equal(got, np.argsort(keys, kind="stable").astype(np.uint32))
+    want = np.argsort(keys, kind="stable").astype(np.uint32)
+    assert np.array_equal(got, want)
+    assert np.array_equal(u32(f.order_counts), counts[want])
 
 
 @pytest.mark.parametrize("n", [0, 1, 2, 4095, 4097, 70_001, 5_000_003])
