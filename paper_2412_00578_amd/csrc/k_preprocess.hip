@@ -33,43 +33,42 @@ struct Inputs {
     int sh_degree, sh_stride;
 };
 
-constexpr int kBlock = 256;
-static_assert(kBlock == kSlotAlign, "a preprocess workgroup must not span two items");
+constexpr int kBlock = 64;                 // one wave: LDS staging per wave
+static_assert(kSlotAlign % kBlock == 0, "a preprocess workgroup must not span two items");
 constexpr int kPack = 16;                  // items per table-writing launch (kernel-argument bytes)
 struct ItemPack {
     Item it[kPack];
 };
-constexpr int kShMax = 48;                 // SH floats per Gaussian staged (degree 3)
-constexpr int kShPitch = kShMax + 1;       // odd LDS pitch: lanes hit distinct banks
+constexpr int kShHalf = 24;                // SH floats staged per round (8 coefficients x 3)
+constexpr int kShPitch = kShHalf + 1;      // odd LDS pitch: lanes hit distinct banks
 
-// Copies the SH coefficients of this workgroup's Gaussians into LDS with
-// coalesced 16-byte loads (the [n, stride, 3] rows of consecutive Gaussians are
-// contiguous), so each lane then reads its own coefficients from LDS instead of
-// issuing strided per-lane loads.  Only the first `need` floats of each
-// Gaussian are kept.
+// Copies floats [f0, f0 + w) of the SH rows of this workgroup's Gaussians into
+// LDS (Gaussian g at s_sh[g * kShPitch]) with coalesced loads: the [n, stride,
+// 3] rows of consecutive Gaussians are contiguous.  Staging a round of at most
+// 24 floats at a time keeps the LDS per wave at 6.4 KB, so LDS does not limit
+// how many waves a CU holds.
 __device__ __forceinline__ void stage_sh(const float* __restrict__ sh, int64_t first, int64_t n,
-                                         int row, int need, float* s_sh) {
+                                         int row, int f0, int w, float* s_sh) {
     const int cnt = (n - first) < kBlock ? (int)(n - first) : kBlock;
-    const unsigned total = (unsigned)(cnt * row);        // floats of this block
-    const unsigned urow = (unsigned)row;
     const float* src = sh + first * row;
-    if (((uintptr_t)src & 15u) == 0 && (row & 3) == 0) {
-        const float4* src4 = reinterpret_cast<const float4*>(src);
-        for (unsigned e = threadIdx.x; e < (total >> 2); e += kBlock) {
-            const float4 v = src4[e];
-            const unsigned f = e << 2, g = f / urow, c = f - g * urow;
-            if ((int)c < need) {  // row % 4 == 0: the four floats stay in one Gaussian
-                float* d = s_sh + g * kShPitch + c;
-                d[0] = v.x;
-                if ((int)c + 1 < need) d[1] = v.y;
-                if ((int)c + 2 < need) d[2] = v.z;
-                if ((int)c + 3 < need) d[3] = v.w;
-            }
+    if (((uintptr_t)src & 15u) == 0 && (row & 3) == 0 && (f0 & 3) == 0) {
+        // float4 j of a Gaussian covers floats f0 + 4j .. f0 + 4j + 3, all inside
+        // its row (row and f0 are multiples of 4); floats past w are not kept
+        const unsigned q = (unsigned)(w + 3) >> 2, urow4 = (unsigned)row >> 2;
+        const float4* src4 = reinterpret_cast<const float4*>(src) + (f0 >> 2);
+        for (unsigned e = threadIdx.x; e < (unsigned)cnt * q; e += kBlock) {
+            const unsigned g = e / q, j = e - g * q;
+            const float4 v = src4[g * urow4 + j];
+            float* d = s_sh + g * kShPitch + 4 * j;
+            d[0] = v.x;
+            if ((int)(4 * j) + 1 < w) d[1] = v.y;
+            if ((int)(4 * j) + 2 < w) d[2] = v.z;
+            if ((int)(4 * j) + 3 < w) d[3] = v.w;
         }
     } else {
-        for (unsigned f = threadIdx.x; f < total; f += kBlock) {
-            const unsigned g = f / urow, c = f - g * urow;
-            if ((int)c < need) s_sh[g * kShPitch + c] = src[f];
+        for (unsigned e = threadIdx.x; e < (unsigned)(cnt * w); e += kBlock) {
+            const unsigned g = e / (unsigned)w, j = e - g * (unsigned)w;
+            s_sh[g * kShPitch + j] = src[(int64_t)g * row + f0 + j];
         }
     }
 }
@@ -90,11 +89,75 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(const Item* __restrict__ 
     const int64_t n = it.n;
     const int tx_n = it.tx_n, ty_n = it.ty_n;
     const int64_t first = slot0 - it.g_off;       // local index of this block's first lane
-    const int nb_coef = (in.sh_degree + 1) * (in.sh_degree + 1);
-    if (first < n) stage_sh(in.sh, first, n, 3 * in.sh_stride, 3 * nb_coef, s_sh);
-    __syncthreads();
     const int64_t i = first + threadIdx.x;        // Gaussian of the item
     const int64_t o = slot0 + threadIdx.x;        // its record slot
+    const bool real = i < n && o < dims.n_slots;
+
+    // Inputs first, so their loads overlap the SH staging below.
+    float m0 = 0.f, m1 = 0.f, m2 = 1.f, s0 = 0.f, s1 = 0.f, s2 = 0.f, op = 0.f;
+    float4 qr = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (real) {
+        m0 = in.means[3 * i]; m1 = in.means[3 * i + 1]; m2 = in.means[3 * i + 2];
+        s0 = in.scales[3 * i]; s1 = in.scales[3 * i + 1]; s2 = in.scales[3 * i + 2];
+        qr = *reinterpret_cast<const float4*>(in.quats + 4 * i);
+        op = in.opacity[i];
+    }
+
+    // View-dependent colour from SH (FP32), accumulated over the coefficients in
+    // order, staged in rounds of 8 coefficients.  Every lane takes part in the
+    // staging, so this comes before any lane leaves.
+    const float cpx = -((cam.R[0] * cam.t[0] + cam.R[3] * cam.t[1]) + cam.R[6] * cam.t[2]);
+    const float cpy = -((cam.R[1] * cam.t[0] + cam.R[4] * cam.t[1]) + cam.R[7] * cam.t[2]);
+    const float cpz = -((cam.R[2] * cam.t[0] + cam.R[5] * cam.t[1]) + cam.R[8] * cam.t[2]);
+    float dx = m0 - cpx, dy = m1 - cpy, dz = m2 - cpz;
+    const float inv = 1.0f / sqrtf(dx * dx + dy * dy + dz * dz);
+    dx *= inv; dy *= inv; dz *= inv;
+    float Y[16];
+    Y[0] = kSH0;
+    int nb = 1;
+    if (in.sh_degree >= 1) {
+        Y[1] = -kSH1 * dy; Y[2] = kSH1 * dz; Y[3] = -kSH1 * dx;
+        nb = 4;
+    }
+    if (in.sh_degree >= 2) {
+        const float xx = dx * dx, yy = dy * dy, zz = dz * dz;
+        Y[4] = kSH2a * (dx * dy);
+        Y[5] = -kSH2a * (dy * dz);
+        Y[6] = kSH2b * (2.0f * zz - xx - yy);
+        Y[7] = -kSH2a * (dx * dz);
+        Y[8] = kSH2c * (xx - yy);
+        nb = 9;
+        if (in.sh_degree >= 3) {
+            Y[9] = -kSH3a * dy * (3.0f * xx - yy);
+            Y[10] = kSH3b * (dx * dy * dz);
+            Y[11] = -kSH3c * dy * (4.0f * zz - xx - yy);
+            Y[12] = kSH3d * dz * (2.0f * zz - 3.0f * xx - 3.0f * yy);
+            Y[13] = -kSH3c * dx * (4.0f * zz - xx - yy);
+            Y[14] = kSH3e * dz * (xx - yy);
+            Y[15] = -kSH3a * dx * (xx - 3.0f * yy);
+            nb = 16;
+        }
+    }
+    const int need = 3 * nb;
+    const int row = 3 * in.sh_stride;
+    const float* h = s_sh + threadIdx.x * kShPitch;
+    float cr = 0.f, cg = 0.f, cbl = 0.f;
+    for (int f0 = 0; f0 < need; f0 += kShHalf) {          // uniform
+        const int w = need - f0 < kShHalf ? need - f0 : kShHalf;
+        if (f0) __syncthreads();                          // previous round consumed
+        if (first < n) stage_sh(in.sh, first, n, row, f0, w, s_sh);
+        __syncthreads();
+        for (int k = f0 / 3; k < (f0 + w) / 3; ++k) {
+            const int c = 3 * k - f0;
+            cr = fmaf(Y[k], h[c], cr);
+            cg = fmaf(Y[k], h[c + 1], cg);
+            cbl = fmaf(Y[k], h[c + 2], cbl);
+        }
+    }
+    cr = fmaxf(cr + 0.5f, 0.0f);
+    cg = fmaxf(cg + 0.5f, 0.0f);
+    cbl = fmaxf(cbl + 0.5f, 0.0f);
+
     if (o >= dims.n_slots) return;
     const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
     if (i >= n) {  // padding slot between items
@@ -103,11 +166,6 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(const Item* __restrict__ 
         tsets[o] = make_uint4(0u, 0u, 0u, 0u);
         return;
     }
-
-    const float m0 = in.means[3 * i], m1 = in.means[3 * i + 1], m2 = in.means[3 * i + 2];
-    const float s0 = in.scales[3 * i], s1 = in.scales[3 * i + 1], s2 = in.scales[3 * i + 2];
-    const float4 qr = *reinterpret_cast<const float4*>(in.quats + 4 * i);
-    const float op = in.opacity[i];
 
     bool ok = finite_f(m0) && finite_f(m1) && finite_f(m2) && finite_f(s0) && finite_f(s1) &&
               finite_f(s2) && finite_f(qr.x) && finite_f(qr.y) && finite_f(qr.z) &&
@@ -200,50 +258,6 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(const Item* __restrict__ 
         tsets[o] = make_uint4(0u, 0u, 0u, 0u);
         return;
     }
-
-    // view-dependent colour from SH (FP32)
-    const float cpx = -((cam.R[0] * cam.t[0] + cam.R[3] * cam.t[1]) + cam.R[6] * cam.t[2]);
-    const float cpy = -((cam.R[1] * cam.t[0] + cam.R[4] * cam.t[1]) + cam.R[7] * cam.t[2]);
-    const float cpz = -((cam.R[2] * cam.t[0] + cam.R[5] * cam.t[1]) + cam.R[8] * cam.t[2]);
-    float dx = m0 - cpx, dy = m1 - cpy, dz = m2 - cpz;
-    const float inv = 1.0f / sqrtf(dx * dx + dy * dy + dz * dz);
-    dx *= inv; dy *= inv; dz *= inv;
-    const float* h = s_sh + threadIdx.x * kShPitch;
-    float Y[16];
-    Y[0] = kSH0;
-    int nb = 1;
-    if (in.sh_degree >= 1) {
-        Y[1] = -kSH1 * dy; Y[2] = kSH1 * dz; Y[3] = -kSH1 * dx;
-        nb = 4;
-    }
-    if (in.sh_degree >= 2) {
-        const float xx = dx * dx, yy = dy * dy, zz = dz * dz;
-        Y[4] = kSH2a * (dx * dy);
-        Y[5] = -kSH2a * (dy * dz);
-        Y[6] = kSH2b * (2.0f * zz - xx - yy);
-        Y[7] = -kSH2a * (dx * dz);
-        Y[8] = kSH2c * (xx - yy);
-        nb = 9;
-        if (in.sh_degree >= 3) {
-            Y[9] = -kSH3a * dy * (3.0f * xx - yy);
-            Y[10] = kSH3b * (dx * dy * dz);
-            Y[11] = -kSH3c * dy * (4.0f * zz - xx - yy);
-            Y[12] = kSH3d * dz * (2.0f * zz - 3.0f * xx - 3.0f * yy);
-            Y[13] = -kSH3c * dx * (4.0f * zz - xx - yy);
-            Y[14] = kSH3e * dz * (xx - yy);
-            Y[15] = -kSH3a * dx * (xx - 3.0f * yy);
-            nb = 16;
-        }
-    }
-    float cr = 0.f, cg = 0.f, cbl = 0.f;
-    for (int k = 0; k < nb; ++k) {
-        cr = fmaf(Y[k], h[3 * k], cr);
-        cg = fmaf(Y[k], h[3 * k + 1], cg);
-        cbl = fmaf(Y[k], h[3 * k + 2], cbl);
-    }
-    cr = fmaxf(cr + 0.5f, 0.0f);
-    cg = fmaxf(cg + 0.5f, 0.0f);
-    cbl = fmaxf(cbl + 0.5f, 0.0f);
 
     const float4 g4 = make_float4((float)u, (float)v, (float)z, tt);
     const float4 q4 = make_float4(ca, cb, cc, op);
