@@ -90,6 +90,36 @@ def cpu_baseline(scene, cam, runs=3):
                       f"on {cpu_model()} ({os.cpu_count()} visible cores)"}
 
 
+def backward_bench(ss, g, cams, steps, warmup):
+    """The adjoint of the AccuTile frame (blend backward + preprocess backward)
+    for a seeded image gradient, with and without the pruning score, timed with
+    events around ss_render_backward.  Forward state is rendered untimed."""
+    dev = g.device
+    r = ss.Renderer(dev)
+    outs = [r.render(g, c, "accutile", full=True) for c in cams[:1]]
+    out = outs[0]
+    gen = torch.Generator(device=dev).manual_seed(7)
+    dl = torch.randn(out.image.shape, generator=gen, device=dev, dtype=torch.float32)
+    res = {}
+    for name, score in (("backward", False), ("backward_with_score", True)):
+        for _ in range(warmup):
+            ss.backward(g, cams[0], out, dl, want_score=score)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record()
+        for _ in range(steps):
+            ss.backward(g, cams[0], out, dl, want_score=score)
+        b.record()
+        torch.cuda.synchronize()
+        res[name + "_ms"] = round(a.elapsed_time(b) / steps, 4)
+    n_last = out.frame.n_last.to(torch.int64)
+    res["blended_entries_walked"] = int(n_last.sum().item())   # per-pixel list entries walked back
+    res["workload"] = ("adjoint of one AccuTile frame of the benchmark scene (camera 0), "
+                       "seeded N(0,1) image gradient")
+    log(f"backward: {res}")
+    return res
+
+
 def serving_bench(ss, dev, scale=1.0, n_sat=400, n_req=1000, max_batch=8, pool_gib=16):
     """Continuous-batching serving over 4 resident scenes (0.3M / 1M / 3M / 6M
     Gaussians, SH-3, clustered) with random orbit cameras at 640x480,
@@ -270,6 +300,7 @@ def main():
                              f"x {OPS_PER_EVAL} FP32 ops per launch",
                      "avg_launch_ms": round(blend_ms, 4)},
     }
+    line["backward"] = backward_bench(ss, g, cams, max(args.steps // 3, 5), args.warmup)
     if not args.no_serve:
         line["serving"] = serving_bench(ss, dev, args.serve_scale)
         line["serving_p50_ms"] = line["serving"]["poisson_0.8X"]["p50_ms"]
