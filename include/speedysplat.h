@@ -17,7 +17,7 @@
  * - `stream` is a hipStream_t (NULL = the null stream).  Every call only
  *   enqueues work on it and returns; outputs are valid once the stream has
  *   been synchronised.  The exceptions, which synchronise `stream` to read the
- *   pair count, are named "SYNC" below.
+ *   frame counts, are named "SYNC" below.
  * - Status: SS_OK (0) or a positive SS_ERR_* code.  Arguments are checked on
  *   the host before anything is enqueued; on an error nothing is enqueued and
  *   ss_last_error() holds a message (thread-local).  A launch failure reported
@@ -60,7 +60,7 @@
 extern "C" {
 #endif
 
-#define SS_ABI_VERSION 2
+#define SS_ABI_VERSION 3
 
 enum ss_status {
     SS_OK = 0,
@@ -114,9 +114,10 @@ typedef struct ss_frame {
     uint32_t *depth_keys;   /* [2n]  depth-order sort keys: the preprocess stage writes
                                [0, n) (bits(depth), or 0xffffffff for a Gaussian with no
                                tiles); [n, 2n) is scratch of ss_depth_order */
-    uint32_t *order;        /* [2n]  after ss_depth_order, [0, n) holds the Gaussians
-                               sorted by (depth key, index); [n, 2n) is scratch */
-    uint32_t *order_counts; /* [n]   after ss_depth_order: counts[order[j]] */
+    uint32_t *order;        /* [2n]  after ss_depth_order, [0, n_visible) holds the
+                               Gaussians with tiles sorted by (depth key, index);
+                               [n, 2n) is scratch */
+    uint32_t *order_counts; /* [n]   after ss_depth_order: counts[order[j]], j < n_visible */
     uint32_t *order_tmp;    /* [order_tmp_words] scratch of ss_depth_order */
     uint32_t *tile_sets;    /* [n,4] per Gaussian, written by the preprocess stage: when
                                its tile rectangle fits 8 x 8 tiles, the 64-bit mask
@@ -124,6 +125,8 @@ typedef struct ss_frame {
                                x0 | y0 << 16 (word 2); mask 0 otherwise */
     uint32_t *offsets;      /* [n]   inclusive prefix sum of counts in depth order */
     uint64_t *scan_tmp;     /* [scan_tmp_words]; word 0 receives the pair count P */
+    uint64_t *totals;       /* [2] the frame counts (ss_frame_counts: P, Gaussians with
+                               tiles), zeroed and accumulated by the preprocess stage */
     uint32_t *ranges;       /* [n_tiles, 2] per-tile [start, end) into the sorted pairs */
     float *t_final;         /* [H, W] final transmittance per pixel */
     uint32_t *n_last;       /* [H, W] 1 + position (within its tile) of the last
@@ -145,6 +148,14 @@ typedef struct ss_frame_info {
     int64_t order_tmp_words; /* uint32 words for ss_frame.order_tmp */
     int64_t table_bytes;    /* bytes for ss_frame.table */
 } ss_frame_info;
+
+/* The frame counts the preprocess stage accumulates and the begin calls read
+ * back: the pair count P (the sum of the tile counts) and the number of
+ * Gaussians with at least one tile. */
+typedef struct ss_frame_counts {
+    uint64_t n_pairs;
+    uint64_t n_visible;
+} ss_frame_counts;
 
 /* One render request of a batch: a camera, a resident scene, an output image. */
 typedef struct ss_batch_item {
@@ -190,9 +201,10 @@ typedef struct ss_grads {
 
 /* Optional stage timing for the composite calls: caller-created hipEvent_t
  * handles (NULL entries are skipped) recorded on the stream at
- *   [0] before preprocess  [1] after preprocess  [2] after the depth order
- *   [3] after the scan  [4] before emit (after the pair count was read back)
- *   [5] after emit  [6] after the sort  [7] after the ranges  [8] after the blend. */
+ *   [0] before preprocess  [1] after preprocess  [2] before the depth order
+ *   (after the frame counts were read back)  [3] after the depth order
+ *   [4] after the scan  [5] after emit  [6] after the sort  [7] after the ranges
+ *   [8] after the blend. */
 typedef struct ss_stage_events {
     void *ev[9];
 } ss_stage_events;
@@ -216,36 +228,40 @@ int ss_sort_tmp_words(uint64_t capacity, int64_t *out_words);
  * Stage 1, preprocess (Sec. 3.2.1 and Sec. 4.1): for every Gaussian, the record
  * (projection, Sigma_3D = R S S^T R^T, EWA Sigma_2D + 0.3 I, conic, t, SH
  * colour) and its tile count under `mode`.  Writes frame->geom, conic, rgb,
- * counts, tile_sets and depth_keys[0, n).
+ * counts, tile_sets and depth_keys[0, n), and the frame counts (P and the
+ * number of Gaussians with tiles) to frame->totals.
  */
 int ss_preprocess(const ss_camera *cam, const ss_gaussians *g, int32_t mode,
                   const ss_frame *frame, void *stream);
 
 /*
  * Stage 2a, depth order (the depth half of the Sec. 3.2.2 sort key): stable LSD
- * radix sort of the n Gaussians on frame->depth_keys; frame->order[0, n)
- * receives the Gaussian indices by (bits(depth), index), Gaussians without
- * tiles last, and frame->order_counts[j] = counts[order[j]].  Uses
- * depth_keys[n, 2n), order[n, 2n) and order_tmp as scratch.
+ * radix sort of the Gaussians with tiles on frame->depth_keys (the n keys the
+ * preprocess stage wrote, of which n_visible differ from 0xffffffff);
+ * frame->order[0, n_visible) receives their indices by (bits(depth), index)
+ * and frame->order_counts[j] = counts[order[j]].  The first pass drops the
+ * Gaussians without tiles, so later passes sort n_visible keys.  Uses
+ * depth_keys[0, 2n), order[n, 2n) and order_tmp as scratch.
  */
-int ss_depth_order(int64_t n, const ss_frame *frame, void *stream);
+int ss_depth_order(int64_t n, int64_t n_visible, const ss_frame *frame, void *stream);
 
 /*
  * Stage 2b, inclusive prefix sum of the tile counts in depth order (Sec. 3.2.2,
- * "InclusiveSum"): frame->offsets[j] = sum_{k <= j} order_counts[k]; the
- * total P goes to frame->scan_tmp[0] (uint64).
+ * "InclusiveSum"): frame->offsets[j] = sum_{k <= j} order_counts[k] for
+ * j < n_visible; the total P goes to frame->scan_tmp[0] (uint64).
  */
-int ss_scan(int64_t n, const ss_frame *frame, void *stream);
+int ss_scan(int64_t n_visible, const ss_frame *frame, void *stream);
 
 /*
  * Stage 3, key emission (Sec. 3.2.2, "duplicateWithKeys"; Alg. 1 "Process"):
- * for each depth-order entry j, Gaussian i = order[j] writes its tiles (in an
- * unspecified order) at [offsets[j] - counts[i], offsets[j]) of
- * pairs->keys[buf] (tile id) / values[buf] (i).  n_pairs must be the P the
- * scan produced and <= pairs->capacity.
+ * for each depth-order entry j < n_visible, Gaussian i = order[j] writes its
+ * tiles (in an unspecified order) at [offsets[j] - counts[i], offsets[j]) of
+ * pairs->keys[buf] (tile id) / values[buf] (i).  n is the number of
+ * Gaussians; n_pairs must be the P the scan produced and <= pairs->capacity.
  */
-int ss_emit(const ss_camera *cam, int64_t n, int32_t mode, const ss_frame *frame,
-            const ss_pairs *pairs, int32_t buf, uint64_t n_pairs, void *stream);
+int ss_emit(const ss_camera *cam, int64_t n, int64_t n_visible, int32_t mode,
+            const ss_frame *frame, const ss_pairs *pairs, int32_t buf, uint64_t n_pairs,
+            void *stream);
 
 /*
  * Stage 4, LSD radix sort of the pairs in buffer `buf` on the low
@@ -276,70 +292,72 @@ int ss_blend(const ss_camera *cam, const ss_frame *frame, const ss_pairs *pairs,
              float *out_rgb, void *stream);
 
 /*
- * SYNC.  Stages 1, 2a and 2b, then reads P back to the host (*n_pairs_out).
+ * SYNC.  Stage 1, then reads the frame counts back to the host (*counts_out).
  * Returns SS_ERR_OVERFLOW if P >= 2^32.  `events` may be NULL.
  */
 int ss_forward_begin(const ss_camera *cam, const ss_gaussians *g, int32_t mode,
-                     const ss_frame *frame, uint64_t *n_pairs_out,
+                     const ss_frame *frame, ss_frame_counts *counts_out,
                      const ss_stage_events *events, void *stream);
 
 /*
- * Stages 1, 2a and 2b like ss_forward_begin, without waiting: the pair count
- * P is copied into the HOST word *n_pairs_host by a copy enqueued on `stream`
- * after the scan, and the call returns at once.  *n_pairs_host is valid once
+ * Stage 1 like ss_forward_begin, without waiting: the frame counts are copied
+ * into the HOST struct *counts_host by a copy enqueued on `stream` after the
+ * preprocess stage, and the call returns at once.  *counts_host is valid once
  * the stream has passed that copy (synchronise an event recorded after this
  * call).  Pinned host memory (hipHostMalloc) keeps the copy asynchronous.  The
  * caller then grows the pair workspace if needed and calls ss_forward_finish;
- * meanwhile it may enqueue other frames' work, e.g. the next frame's stages
- * 1-2b into a second ss_frame, so that the GPU never waits for the host.
+ * meanwhile it may enqueue other frames' work, e.g. the next frame's stage 1
+ * into a second ss_frame, so that the GPU never waits for the host.
  */
 int ss_forward_begin_async(const ss_camera *cam, const ss_gaussians *g, int32_t mode,
-                           const ss_frame *frame, uint64_t *n_pairs_host,
+                           const ss_frame *frame, ss_frame_counts *counts_host,
                            const ss_stage_events *events, void *stream);
 
 /*
- * Stages 3-6 for the P returned by ss_forward_begin (or ss_forward_begin_async).  Returns
- * SS_ERR_WORKSPACE if pairs->capacity < n_pairs.  *out_buf (may be NULL)
- * receives the pair buffer holding the sorted pairs.  `events` may be NULL.
+ * Stages 2a-6 for the frame counts returned by ss_forward_begin (or
+ * ss_forward_begin_async).  Returns SS_ERR_WORKSPACE if pairs->capacity <
+ * counts->n_pairs.  *out_buf (may be NULL) receives the pair buffer holding the
+ * sorted pairs.  `events` may be NULL.
  */
 int ss_forward_finish(const ss_camera *cam, int64_t n, int32_t mode, const ss_frame *frame,
-                      const ss_pairs *pairs, uint64_t n_pairs, float *out_rgb,
+                      const ss_pairs *pairs, const ss_frame_counts *counts, float *out_rgb,
                       int32_t *out_buf, const ss_stage_events *events, void *stream);
 
 /*
- * SYNC.  The whole forward render (stages 1-6).  *n_pairs_out receives P.  If
- * pairs->capacity < P, returns SS_ERR_WORKSPACE after stage 2 without touching
- * the pair buffers; the caller grows them to P and calls again.  `events`
- * may be NULL.
+ * SYNC.  The whole forward render (stages 1-6).  *counts_out (may be NULL)
+ * receives the frame counts.  If pairs->capacity < P, returns SS_ERR_WORKSPACE
+ * after stage 1 without touching the pair buffers; the caller grows them to P
+ * and calls again.  `events` may be NULL.
  */
 int ss_render(const ss_camera *cam, const ss_gaussians *g, int32_t mode, const ss_frame *frame,
-              const ss_pairs *pairs, float *out_rgb, uint64_t *n_pairs_out, int32_t *out_buf,
-              const ss_stage_events *events, void *stream);
+              const ss_pairs *pairs, float *out_rgb, ss_frame_counts *counts_out,
+              int32_t *out_buf, const ss_stage_events *events, void *stream);
 
 /* Sizes for a batch of n_items (1 .. 4096) items. */
 int ss_batch_sizes(const ss_batch_item *items, int32_t n_items, ss_batch_info *out);
 
 /*
- * SYNC.  Batched stages 1-2b for n_items render requests (different scenes and
- * resolutions) in one launch per stage: the item table is written to
- * frame->table, records go to the items' slots, and the pair count P of the
- * whole batch is read back.  Pair keys carry a batch-global tile id (the
+ * SYNC.  Batched stage 1 for n_items render requests (different scenes and
+ * resolutions) in one launch: the item table is written to frame->table,
+ * records go to the items' slots, and the frame counts of the whole batch
+ * are read back.  Pair keys carry a batch-global tile id (the
  * item's first tile + its tile), so one depth order and one tile sort order
  * every item's tiles, and an item's pairs, sorted and blended, are those it
  * would have alone.
  */
 int ss_batch_begin(const ss_batch_item *items, int32_t n_items, int32_t mode,
-                   const ss_frame *frame, uint64_t *n_pairs_out,
+                   const ss_frame *frame, ss_frame_counts *counts_out,
                    const ss_stage_events *events, void *stream);
 
 /*
- * Batched stages 3-6 for the P returned by ss_batch_begin (same items, mode
- * and frame); each item's image goes to its out_rgb.  Returns
- * SS_ERR_WORKSPACE if pairs->capacity < n_pairs.
+ * Batched stages 2a-6 for the counts returned by ss_batch_begin (same items,
+ * mode and frame); each item's image goes to its out_rgb.  Returns
+ * SS_ERR_WORKSPACE if pairs->capacity < counts->n_pairs.
  */
 int ss_batch_finish(const ss_batch_item *items, int32_t n_items, int32_t mode,
-                    const ss_frame *frame, const ss_pairs *pairs, uint64_t n_pairs,
-                    int32_t *out_buf, const ss_stage_events *events, void *stream);
+                    const ss_frame *frame, const ss_pairs *pairs,
+                    const ss_frame_counts *counts, int32_t *out_buf,
+                    const ss_stage_events *events, void *stream);
 
 /*
  * Adjoint of the forward render (the gradient flow of Sec. 4.2: per-pixel

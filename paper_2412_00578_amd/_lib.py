@@ -45,10 +45,9 @@ class SSGaussians(ctypes.Structure):
 class SSFrame(ctypes.Structure):
     _fields_ = [("geom", _vp), ("conic", _vp), ("rgb", _vp), ("counts", _vp),
                 ("depth_keys", _vp), ("order", _vp), ("order_counts", _vp), ("order_tmp", _vp),
-                ("tile_sets", _vp),
-                ("offsets", _vp),
-                ("scan_tmp", _vp), ("ranges", _vp), ("t_final", _vp), ("n_last", _vp),
-                ("n_eval", _vp), ("emit_tmp", _vp), ("table", _vp)]
+                ("tile_sets", _vp), ("offsets", _vp), ("scan_tmp", _vp), ("totals", _vp),
+                ("ranges", _vp), ("t_final", _vp), ("n_last", _vp), ("n_eval", _vp),
+                ("emit_tmp", _vp), ("table", _vp)]
 
 
 class SSFrameInfo(ctypes.Structure):
@@ -56,6 +55,10 @@ class SSFrameInfo(ctypes.Structure):
                 ("n_tiles", ctypes.c_int32), ("sort_bits", ctypes.c_int32),
                 ("scan_tmp_words", ctypes.c_int64), ("order_tmp_words", ctypes.c_int64),
                 ("table_bytes", ctypes.c_int64)]
+
+
+class SSFrameCounts(ctypes.Structure):
+    _fields_ = [("n_pairs", ctypes.c_uint64), ("n_visible", ctypes.c_uint64)]
 
 
 class SSBatchItem(ctypes.Structure):
@@ -92,28 +95,29 @@ PROTOTYPES = {
     "ss_frame_sizes": [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _P(SSFrameInfo)],
     "ss_sort_tmp_words": [ctypes.c_uint64, _P(ctypes.c_int64)],
     "ss_preprocess": [_P(SSCamera), _P(SSGaussians), ctypes.c_int32, _P(SSFrame), _vp],
-    "ss_depth_order": [ctypes.c_int64, _P(SSFrame), _vp],
+    "ss_depth_order": [ctypes.c_int64, ctypes.c_int64, _P(SSFrame), _vp],
     "ss_scan": [ctypes.c_int64, _P(SSFrame), _vp],
-    "ss_emit": [_P(SSCamera), ctypes.c_int64, ctypes.c_int32, _P(SSFrame), _P(SSPairs),
-                ctypes.c_int32, ctypes.c_uint64, _vp],
+    "ss_emit": [_P(SSCamera), ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, _P(SSFrame),
+                _P(SSPairs), ctypes.c_int32, ctypes.c_uint64, _vp],
     "ss_sort": [_P(SSCamera), _P(SSPairs), ctypes.c_int32, ctypes.c_uint64,
                 _P(ctypes.c_int32), _vp],
     "ss_ranges": [_P(SSCamera), _P(SSFrame), _P(SSPairs), ctypes.c_int32, ctypes.c_uint64, _vp],
     "ss_blend": [_P(SSCamera), _P(SSFrame), _P(SSPairs), ctypes.c_int32, _vp, _vp],
     "ss_forward_begin": [_P(SSCamera), _P(SSGaussians), ctypes.c_int32, _P(SSFrame),
-                         _P(ctypes.c_uint64), _P(SSStageEvents), _vp],
+                         _P(SSFrameCounts), _P(SSStageEvents), _vp],
     "ss_forward_begin_async": [_P(SSCamera), _P(SSGaussians), ctypes.c_int32, _P(SSFrame),
                                _vp, _P(SSStageEvents), _vp],
     "ss_forward_finish": [_P(SSCamera), ctypes.c_int64, ctypes.c_int32, _P(SSFrame),
-                          _P(SSPairs), ctypes.c_uint64, _vp, _P(ctypes.c_int32),
+                          _P(SSPairs), _P(SSFrameCounts), _vp, _P(ctypes.c_int32),
                           _P(SSStageEvents), _vp],
     "ss_render": [_P(SSCamera), _P(SSGaussians), ctypes.c_int32, _P(SSFrame), _P(SSPairs), _vp,
-                  _P(ctypes.c_uint64), _P(ctypes.c_int32), _P(SSStageEvents), _vp],
+                  _P(SSFrameCounts), _P(ctypes.c_int32), _P(SSStageEvents), _vp],
     "ss_batch_sizes": [_P(SSBatchItem), ctypes.c_int32, _P(SSBatchInfo)],
     "ss_batch_begin": [_P(SSBatchItem), ctypes.c_int32, ctypes.c_int32, _P(SSFrame),
-                       _P(ctypes.c_uint64), _P(SSStageEvents), _vp],
+                       _P(SSFrameCounts), _P(SSStageEvents), _vp],
     "ss_batch_finish": [_P(SSBatchItem), ctypes.c_int32, ctypes.c_int32, _P(SSFrame),
-                        _P(SSPairs), ctypes.c_uint64, _P(ctypes.c_int32), _P(SSStageEvents), _vp],
+                        _P(SSPairs), _P(SSFrameCounts), _P(ctypes.c_int32), _P(SSStageEvents),
+                        _vp],
     "ss_render_backward": [_P(SSCamera), _P(SSGaussians), _P(SSFrame), _P(SSPairs),
                            ctypes.c_int32, _vp, _P(SSGrads), _vp],
 }

@@ -78,6 +78,7 @@ int check_frame_records(const ss_frame* f, int64_t n) {
                   !f->depth_keys || !f->order || !f->order_counts || !f->order_tmp ||
                   !f->tile_sets))
         return fail(SS_ERR_INVALID_ARG, "a per-Gaussian frame buffer is NULL");
+    if (!f->totals) return fail(SS_ERR_INVALID_ARG, "frame totals is NULL");
     if (!aligned16(f->geom) || !aligned16(f->conic) || !aligned16(f->rgb) ||
         !aligned16(f->tile_sets))
         return fail(SS_ERR_INVALID_ARG, "frame records must be 16-byte aligned");
@@ -195,53 +196,63 @@ int check_table(const ss_frame* f) {
     return SS_OK;
 }
 
-// Stages 1-2b.  sync: wait for P and store it in *n_pairs_out; otherwise
-// enqueue its copy into the host word *n_pairs_out and return.
-int begin_impl(const Layout& L, int32_t mode, const ss_frame* f, uint64_t* n_pairs_out,
+// Stage 1 and the read-back of the frame counts (P, visible Gaussians).
+// sync: wait and store them in *out; otherwise enqueue their copy into the
+// host struct *out and return.
+int begin_impl(const Layout& L, int32_t mode, const ss_frame* f, ss_frame_counts* out,
                const ss_stage_events* ev, bool sync, hipStream_t s) {
     SS_TRY(check_mode(mode));
     SS_TRY(check_frame_records(f, L.d.n_slots));
     SS_TRY(check_table(f));
-    if (!n_pairs_out) return fail(SS_ERR_INVALID_ARG, "n_pairs_out is NULL");
+    if (!out) return fail(SS_ERR_INVALID_ARG, "frame counts pointer is NULL");
     ss::Item* table = reinterpret_cast<ss::Item*>(f->table);
     record(ev, 0, s);
     SS_TRY(hip_status(ss::write_items(table, L.items.data(), L.d.n_items, s), "item table"));
     SS_TRY(hip_status(ss::launch_preprocess(table, L.d, mode, *f, s), "preprocess"));
     record(ev, 1, s);
-    SS_TRY(hip_status(ss::launch_depth_order(L.d.n_slots, *f, s), "depth order"));
-    record(ev, 2, s);
-    SS_TRY(hip_status(ss::launch_scan(L.d.n_slots, *f, s), "scan"));
-    record(ev, 3, s);
+    static_assert(sizeof(ss_frame_counts) == 2 * sizeof(uint64_t), "counts layout");
     if (!sync)
-        return hip_status(hipMemcpyAsync(n_pairs_out, f->scan_tmp, sizeof(uint64_t),
+        return hip_status(hipMemcpyAsync(out, f->totals, sizeof(ss_frame_counts),
                                          hipMemcpyDeviceToHost, s),
-                          "copy pair count");
-    uint64_t p = 0;
-    SS_TRY(hip_status(hipMemcpyAsync(&p, f->scan_tmp, sizeof(p), hipMemcpyDeviceToHost, s),
-                      "read pair count"));
+                          "copy frame counts");
+    ss_frame_counts c{};
+    SS_TRY(hip_status(hipMemcpyAsync(&c, f->totals, sizeof(c), hipMemcpyDeviceToHost, s),
+                      "read frame counts"));
     SS_TRY(hip_status(hipStreamSynchronize(s), "synchronise"));
-    *n_pairs_out = p;
-    if (p >= 0xffffffffull)
-        return fail(SS_ERR_OVERFLOW, "%llu pairs do not fit 32-bit offsets", (unsigned long long)p);
+    *out = c;
+    if (c.n_pairs >= 0xffffffffull)
+        return fail(SS_ERR_OVERFLOW, "%llu pairs do not fit 32-bit offsets",
+                    (unsigned long long)c.n_pairs);
     return SS_OK;
 }
 
+// Stages 2a-6 for the counts begin_impl returned.
 int finish_impl(const ss::BatchDims& d, int32_t mode, const ss_frame* f, const ss_pairs* p,
-                uint64_t n_pairs, float* out_single, int32_t* out_buf, const ss_stage_events* ev,
-                hipStream_t s) {
+                const ss_frame_counts* c, float* out_single, int32_t* out_buf,
+                const ss_stage_events* ev, hipStream_t s) {
     SS_TRY(check_mode(mode));
     SS_TRY(check_frame_records(f, d.n_slots));
     SS_TRY(check_frame_pixels(f));
     SS_TRY(check_table(f));
+    if (!c) return fail(SS_ERR_INVALID_ARG, "frame counts pointer is NULL");
+    if (c->n_visible > (uint64_t)d.n_slots)
+        return fail(SS_ERR_INVALID_ARG, "n_visible %llu exceeds the %lld record slots",
+                    (unsigned long long)c->n_visible, (long long)d.n_slots);
+    const uint64_t n_pairs = c->n_pairs;
+    const int64_t n_vis = (int64_t)c->n_visible;
     SS_TRY(check_pairs(p, 0, n_pairs));
     const ss::Item* table = reinterpret_cast<const ss::Item*>(f->table);
     const int bits = sort_bits_for(d.n_tiles);
     // Emit into the buffer that makes the sorted result land in buffer 0.
     const int passes = n_pairs > 1 ? ss::sort_passes(bits) : 0;
     const int first = passes & 1;
+    record(ev, 2, s);
+    SS_TRY(hip_status(ss::launch_depth_order(d.n_slots, n_vis, *f, s), "depth order"));
+    record(ev, 3, s);
+    SS_TRY(hip_status(ss::launch_scan(n_vis, *f, s), "scan"));
     record(ev, 4, s);
-    SS_TRY(hip_status(ss::launch_emit(table, d, mode, *f, p->keys[first], p->values[first],
-                                      n_pairs, s),
+    SS_TRY(hip_status(ss::launch_emit(table, d, mode, *f, n_vis, p->keys[first],
+                                      p->values[first], n_pairs, s),
                       "emit"));
     record(ev, 5, s);
     int cur = first;
@@ -320,28 +331,31 @@ int ss_preprocess(const ss_camera* cam, const ss_gaussians* g, int32_t mode, con
     return hip_status(ss::launch_preprocess(table, L.d, mode, *f, s), "preprocess");
 }
 
-int ss_depth_order(int64_t n, const ss_frame* f, void* stream) {
-    if (n < 0) return fail(SS_ERR_INVALID_ARG, "n < 0");
+int ss_depth_order(int64_t n, int64_t n_visible, const ss_frame* f, void* stream) {
+    if (n < 0 || n_visible < 0 || n_visible > n)
+        return fail(SS_ERR_INVALID_ARG, "need 0 <= n_visible <= n");
     SS_TRY(check_frame_records(f, n));
-    return hip_status(ss::launch_depth_order(n, *f, (hipStream_t)stream), "depth order");
+    return hip_status(ss::launch_depth_order(n, n_visible, *f, (hipStream_t)stream),
+                      "depth order");
 }
 
-int ss_scan(int64_t n, const ss_frame* f, void* stream) {
-    if (n < 0) return fail(SS_ERR_INVALID_ARG, "n < 0");
-    SS_TRY(check_frame_records(f, n));
-    return hip_status(ss::launch_scan(n, *f, (hipStream_t)stream), "scan");
+int ss_scan(int64_t n_visible, const ss_frame* f, void* stream) {
+    if (n_visible < 0) return fail(SS_ERR_INVALID_ARG, "n_visible < 0");
+    SS_TRY(check_frame_records(f, n_visible));
+    return hip_status(ss::launch_scan(n_visible, *f, (hipStream_t)stream), "scan");
 }
 
-int ss_emit(const ss_camera* cam, int64_t n, int32_t mode, const ss_frame* f, const ss_pairs* p,
-            int32_t buf, uint64_t n_pairs, void* stream) {
+int ss_emit(const ss_camera* cam, int64_t n, int64_t n_visible, int32_t mode, const ss_frame* f,
+            const ss_pairs* p, int32_t buf, uint64_t n_pairs, void* stream) {
     SS_TRY(check_camera(cam));
     SS_TRY(check_mode(mode));
-    if (n < 0) return fail(SS_ERR_INVALID_ARG, "n < 0");
+    if (n < 0 || n_visible < 0 || n_visible > n)
+        return fail(SS_ERR_INVALID_ARG, "need 0 <= n_visible <= n");
     SS_TRY(check_frame_records(f, n));
     SS_TRY(check_table(f));
     SS_TRY(check_pairs(p, buf, n_pairs));
     return hip_status(ss::launch_emit(reinterpret_cast<const ss::Item*>(f->table),
-                                      single_dims(*cam, n), mode, *f, p->keys[buf],
+                                      single_dims(*cam, n), mode, *f, n_visible, p->keys[buf],
                                       p->values[buf], n_pairs, (hipStream_t)stream),
                       "emit");
 }
@@ -389,43 +403,43 @@ int ss_blend(const ss_camera* cam, const ss_frame* f, const ss_pairs* p, int32_t
 }
 
 int ss_forward_begin(const ss_camera* cam, const ss_gaussians* g, int32_t mode, const ss_frame* f,
-                     uint64_t* n_pairs_out, const ss_stage_events* ev, void* stream) {
+                     ss_frame_counts* counts_out, const ss_stage_events* ev, void* stream) {
     SS_TRY(check_camera(cam));
     SS_TRY(check_gaussians(g));
-    return begin_impl(single_layout(*cam, *g), mode, f, n_pairs_out, ev, true,
+    return begin_impl(single_layout(*cam, *g), mode, f, counts_out, ev, true,
                       (hipStream_t)stream);
 }
 
 int ss_forward_begin_async(const ss_camera* cam, const ss_gaussians* g, int32_t mode,
-                           const ss_frame* f, uint64_t* n_pairs_host, const ss_stage_events* ev,
-                           void* stream) {
+                           const ss_frame* f, ss_frame_counts* counts_host,
+                           const ss_stage_events* ev, void* stream) {
     SS_TRY(check_camera(cam));
     SS_TRY(check_gaussians(g));
-    return begin_impl(single_layout(*cam, *g), mode, f, n_pairs_host, ev, false,
+    return begin_impl(single_layout(*cam, *g), mode, f, counts_host, ev, false,
                       (hipStream_t)stream);
 }
 
 int ss_forward_finish(const ss_camera* cam, int64_t n, int32_t mode, const ss_frame* f,
-                      const ss_pairs* p, uint64_t n_pairs, float* out_rgb, int32_t* out_buf,
-                      const ss_stage_events* ev, void* stream) {
+                      const ss_pairs* p, const ss_frame_counts* counts, float* out_rgb,
+                      int32_t* out_buf, const ss_stage_events* ev, void* stream) {
     SS_TRY(check_camera(cam));
     if (n < 0) return fail(SS_ERR_INVALID_ARG, "n < 0");
     if (!out_rgb) return fail(SS_ERR_INVALID_ARG, "out_rgb is NULL");
-    return finish_impl(single_dims(*cam, n), mode, f, p, n_pairs, out_rgb, out_buf, ev,
+    return finish_impl(single_dims(*cam, n), mode, f, p, counts, out_rgb, out_buf, ev,
                        (hipStream_t)stream);
 }
 
 int ss_render(const ss_camera* cam, const ss_gaussians* g, int32_t mode, const ss_frame* f,
-              const ss_pairs* p, float* out_rgb, uint64_t* n_pairs_out, int32_t* out_buf,
+              const ss_pairs* p, float* out_rgb, ss_frame_counts* counts_out, int32_t* out_buf,
               const ss_stage_events* ev, void* stream) {
     if (!p) return fail(SS_ERR_INVALID_ARG, "pairs is NULL");
-    uint64_t n_pairs = 0;
-    SS_TRY(ss_forward_begin(cam, g, mode, f, &n_pairs, ev, stream));
-    if (n_pairs_out) *n_pairs_out = n_pairs;
-    if (n_pairs > p->capacity)
+    ss_frame_counts c{};
+    SS_TRY(ss_forward_begin(cam, g, mode, f, &c, ev, stream));
+    if (counts_out) *counts_out = c;
+    if (c.n_pairs > p->capacity)
         return fail(SS_ERR_WORKSPACE, "%llu pairs exceed the workspace capacity %llu",
-                    (unsigned long long)n_pairs, (unsigned long long)p->capacity);
-    return ss_forward_finish(cam, g->n, mode, f, p, n_pairs, out_rgb, out_buf, ev, stream);
+                    (unsigned long long)c.n_pairs, (unsigned long long)p->capacity);
+    return ss_forward_finish(cam, g->n, mode, f, p, &c, out_rgb, out_buf, ev, stream);
 }
 
 int ss_batch_sizes(const ss_batch_item* items, int32_t n_items, ss_batch_info* out) {
@@ -443,20 +457,20 @@ int ss_batch_sizes(const ss_batch_item* items, int32_t n_items, ss_batch_info* o
 }
 
 int ss_batch_begin(const ss_batch_item* items, int32_t n_items, int32_t mode, const ss_frame* f,
-                   uint64_t* n_pairs_out, const ss_stage_events* ev, void* stream) {
+                   ss_frame_counts* counts_out, const ss_stage_events* ev, void* stream) {
     Layout L;
     SS_TRY(lay_out(items, n_items, L));
     for (int k = 0; k < n_items; ++k)
         if (!items[k].out_rgb) return fail(SS_ERR_INVALID_ARG, "item %d has no out_rgb", k);
-    return begin_impl(L, mode, f, n_pairs_out, ev, true, (hipStream_t)stream);
+    return begin_impl(L, mode, f, counts_out, ev, true, (hipStream_t)stream);
 }
 
 int ss_batch_finish(const ss_batch_item* items, int32_t n_items, int32_t mode, const ss_frame* f,
-                    const ss_pairs* p, uint64_t n_pairs, int32_t* out_buf,
+                    const ss_pairs* p, const ss_frame_counts* counts, int32_t* out_buf,
                     const ss_stage_events* ev, void* stream) {
     Layout L;
     SS_TRY(lay_out(items, n_items, L));
-    return finish_impl(L.d, mode, f, p, n_pairs, nullptr, out_buf, ev, (hipStream_t)stream);
+    return finish_impl(L.d, mode, f, p, counts, nullptr, out_buf, ev, (hipStream_t)stream);
 }
 
 int ss_render_backward(const ss_camera* cam, const ss_gaussians* g, const ss_frame* f,

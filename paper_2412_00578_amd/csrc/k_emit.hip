@@ -53,7 +53,8 @@ constexpr int kEmitWaves = kEmitBlock / 64;
 constexpr int kStage = 64 * (int)kSmall;     // tile ids one wave can stage
 
 __global__ __launch_bounds__(kEmitBlock) void k_emit(const Item* __restrict__ items,
-                                                     BatchDims dims, uint32_t limit,
+                                                     BatchDims dims, uint32_t n_entries,
+                                                     uint32_t limit,
                                                      const uint4* __restrict__ tsets,
                                                      const uint32_t* __restrict__ order,
                                                      const uint32_t* __restrict__ offsets,
@@ -67,7 +68,7 @@ __global__ __launch_bounds__(kEmitBlock) void k_emit(const Item* __restrict__ it
     const int w = threadIdx.x >> 6;
     const int lane = (int)__lane_id();
     const int64_t j = (int64_t)blockIdx.x * kEmitBlock + threadIdx.x;   // depth-order entry
-    const bool valid = j < dims.n_slots;
+    const bool valid = j < n_entries;
     const uint32_t end = valid ? offsets[j] : 0u;
     uint32_t prev = __shfl_up(end, 1, 64);
     if (lane == 0) prev = (valid && j > 0) ? offsets[j - 1] : 0u;
@@ -86,7 +87,7 @@ __global__ __launch_bounds__(kEmitBlock) void k_emit(const Item* __restrict__ it
         const uint32_t slot = base + __builtin_amdgcn_mbcnt_hi(
                                          (uint32_t)(bigs >> 32),
                                          __builtin_amdgcn_mbcnt_lo((uint32_t)bigs, 0u));
-        if (big && slot < (uint32_t)dims.n_slots) queue[1 + slot] = (uint32_t)j;
+        if (big && slot < n_entries) queue[1 + slot] = (uint32_t)j;
     }
     const uint32_t small = big ? 0u : cnt;
     const uint32_t incl = wave_incl_scan_u32(small);
@@ -236,15 +237,17 @@ __global__ __launch_bounds__(kBigBlock) void k_emit_big(const Item* __restrict__
 }  // namespace
 
 hipError_t launch_emit(const Item* items, const BatchDims& d, int mode, const ss_frame& f,
-                       uint32_t* keys, uint32_t* values, uint64_t n_pairs, hipStream_t s) {
-    if (d.n_slots == 0) return hipSuccess;
+                       int64_t n_entries, uint32_t* keys, uint32_t* values, uint64_t n_pairs,
+                       hipStream_t s) {
+    if (n_entries <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_zero, dim3(1), dim3(1), 0, s, f.emit_tmp);
-    const int64_t grid = (d.n_slots + kEmitBlock - 1) / kEmitBlock;
+    const int64_t grid = (n_entries + kEmitBlock - 1) / kEmitBlock;
     hipLaunchKernelGGL(k_emit, dim3((unsigned)grid), dim3(kEmitBlock), 0, s, items, d,
-                       (uint32_t)n_pairs, reinterpret_cast<const uint4*>(f.tile_sets), f.order,
-                       f.offsets, keys, values, f.emit_tmp);
+                       (uint32_t)n_entries, (uint32_t)n_pairs,
+                       reinterpret_cast<const uint4*>(f.tile_sets), f.order, f.offsets, keys,
+                       values, f.emit_tmp);
     hipLaunchKernelGGL(k_emit_big, dim3(kBigGrid), dim3(kBigBlock), 0, s, items, d, mode,
-                       (uint32_t)n_pairs, (uint32_t)d.n_slots,
+                       (uint32_t)n_pairs, (uint32_t)n_entries,
                        reinterpret_cast<const float4*>(f.geom),
                        reinterpret_cast<const float4*>(f.conic), f.order, f.offsets, keys,
                        values, f.emit_tmp);

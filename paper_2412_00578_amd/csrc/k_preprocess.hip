@@ -80,7 +80,8 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(const Item* __restrict__ 
                                                        float4* __restrict__ rgb_out,
                                                        uint32_t* __restrict__ counts,
                                                        uint32_t* __restrict__ dkeys,
-                                                       uint4* __restrict__ tsets) {
+                                                       uint4* __restrict__ tsets,
+                                                       uint64_t* __restrict__ totals) {
     __shared__ float s_sh[kBlock * kShPitch];
     const int64_t slot0 = (int64_t)blockIdx.x * kBlock;
     const Item& it = items[dims.n_items == 1 ? 0 : item_of_slot(items, dims.n_items, slot0)];
@@ -158,130 +159,154 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(const Item* __restrict__ 
     cg = fmaxf(cg + 0.5f, 0.0f);
     cbl = fmaxf(cbl + 0.5f, 0.0f);
 
-    if (o >= dims.n_slots) return;
-    const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (i >= n) {  // padding slot between items
-        geom[o] = zero; conic[o] = zero; rgb_out[o] = zero; counts[o] = 0u;
-        dkeys[o] = kCulledKey;
-        tsets[o] = make_uint4(0u, 0u, 0u, 0u);
-        return;
+    // The record, its count and its tile set; 0 for a padding slot or a culled
+    // Gaussian (whose record is zeroed).
+    auto record = [&]() -> uint32_t {
+        const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (i >= n) {  // padding slot between items
+            geom[o] = zero; conic[o] = zero; rgb_out[o] = zero; counts[o] = 0u;
+            dkeys[o] = kCulledKey;
+            tsets[o] = make_uint4(0u, 0u, 0u, 0u);
+            return 0u;
+        }
+
+        bool ok = finite_f(m0) && finite_f(m1) && finite_f(m2) && finite_f(s0) && finite_f(s1) &&
+                  finite_f(s2) && finite_f(qr.x) && finite_f(qr.y) && finite_f(qr.z) &&
+                  finite_f(qr.w) && finite_f(op) && (op > 0.0f);
+
+        // camera space p_c = R mu + t
+        const double R0 = cam.R[0], R1 = cam.R[1], R2 = cam.R[2], R3 = cam.R[3], R4 = cam.R[4],
+                     R5 = cam.R[5], R6 = cam.R[6], R7 = cam.R[7], R8 = cam.R[8];
+        const double mx = m0, my = m1, mz = m2;
+        const double x = ((R0 * mx + R1 * my) + R2 * mz) + (double)cam.t[0];
+        const double y = ((R3 * mx + R4 * my) + R5 * mz) + (double)cam.t[1];
+        const double z = ((R6 * mx + R7 * my) + R8 * mz) + (double)cam.t[2];
+        ok = ok && (z > (double)cam.near_z);
+
+        // quaternion (w, x, y, z) normalised in FP64
+        double qw = qr.x, qx = qr.y, qy = qr.z, qz = qr.w;
+        const double nn = ((qw * qw + qx * qx) + qy * qy) + qz * qz;
+        ok = ok && (nn > 0.0);
+        if (!ok) {
+            geom[o] = zero; conic[o] = zero; rgb_out[o] = zero; counts[o] = 0u;
+            dkeys[o] = kCulledKey;
+            tsets[o] = make_uint4(0u, 0u, 0u, 0u);
+            return 0u;
+        }
+        const double fx = cam.fx, fy = cam.fy;
+        const double u = (fx * x) / z + (double)cam.cx;
+        const double v = (fy * y) / z + (double)cam.cy;
+
+        const double qn = sqrt(nn);
+        qw = qw / qn; qx = qx / qn; qy = qy / qn; qz = qz / qn;
+        double Rq[9];
+        Rq[0] = 1.0 - 2.0 * (qy * qy + qz * qz);
+        Rq[1] = 2.0 * (qx * qy - qw * qz);
+        Rq[2] = 2.0 * (qx * qz + qw * qy);
+        Rq[3] = 2.0 * (qx * qy + qw * qz);
+        Rq[4] = 1.0 - 2.0 * (qx * qx + qz * qz);
+        Rq[5] = 2.0 * (qy * qz - qw * qx);
+        Rq[6] = 2.0 * (qx * qz - qw * qy);
+        Rq[7] = 2.0 * (qy * qz + qw * qx);
+        Rq[8] = 1.0 - 2.0 * (qx * qx + qy * qy);
+
+        // Sigma_3D = (R S)(R S)^T
+        const double sc[3] = {(double)s0, (double)s1, (double)s2};
+        double M[9];
+    #pragma unroll
+        for (int r = 0; r < 3; ++r)
+    #pragma unroll
+            for (int c = 0; c < 3; ++c) M[3 * r + c] = Rq[3 * r + c] * sc[c];
+        double S3[9];
+    #pragma unroll
+        for (int r = 0; r < 3; ++r)
+    #pragma unroll
+            for (int c = 0; c < 3; ++c)
+                S3[3 * r + c] = (M[3 * r] * M[3 * c] + M[3 * r + 1] * M[3 * c + 1]) +
+                                M[3 * r + 2] * M[3 * c + 2];
+
+        // EWA projection with the Jacobian at the FOV-clamped mean
+        const double limx = kFovClamp * ((0.5 * (double)cam.width) / fx);
+        const double limy = kFovClamp * ((0.5 * (double)cam.height) / fy);
+        double txz = x / z, tyz = y / z;
+        txz = txz < -limx ? -limx : txz;
+        txz = txz > limx ? limx : txz;
+        tyz = tyz < -limy ? -limy : tyz;
+        tyz = tyz > limy ? limy : tyz;
+        const double J00 = fx / z, J02 = -(fx * txz) / z;
+        const double J11 = fy / z, J12 = -(fy * tyz) / z;
+        const double Rc[9] = {R0, R1, R2, R3, R4, R5, R6, R7, R8};
+        double T[6];
+    #pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            T[j] = J00 * Rc[j] + J02 * Rc[6 + j];
+            T[3 + j] = J11 * Rc[3 + j] + J12 * Rc[6 + j];
+        }
+        double V[6];
+    #pragma unroll
+        for (int r = 0; r < 2; ++r)
+    #pragma unroll
+            for (int c = 0; c < 3; ++c)
+                V[3 * r + c] = (T[3 * r] * S3[c] + T[3 * r + 1] * S3[3 + c]) + T[3 * r + 2] * S3[6 + c];
+        const double s00 = (V[0] * T[0] + V[1] * T[1]) + V[2] * T[2];
+        const double s01 = (V[0] * T[3] + V[1] * T[4]) + V[2] * T[5];
+        const double s11 = (V[3] * T[3] + V[4] * T[4]) + V[5] * T[5];
+        const double A = s00 + kDilation, B = s01, C = s11 + kDilation;
+        const double D = A * C - B * B;
+        const float ca = (float)(C / D), cb = (float)(-B / D), cc = (float)(A / D);
+        const float tt = (float)(2.0 * log(255.0 * (double)op));
+        if (!(D > 0.0) || (mode != SS_TILE_3SIGMA && !(tt > 0.0f))) {
+            geom[o] = zero; conic[o] = zero; rgb_out[o] = zero; counts[o] = 0u;
+            dkeys[o] = kCulledKey;
+            tsets[o] = make_uint4(0u, 0u, 0u, 0u);
+            return 0u;
+        }
+
+        const float4 g4 = make_float4((float)u, (float)v, (float)z, tt);
+        const float4 q4 = make_float4(ca, cb, cc, op);
+        geom[o] = g4;
+        conic[o] = q4;
+        rgb_out[o] = make_float4(cr, cg, cbl, 0.0f);
+        uint64_t mask;
+        uint32_t origin;
+        const uint32_t cnt = tile_set(g4, q4, mode, tx_n, ty_n, &mask, &origin);
+        counts[o] = cnt;
+        dkeys[o] = cnt ? __float_as_uint(g4.z) : kCulledKey;
+        tsets[o] = make_uint4((uint32_t)mask, (uint32_t)(mask >> 32), origin, 0u);
+        return cnt;
+    };
+    const uint32_t cnt = o < dims.n_slots ? record() : 0u;
+
+    // Wave totals of the pair count P and of the Gaussians with tiles, one
+    // atomic each per wave (a wave is the whole workgroup).
+    uint32_t sp = cnt, sv = cnt ? 1u : 0u;
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        sp += __shfl_xor(sp, d, 64);
+        sv += __shfl_xor(sv, d, 64);
     }
-
-    bool ok = finite_f(m0) && finite_f(m1) && finite_f(m2) && finite_f(s0) && finite_f(s1) &&
-              finite_f(s2) && finite_f(qr.x) && finite_f(qr.y) && finite_f(qr.z) &&
-              finite_f(qr.w) && finite_f(op) && (op > 0.0f);
-
-    // camera space p_c = R mu + t
-    const double R0 = cam.R[0], R1 = cam.R[1], R2 = cam.R[2], R3 = cam.R[3], R4 = cam.R[4],
-                 R5 = cam.R[5], R6 = cam.R[6], R7 = cam.R[7], R8 = cam.R[8];
-    const double mx = m0, my = m1, mz = m2;
-    const double x = ((R0 * mx + R1 * my) + R2 * mz) + (double)cam.t[0];
-    const double y = ((R3 * mx + R4 * my) + R5 * mz) + (double)cam.t[1];
-    const double z = ((R6 * mx + R7 * my) + R8 * mz) + (double)cam.t[2];
-    ok = ok && (z > (double)cam.near_z);
-
-    // quaternion (w, x, y, z) normalised in FP64
-    double qw = qr.x, qx = qr.y, qy = qr.z, qz = qr.w;
-    const double nn = ((qw * qw + qx * qx) + qy * qy) + qz * qz;
-    ok = ok && (nn > 0.0);
-    if (!ok) {
-        geom[o] = zero; conic[o] = zero; rgb_out[o] = zero; counts[o] = 0u;
-        dkeys[o] = kCulledKey;
-        tsets[o] = make_uint4(0u, 0u, 0u, 0u);
-        return;
+    if (threadIdx.x == 0 && sv) {
+        atomicAdd(reinterpret_cast<unsigned long long*>(totals), (unsigned long long)sp);
+        atomicAdd(reinterpret_cast<unsigned long long*>(totals) + 1, (unsigned long long)sv);
     }
-    const double fx = cam.fx, fy = cam.fy;
-    const double u = (fx * x) / z + (double)cam.cx;
-    const double v = (fy * y) / z + (double)cam.cy;
-
-    const double qn = sqrt(nn);
-    qw = qw / qn; qx = qx / qn; qy = qy / qn; qz = qz / qn;
-    double Rq[9];
-    Rq[0] = 1.0 - 2.0 * (qy * qy + qz * qz);
-    Rq[1] = 2.0 * (qx * qy - qw * qz);
-    Rq[2] = 2.0 * (qx * qz + qw * qy);
-    Rq[3] = 2.0 * (qx * qy + qw * qz);
-    Rq[4] = 1.0 - 2.0 * (qx * qx + qz * qz);
-    Rq[5] = 2.0 * (qy * qz - qw * qx);
-    Rq[6] = 2.0 * (qx * qz - qw * qy);
-    Rq[7] = 2.0 * (qy * qz + qw * qx);
-    Rq[8] = 1.0 - 2.0 * (qx * qx + qy * qy);
-
-    // Sigma_3D = (R S)(R S)^T
-    const double sc[3] = {(double)s0, (double)s1, (double)s2};
-    double M[9];
-#pragma unroll
-    for (int r = 0; r < 3; ++r)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) M[3 * r + c] = Rq[3 * r + c] * sc[c];
-    double S3[9];
-#pragma unroll
-    for (int r = 0; r < 3; ++r)
-#pragma unroll
-        for (int c = 0; c < 3; ++c)
-            S3[3 * r + c] = (M[3 * r] * M[3 * c] + M[3 * r + 1] * M[3 * c + 1]) +
-                            M[3 * r + 2] * M[3 * c + 2];
-
-    // EWA projection with the Jacobian at the FOV-clamped mean
-    const double limx = kFovClamp * ((0.5 * (double)cam.width) / fx);
-    const double limy = kFovClamp * ((0.5 * (double)cam.height) / fy);
-    double txz = x / z, tyz = y / z;
-    txz = txz < -limx ? -limx : txz;
-    txz = txz > limx ? limx : txz;
-    tyz = tyz < -limy ? -limy : tyz;
-    tyz = tyz > limy ? limy : tyz;
-    const double J00 = fx / z, J02 = -(fx * txz) / z;
-    const double J11 = fy / z, J12 = -(fy * tyz) / z;
-    const double Rc[9] = {R0, R1, R2, R3, R4, R5, R6, R7, R8};
-    double T[6];
-#pragma unroll
-    for (int j = 0; j < 3; ++j) {
-        T[j] = J00 * Rc[j] + J02 * Rc[6 + j];
-        T[3 + j] = J11 * Rc[3 + j] + J12 * Rc[6 + j];
-    }
-    double V[6];
-#pragma unroll
-    for (int r = 0; r < 2; ++r)
-#pragma unroll
-        for (int c = 0; c < 3; ++c)
-            V[3 * r + c] = (T[3 * r] * S3[c] + T[3 * r + 1] * S3[3 + c]) + T[3 * r + 2] * S3[6 + c];
-    const double s00 = (V[0] * T[0] + V[1] * T[1]) + V[2] * T[2];
-    const double s01 = (V[0] * T[3] + V[1] * T[4]) + V[2] * T[5];
-    const double s11 = (V[3] * T[3] + V[4] * T[4]) + V[5] * T[5];
-    const double A = s00 + kDilation, B = s01, C = s11 + kDilation;
-    const double D = A * C - B * B;
-    const float ca = (float)(C / D), cb = (float)(-B / D), cc = (float)(A / D);
-    const float tt = (float)(2.0 * log(255.0 * (double)op));
-    if (!(D > 0.0) || (mode != SS_TILE_3SIGMA && !(tt > 0.0f))) {
-        geom[o] = zero; conic[o] = zero; rgb_out[o] = zero; counts[o] = 0u;
-        dkeys[o] = kCulledKey;
-        tsets[o] = make_uint4(0u, 0u, 0u, 0u);
-        return;
-    }
-
-    const float4 g4 = make_float4((float)u, (float)v, (float)z, tt);
-    const float4 q4 = make_float4(ca, cb, cc, op);
-    geom[o] = g4;
-    conic[o] = q4;
-    rgb_out[o] = make_float4(cr, cg, cbl, 0.0f);
-    uint64_t mask;
-    uint32_t origin;
-    const uint32_t cnt = tile_set(g4, q4, mode, tx_n, ty_n, &mask, &origin);
-    counts[o] = cnt;
-    dkeys[o] = cnt ? __float_as_uint(g4.z) : kCulledKey;
-    tsets[o] = make_uint4((uint32_t)mask, (uint32_t)(mask >> 32), origin, 0u);
 }
 
 }  // namespace
 
+__global__ void k_zero_totals(uint64_t* t) {
+    t[0] = 0ull;
+    t[1] = 0ull;
+}
+
 hipError_t launch_preprocess(const Item* items, const BatchDims& d, int mode, const ss_frame& f,
                              hipStream_t s) {
-    if (d.n_slots == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero_totals, dim3(1), dim3(1), 0, s, f.totals);
+    if (d.n_slots == 0) return hipGetLastError();
     const int64_t grid = (d.n_slots + kBlock - 1) / kBlock;
     hipLaunchKernelGGL(k_preprocess, dim3((unsigned)grid), dim3(kBlock), 0, s, items, d, mode,
                        reinterpret_cast<float4*>(f.geom), reinterpret_cast<float4*>(f.conic),
                        reinterpret_cast<float4*>(f.rgb), f.counts, f.depth_keys,
-                       reinterpret_cast<uint4*>(f.tile_sets));
+                       reinterpret_cast<uint4*>(f.tile_sets), f.totals);
     return hipGetLastError();
 }
 

@@ -73,9 +73,11 @@ __device__ __forceinline__ uint32_t lanes_below(uint64_t m) {
 // Each wave counts 64 keys at a time: lanes with equal digits are matched and
 // the lowest of them adds the group's size, so a digit shared by many keys
 // costs one LDS atomic per wave instead of one per key.
+// drop: keys equal to kCulledKey are left out (the compacting first pass of
+// the depth order).
 template <class K>
 __global__ __launch_bounds__(kBlock) void k_hist(const K* __restrict__ keys, uint64_t n, int shift,
-                                                 uint64_t chunk, uint32_t grid,
+                                                 uint64_t chunk, uint32_t grid, bool drop,
                                                  uint32_t* __restrict__ hist) {
     __shared__ uint32_t h[kWaves][kRadix];
     for (int k = threadIdx.x; k < kWaves * kRadix; k += kBlock) (&h[0][0])[k] = 0u;
@@ -85,8 +87,9 @@ __global__ __launch_bounds__(kBlock) void k_hist(const K* __restrict__ keys, uin
     const int w = threadIdx.x >> 6;
     for (uint64_t base = lo; base < hi; base += kBlock) {   // uniform trip count
         const uint64_t i = base + threadIdx.x;
-        const bool valid = i < hi;
-        const uint32_t d = valid ? digit_of(keys[i], shift) : 0u;
+        const K key = i < hi ? keys[i] : (K)0;
+        const bool valid = i < hi && !(drop && key == (K)kCulledKey);
+        const uint32_t d = valid ? digit_of(key, shift) : 0u;
         const uint64_t m = match_digit(d, valid);
         if (valid && lanes_below(m) == 0u) atomicAdd(&h[w][d], (uint32_t)__popcll(m));
     }
@@ -152,13 +155,15 @@ __global__ __launch_bounds__(kBlock) void k_dscan(uint32_t* __restrict__ hist, u
 
 // vals_in == nullptr stands for the identity (value = input position);
 // keys_out == nullptr skips the key writes (a last pass whose keys are unused);
-// with gather_out, gather_out[p] = gather[value] for every output position p.
+// with gather_out, gather_out[p] = gather[value] for every output position p;
+// drop: keys equal to kCulledKey are left out, as in k_hist.
 template <class K>
 __global__ __launch_bounds__(kBlock) void k_scatter(const K* __restrict__ keys_in,
                                                     const uint32_t* __restrict__ vals_in,
                                                     K* __restrict__ keys_out,
                                                     uint32_t* __restrict__ vals_out, uint64_t n,
                                                     int shift, uint64_t chunk, uint32_t grid,
+                                                    bool drop,
                                                     const uint32_t* __restrict__ hist,
                                                     const uint32_t* __restrict__ gather,
                                                     uint32_t* __restrict__ gather_out) {
@@ -198,7 +203,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const K* __restrict__ keys_i
 #pragma unroll
         for (int k = 0; k < kItems; ++k) {
             const uint64_t idx = sub + (uint64_t)w * (64 * kItems) + (uint64_t)k * 64 + lane;
-            const bool valid = idx < hi;
+            const bool valid = idx < hi && !(drop && key[k] == (K)kCulledKey);
             const uint32_t d = digit_of(key[k], shift);
             const uint64_t m = match_digit(d, valid);
             const uint32_t below = lanes_below(m);
@@ -223,7 +228,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const K* __restrict__ keys_i
 #pragma unroll
         for (int k = 0; k < kItems; ++k) {
             const uint64_t idx = sub + (uint64_t)w * (64 * kItems) + (uint64_t)k * 64 + lane;
-            if (idx < hi) {
+            if (idx < hi && !(drop && key[k] == (K)kCulledKey)) {
                 const uint32_t d = digit_of(key[k], shift);
                 const uint32_t lp = lstart[d] + wcnt[w][d] + rank[k];
                 if (lp < (uint32_t)kSub) {
@@ -233,7 +238,8 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const K* __restrict__ keys_i
             }
         }
         __syncthreads();
-        const uint32_t n_sub = (uint32_t)(hi - sub < (uint64_t)kSub ? hi - sub : (uint64_t)kSub);
+        // keys kept in this sub-tile: the end of the last digit's run
+        const uint32_t n_sub = lstart[kRadix - 1] + tot[kRadix - 1];
         for (uint32_t i = t; i < n_sub; i += kBlock) {
             const K kk = s_key[i];
             const uint32_t d = digit_of(kk, shift);
@@ -264,39 +270,37 @@ __global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ key
     for (int t = prev < 0 ? 0 : prev; t < cur && t < n_tiles; ++t) ranges[2 * t + 1] = (uint32_t)i;
 }
 
-// Sorts n (key, value) pairs on the low `bits` key bits, ping-ponging between
+// Sorts (key, value) pairs on the low `bits` key bits, ping-ponging between
 // buffers 0 and 1 from buffer `cur`; *out_buf receives the buffer holding the
-// result.  identity: the input values are 0..n-1 and are not read.  With
-// last_keys false the final pass writes values only; with gather_out it also
-// writes gather[value] in the sorted order.
+// result.  The first pass reads n0 pairs; with drop it leaves out the keys
+// equal to kCulledKey, of which there must be n0 - n, and every later pass
+// sorts the n kept pairs (without drop, n0 == n).  identity: the input values
+// are 0..n0-1 and are not read.  With last_keys false the final pass writes
+// values only; with gather_out it also writes gather[value] in sorted order.
 template <class K>
-hipError_t radix_sort(K* keys[2], uint32_t* vals[2], int cur, uint64_t n, int bits,
-                      uint32_t* tmp, bool identity, bool last_keys, const uint32_t* gather,
-                      uint32_t* gather_out, int* out_buf, hipStream_t s) {
-    if (n > 1) {
-        const Plan plan = make_plan(n);
-        const int passes = (bits + 7) / 8;
-        for (int pass = 0; pass < passes; ++pass) {
-            const int shift = pass * 8;
-            K* kout = (pass + 1 == passes && !last_keys) ? nullptr : keys[1 - cur];
-            const uint32_t* vin = (pass == 0 && identity) ? nullptr : vals[cur];
-            hipLaunchKernelGGL(k_hist<K>, dim3(plan.grid), dim3(kBlock), 0, s, keys[cur], n,
-                               shift, plan.chunk, plan.grid, tmp);
-            hipLaunchKernelGGL(k_dscan, dim3(kRadix), dim3(kBlock), 0, s, tmp, plan.grid);
-            const bool last = pass + 1 == passes;
-            hipLaunchKernelGGL(k_scatter<K>, dim3(plan.grid), dim3(kBlock), 0, s, keys[cur],
-                               vin, kout, vals[1 - cur], n, shift, plan.chunk, plan.grid, tmp,
-                               gather, last ? gather_out : nullptr);
-            cur = 1 - cur;
-        }
+hipError_t radix_sort(K* keys[2], uint32_t* vals[2], int cur, uint64_t n0, uint64_t n, int bits,
+                      uint32_t* tmp, bool drop, bool identity, bool last_keys,
+                      const uint32_t* gather, uint32_t* gather_out, int* out_buf,
+                      hipStream_t s) {
+    const int passes = (bits + 7) / 8;
+    for (int pass = 0; pass < passes; ++pass) {
+        const uint64_t m = pass == 0 ? n0 : n;       // pairs this pass reads
+        const Plan plan = make_plan(m);
+        const int shift = pass * 8;
+        const bool last = pass + 1 == passes;
+        const bool dr = pass == 0 && drop;
+        K* kout = (last && !last_keys) ? nullptr : keys[1 - cur];
+        const uint32_t* vin = (pass == 0 && identity) ? nullptr : vals[cur];
+        hipLaunchKernelGGL(k_hist<K>, dim3(plan.grid), dim3(kBlock), 0, s, keys[cur], m, shift,
+                           plan.chunk, plan.grid, dr, tmp);
+        hipLaunchKernelGGL(k_dscan, dim3(kRadix), dim3(kBlock), 0, s, tmp, plan.grid);
+        hipLaunchKernelGGL(k_scatter<K>, dim3(plan.grid), dim3(kBlock), 0, s, keys[cur], vin,
+                           kout, vals[1 - cur], m, shift, plan.chunk, plan.grid, dr, tmp, gather,
+                           last ? gather_out : nullptr);
+        cur = 1 - cur;
     }
     *out_buf = cur;
     return hipGetLastError();
-}
-
-__global__ void k_identity1(uint32_t* v, const uint32_t* counts, uint32_t* order_counts) {
-    v[0] = 0u;
-    order_counts[0] = counts[0];
 }
 
 }  // namespace
@@ -305,28 +309,28 @@ int sort_passes(int bits) { return (bits + 7) / 8; }
 
 int64_t sort_tmp_words(uint64_t) { return (int64_t)kRadix * kMaxGrid + kRadix; }
 
-hipError_t launch_depth_order(int64_t n, const ss_frame& f, hipStream_t s) {
-    if (n <= 0) return hipSuccess;
-    if (n == 1) {   // a single slot is its own order
-        hipLaunchKernelGGL(k_identity1, dim3(1), dim3(1), 0, s, f.order, f.counts,
-                           f.order_counts);
-        return hipGetLastError();
-    }
+hipError_t launch_depth_order(int64_t n, int64_t n_visible, const ss_frame& f, hipStream_t s) {
+    if (n <= 0 || n_visible <= 0) return hipSuccess;
     uint32_t* keys[2] = {f.depth_keys, f.depth_keys + n};
     uint32_t* vals[2] = {f.order, f.order + n};
     int out = 0;
-    // 4 passes from buffer 0 end in buffer 0: the order lands in f.order[0, n),
-    // and the last pass writes the tile counts in that order.
-    return radix_sort<uint32_t>(keys, vals, 0, (uint64_t)n, 32, f.order_tmp, true, false,
-                                f.counts, f.order_counts, &out, s);
+    // 4 passes from buffer 0 end in buffer 0: the first drops the Gaussians
+    // without tiles, the order lands in f.order[0, n_visible) and the last pass
+    // writes the tile counts in that order.
+    return radix_sort<uint32_t>(keys, vals, 0, (uint64_t)n, (uint64_t)n_visible, 32, f.order_tmp,
+                                true, true, false, f.counts, f.order_counts, &out, s);
 }
 
 hipError_t launch_sort(const ss_pairs& p, int buf, uint64_t n, int bits, int* out_buf,
                        hipStream_t s) {
     uint32_t* keys[2] = {p.keys[0], p.keys[1]};
     uint32_t* vals[2] = {p.values[0], p.values[1]};
-    return radix_sort<uint32_t>(keys, vals, buf, n, bits, p.sort_tmp, false, true, nullptr,
-                                nullptr, out_buf, s);
+    if (n <= 1) {
+        *out_buf = buf;
+        return hipSuccess;
+    }
+    return radix_sort<uint32_t>(keys, vals, buf, n, n, bits, p.sort_tmp, false, false, true,
+                                nullptr, nullptr, out_buf, s);
 }
 
 hipError_t launch_ranges(const uint32_t* keys, uint64_t n, int n_tiles, uint32_t* ranges,

@@ -276,11 +276,12 @@ __device__ __forceinline__ int item_of_tile(const Item* items, int n_items, int 
 hipError_t write_items(Item* table, const Item* host_items, int n_items, hipStream_t s);
 hipError_t launch_preprocess(const Item* items, const BatchDims& d, int mode, const ss_frame& f,
                              hipStream_t s);
-hipError_t launch_depth_order(int64_t n, const ss_frame& f, hipStream_t s);
+hipError_t launch_depth_order(int64_t n, int64_t n_visible, const ss_frame& f, hipStream_t s);
 hipError_t launch_scan(int64_t n, const ss_frame& f, hipStream_t s);
 int64_t scan_tmp_words(int64_t n);
 hipError_t launch_emit(const Item* items, const BatchDims& d, int mode, const ss_frame& f,
-                       uint32_t* keys, uint32_t* values, uint64_t n_pairs, hipStream_t s);
+                       int64_t n_entries, uint32_t* keys, uint32_t* values, uint64_t n_pairs,
+                       hipStream_t s);
 int64_t sort_tmp_words(uint64_t capacity);
 int sort_passes(int bits);
 hipError_t launch_sort(const ss_pairs& p, int buf, uint64_t n_pairs, int bits, int* out_buf,

@@ -96,6 +96,7 @@ class Frame:
         self.tile_sets = torch.empty((n, 4), dtype=torch.int32, device=dev)
         self.offsets = torch.empty(n, dtype=torch.int32, device=dev)
         self.scan_tmp = torch.zeros(int(info.scan_tmp_words), dtype=torch.int64, device=dev)
+        self.totals = torch.zeros(2, dtype=torch.int64, device=dev)
         self.ranges = torch.empty((info.n_tiles, 2), dtype=torch.int32, device=dev)
         self.t_final = torch.empty((height, width), dtype=torch.float32, device=dev)
         self.n_last = torch.empty((height, width), dtype=torch.int32, device=dev)
@@ -107,8 +108,8 @@ class Frame:
     def struct(self) -> _lib.SSFrame:
         f = _lib.SSFrame()
         for name in ("geom", "conic", "rgb", "counts", "depth_keys", "order", "order_counts",
-                     "order_tmp", "tile_sets", "offsets", "scan_tmp", "ranges", "t_final", "n_last", "n_eval",
-                     "emit_tmp", "table"):
+                     "order_tmp", "tile_sets", "offsets", "scan_tmp", "totals", "ranges",
+                     "t_final", "n_last", "n_eval", "emit_tmp", "table"):
             t = getattr(self, name)
             setattr(f, name, t.data_ptr() if t is not None else None)
         return f
@@ -140,7 +141,7 @@ class Pairs:
         return p
 
 
-STAGES = ("preprocess", "depth_order", "scan", "readback", "emit", "sort", "ranges", "blend")
+STAGES = ("preprocess", "readback", "depth_order", "scan", "emit", "sort", "ranges", "blend")
 
 
 class StageEvents:
@@ -172,6 +173,7 @@ class StageEvents:
 class RenderOutput:
     image: torch.Tensor      # [3, H, W]
     n_pairs: int
+    n_visible: int           # Gaussians with at least one tile
     frame: Frame
     pairs: Pairs
     buf: int                 # pair buffer holding the sorted pairs
@@ -215,19 +217,20 @@ class Renderer:
             out = torch.empty((3, c.height, c.width), dtype=torch.float32, device=self.device)
         gs, fs = g.struct(), frame.struct()
         stream = _stream(self.device)
-        n_pairs = ctypes.c_uint64()
+        counts = _lib.SSFrameCounts()
         ev = events.struct() if events is not None else None
         evp = ctypes.byref(ev) if ev is not None else None
         check(lib().ss_forward_begin(ctypes.byref(c), ctypes.byref(gs), m, ctypes.byref(fs),
-                                     ctypes.byref(n_pairs), evp, stream), "ss_forward_begin")
-        pairs = self.pairs_for(n_pairs.value)
+                                     ctypes.byref(counts), evp, stream), "ss_forward_begin")
+        pairs = self.pairs_for(counts.n_pairs)
         ps = pairs.struct()
         buf = ctypes.c_int32()
         check(lib().ss_forward_finish(ctypes.byref(c), g.n, m, ctypes.byref(fs), ctypes.byref(ps),
-                                      n_pairs.value, _ptr(out), ctypes.byref(buf), evp, stream),
-              "ss_forward_finish")
+                                      ctypes.byref(counts), _ptr(out), ctypes.byref(buf), evp,
+                                      stream), "ss_forward_finish")
         if full:
-            return RenderOutput(out, int(n_pairs.value), frame, pairs, int(buf.value))
+            return RenderOutput(out, int(counts.n_pairs), int(counts.n_visible), frame, pairs,
+                                int(buf.value))
         return out
 
     def _ring_frame(self, s, n, width, height) -> Frame:
@@ -239,9 +242,9 @@ class Renderer:
 
     def render_many(self, g: Gaussians, cams, mode="accutile", outs=None) -> list:
         """Renders one frame per camera, keeping the host one frame ahead of the
-        GPU: frame k+1's preprocess, depth order and scan are enqueued (into the
-        second of two frame buffers) before frame k's emit, sort, ranges and
-        blend, and each pair count comes back by an asynchronous copy, so the
+        GPU: frame k+1's preprocess is enqueued (into the second of two frame
+        buffers) before frame k's depth order, scan, emit, sort, ranges and
+        blend, and each frame's counts come back by an asynchronous copy, so the
         GPU never idles waiting for the host between frames.  Every frame is
         rendered completely; the images are valid once the stream syncs."""
         m = mode_id(mode)
@@ -254,8 +257,8 @@ class Renderer:
         st = torch.cuda.current_stream(self.device)
         sp = ctypes.c_void_p(st.cuda_stream)
         gs = g.struct()
-        if self._host_p is None:
-            self._host_p = torch.zeros(2, dtype=torch.int64, pin_memory=True)
+        if self._host_p is None:   # two ss_frame_counts, one per frame buffer
+            self._host_p = torch.zeros((2, 2), dtype=torch.int64, pin_memory=True)
         host = self._host_p
         ready = [torch.cuda.Event(), torch.cuda.Event()]
         fss = [None, None]
@@ -265,7 +268,7 @@ class Renderer:
             fss[s] = self._ring_frame(s, g.n, cs[k].width, cs[k].height).struct()
             check(lib().ss_forward_begin_async(ctypes.byref(cs[k]), ctypes.byref(gs), m,
                                                ctypes.byref(fss[s]),
-                                               ctypes.c_void_p(host.data_ptr() + 8 * s), None,
+                                               ctypes.c_void_p(host.data_ptr() + 16 * s), None,
                                                sp), "ss_forward_begin_async")
             ready[s].record(st)
 
@@ -276,10 +279,10 @@ class Renderer:
                 begin(k + 1)
             s = k % 2
             ready[s].synchronize()
-            n_pairs = int(host[s])
-            ps = self.pairs_for(n_pairs).struct()
+            counts = _lib.SSFrameCounts(int(host[s, 0]), int(host[s, 1]))
+            ps = self.pairs_for(counts.n_pairs).struct()
             check(lib().ss_forward_finish(ctypes.byref(cs[k]), g.n, m, ctypes.byref(fss[s]),
-                                          ctypes.byref(ps), n_pairs, _ptr(outs[k]),
+                                          ctypes.byref(ps), ctypes.byref(counts), _ptr(outs[k]),
                                           ctypes.byref(buf), None, sp), "ss_forward_finish")
         return outs
 
@@ -292,24 +295,31 @@ class Renderer:
                                   ctypes.byref(fs), _stream(self.device)), "ss_preprocess")
         return frame
 
-    def depth_order(self, frame: Frame) -> torch.Tensor:
-        """Stage 2a; returns frame.order[:n] (Gaussians by depth, then index)."""
-        fs = frame.struct()
-        check(lib().ss_depth_order(frame.n, ctypes.byref(fs), _stream(self.device)),
-              "ss_depth_order")
-        return frame.order[:frame.n]
+    def counts(self, frame: Frame) -> tuple:
+        """(P, n_visible) the preprocess stage accumulated (synchronises)."""
+        torch.cuda.current_stream(self.device).synchronize()
+        t = frame.totals.cpu()
+        return int(t[0]), int(t[1])
 
-    def scan(self, frame: Frame) -> int:
+    def depth_order(self, frame: Frame, n_visible: int) -> torch.Tensor:
+        """Stage 2a; returns frame.order[:n_visible] (Gaussians with tiles by
+        depth, then index)."""
         fs = frame.struct()
-        check(lib().ss_scan(frame.n, ctypes.byref(fs), _stream(self.device)), "ss_scan")
+        check(lib().ss_depth_order(frame.n, n_visible, ctypes.byref(fs), _stream(self.device)),
+              "ss_depth_order")
+        return frame.order[:n_visible]
+
+    def scan(self, frame: Frame, n_visible: int) -> int:
+        fs = frame.struct()
+        check(lib().ss_scan(n_visible, ctypes.byref(fs), _stream(self.device)), "ss_scan")
         torch.cuda.current_stream(self.device).synchronize()
         return int(frame.scan_tmp[0].item())
 
-    def emit(self, cam, frame: Frame, mode, n_pairs: int, buf: int = 0) -> Pairs:
+    def emit(self, cam, frame: Frame, mode, n_visible: int, n_pairs: int, buf: int = 0) -> Pairs:
         c = make_camera(cam)
         pairs = self.pairs_for(n_pairs)
         fs, ps = frame.struct(), pairs.struct()
-        check(lib().ss_emit(ctypes.byref(c), frame.n, mode_id(mode), ctypes.byref(fs),
+        check(lib().ss_emit(ctypes.byref(c), frame.n, n_visible, mode_id(mode), ctypes.byref(fs),
                             ctypes.byref(ps), buf, n_pairs, _stream(self.device)), "ss_emit")
         return pairs
 
@@ -346,7 +356,8 @@ class Grads:
     quats: torch.Tensor
     opacity: torch.Tensor
     sh: torch.Tensor
-    g2d: torch.Tensor        # [n, 12] screen-space gradients (u, v, -, -, a, b, c, sigma, r, g, b, -)
+    g2d: torch.Tensor        # [n, 12] screen-space gradients
+    #                          (u, v, -, -, a, b, c, sigma, r, g, b, -)
     score: torch.Tensor | None
 
 
@@ -434,6 +445,7 @@ class BatchFrame:
         self.tile_sets = torch.empty((ns, 4), dtype=torch.int32, device=dev)
         self.offsets = torch.empty(ns, dtype=torch.int32, device=dev)
         self.scan_tmp = torch.zeros(int(info.scan_tmp_words), dtype=torch.int64, device=dev)
+        self.totals = torch.zeros(2, dtype=torch.int64, device=dev)
         self.ranges = torch.empty((max(int(info.n_tiles), 1), 2), dtype=torch.int32, device=dev)
         self.t_final = torch.empty(max(npx, 1), dtype=torch.float32, device=dev)
         self.n_last = torch.empty(max(npx, 1), dtype=torch.int32, device=dev)
@@ -447,8 +459,9 @@ class BatchFrame:
     def nbytes(self) -> int:
         return sum(t.numel() * t.element_size() for t in
                    (self.geom, self.conic, self.rgb, self.counts, self.depth_keys, self.order,
-                    self.order_counts, self.order_tmp, self.tile_sets, self.offsets, self.scan_tmp, self.ranges, self.t_final,
-                    self.n_last, self.emit_tmp, self.table))
+                    self.order_counts, self.order_tmp, self.tile_sets, self.offsets,
+                    self.scan_tmp, self.totals, self.ranges, self.t_final, self.n_last,
+                    self.emit_tmp, self.table))
 
 
 def batch_items(requests, outs) -> "ctypes.Array":
@@ -476,7 +489,7 @@ class BatchRenderer:
         self.growth = growth
 
     def begin(self, requests, mode="accutile", outs=None, stream=None):
-        """Stages 1-2b for [(Gaussians, camera), ...]; returns a handle with the
+        """Stage 1 for [(Gaussians, camera), ...]; returns a handle with the
         pair count (synchronises `stream`)."""
         n = len(requests)
         if outs is None:
@@ -488,10 +501,10 @@ class BatchRenderer:
         fs = frame.struct()
         st = ctypes.c_void_p(stream.cuda_stream if stream is not None else
                              torch.cuda.current_stream(self.device).cuda_stream)
-        n_pairs = ctypes.c_uint64()
+        counts = _lib.SSFrameCounts()
         check(lib().ss_batch_begin(items, n, mode_id(mode), ctypes.byref(fs),
-                                   ctypes.byref(n_pairs), None, st), "ss_batch_begin")
-        return _BatchHandle(items, n, mode_id(mode), frame, int(n_pairs.value), outs, st)
+                                   ctypes.byref(counts), None, st), "ss_batch_begin")
+        return _BatchHandle(items, n, mode_id(mode), frame, counts, outs, st)
 
     def finish(self, h: "_BatchHandle"):
         """Stages 3-6; returns the output images (valid after the stream syncs)."""
@@ -499,7 +512,7 @@ class BatchRenderer:
         fs, ps = h.frame.struct(), h.pairs.struct()
         buf = ctypes.c_int32()
         check(lib().ss_batch_finish(h.items, h.n, h.mode, ctypes.byref(fs), ctypes.byref(ps),
-                                    h.n_pairs, ctypes.byref(buf), None, h.stream),
+                                    ctypes.byref(h.counts), ctypes.byref(buf), None, h.stream),
               "ss_batch_finish")
         return h.outs
 
@@ -513,10 +526,14 @@ class _BatchHandle:
     n: int
     mode: int
     frame: BatchFrame
-    n_pairs: int
+    counts: _lib.SSFrameCounts
     outs: list
     stream: ctypes.c_void_p
     pairs: Pairs | None = None
+
+    @property
+    def n_pairs(self) -> int:
+        return int(self.counts.n_pairs)
 
     @property
     def nbytes(self) -> int:

@@ -27,13 +27,16 @@ def gpu_stages(renderer, g, cam, mode):
         "tiles_x": int(cam.tiles_x),
     }
     out["depth_keys"] = u32(frame.depth_keys[:frame.n]).copy()
-    out["order"] = u32(renderer.depth_order(frame)).copy()
+    p_pre, nv = renderer.counts(frame)
+    out["n_visible"] = nv
+    out["n_pairs_pre"] = p_pre
+    out["order"] = u32(renderer.depth_order(frame, nv)).copy()
     torch.cuda.synchronize()
-    out["order_counts"] = u32(frame.order_counts).copy()
-    p = renderer.scan(frame)
+    out["order_counts"] = u32(frame.order_counts[:nv]).copy()
+    p = renderer.scan(frame, nv)
     out["n_pairs"] = p
-    out["offsets"] = u32(frame.offsets).copy()
-    pairs = renderer.emit(cam, frame, mode, p, buf=0)
+    out["offsets"] = u32(frame.offsets[:nv]).copy()
+    pairs = renderer.emit(cam, frame, mode, nv, p, buf=0)
     torch.cuda.synchronize()
     out["keys"] = u32(pairs.keys[0][:p]).copy()
     out["values"] = u32(pairs.values[0][:p]).copy()
@@ -146,7 +149,10 @@ def assert_pipeline_equal(gpu, fr, image_tol=1e-4):
     assert_tile_sets(gpu["tile_sets"], fr, gpu["tiles_x"])
     dk = expected_depth_keys(fr.records)
     assert np.array_equal(gpu["depth_keys"], dk), first_diffs(gpu["depth_keys"], dk)
-    order = expected_order(dk)
+    nv = int((fr.records.counts > 0).sum())
+    assert gpu["n_visible"] == nv
+    assert gpu["n_pairs_pre"] == fr.n_pairs
+    order = expected_order(dk)[:nv]         # Gaussians without tiles sort last
     assert np.array_equal(gpu["order"], order), first_diffs(gpu["order"], order)
     assert np.array_equal(gpu["order_counts"], fr.records.counts[order])
     assert gpu["n_pairs"] == fr.n_pairs

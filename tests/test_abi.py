@@ -40,7 +40,7 @@ def test_every_declared_symbol_is_exported_and_bound(L):
 def test_constants_match_independent_values(L):
     from paper_2412_00578_amd import _lib
     c = _lib.constants()
-    assert c.abi_version == 2 and c.tile == 16
+    assert c.abi_version == 3 and c.tile == 16
     assert c.alpha_min == pytest.approx(1 / 255, rel=1e-7)
     assert c.alpha_max == pytest.approx(0.99, rel=1e-7)
     assert c.t_min == pytest.approx(1e-4, rel=1e-7)
@@ -130,7 +130,8 @@ def test_ctypes_layouts_match_the_header(tmp_path):
         pytest.skip("gcc not available")
     structs = {"ss_constants": _lib.SSConstants, "ss_camera": _lib.SSCamera,
                "ss_gaussians": _lib.SSGaussians, "ss_frame": _lib.SSFrame,
-               "ss_frame_info": _lib.SSFrameInfo, "ss_batch_item": _lib.SSBatchItem,
+               "ss_frame_info": _lib.SSFrameInfo, "ss_frame_counts": _lib.SSFrameCounts,
+               "ss_batch_item": _lib.SSBatchItem,
                "ss_batch_info": _lib.SSBatchInfo, "ss_pairs": _lib.SSPairs,
                "ss_grads": _lib.SSGrads, "ss_stage_events": _lib.SSStageEvents}
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "speedysplat.h"',
@@ -146,8 +147,8 @@ def test_ctypes_layouts_match_the_header(tmp_path):
     src = tmp_path / "layout.c"
     src.write_text("\n".join(lines) + "\n")
     exe = tmp_path / "layout"
-    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
-                   check=True)
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o",
+                    str(exe)], check=True)
     got = [int(x) for x in subprocess.run([str(exe)], check=True, capture_output=True,
                                           text=True).stdout.split()]
     assert got == want
