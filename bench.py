@@ -49,13 +49,12 @@ PEAK_HBM_GBS = 8000.0
 # (a dx) dx, (2b) dx, two FMAs and the compare (an FMA counts as one).
 OPS_PER_EVAL = 8
 # Algorithmic HBM bytes: preprocess reads 236 B (SH-3 inputs) and writes a 56 B
-# record (geom, conic, rgb, count, depth key) per Gaussian; the depth order
-# moves 72 B per Gaussian over its four passes (histogram read 4 B, key and
-# value read and write 4 B each, less the identity values the first pass does
-# not read and the keys the last pass does not write); the tile sort moves
-# 20 B per pair per 8-bit pass.
-PRE_BYTES_PER_G = 236 + 56
-DEPTH_ORDER_BYTES_PER_G = 72
+# record (geom, conic, rgb, count, depth key, tile set: 72 B) per Gaussian;
+# the depth order moves 8 B per slot in its compacting first pass plus 60 B
+# per Gaussian with tiles over all four passes; the tile sort moves 20 B per
+# pair per 8-bit pass.
+PRE_BYTES_PER_G = 236 + 72
+DEPTH_ORDER_BYTES_PER_SLOT, DEPTH_ORDER_BYTES_PER_VISIBLE = 8, 60
 SORT_BYTES_PER_PAIR_PASS = 20
 
 
@@ -208,14 +207,16 @@ def main():
     # Work counters per camera (untimed): pairs and evaluated pixel-Gaussian pairs.
     work = {}
     for mode in modes:
-        P, E = [], []
+        P, E, V = [], [], []
         for cam in cams:
             out = r_stats.render(g, cam, mode, full=True)
             torch.cuda.synchronize()
             P.append(out.n_pairs)
+            V.append(out.n_visible)
             E.append(int(out.frame.n_eval.to(torch.int64).sum().item()))
-        work[mode] = (P, E)
-        log(f"{mode}: pairs/frame {np.mean(P):.0f}, evaluated pairs/frame {np.mean(E):.3e}")
+        work[mode] = (P, E, V)
+        log(f"{mode}: pairs/frame {np.mean(P):.0f}, evaluated pairs/frame {np.mean(E):.3e}, "
+            f"Gaussians with tiles {np.mean(V):.0f}")
     del r_stats
 
     results = {}
@@ -233,19 +234,22 @@ def main():
         total_ms = start.elapsed_time(stop)
         ms = total_ms / args.steps
         stages = {s: statistics.mean(e.stage_ms()[s] for e in evs) for s in ss.STAGES}
-        P, E = work[mode]
+        P, E, V = work[mode]
         steps_cam = [k % len(cams) for k in range(args.steps)]
         p_mean = statistics.mean(P[c] for c in steps_cam)
         e_mean = statistics.mean(E[c] for c in steps_cam)
+        v_mean = statistics.mean(V[c] for c in steps_cam)
         passes = (int(np.ceil(np.log2(cams[0].tiles_x * cams[0].tiles_y))) + 7) // 8
         results[mode] = {
             "fps": round(1000.0 / ms, 2), "ms_per_frame": round(ms, 4),
             "stage_ms": {k: round(v, 4) for k, v in stages.items()},
             "pairs_per_frame": int(p_mean), "evaluated_pairs_per_frame": int(e_mean),
+            "gaussians_with_tiles": int(v_mean),
             "blend_tflops": round(e_mean * OPS_PER_EVAL / (stages["blend"] * 1e-3) / 1e12, 3),
             "preprocess_gbs": round(args.n * PRE_BYTES_PER_G / (stages["preprocess"] * 1e-3) / 1e9,
                                     1),
-            "depth_order_gbs": round(args.n * DEPTH_ORDER_BYTES_PER_G /
+            "depth_order_gbs": round((args.n * DEPTH_ORDER_BYTES_PER_SLOT +
+                                      v_mean * DEPTH_ORDER_BYTES_PER_VISIBLE) /
                                      (stages["depth_order"] * 1e-3) / 1e9, 1),
             "sort_gbs": round(p_mean * SORT_BYTES_PER_PAIR_PASS * passes /
                               (stages["sort"] * 1e-3) / 1e9, 1),
