@@ -25,6 +25,8 @@ def gpu_stages(renderer, g, cam, mode):
         "counts": u32(frame.counts).copy(),
         "tile_sets": u32(frame.tile_sets).copy(),
         "tiles_x": int(cam.tiles_x),
+        "tiles_y": int(cam.tiles_y),
+        "mode": mode,
     }
     out["depth_keys"] = u32(frame.depth_keys[:frame.n]).copy()
     p_pre, nv = renderer.counts(frame)
@@ -96,9 +98,11 @@ def segment_sorted(keys, counts_in_order):
     return keys[np.lexsort((keys, seg))]
 
 
-def assert_tile_sets(tsets, fr, tiles_x):
+def assert_tile_sets(tsets, fr, tiles_x, tiles_y, mode):
     """Every stored tile mask expands to exactly the oracle's tile list, and a
-    Gaussian without a mask has a tile rectangle wider or taller than 8."""
+    Gaussian with tiles but without a mask has a tile rectangle wider or taller
+    than 8 tiles (the rectangle, not the tile list: an AccuTile list can miss a
+    corner tile of its rectangle)."""
     counts = fr.records.counts.astype(np.int64)
     mask = tsets[:, 0].astype(np.uint64) | (tsets[:, 1].astype(np.uint64) << np.uint64(32))
     x0, y0 = (tsets[:, 2] & 0xFFFF).astype(np.int64), (tsets[:, 2] >> 16).astype(np.int64)
@@ -112,16 +116,11 @@ def assert_tile_sets(tsets, fr, tiles_x):
     gi = np.nonzero(has)[0][g]
     got = (y0[gi] + b // 8) * tiles_x + x0[gi] + b % 8
     assert np.array_equal(got, tiles[has[owner]])
-    # unmasked Gaussians with tiles: their tile extent exceeds 8 on a side
-    rest = (~has) & (counts > 0)
-    sel = rest[owner]
-    if sel.any():
-        t, o = tiles[sel], owner[sel]
-        first = np.r_[0, np.nonzero(np.diff(o))[0] + 1]
-        tx, ty = t % tiles_x, t // tiles_x
-        wide = (np.maximum.reduceat(tx, first) - np.minimum.reduceat(tx, first) >= 8) | \
-            (np.maximum.reduceat(ty, first) - np.minimum.reduceat(ty, first) >= 8)
-        assert wide.all()
+    # unmasked Gaussians with tiles: their tile rectangle exceeds 8 on a side
+    rec = fr.records
+    for i in np.nonzero((~has) & (counts > 0))[0]:
+        x0r, y0r, x1r, y1r = oracle.tile_rect(rec.geom[i], rec.conic[i], mode, tiles_x, tiles_y)
+        assert x1r - x0r >= 8 or y1r - y0r >= 8, (int(i), (x0r, y0r, x1r, y1r))
 
 
 def depth_ordered_pairs(fr, order):
@@ -146,7 +145,7 @@ def assert_pipeline_equal(gpu, fr, image_tol=1e-4):
     them stably by tile.  The expected GPU intermediates are derived from the
     oracle's: the final sorted values and ranges must be identical."""
     assert_records_equal(gpu, fr.records)
-    assert_tile_sets(gpu["tile_sets"], fr, gpu["tiles_x"])
+    assert_tile_sets(gpu["tile_sets"], fr, gpu["tiles_x"], gpu["tiles_y"], gpu["mode"])
     dk = expected_depth_keys(fr.records)
     assert np.array_equal(gpu["depth_keys"], dk), first_diffs(gpu["depth_keys"], dk)
     nv = int((fr.records.counts > 0).sum())
