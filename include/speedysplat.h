@@ -133,6 +133,8 @@ typedef struct ss_frame {
                                Gaussian blended into the pixel, 0 if none */
     uint32_t *n_eval;       /* optional [H, W] (NULL: not written): Gaussians of the
                                tile's list the pixel evaluated before it stopped */
+    uint32_t *n_contrib;    /* optional [H, W], written only with n_eval: Gaussians
+                               blended into the pixel */
     uint32_t *emit_tmp;     /* [n + 1] scratch of the emit stage (queue of Gaussians
                                with many tiles); contents are not an output */
     void *table;            /* [table_bytes] 16-byte aligned: the frame's item table

@@ -80,7 +80,7 @@ def lib():
             L.orc_ranges.argtypes = [_i64, _u64p, _i64, _u32p]
             L.orc_ranges.restype = None
             L.orc_blend.argtypes = [_f32p, _u32p, _u32p, _f32p, _f32p, _f32p, _i64, _vp,
-                                    _f32p, _f32p, _u32p, _u32p, _u8p]
+                                    _f32p, _f32p, _u32p, _u32p, _u32p, _u8p]
             L.orc_blend.restype = None
             L.orc_brute_pixels.argtypes = [_f32p, _i64, _f32p, _f32p, _f32p, _i64p, _i64, _int,
                                            _i64, _i32p, _f64p, _u8p]
@@ -209,10 +209,12 @@ def tile_ranges(keys, n_tiles) -> np.ndarray:
 
 def blend(cam, ranges, values, rec: Records, tiles=None):
     """FP32 tiled blend.  Returns (img[3,H,W], T_final[H,W], n_last[H,W],
-    ambiguous[H,W], n_eval[H,W]).  With ``tiles`` given, only those tile ids are
-    written.  n_eval counts the list entries a pixel evaluated before it stopped."""
+    ambiguous[H,W], n_eval[H,W], n_contrib[H,W]).  With ``tiles`` given, only
+    those tile ids are written.  n_eval counts the list entries a pixel
+    evaluated before it stopped, n_contrib the Gaussians blended into it."""
     H, W = cam.height, cam.width
     ne = np.zeros((H, W), np.uint32)
+    nc = np.zeros((H, W), np.uint32)
     img = np.zeros((3, H, W), np.float32)
     tf = np.zeros((H, W), np.float32)
     nl = np.zeros((H, W), np.uint32)
@@ -220,12 +222,13 @@ def blend(cam, ranges, values, rec: Records, tiles=None):
     vals = values if len(values) else np.zeros(1, np.uint32)
     if tiles is None:
         lib().orc_blend(camera_pack(cam), _c(ranges, np.uint32).reshape(-1), _c(vals, np.uint32),
-                        rec.geom, rec.conic, rec.rgb, -1, None, img, tf, nl, ne, amb)
+                        rec.geom, rec.conic, rec.rgb, -1, None, img, tf, nl, ne, nc, amb)
     else:
         tl = _c(tiles, np.int32)
         lib().orc_blend(camera_pack(cam), _c(ranges, np.uint32).reshape(-1), _c(vals, np.uint32),
-                        rec.geom, rec.conic, rec.rgb, len(tl), tl.ctypes.data, img, tf, nl, ne, amb)
-    return img, tf, nl, amb.astype(bool), ne
+                        rec.geom, rec.conic, rec.rgb, len(tl), tl.ctypes.data, img, tf, nl, ne,
+                        nc, amb)
+    return img, tf, nl, amb.astype(bool), ne, nc
 
 
 def depth_order(rec: Records) -> np.ndarray:
@@ -272,11 +275,11 @@ def render(scene, cam, mode, blend_tiles="all") -> Frame:
     skeys, svals = sort_pairs(keys, vals)
     n_tiles = cam.tiles_x * cam.tiles_y
     ranges = tile_ranges(skeys, n_tiles)
-    img = tf = nl = amb = ne = None
+    img = tf = nl = amb = ne = nc = None
     if blend_tiles is not None:
-        img, tf, nl, amb, ne = blend(cam, ranges, svals, rec,
-                                 None if isinstance(blend_tiles, str) else blend_tiles)
+        img, tf, nl, amb, ne, nc = blend(cam, ranges, svals, rec,
+                                         None if isinstance(blend_tiles, str) else blend_tiles)
     return Frame(records=rec, offsets=offsets, n_pairs=int(offsets[-1]) if len(offsets) else 0,
                  keys=keys, values=vals, sorted_keys=skeys, sorted_values=svals,
                  ranges=ranges, image=img, t_final=tf, n_last=nl, ambiguous=amb,
-                 n_eval=ne)
+                 n_eval=ne, n_contrib=nc)

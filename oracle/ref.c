@@ -461,11 +461,12 @@ void orc_ranges(int64_t p, const uint64_t *keys, int64_t n_tiles, uint32_t *rang
  * different (still faithful) exp: the relative error of T that exp can cause
  * is tracked as err, each unclamped alpha adding 16 ulp * alpha / (1 - alpha),
  * and a stop test within T_MIN * (err + 4 ulp) of the threshold is flagged.
+ * n_contrib (optional) counts the Gaussians blended into each pixel.
  */
 static void blend_tile(const orc_cam *cam, int tx, int ty, const uint32_t *ranges,
                        const uint32_t *values, const float *geom, const float *conic,
                        const float *rgb, float *img, float *t_final, uint32_t *n_last,
-                       uint32_t *n_eval, uint8_t *ambig)
+                       uint32_t *n_eval, uint32_t *n_contrib, uint8_t *ambig)
 {
     int tile = ty * cam->tiles_x + tx;
     uint32_t start = ranges[2 * tile], end = ranges[2 * tile + 1];
@@ -473,7 +474,7 @@ static void blend_tile(const orc_cam *cam, int tx, int ty, const uint32_t *range
     for (int py = ty * ORC_TILE; py < ty * ORC_TILE + ORC_TILE && py < cam->height; ++py)
         for (int px = tx * ORC_TILE; px < tx * ORC_TILE + ORC_TILE && px < cam->width; ++px) {
             float T = 1.0f, C[3] = {0.0f, 0.0f, 0.0f};
-            uint32_t last = 0, evals = end - start;
+            uint32_t last = 0, evals = end - start, contrib = 0;
             int amb = 0;
             double err = 0.0;
             const double ulp = ldexp(1.0, -24);
@@ -502,12 +503,14 @@ static void blend_tile(const orc_cam *cam, int tx, int ty, const uint32_t *range
                 C[2] = C[2] + col[2] * w;
                 T = tn;
                 last = j - start + 1;
+                ++contrib;
             }
             int64_t pix = (int64_t)py * cam->width + px;
             for (int ch = 0; ch < 3; ++ch) img[ch * hw + pix] = C[ch] + T * cam->bg[ch];
             if (t_final) t_final[pix] = T;
             if (n_last) n_last[pix] = last;
             if (n_eval) n_eval[pix] = evals;
+            if (n_contrib) n_contrib[pix] = contrib;
             if (ambig) ambig[pix] = (uint8_t)amb;
         }
 }
@@ -516,7 +519,8 @@ static void blend_tile(const orc_cam *cam, int tx, int ty, const uint32_t *range
 void orc_blend(const float *campack, const uint32_t *ranges, const uint32_t *values,
                const float *geom, const float *conic, const float *rgb,
                int64_t n_list, const int32_t *tile_list,
-               float *img, float *t_final, uint32_t *n_last, uint32_t *n_eval, uint8_t *ambig)
+               float *img, float *t_final, uint32_t *n_last, uint32_t *n_eval,
+               uint32_t *n_contrib, uint8_t *ambig)
 {
     orc_cam cam;
     cam_unpack(campack, &cam);
@@ -524,12 +528,12 @@ void orc_blend(const float *campack, const uint32_t *ranges, const uint32_t *val
         for (int ty = 0; ty < cam.tiles_y; ++ty)
             for (int tx = 0; tx < cam.tiles_x; ++tx)
                 blend_tile(&cam, tx, ty, ranges, values, geom, conic, rgb, img, t_final, n_last,
-                           n_eval, ambig);
+                           n_eval, n_contrib, ambig);
     } else {
         for (int64_t k = 0; k < n_list; ++k) {
             int tile = tile_list[k];
             blend_tile(&cam, tile % cam.tiles_x, tile / cam.tiles_x, ranges, values, geom, conic,
-                       rgb, img, t_final, n_last, n_eval, ambig);
+                       rgb, img, t_final, n_last, n_eval, n_contrib, ambig);
         }
     }
 }

@@ -47,7 +47,7 @@ class SSFrame(ctypes.Structure):
                 ("depth_keys", _vp), ("order", _vp), ("order_counts", _vp), ("order_tmp", _vp),
                 ("tile_sets", _vp), ("offsets", _vp), ("scan_tmp", _vp), ("totals", _vp),
                 ("ranges", _vp), ("t_final", _vp), ("n_last", _vp), ("n_eval", _vp),
-                ("emit_tmp", _vp), ("table", _vp)]
+                ("n_contrib", _vp), ("emit_tmp", _vp), ("table", _vp)]
 
 
 class SSFrameInfo(ctypes.Structure):

@@ -61,7 +61,8 @@ __global__ __launch_bounds__(64) void k_blend(const Item* __restrict__ items, Ba
                                               float* __restrict__ out_single,
                                               float* __restrict__ t_final_all,
                                               uint32_t* __restrict__ n_last_all,
-                                              uint32_t* __restrict__ n_eval_all) {
+                                              uint32_t* __restrict__ n_eval_all,
+                                              uint32_t* __restrict__ n_contrib_all) {
     __shared__ float4 s_geo[kBatch];
     __shared__ float4 s_con[kBatch];
     __shared__ float4 s_col[kBatch];
@@ -74,6 +75,8 @@ __global__ __launch_bounds__(64) void k_blend(const Item* __restrict__ items, Ba
     float* __restrict__ t_final = t_final_all + it.pix_off;
     uint32_t* __restrict__ n_last = n_last_all + it.pix_off;
     uint32_t* __restrict__ n_eval = STATS ? n_eval_all + it.pix_off : nullptr;
+    uint32_t* __restrict__ n_contrib =
+        STATS && n_contrib_all ? n_contrib_all + it.pix_off : nullptr;
     const int lt = tile - it.tile_off;      // tile within the item's image
     const int lane = (int)threadIdx.x;
     const int tx = lt % tx_n, ty = lt / tx_n;
@@ -81,7 +84,7 @@ __global__ __launch_bounds__(64) void k_blend(const Item* __restrict__ items, Ba
     const int py0 = ty * kTile + (lane >> 4);
     const float fx = (float)px + 0.5f;
     float fy[4], T[4], C[4][3];
-    uint32_t last[4], stop[4];
+    uint32_t last[4], stop[4], ncon[4];
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
         const bool in = px < W && (py0 + 4 * s) < H;
@@ -90,6 +93,7 @@ __global__ __launch_bounds__(64) void k_blend(const Item* __restrict__ items, Ba
         C[s][0] = C[s][1] = C[s][2] = 0.0f;
         last[s] = 0u;
         stop[s] = 0u;
+        ncon[s] = 0u;
     }
     uint32_t sl = 0;                              // bit s: strip s has an unfinished pixel
 #pragma unroll
@@ -121,6 +125,7 @@ __global__ __launch_bounds__(64) void k_blend(const Item* __restrict__ items, Ba
                     float tn = T[s] * (1.0f - al);
                     float wgt = al * T[s];
                     uint32_t lp = pos;
+                    uint32_t blended = 1u;
                     if (__ballot(tn < kTMin) != 0ull) {   // some included pixel stops here
                         const bool ok = tn >= kTMin;
                         wgt = ok ? wgt : 0.0f;
@@ -128,7 +133,9 @@ __global__ __launch_bounds__(64) void k_blend(const Item* __restrict__ items, Ba
                         lp = ok ? pos : last[s];
                         fy[s] = ok ? fy[s] : kDone;
                         if (STATS) stop[s] = ok ? stop[s] : pos;
+                        blended = ok ? 1u : 0u;
                     }
+                    if (STATS) ncon[s] += blended;
                     C[s][0] = fmaf(c.x, wgt, C[s][0]);
                     C[s][1] = fmaf(c.y, wgt, C[s][1]);
                     C[s][2] = fmaf(c.z, wgt, C[s][2]);
@@ -158,6 +165,7 @@ __global__ __launch_bounds__(64) void k_blend(const Item* __restrict__ items, Ba
             t_final[p] = T[s];
             n_last[p] = last[s];
             if (STATS) n_eval[p] = stop[s] ? stop[s] : end - start;
+            if (STATS && n_contrib) n_contrib[p] = ncon[s];
         }
     }
 }
@@ -173,7 +181,7 @@ hipError_t launch_blend(const Item* items, const BatchDims& d, const ss_frame& f
                            reinterpret_cast<const float4*>(f.geom),
                            reinterpret_cast<const float4*>(f.conic),
                            reinterpret_cast<const float4*>(f.rgb), out_rgb_single, f.t_final,
-                           f.n_last, f.n_eval);
+                           f.n_last, f.n_eval, f.n_contrib);
     };
     if (f.n_eval) go(k_blend<true>);
     else go(k_blend<false>);

@@ -100,8 +100,11 @@ class Frame:
         self.ranges = torch.empty((info.n_tiles, 2), dtype=torch.int32, device=dev)
         self.t_final = torch.empty((height, width), dtype=torch.float32, device=dev)
         self.n_last = torch.empty((height, width), dtype=torch.int32, device=dev)
-        # per-pixel count of evaluated list entries (a statistic; NULL skips it)
+        # per-pixel counts of evaluated list entries and of blended Gaussians
+        # (statistics; NULL skips them)
         self.n_eval = torch.empty((height, width), dtype=torch.int32, device=dev) if stats else None
+        self.n_contrib = (torch.empty((height, width), dtype=torch.int32, device=dev)
+                          if stats else None)
         self.emit_tmp = torch.empty(n + 1, dtype=torch.int32, device=dev)
         self.table = torch.empty(int(info.table_bytes), dtype=torch.uint8, device=dev)
 
@@ -109,7 +112,7 @@ class Frame:
         f = _lib.SSFrame()
         for name in ("geom", "conic", "rgb", "counts", "depth_keys", "order", "order_counts",
                      "order_tmp", "tile_sets", "offsets", "scan_tmp", "totals", "ranges",
-                     "t_final", "n_last", "n_eval", "emit_tmp", "table"):
+                     "t_final", "n_last", "n_eval", "n_contrib", "emit_tmp", "table"):
             t = getattr(self, name)
             setattr(f, name, t.data_ptr() if t is not None else None)
         return f
@@ -450,6 +453,8 @@ class BatchFrame:
         self.t_final = torch.empty(max(npx, 1), dtype=torch.float32, device=dev)
         self.n_last = torch.empty(max(npx, 1), dtype=torch.int32, device=dev)
         self.n_eval = torch.empty(max(npx, 1), dtype=torch.int32, device=dev) if stats else None
+        self.n_contrib = (torch.empty(max(npx, 1), dtype=torch.int32, device=dev)
+                          if stats else None)
         self.emit_tmp = torch.empty(ns + 1, dtype=torch.int32, device=dev)
         self.table = torch.empty(int(info.table_bytes), dtype=torch.uint8, device=dev)
 

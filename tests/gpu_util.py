@@ -53,6 +53,7 @@ def gpu_stages(renderer, g, cam, mode):
     out["t_final"] = frame.t_final.cpu().numpy().copy()
     out["n_last"] = u32(frame.n_last).copy()
     out["n_eval"] = u32(frame.n_eval).copy()
+    out["n_contrib"] = u32(frame.n_contrib).copy()
     return out
 
 
@@ -173,4 +174,5 @@ def assert_pipeline_equal(gpu, fr, image_tol=1e-4):
         assert np.abs(gpu["t_final"] - fr.t_final)[ok].max(initial=0.0) <= 1e-5
         assert np.array_equal(gpu["n_last"][ok], fr.n_last[ok])
         assert np.array_equal(gpu["n_eval"][ok], fr.n_eval[ok])
+        assert np.array_equal(gpu["n_contrib"][ok], fr.n_contrib[ok])
         assert ok.mean() > 0.999

@@ -163,7 +163,7 @@ def test_backward_full_size_masked_tiles(ss, gpu_device):
     lens = fr.ranges[:, 1] - fr.ranges[:, 0]
     cand = np.nonzero(lens > 50)[0]
     tiles = rng.choice(cand, size=12, replace=False)
-    img, tf, nl, amb, ne = oracle.blend(cam, fr.ranges, fr.sorted_values, fr.records, tiles)
+    img, tf, nl, amb, ne, _ = oracle.blend(cam, fr.ranges, fr.sorted_values, fr.records, tiles)
     fr.image, fr.t_final, fr.n_last, fr.ambiguous = img, tf, nl, amb
     w = np.zeros((3, cam.height, cam.width))
     for tl in tiles:

@@ -462,6 +462,9 @@ def test_single_gaussian_closed_form():
         al = np.minimum(0.99, sig * np.exp(-0.5 * q)) * (q <= t)
         want = al[None] * rec.rgb[0, :3, None, None]
         np.testing.assert_allclose(fr.image, want, atol=2e-6)
+        # one contribution exactly where q <= t (away from FP32 rounding of q)
+        clear = np.abs(q - t) > 1e-4 * (1.0 + t)
+        assert np.array_equal(fr.n_contrib[clear], (q <= t)[clear].astype(np.uint32))
 
 
 def test_opaque_stack_terminates():
@@ -475,6 +478,7 @@ def test_opaque_stack_terminates():
     c0 = fr.records.rgb[0, :3]
     np.testing.assert_allclose(fr.image[:, 16, 16], F32(0.99) * c0, rtol=1e-6)
     assert fr.n_last[16, 16] == 1
+    assert fr.n_contrib[16, 16] == 1
     assert fr.t_final[16, 16] == F32(1.0) - F32(0.99)
 
 
@@ -489,6 +493,8 @@ def test_two_gaussians_closed_form():
     ys, xs = np.mgrid[0:cam.height, 0:cam.width] + 0.5
     out = np.zeros((3, cam.height, cam.width))
     T = np.ones((cam.height, cam.width))
+    n_in = np.zeros((cam.height, cam.width), np.uint32)
+    clear = np.ones((cam.height, cam.width), bool)
     for i in (0, 1):  # depth order = index order here
         u, v, _, t = rec.geom[i].astype(np.float64)
         a, b, c, sig = rec.conic[i].astype(np.float64)
@@ -496,7 +502,10 @@ def test_two_gaussians_closed_form():
         al = np.minimum(0.99, sig * np.exp(-0.5 * q)) * (q <= t)
         out += rec.rgb[i, :3, None, None] * (al * T)[None]
         T = T * (1 - al)
+        n_in += (q <= t)
+        clear &= np.abs(q - t) > 1e-4 * (1.0 + t)
     np.testing.assert_allclose(fr.image, out, atol=3e-6)
+    assert np.array_equal(fr.n_contrib[clear], n_in[clear])
 
 
 @pytest.mark.parametrize("mode", ["snugbox", "accutile"])
