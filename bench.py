@@ -96,6 +96,7 @@ def backward_bench(ss, g, cams, steps, warmup):
     """The adjoint of the AccuTile frame (blend backward + preprocess backward)
     for a seeded image gradient, with and without the pruning score, timed with
     events around ss_render_backward.  Forward state is rendered untimed."""
+    import torch
     dev = g.device
     r = ss.Renderer(dev)
     outs = [r.render(g, c, "accutile", full=True) for c in cams[:1]]

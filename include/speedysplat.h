@@ -135,8 +135,9 @@ typedef struct ss_frame {
                                tile's list the pixel evaluated before it stopped */
     uint32_t *n_contrib;    /* optional [H, W], written only with n_eval: Gaussians
                                blended into the pixel */
-    uint32_t *emit_tmp;     /* [n + 1] scratch of the emit stage (queue of Gaussians
-                               with many tiles); contents are not an output */
+    uint32_t *emit_tmp;     /* [emit_tmp_words] scratch of the preprocess stage (partial
+                               frame counts) and the emit stage (queue of Gaussians with
+                               many tiles); contents are not an output */
     void *table;            /* [table_bytes] 16-byte aligned: the frame's item table
                                (camera, scene pointers, offsets), written by
                                ss_preprocess / ss_forward_begin / ss_batch_begin and
@@ -148,6 +149,7 @@ typedef struct ss_frame_info {
     int32_t sort_bits;      /* significant tile-key bits: ceil(log2(n_tiles)) */
     int64_t scan_tmp_words; /* uint64 words for ss_frame.scan_tmp */
     int64_t order_tmp_words; /* uint32 words for ss_frame.order_tmp */
+    int64_t emit_tmp_words; /* uint32 words for ss_frame.emit_tmp */
     int64_t table_bytes;    /* bytes for ss_frame.table */
 } ss_frame_info;
 
@@ -177,6 +179,7 @@ typedef struct ss_batch_info {
     int32_t sort_bits;      /* ceil(log2(n_tiles)) */
     int64_t scan_tmp_words;
     int64_t order_tmp_words;
+    int64_t emit_tmp_words;
     int64_t table_bytes;
 } ss_batch_info;
 

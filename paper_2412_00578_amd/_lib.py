@@ -54,7 +54,7 @@ class SSFrameInfo(ctypes.Structure):
     _fields_ = [("tiles_x", ctypes.c_int32), ("tiles_y", ctypes.c_int32),
                 ("n_tiles", ctypes.c_int32), ("sort_bits", ctypes.c_int32),
                 ("scan_tmp_words", ctypes.c_int64), ("order_tmp_words", ctypes.c_int64),
-                ("table_bytes", ctypes.c_int64)]
+                ("emit_tmp_words", ctypes.c_int64), ("table_bytes", ctypes.c_int64)]
 
 
 class SSFrameCounts(ctypes.Structure):
@@ -69,7 +69,7 @@ class SSBatchInfo(ctypes.Structure):
     _fields_ = [("n_slots", ctypes.c_int64), ("n_pixels", ctypes.c_int64),
                 ("n_tiles", ctypes.c_int32), ("sort_bits", ctypes.c_int32),
                 ("scan_tmp_words", ctypes.c_int64), ("order_tmp_words", ctypes.c_int64),
-                ("table_bytes", ctypes.c_int64)]
+                ("emit_tmp_words", ctypes.c_int64), ("table_bytes", ctypes.c_int64)]
 
 
 class SSPairs(ctypes.Structure):

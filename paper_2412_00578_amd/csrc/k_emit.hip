@@ -13,8 +13,10 @@
 //               as a mask (tile rectangle within 8 x 8) with <= 32 tiles: each
 //               lane expands its mask into its wave's LDS stage, then the wave
 //               copies the stage to the pair buffers with consecutive lanes on
-//               consecutive addresses.  Other entries are queued (one atomic
-//               per wave);
+//               consecutive addresses.  Each workgroup lists its other entries
+//               in its own segment of the scratch (no atomics: thousands on one
+//               counter would serialise), and one workgroup turns the
+//               per-segment counts into offsets;
 //   k_emit_big  one wave per queued entry re-walks the FP64 tile spans of the
 //               record: lanes compute up to 64 spans (rows, or columns for
 //               AccuTile on tall extents) at once, a wave prefix sum places
@@ -29,7 +31,10 @@ constexpr uint32_t kSmall = 32;
 constexpr int kBigBlock = 256;
 constexpr int kBigGrid = 1024;
 
-__global__ void k_zero(uint32_t* p) { *p = 0u; }
+// Scratch layout for n entries, nb = ceil(n / 256) workgroups: segments of
+// queued entries [0, 256 nb), their counts [256 nb, 257 nb), exclusive segment
+// offsets with the total last [257 nb, 258 nb + 1).
+__host__ __device__ __forceinline__ int64_t queue_blocks(int64_t n) { return (n + 255) / 256; }
 
 __device__ __forceinline__ uint32_t wave_incl_scan_u32(uint32_t x) {
     const int lane = (int)__lane_id();
@@ -78,16 +83,24 @@ __global__ __launch_bounds__(kEmitBlock) void k_emit(const Item* __restrict__ it
     if (cnt) ts = tsets[gid];
     const uint64_t mask = (uint64_t)ts.x | ((uint64_t)ts.y << 32);
     const bool big = cnt > kSmall || (cnt && mask == 0ull);
-    const uint64_t bigs = __ballot(big);
-    if (bigs) {
-        const int leader = __builtin_ctzll(bigs);
-        uint32_t base = 0;
-        if (lane == leader) base = atomicAdd(queue, (uint32_t)__popcll(bigs));
-        base = __shfl(base, leader, 64);
-        const uint32_t slot = base + __builtin_amdgcn_mbcnt_hi(
-                                         (uint32_t)(bigs >> 32),
-                                         __builtin_amdgcn_mbcnt_lo((uint32_t)bigs, 0u));
-        if (big && slot < n_entries) queue[1 + slot] = (uint32_t)j;
+    {   // list the big entries in this workgroup's segment
+        __shared__ uint32_t s_nbig[kEmitWaves];
+        const uint64_t bigs = __ballot(big);
+        if (lane == 0) s_nbig[w] = (uint32_t)__popcll(bigs);
+        __syncthreads();
+        uint32_t before = 0, all = 0;
+#pragma unroll
+        for (int k = 0; k < kEmitWaves; ++k) {
+            before += k < w ? s_nbig[k] : 0u;
+            all += s_nbig[k];
+        }
+        const int64_t nb = queue_blocks(n_entries);
+        if (big) {
+            const uint32_t below = __builtin_amdgcn_mbcnt_hi(
+                (uint32_t)(bigs >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bigs, 0u));
+            queue[(int64_t)blockIdx.x * kEmitBlock + before + below] = (uint32_t)j;
+        }
+        if (threadIdx.x == 0) queue[nb * kEmitBlock + blockIdx.x] = all;
     }
     const uint32_t small = big ? 0u : cnt;
     const uint32_t incl = wave_incl_scan_u32(small);
@@ -171,9 +184,35 @@ __device__ __forceinline__ void one_span(const Ellipse& e, int mode, int tx_n, i
     }
 }
 
+// One workgroup: exclusive offsets of the nb segment counts, total last.
+__global__ __launch_bounds__(1024) void k_emit_offsets(uint32_t* __restrict__ queue,
+                                                       int64_t nb) {
+    __shared__ uint32_t s_w[16];
+    __shared__ uint32_t s_carry;
+    const uint32_t* cnt = queue + nb * kEmitBlock;
+    uint32_t* off = queue + nb * kEmitBlock + nb;
+    if (threadIdx.x == 0) s_carry = 0u;
+    __syncthreads();
+    for (int64_t base = 0; base < nb; base += 1024) {
+        const int64_t b = base + threadIdx.x;
+        const uint32_t x = b < nb ? cnt[b] : 0u;
+        const uint32_t inc = wave_incl_scan_u32(x);
+        const int w = threadIdx.x >> 6;
+        if ((threadIdx.x & 63) == 63) s_w[w] = inc;
+        __syncthreads();
+        uint32_t before = s_carry;
+        for (int k = 0; k < w; ++k) before += s_w[k];
+        if (b < nb) off[b] = before + inc - x;
+        __syncthreads();
+        if (threadIdx.x == 1023) s_carry = before + inc;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) off[nb] = s_carry;
+}
+
 __global__ __launch_bounds__(kBigBlock) void k_emit_big(const Item* __restrict__ items,
                                                         BatchDims dims, int mode, uint32_t limit,
-                                                        uint32_t qcap,
+                                                        int64_t nb,
                                                         const float4* __restrict__ geom,
                                                         const float4* __restrict__ conic,
                                                         const uint32_t* __restrict__ order,
@@ -185,11 +224,18 @@ __global__ __launch_bounds__(kBigBlock) void k_emit_big(const Item* __restrict__
     __shared__ int s_lo[kBigBlock / 64][64];
     const int w = threadIdx.x >> 6;
     const int lane = (int)__lane_id();
-    const uint32_t nq = queue[0] < qcap ? queue[0] : qcap;
+    const uint32_t* seg_off = queue + nb * kEmitBlock + nb;
+    const uint32_t nq = seg_off[nb];
     const uint32_t wave0 = blockIdx.x * (kBigBlock / 64) + w;
     const uint32_t waves = gridDim.x * (kBigBlock / 64);
     for (uint32_t b = wave0; b < nq; b += waves) {
-        const uint32_t j = queue[1 + b];          // depth-order entry
+        // the segment holding queued entry b: the last with offset <= b
+        int64_t lo = 0, hi = nb - 1;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi + 1) >> 1;
+            if (seg_off[mid] <= b) lo = mid; else hi = mid - 1;
+        }
+        const uint32_t j = queue[lo * kEmitBlock + (b - seg_off[lo])];   // depth-order entry
         const uint32_t i = order[j];
         const Item& it = items[dims.n_items == 1 ? 0 : item_of_slot(items, dims.n_items, i)];
         const int tx_n = it.tx_n, ty_n = it.ty_n;
@@ -236,19 +282,25 @@ __global__ __launch_bounds__(kBigBlock) void k_emit_big(const Item* __restrict__
 
 }  // namespace
 
+int64_t emit_tmp_words(int64_t n) {
+    const int64_t nb = queue_blocks(n);
+    const int64_t q = nb * kEmitBlock + 2 * nb + 1;
+    const int64_t pre = 2 * ((n + 63) / 64);     // the preprocess stage's partial counts
+    return q > pre ? q : pre;
+}
+
 hipError_t launch_emit(const Item* items, const BatchDims& d, int mode, const ss_frame& f,
                        int64_t n_entries, uint32_t* keys, uint32_t* values, uint64_t n_pairs,
                        hipStream_t s) {
     if (n_entries <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_zero, dim3(1), dim3(1), 0, s, f.emit_tmp);
-    const int64_t grid = (n_entries + kEmitBlock - 1) / kEmitBlock;
-    hipLaunchKernelGGL(k_emit, dim3((unsigned)grid), dim3(kEmitBlock), 0, s, items, d,
+    const int64_t nb = queue_blocks(n_entries);
+    hipLaunchKernelGGL(k_emit, dim3((unsigned)nb), dim3(kEmitBlock), 0, s, items, d,
                        (uint32_t)n_entries, (uint32_t)n_pairs,
                        reinterpret_cast<const uint4*>(f.tile_sets), f.order, f.offsets, keys,
                        values, f.emit_tmp);
+    hipLaunchKernelGGL(k_emit_offsets, dim3(1), dim3(1024), 0, s, f.emit_tmp, nb);
     hipLaunchKernelGGL(k_emit_big, dim3(kBigGrid), dim3(kBigBlock), 0, s, items, d, mode,
-                       (uint32_t)n_pairs, (uint32_t)n_entries,
-                       reinterpret_cast<const float4*>(f.geom),
+                       (uint32_t)n_pairs, nb, reinterpret_cast<const float4*>(f.geom),
                        reinterpret_cast<const float4*>(f.conic), f.order, f.offsets, keys,
                        values, f.emit_tmp);
     return hipGetLastError();

@@ -81,7 +81,7 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(const Item* __restrict__ 
                                                        uint32_t* __restrict__ counts,
                                                        uint32_t* __restrict__ dkeys,
                                                        uint4* __restrict__ tsets,
-                                                       uint64_t* __restrict__ totals) {
+                                                       uint32_t* __restrict__ partials) {
     __shared__ float s_sh[kBlock * kShPitch];
     const int64_t slot0 = (int64_t)blockIdx.x * kBlock;
     const Item& it = items[dims.n_items == 1 ? 0 : item_of_slot(items, dims.n_items, slot0)];
@@ -277,36 +277,66 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(const Item* __restrict__ 
     };
     const uint32_t cnt = o < dims.n_slots ? record() : 0u;
 
-    // Wave totals of the pair count P and of the Gaussians with tiles, one
-    // atomic each per wave (a wave is the whole workgroup).
+    // This workgroup's (one wave's) share of the pair count P and of the
+    // Gaussians with tiles, summed by k_totals: plain stores, since thousands
+    // of atomics on one address would serialise.
     uint32_t sp = cnt, sv = cnt ? 1u : 0u;
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) {
         sp += __shfl_xor(sp, d, 64);
         sv += __shfl_xor(sv, d, 64);
     }
-    if (threadIdx.x == 0 && sv) {
-        atomicAdd(reinterpret_cast<unsigned long long*>(totals), (unsigned long long)sp);
-        atomicAdd(reinterpret_cast<unsigned long long*>(totals) + 1, (unsigned long long)sv);
+    if (threadIdx.x == 0) {
+        partials[2 * blockIdx.x] = sp;
+        partials[2 * blockIdx.x + 1] = sv;
+    }
+}
+
+// One workgroup: totals = (sum of the pair-count partials, sum of the
+// visible-count partials) over nb workgroups of k_preprocess.
+__global__ __launch_bounds__(1024) void k_totals(const uint32_t* __restrict__ partials, int64_t nb,
+                                                 uint64_t* __restrict__ totals) {
+    __shared__ uint64_t s_p[16], s_v[16];
+    uint64_t p = 0, v = 0;
+    for (int64_t b = threadIdx.x; b < nb; b += 1024) {
+        p += partials[2 * b];
+        v += partials[2 * b + 1];
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        p += __shfl_xor(p, d, 64);
+        v += __shfl_xor(v, d, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        s_p[threadIdx.x >> 6] = p;
+        s_v[threadIdx.x >> 6] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t tp = 0, tv = 0;
+        for (int w = 0; w < 16; ++w) {
+            tp += s_p[w];
+            tv += s_v[w];
+        }
+        totals[0] = tp;
+        totals[1] = tv;
     }
 }
 
 }  // namespace
 
-__global__ void k_zero_totals(uint64_t* t) {
-    t[0] = 0ull;
-    t[1] = 0ull;
-}
-
 hipError_t launch_preprocess(const Item* items, const BatchDims& d, int mode, const ss_frame& f,
                              hipStream_t s) {
-    hipLaunchKernelGGL(k_zero_totals, dim3(1), dim3(1), 0, s, f.totals);
-    if (d.n_slots == 0) return hipGetLastError();
+    // per-workgroup partial counts go to the emit stage's scratch, free until then
     const int64_t grid = (d.n_slots + kBlock - 1) / kBlock;
-    hipLaunchKernelGGL(k_preprocess, dim3((unsigned)grid), dim3(kBlock), 0, s, items, d, mode,
-                       reinterpret_cast<float4*>(f.geom), reinterpret_cast<float4*>(f.conic),
-                       reinterpret_cast<float4*>(f.rgb), f.counts, f.depth_keys,
-                       reinterpret_cast<uint4*>(f.tile_sets), f.totals);
+    if (grid > 0) {
+        hipLaunchKernelGGL(k_preprocess, dim3((unsigned)grid), dim3(kBlock), 0, s, items, d,
+                           mode, reinterpret_cast<float4*>(f.geom),
+                           reinterpret_cast<float4*>(f.conic), reinterpret_cast<float4*>(f.rgb),
+                           f.counts, f.depth_keys, reinterpret_cast<uint4*>(f.tile_sets),
+                           f.emit_tmp);
+    }
+    hipLaunchKernelGGL(k_totals, dim3(1), dim3(1024), 0, s, f.emit_tmp, grid, f.totals);
     return hipGetLastError();
 }
 

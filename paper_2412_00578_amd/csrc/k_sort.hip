@@ -70,15 +70,16 @@ __device__ __forceinline__ uint32_t lanes_below(uint64_t m) {
                                      __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
-// Each wave counts 64 keys at a time: lanes with equal digits are matched and
-// the lowest of them adds the group's size, so a digit shared by many keys
-// costs one LDS atomic per wave instead of one per key.
+// Per-wave LDS histograms.  match: lanes with equal digits are matched and the
+// lowest of them adds the group's size (one LDS atomic per distinct digit per
+// wave), for a pass whose digits are few (the depth keys' exponent byte), where
+// per-key atomics on one address would serialise; otherwise one atomic per key.
 // drop: keys equal to kCulledKey are left out (the compacting first pass of
 // the depth order).
 template <class K>
 __global__ __launch_bounds__(kBlock) void k_hist(const K* __restrict__ keys, uint64_t n, int shift,
                                                  uint64_t chunk, uint32_t grid, bool drop,
-                                                 uint32_t* __restrict__ hist) {
+                                                 bool match, uint32_t* __restrict__ hist) {
     __shared__ uint32_t h[kWaves][kRadix];
     for (int k = threadIdx.x; k < kWaves * kRadix; k += kBlock) (&h[0][0])[k] = 0u;
     __syncthreads();
@@ -90,8 +91,12 @@ __global__ __launch_bounds__(kBlock) void k_hist(const K* __restrict__ keys, uin
         const K key = i < hi ? keys[i] : (K)0;
         const bool valid = i < hi && !(drop && key == (K)kCulledKey);
         const uint32_t d = valid ? digit_of(key, shift) : 0u;
-        const uint64_t m = match_digit(d, valid);
-        if (valid && lanes_below(m) == 0u) atomicAdd(&h[w][d], (uint32_t)__popcll(m));
+        if (match) {
+            const uint64_t m = match_digit(d, valid);
+            if (valid && lanes_below(m) == 0u) atomicAdd(&h[w][d], (uint32_t)__popcll(m));
+        } else if (valid) {
+            atomicAdd(&h[w][d], 1u);
+        }
     }
     __syncthreads();
     for (int d = threadIdx.x; d < kRadix; d += kBlock) {
@@ -291,8 +296,10 @@ hipError_t radix_sort(K* keys[2], uint32_t* vals[2], int cur, uint64_t n0, uint6
         const bool dr = pass == 0 && drop;
         K* kout = (last && !last_keys) ? nullptr : keys[1 - cur];
         const uint32_t* vin = (pass == 0 && identity) ? nullptr : vals[cur];
+        // the depth keys' top byte (sign and exponent) takes few values
+        const bool match = drop && shift == 24;
         hipLaunchKernelGGL(k_hist<K>, dim3(plan.grid), dim3(kBlock), 0, s, keys[cur], m, shift,
-                           plan.chunk, plan.grid, dr, tmp);
+                           plan.chunk, plan.grid, dr, match, tmp);
         hipLaunchKernelGGL(k_dscan, dim3(kRadix), dim3(kBlock), 0, s, tmp, plan.grid);
         hipLaunchKernelGGL(k_scatter<K>, dim3(plan.grid), dim3(kBlock), 0, s, keys[cur], vin,
                            kout, vals[1 - cur], m, shift, plan.chunk, plan.grid, dr, tmp, gather,

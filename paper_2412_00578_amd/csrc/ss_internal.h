@@ -279,6 +279,7 @@ hipError_t launch_preprocess(const Item* items, const BatchDims& d, int mode, co
 hipError_t launch_depth_order(int64_t n, int64_t n_visible, const ss_frame& f, hipStream_t s);
 hipError_t launch_scan(int64_t n, const ss_frame& f, hipStream_t s);
 int64_t scan_tmp_words(int64_t n);
+int64_t emit_tmp_words(int64_t n);
 hipError_t launch_emit(const Item* items, const BatchDims& d, int mode, const ss_frame& f,
                        int64_t n_entries, uint32_t* keys, uint32_t* values, uint64_t n_pairs,
                        hipStream_t s);

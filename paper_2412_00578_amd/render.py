@@ -105,7 +105,7 @@ class Frame:
         self.n_eval = torch.empty((height, width), dtype=torch.int32, device=dev) if stats else None
         self.n_contrib = (torch.empty((height, width), dtype=torch.int32, device=dev)
                           if stats else None)
-        self.emit_tmp = torch.empty(n + 1, dtype=torch.int32, device=dev)
+        self.emit_tmp = torch.empty(int(info.emit_tmp_words), dtype=torch.int32, device=dev)
         self.table = torch.empty(int(info.table_bytes), dtype=torch.uint8, device=dev)
 
     def struct(self) -> _lib.SSFrame:
@@ -455,7 +455,7 @@ class BatchFrame:
         self.n_eval = torch.empty(max(npx, 1), dtype=torch.int32, device=dev) if stats else None
         self.n_contrib = (torch.empty(max(npx, 1), dtype=torch.int32, device=dev)
                           if stats else None)
-        self.emit_tmp = torch.empty(ns + 1, dtype=torch.int32, device=dev)
+        self.emit_tmp = torch.empty(int(info.emit_tmp_words), dtype=torch.int32, device=dev)
         self.table = torch.empty(int(info.table_bytes), dtype=torch.uint8, device=dev)
 
     struct = Frame.struct
