@@ -16,7 +16,8 @@
 //   dscan    256 workgroups, one per digit: exclusive scan of that digit's
 //            per-workgroup counts, and the digit's total
 //   scatter  workgroup b turns the digit totals into digit starts, re-reads its
-//            chunk in 4096-key sub-tiles, ranks each key stably (each wave
+//            chunk in 4096-key (or, for short sorts, 1024-key) sub-tiles, ranks
+//            each key stably (each wave
 //            matches 64 digits at a time with 8 ballots; per-wave running
 //            counts live in LDS), reorders the sub-tile by digit in LDS and
 //            writes every digit run to its global offset with consecutive
@@ -28,23 +29,28 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / 64;
-constexpr int kItems = 16;                    // keys per lane per sub-tile
-constexpr int kSub = kBlock * kItems;         // 4096 keys
+constexpr int kItemsLarge = 16;               // keys per lane per sub-tile: 4096 keys
+constexpr int kItemsSmall = 4;                // 1024 keys, for sorts of < 2M keys
 constexpr int kRadix = 256;
 constexpr int kMaxGrid = 1024;
 
 struct Plan {
     uint32_t grid;        // workgroups
-    uint64_t chunk;       // keys per workgroup (multiple of kSub)
+    uint64_t chunk;       // keys per workgroup (multiple of the sub-tile)
+    int items;            // keys per lane per sub-tile
 };
 
+// Sub-tiles of 4096 keys, or of 1024 when that leaves fewer than 512
+// workgroups (a CU would otherwise sit idle or walk one long chunk).
 Plan make_plan(uint64_t n) {
+    const int items = (n + 4095) / 4096 < 512 ? kItemsSmall : kItemsLarge;
+    const uint64_t kSub = (uint64_t)kBlock * items;
     const uint64_t subs = (n + kSub - 1) / kSub;
     uint64_t g = subs < (uint64_t)kMaxGrid ? subs : (uint64_t)kMaxGrid;
     if (g == 0) g = 1;
     const uint64_t per = (subs + g - 1) / g;
     const uint64_t grid = per ? (subs + per - 1) / per : 1;
-    return Plan{(uint32_t)(grid ? grid : 1), (per ? per : 1) * kSub};
+    return Plan{(uint32_t)(grid ? grid : 1), (per ? per : 1) * kSub, items};
 }
 
 template <class K>
@@ -161,8 +167,9 @@ __global__ __launch_bounds__(kBlock) void k_dscan(uint32_t* __restrict__ hist, u
 // vals_in == nullptr stands for the identity (value = input position);
 // keys_out == nullptr skips the key writes (a last pass whose keys are unused);
 // with gather_out, gather_out[p] = gather[value] for every output position p;
-// drop: keys equal to kCulledKey are left out, as in k_hist.
-template <class K>
+// drop: keys equal to kCulledKey are left out, as in k_hist.  A workgroup
+// walks its chunk in sub-tiles of kBlock * ITEMS keys.
+template <class K, int ITEMS>
 __global__ __launch_bounds__(kBlock) void k_scatter(const K* __restrict__ keys_in,
                                                     const uint32_t* __restrict__ vals_in,
                                                     K* __restrict__ keys_out,
@@ -172,6 +179,8 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const K* __restrict__ keys_i
                                                     const uint32_t* __restrict__ hist,
                                                     const uint32_t* __restrict__ gather,
                                                     uint32_t* __restrict__ gather_out) {
+    constexpr int kItems = ITEMS;
+    constexpr int kSub = kBlock * ITEMS;
     __shared__ K s_key[kSub];
     __shared__ uint32_t s_val[kSub];
     __shared__ uint32_t base[kRadix];     // global position of this chunk's next key per digit
@@ -301,8 +310,10 @@ hipError_t radix_sort(K* keys[2], uint32_t* vals[2], int cur, uint64_t n0, uint6
         hipLaunchKernelGGL(k_hist<K>, dim3(plan.grid), dim3(kBlock), 0, s, keys[cur], m, shift,
                            plan.chunk, plan.grid, dr, match, tmp);
         hipLaunchKernelGGL(k_dscan, dim3(kRadix), dim3(kBlock), 0, s, tmp, plan.grid);
-        hipLaunchKernelGGL(k_scatter<K>, dim3(plan.grid), dim3(kBlock), 0, s, keys[cur], vin,
-                           kout, vals[1 - cur], m, shift, plan.chunk, plan.grid, dr, tmp, gather,
+        auto scatter = plan.items == kItemsSmall ? k_scatter<K, kItemsSmall>
+                                                 : k_scatter<K, kItemsLarge>;
+        hipLaunchKernelGGL(scatter, dim3(plan.grid), dim3(kBlock), 0, s, keys[cur], vin, kout,
+                           vals[1 - cur], m, shift, plan.chunk, plan.grid, dr, tmp, gather,
                            last ? gather_out : nullptr);
         cur = 1 - cur;
     }

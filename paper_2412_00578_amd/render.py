@@ -193,8 +193,9 @@ class Renderer:
         self.stats = stats
         self._frame: Frame | None = None
         self._pairs: Pairs | None = None
-        self._ring: list = [None, None]          # frames of render_many
+        self._ring: list = [None] * self.RING    # frames of render_many
         self._host_p: torch.Tensor | None = None
+        self._side = None                        # side stream of render_many
 
     def frame_for(self, n, width, height) -> Frame:
         if self._frame is None or not self._frame.fits(n, width, height, self.stats):
@@ -236,20 +237,17 @@ class Renderer:
                                 int(buf.value))
         return out
 
-    def _ring_frame(self, s, n, width, height) -> Frame:
-        f = self._ring[s]
-        if f is None or not f.fits(n, width, height, self.stats):
-            self._ring[s] = None
-            self._ring[s] = f = Frame(n, width, height, self.device, self.stats)
-        return f
+    RING = 3   # frame buffers of render_many
 
     def render_many(self, g: Gaussians, cams, mode="accutile", outs=None) -> list:
-        """Renders one frame per camera, keeping the host one frame ahead of the
-        GPU: frame k+1's preprocess is enqueued (into the second of two frame
-        buffers) before frame k's depth order, scan, emit, sort, ranges and
-        blend, and each frame's counts come back by an asynchronous copy, so the
-        GPU never idles waiting for the host between frames.  Every frame is
-        rendered completely; the images are valid once the stream syncs."""
+        """Renders one frame per camera as a pipeline over two HIP streams and
+        three frame buffers: frame k+1's preprocess and frame-count read-back run
+        on a side stream while frame k's depth order, scan, emit, sort, ranges
+        and blend run on the current stream.  The preprocess is bound by memory
+        latency and the blend by the vector ALUs, so the two overlap on the GPU,
+        and the counts come back by asynchronous copies, so the GPU never waits
+        for the host.  Every frame is rendered completely and identically to
+        render(); the images are valid once the current stream syncs."""
         m = mode_id(mode)
         cs = [make_camera(c) for c in cams]
         if outs is None:
@@ -257,36 +255,54 @@ class Renderer:
                     for c in cs]
         if not cs:
             return outs
-        st = torch.cuda.current_stream(self.device)
-        sp = ctypes.c_void_p(st.cuda_stream)
+        main = torch.cuda.current_stream(self.device)
+        if self._side is None:
+            self._side = torch.cuda.Stream(self.device)     # default priority
+        side = self._side
+        side.wait_stream(main)             # earlier work on the ring buffers is done
+        smain = ctypes.c_void_p(main.cuda_stream)
+        sside = ctypes.c_void_p(side.cuda_stream)
         gs = g.struct()
-        if self._host_p is None:   # two ss_frame_counts, one per frame buffer
-            self._host_p = torch.zeros((2, 2), dtype=torch.int64, pin_memory=True)
+        R = self.RING
+        if self._host_p is None:           # one ss_frame_counts per frame buffer
+            self._host_p = torch.zeros((R, 2), dtype=torch.int64, pin_memory=True)
         host = self._host_p
-        ready = [torch.cuda.Event(), torch.cuda.Event()]
-        fss = [None, None]
+        ready = [torch.cuda.Event() for _ in range(R)]   # counts copied (side stream)
+        free = [torch.cuda.Event() for _ in range(R)]    # frame buffer released (main)
+        fss = [None] * R
 
         def begin(k):
-            s = k % 2
-            fss[s] = self._ring_frame(s, g.n, cs[k].width, cs[k].height).struct()
+            r = k % R
+            if k >= R:
+                side.wait_event(free[r])
+            f = self._ring[r]
+            if f is None or not f.fits(g.n, cs[k].width, cs[k].height, self.stats):
+                side.synchronize()         # a resize: nothing may still use the old buffers
+                main.synchronize()
+                self._ring[r] = None
+                self._ring[r] = f = Frame(g.n, cs[k].width, cs[k].height, self.device,
+                                          self.stats)
+            fss[r] = f.struct()
             check(lib().ss_forward_begin_async(ctypes.byref(cs[k]), ctypes.byref(gs), m,
-                                               ctypes.byref(fss[s]),
-                                               ctypes.c_void_p(host.data_ptr() + 16 * s), None,
-                                               sp), "ss_forward_begin_async")
-            ready[s].record(st)
+                                               ctypes.byref(fss[r]),
+                                               ctypes.c_void_p(host.data_ptr() + 16 * r), None,
+                                               sside), "ss_forward_begin_async")
+            ready[r].record(side)
 
         begin(0)
         buf = ctypes.c_int32()
         for k in range(len(cs)):
             if k + 1 < len(cs):
                 begin(k + 1)
-            s = k % 2
-            ready[s].synchronize()
-            counts = _lib.SSFrameCounts(int(host[s, 0]), int(host[s, 1]))
+            r = k % R
+            ready[r].synchronize()
+            counts = _lib.SSFrameCounts(int(host[r, 0]), int(host[r, 1]))
+            main.wait_event(ready[r])
             ps = self.pairs_for(counts.n_pairs).struct()
-            check(lib().ss_forward_finish(ctypes.byref(cs[k]), g.n, m, ctypes.byref(fss[s]),
+            check(lib().ss_forward_finish(ctypes.byref(cs[k]), g.n, m, ctypes.byref(fss[r]),
                                           ctypes.byref(ps), ctypes.byref(counts), _ptr(outs[k]),
-                                          ctypes.byref(buf), None, sp), "ss_forward_finish")
+                                          ctypes.byref(buf), None, smain), "ss_forward_finish")
+            free[r].record(main)
         return outs
 
     # ---- single stages (for tests and profiling) ---------------------------
