@@ -375,7 +375,9 @@ int orc_tile_rect(const float *geom, const float *conic, int mode, int tx_n, int
     return ok;
 }
 
-/* Preprocess all Gaussians: records and tile counts. Returns visible count. */
+/* Preprocess all Gaussians: records and tile counts. Returns visible count.
+ * The colour is kept only for a Gaussian that touches at least one tile: one
+ * without tiles is never blended, and its rgb record is zero. */
 int64_t orc_preprocess(const float *campack, int64_t n, int sh_degree, int sh_stride,
                        const float *means, const float *scales, const float *quats,
                        const float *opacity, const float *sh, int mode,
@@ -390,6 +392,7 @@ int64_t orc_preprocess(const float *campack, int64_t n, int sh_degree, int sh_st
                             sh + (int64_t)3 * sh_stride * i, sh_degree, sh_stride, mode,
                             g, q, c);
         counts[i] = ok ? (uint32_t)orc_tile_list(g, q, mode, cam.tiles_x, cam.tiles_y, NULL) : 0u;
+        if (counts[i] == 0u) c[0] = c[1] = c[2] = c[3] = 0.0f;
         visible += ok;
     }
     return visible;

@@ -6,7 +6,9 @@
 // FP64 function of the stored record.  A record whose tile rectangle fits 8 x 8
 // tiles also stores its tile set as a bit mask, which the emit stage expands;
 // the emit stage re-walks the same FP64 function for the others, so counts and
-// emitted pairs agree by construction.  The colour is FP32.
+// emitted pairs agree by construction.  A second kernel evaluates the FP32
+// colour of the Gaussians with tiles, reading only their SH rows (about half
+// of the SH data of a typical frame).
 #include "ss_internal.h"
 
 namespace ss {
@@ -39,36 +41,37 @@ constexpr int kPack = 16;                  // items per table-writing launch (ke
 struct ItemPack {
     Item it[kPack];
 };
-constexpr int kShHalf = 24;                // SH floats staged per round (8 coefficients x 3)
-constexpr int kShPitch = kShHalf + 1;      // odd LDS pitch: lanes hit distinct banks
+constexpr int kShMax = 48;                 // SH floats per Gaussian (degree 3)
+constexpr int kShPitch = kShMax + 1;       // odd LDS pitch: lanes hit distinct banks
 
-// Copies floats [f0, f0 + w) of the SH rows of this workgroup's Gaussians into
-// LDS (Gaussian g at s_sh[g * kShPitch]) with coalesced loads: the [n, stride,
-// 3] rows of consecutive Gaussians are contiguous.  Staging a round of at most
-// 24 floats at a time keeps the LDS per wave at 6.4 KB, so LDS does not limit
-// how many waves a CU holds.
+// Copies the first `need` floats of the SH rows of this workgroup's Gaussians
+// whose s_vis flag is set into LDS (Gaussian g at s_sh[g * kShPitch]) with
+// coalesced loads: the [n, stride, 3] rows of consecutive Gaussians are
+// contiguous.  Rows of Gaussians without tiles are not read.
 __device__ __forceinline__ void stage_sh(const float* __restrict__ sh, int64_t first, int64_t n,
-                                         int row, int f0, int w, float* s_sh) {
+                                         int row, int need, const uint32_t* s_vis,
+                                         float* s_sh) {
     const int cnt = (n - first) < kBlock ? (int)(n - first) : kBlock;
     const float* src = sh + first * row;
-    if (((uintptr_t)src & 15u) == 0 && (row & 3) == 0 && (f0 & 3) == 0) {
-        // float4 j of a Gaussian covers floats f0 + 4j .. f0 + 4j + 3, all inside
-        // its row (row and f0 are multiples of 4); floats past w are not kept
-        const unsigned q = (unsigned)(w + 3) >> 2, urow4 = (unsigned)row >> 2;
-        const float4* src4 = reinterpret_cast<const float4*>(src) + (f0 >> 2);
+    if (((uintptr_t)src & 15u) == 0 && (row & 3) == 0) {
+        // float4 j of a Gaussian covers floats 4j .. 4j + 3, all inside its row
+        // (row is a multiple of 4); floats past `need` are not kept
+        const unsigned q = (unsigned)(need + 3) >> 2, urow4 = (unsigned)row >> 2;
+        const float4* src4 = reinterpret_cast<const float4*>(src);
         for (unsigned e = threadIdx.x; e < (unsigned)cnt * q; e += kBlock) {
             const unsigned g = e / q, j = e - g * q;
+            if (!s_vis[g]) continue;
             const float4 v = src4[g * urow4 + j];
             float* d = s_sh + g * kShPitch + 4 * j;
             d[0] = v.x;
-            if ((int)(4 * j) + 1 < w) d[1] = v.y;
-            if ((int)(4 * j) + 2 < w) d[2] = v.z;
-            if ((int)(4 * j) + 3 < w) d[3] = v.w;
+            if ((int)(4 * j) + 1 < need) d[1] = v.y;
+            if ((int)(4 * j) + 2 < need) d[2] = v.z;
+            if ((int)(4 * j) + 3 < need) d[3] = v.w;
         }
     } else {
-        for (unsigned e = threadIdx.x; e < (unsigned)(cnt * w); e += kBlock) {
-            const unsigned g = e / (unsigned)w, j = e - g * (unsigned)w;
-            s_sh[g * kShPitch + j] = src[(int64_t)g * row + f0 + j];
+        for (unsigned e = threadIdx.x; e < (unsigned)(cnt * need); e += kBlock) {
+            const unsigned g = e / (unsigned)need, j = e - g * (unsigned)need;
+            if (s_vis[g]) s_sh[g * kShPitch + j] = src[(int64_t)g * row + j];
         }
     }
 }
@@ -77,12 +80,10 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(const Item* __restrict__ 
                                                        BatchDims dims, int mode,
                                                        float4* __restrict__ geom,
                                                        float4* __restrict__ conic,
-                                                       float4* __restrict__ rgb_out,
                                                        uint32_t* __restrict__ counts,
                                                        uint32_t* __restrict__ dkeys,
                                                        uint4* __restrict__ tsets,
                                                        uint32_t* __restrict__ partials) {
-    __shared__ float s_sh[kBlock * kShPitch];
     const int64_t slot0 = (int64_t)blockIdx.x * kBlock;
     const Item& it = items[dims.n_items == 1 ? 0 : item_of_slot(items, dims.n_items, slot0)];
     const ss_camera cam = it.cam;
@@ -94,7 +95,6 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(const Item* __restrict__ 
     const int64_t o = slot0 + threadIdx.x;        // its record slot
     const bool real = i < n && o < dims.n_slots;
 
-    // Inputs first, so their loads overlap the SH staging below.
     float m0 = 0.f, m1 = 0.f, m2 = 1.f, s0 = 0.f, s1 = 0.f, s2 = 0.f, op = 0.f;
     float4 qr = make_float4(0.f, 0.f, 0.f, 0.f);
     if (real) {
@@ -104,67 +104,12 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(const Item* __restrict__ 
         op = in.opacity[i];
     }
 
-    // View-dependent colour from SH (FP32), accumulated over the coefficients in
-    // order, staged in rounds of 8 coefficients.  Every lane takes part in the
-    // staging, so this comes before any lane leaves.
-    const float cpx = -((cam.R[0] * cam.t[0] + cam.R[3] * cam.t[1]) + cam.R[6] * cam.t[2]);
-    const float cpy = -((cam.R[1] * cam.t[0] + cam.R[4] * cam.t[1]) + cam.R[7] * cam.t[2]);
-    const float cpz = -((cam.R[2] * cam.t[0] + cam.R[5] * cam.t[1]) + cam.R[8] * cam.t[2]);
-    float dx = m0 - cpx, dy = m1 - cpy, dz = m2 - cpz;
-    const float inv = 1.0f / sqrtf(dx * dx + dy * dy + dz * dz);
-    dx *= inv; dy *= inv; dz *= inv;
-    float Y[16];
-    Y[0] = kSH0;
-    int nb = 1;
-    if (in.sh_degree >= 1) {
-        Y[1] = -kSH1 * dy; Y[2] = kSH1 * dz; Y[3] = -kSH1 * dx;
-        nb = 4;
-    }
-    if (in.sh_degree >= 2) {
-        const float xx = dx * dx, yy = dy * dy, zz = dz * dz;
-        Y[4] = kSH2a * (dx * dy);
-        Y[5] = -kSH2a * (dy * dz);
-        Y[6] = kSH2b * (2.0f * zz - xx - yy);
-        Y[7] = -kSH2a * (dx * dz);
-        Y[8] = kSH2c * (xx - yy);
-        nb = 9;
-        if (in.sh_degree >= 3) {
-            Y[9] = -kSH3a * dy * (3.0f * xx - yy);
-            Y[10] = kSH3b * (dx * dy * dz);
-            Y[11] = -kSH3c * dy * (4.0f * zz - xx - yy);
-            Y[12] = kSH3d * dz * (2.0f * zz - 3.0f * xx - 3.0f * yy);
-            Y[13] = -kSH3c * dx * (4.0f * zz - xx - yy);
-            Y[14] = kSH3e * dz * (xx - yy);
-            Y[15] = -kSH3a * dx * (xx - 3.0f * yy);
-            nb = 16;
-        }
-    }
-    const int need = 3 * nb;
-    const int row = 3 * in.sh_stride;
-    const float* h = s_sh + threadIdx.x * kShPitch;
-    float cr = 0.f, cg = 0.f, cbl = 0.f;
-    for (int f0 = 0; f0 < need; f0 += kShHalf) {          // uniform
-        const int w = need - f0 < kShHalf ? need - f0 : kShHalf;
-        if (f0) __syncthreads();                          // previous round consumed
-        if (first < n) stage_sh(in.sh, first, n, row, f0, w, s_sh);
-        __syncthreads();
-        for (int k = f0 / 3; k < (f0 + w) / 3; ++k) {
-            const int c = 3 * k - f0;
-            cr = fmaf(Y[k], h[c], cr);
-            cg = fmaf(Y[k], h[c + 1], cg);
-            cbl = fmaf(Y[k], h[c + 2], cbl);
-        }
-    }
-    cr = fmaxf(cr + 0.5f, 0.0f);
-    cg = fmaxf(cg + 0.5f, 0.0f);
-    cbl = fmaxf(cbl + 0.5f, 0.0f);
-
     // The record, its count and its tile set; 0 for a padding slot or a culled
     // Gaussian (whose record is zeroed).
     auto record = [&]() -> uint32_t {
         const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
         if (i >= n) {  // padding slot between items
-            geom[o] = zero; conic[o] = zero; rgb_out[o] = zero; counts[o] = 0u;
+            geom[o] = zero; conic[o] = zero; counts[o] = 0u;
             dkeys[o] = kCulledKey;
             tsets[o] = make_uint4(0u, 0u, 0u, 0u);
             return 0u;
@@ -188,7 +133,7 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(const Item* __restrict__ 
         const double nn = ((qw * qw + qx * qx) + qy * qy) + qz * qz;
         ok = ok && (nn > 0.0);
         if (!ok) {
-            geom[o] = zero; conic[o] = zero; rgb_out[o] = zero; counts[o] = 0u;
+            geom[o] = zero; conic[o] = zero; counts[o] = 0u;
             dkeys[o] = kCulledKey;
             tsets[o] = make_uint4(0u, 0u, 0u, 0u);
             return 0u;
@@ -256,7 +201,7 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(const Item* __restrict__ 
         const float ca = (float)(C / D), cb = (float)(-B / D), cc = (float)(A / D);
         const float tt = (float)(2.0 * log(255.0 * (double)op));
         if (!(D > 0.0) || (mode != SS_TILE_3SIGMA && !(tt > 0.0f))) {
-            geom[o] = zero; conic[o] = zero; rgb_out[o] = zero; counts[o] = 0u;
+            geom[o] = zero; conic[o] = zero; counts[o] = 0u;
             dkeys[o] = kCulledKey;
             tsets[o] = make_uint4(0u, 0u, 0u, 0u);
             return 0u;
@@ -266,7 +211,6 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(const Item* __restrict__ 
         const float4 q4 = make_float4(ca, cb, cc, op);
         geom[o] = g4;
         conic[o] = q4;
-        rgb_out[o] = make_float4(cr, cg, cbl, 0.0f);
         uint64_t mask;
         uint32_t origin;
         const uint32_t cnt = tile_set(g4, q4, mode, tx_n, ty_n, &mask, &origin);
@@ -290,6 +234,73 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(const Item* __restrict__ 
         partials[2 * blockIdx.x] = sp;
         partials[2 * blockIdx.x + 1] = sv;
     }
+}
+
+// View-dependent colour from SH (FP32), for the Gaussians with tiles (the
+// others get rgb = 0).  One wave per workgroup; the workgroup's SH rows are
+// staged through LDS with coalesced loads, skipping the rows of Gaussians
+// without tiles.
+__global__ __launch_bounds__(kBlock) void k_colour(const Item* __restrict__ items, BatchDims dims,
+                                                   const uint32_t* __restrict__ counts,
+                                                   float4* __restrict__ rgb_out) {
+    __shared__ float s_sh[kBlock * kShPitch];
+    __shared__ uint32_t s_vis[kBlock];
+    const int64_t slot0 = (int64_t)blockIdx.x * kBlock;
+    const Item& it = items[dims.n_items == 1 ? 0 : item_of_slot(items, dims.n_items, slot0)];
+    const ss_camera cam = it.cam;
+    const int64_t n = it.n;
+    const int64_t first = slot0 - it.g_off;
+    const int64_t i = first + threadIdx.x;
+    const int64_t o = slot0 + threadIdx.x;
+    const bool vis = i < n && o < dims.n_slots && counts[o] > 0u;
+    s_vis[threadIdx.x] = vis ? 1u : 0u;
+    const int nb = (it.sh_degree + 1) * (it.sh_degree + 1);
+    __syncthreads();
+    if (first < n) stage_sh(it.sh, first, n, 3 * it.sh_stride, 3 * nb, s_vis, s_sh);
+    __syncthreads();
+    if (o >= dims.n_slots) return;
+    if (!vis) {
+        rgb_out[o] = make_float4(0.f, 0.f, 0.f, 0.f);
+        return;
+    }
+    const float m0 = it.means[3 * i], m1 = it.means[3 * i + 1], m2 = it.means[3 * i + 2];
+    const float cpx = -((cam.R[0] * cam.t[0] + cam.R[3] * cam.t[1]) + cam.R[6] * cam.t[2]);
+    const float cpy = -((cam.R[1] * cam.t[0] + cam.R[4] * cam.t[1]) + cam.R[7] * cam.t[2]);
+    const float cpz = -((cam.R[2] * cam.t[0] + cam.R[5] * cam.t[1]) + cam.R[8] * cam.t[2]);
+    float dx = m0 - cpx, dy = m1 - cpy, dz = m2 - cpz;
+    const float inv = 1.0f / sqrtf(dx * dx + dy * dy + dz * dz);
+    dx *= inv; dy *= inv; dz *= inv;
+    float Y[16];
+    Y[0] = kSH0;
+    if (it.sh_degree >= 1) {
+        Y[1] = -kSH1 * dy; Y[2] = kSH1 * dz; Y[3] = -kSH1 * dx;
+    }
+    if (it.sh_degree >= 2) {
+        const float xx = dx * dx, yy = dy * dy, zz = dz * dz;
+        Y[4] = kSH2a * (dx * dy);
+        Y[5] = -kSH2a * (dy * dz);
+        Y[6] = kSH2b * (2.0f * zz - xx - yy);
+        Y[7] = -kSH2a * (dx * dz);
+        Y[8] = kSH2c * (xx - yy);
+        if (it.sh_degree >= 3) {
+            Y[9] = -kSH3a * dy * (3.0f * xx - yy);
+            Y[10] = kSH3b * (dx * dy * dz);
+            Y[11] = -kSH3c * dy * (4.0f * zz - xx - yy);
+            Y[12] = kSH3d * dz * (2.0f * zz - 3.0f * xx - 3.0f * yy);
+            Y[13] = -kSH3c * dx * (4.0f * zz - xx - yy);
+            Y[14] = kSH3e * dz * (xx - yy);
+            Y[15] = -kSH3a * dx * (xx - 3.0f * yy);
+        }
+    }
+    const float* h = s_sh + threadIdx.x * kShPitch;
+    float cr = 0.f, cg = 0.f, cbl = 0.f;
+    for (int k = 0; k < nb; ++k) {
+        cr = fmaf(Y[k], h[3 * k], cr);
+        cg = fmaf(Y[k], h[3 * k + 1], cg);
+        cbl = fmaf(Y[k], h[3 * k + 2], cbl);
+    }
+    rgb_out[o] = make_float4(fmaxf(cr + 0.5f, 0.0f), fmaxf(cg + 0.5f, 0.0f),
+                             fmaxf(cbl + 0.5f, 0.0f), 0.0f);
 }
 
 // One workgroup: totals = (sum of the pair-count partials, sum of the
@@ -332,9 +343,10 @@ hipError_t launch_preprocess(const Item* items, const BatchDims& d, int mode, co
     if (grid > 0) {
         hipLaunchKernelGGL(k_preprocess, dim3((unsigned)grid), dim3(kBlock), 0, s, items, d,
                            mode, reinterpret_cast<float4*>(f.geom),
-                           reinterpret_cast<float4*>(f.conic), reinterpret_cast<float4*>(f.rgb),
-                           f.counts, f.depth_keys, reinterpret_cast<uint4*>(f.tile_sets),
-                           f.emit_tmp);
+                           reinterpret_cast<float4*>(f.conic), f.counts, f.depth_keys,
+                           reinterpret_cast<uint4*>(f.tile_sets), f.emit_tmp);
+        hipLaunchKernelGGL(k_colour, dim3((unsigned)grid), dim3(kBlock), 0, s, items, d, f.counts,
+                           reinterpret_cast<float4*>(f.rgb));
     }
     hipLaunchKernelGGL(k_totals, dim3(1), dim3(1024), 0, s, f.emit_tmp, grid, f.totals);
     return hipGetLastError();
