@@ -200,49 +200,50 @@ __global__ void k_fill_zero(float* __restrict__ p, int64_t n) {
 
 // ------------------------------------------------------------ preprocess backward
 
-constexpr double kC0 = 0.28209479177387814;
-constexpr double kC1 = 0.4886025119029199;
-constexpr double kC2a = 1.0925484305920792, kC2b = 0.31539156525252005, kC2c = 0.5462742152960396;
-constexpr double kC3a = 0.5900435899266435, kC3b = 2.890611442640554, kC3c = 0.4570457994644658,
-                 kC3d = 0.3731763325901154, kC3e = 1.445305721320277;
+// Real SH constants (degrees 0..3, Condon-Shortley phase), as in the forward.
+constexpr float kC0 = 0.28209479177387814f;
+constexpr float kC1 = 0.4886025119029199f;
+constexpr float kC2a = 1.0925484305920792f, kC2b = 0.31539156525252005f,
+                kC2c = 0.5462742152960396f;
+constexpr float kC3a = 0.5900435899266435f, kC3b = 2.890611442640554f,
+                kC3c = 0.4570457994644658f, kC3d = 0.3731763325901154f,
+                kC3e = 1.445305721320277f;
 
-// SH basis Y[16] and its partial derivatives dY[16][3] with respect to the
-// (unnormalised) direction components, evaluated at a unit direction.
-__device__ void sh_basis_grad(double x, double y, double z, int nb, double* Y, double (*dY)[3]) {
-    const double xx = x * x, yy = y * y, zz = z * z;
-    for (int k = 0; k < 16; ++k) { Y[k] = 0.0; dY[k][0] = dY[k][1] = dY[k][2] = 0.0; }
-    Y[0] = kC0;
-    if (nb > 1) {
-        Y[1] = -kC1 * y; dY[1][1] = -kC1;
-        Y[2] = kC1 * z;  dY[2][2] = kC1;
-        Y[3] = -kC1 * x; dY[3][0] = -kC1;
-    }
-    if (nb > 4) {
-        Y[4] = kC2a * x * y;  dY[4][0] = kC2a * y;  dY[4][1] = kC2a * x;
-        Y[5] = -kC2a * y * z; dY[5][1] = -kC2a * z; dY[5][2] = -kC2a * y;
-        Y[6] = kC2b * (2 * zz - xx - yy);
-        dY[6][0] = -2 * kC2b * x; dY[6][1] = -2 * kC2b * y; dY[6][2] = 4 * kC2b * z;
-        Y[7] = -kC2a * x * z; dY[7][0] = -kC2a * z; dY[7][2] = -kC2a * x;
-        Y[8] = kC2c * (xx - yy); dY[8][0] = 2 * kC2c * x; dY[8][1] = -2 * kC2c * y;
-    }
-    if (nb > 9) {
-        Y[9] = -kC3a * y * (3 * xx - yy);
-        dY[9][0] = -6 * kC3a * x * y; dY[9][1] = -kC3a * (3 * xx - 3 * yy);
-        Y[10] = kC3b * x * y * z;
-        dY[10][0] = kC3b * y * z; dY[10][1] = kC3b * x * z; dY[10][2] = kC3b * x * y;
-        Y[11] = -kC3c * y * (4 * zz - xx - yy);
-        dY[11][0] = 2 * kC3c * x * y; dY[11][1] = -kC3c * (4 * zz - xx - 3 * yy);
-        dY[11][2] = -8 * kC3c * y * z;
-        Y[12] = kC3d * z * (2 * zz - 3 * xx - 3 * yy);
-        dY[12][0] = -6 * kC3d * x * z; dY[12][1] = -6 * kC3d * y * z;
-        dY[12][2] = kC3d * (6 * zz - 3 * xx - 3 * yy);
-        Y[13] = -kC3c * x * (4 * zz - xx - yy);
-        dY[13][0] = -kC3c * (4 * zz - 3 * xx - yy); dY[13][1] = 2 * kC3c * x * y;
-        dY[13][2] = -8 * kC3c * x * z;
-        Y[14] = kC3e * z * (xx - yy);
-        dY[14][0] = 2 * kC3e * x * z; dY[14][1] = -2 * kC3e * y * z; dY[14][2] = kC3e * (xx - yy);
-        Y[15] = -kC3a * x * (xx - 3 * yy);
-        dY[15][0] = -kC3a * (3 * xx - 3 * yy); dY[15][1] = 6 * kC3a * x * y;
+// Basis function k and its partial derivatives with respect to the direction
+// components (x, y, z), at a unit direction; k is a compile-time constant in
+// the unrolled callers, so no table is materialised.
+__device__ __forceinline__ void sh_term(int k, float x, float y, float z, float& Y, float& gx,
+                                        float& gy, float& gz) {
+    const float xx = x * x, yy = y * y, zz = z * z;
+    gx = gy = gz = 0.0f;
+    switch (k) {
+        case 0: Y = kC0; break;
+        case 1: Y = -kC1 * y; gy = -kC1; break;
+        case 2: Y = kC1 * z; gz = kC1; break;
+        case 3: Y = -kC1 * x; gx = -kC1; break;
+        case 4: Y = kC2a * x * y; gx = kC2a * y; gy = kC2a * x; break;
+        case 5: Y = -kC2a * y * z; gy = -kC2a * z; gz = -kC2a * y; break;
+        case 6: Y = kC2b * (2.0f * zz - xx - yy);
+                gx = -2.0f * kC2b * x; gy = -2.0f * kC2b * y; gz = 4.0f * kC2b * z; break;
+        case 7: Y = -kC2a * x * z; gx = -kC2a * z; gz = -kC2a * x; break;
+        case 8: Y = kC2c * (xx - yy); gx = 2.0f * kC2c * x; gy = -2.0f * kC2c * y; break;
+        case 9: Y = -kC3a * y * (3.0f * xx - yy);
+                gx = -6.0f * kC3a * x * y; gy = -kC3a * (3.0f * xx - 3.0f * yy); break;
+        case 10: Y = kC3b * x * y * z; gx = kC3b * y * z; gy = kC3b * x * z; gz = kC3b * x * y;
+                 break;
+        case 11: Y = -kC3c * y * (4.0f * zz - xx - yy);
+                 gx = 2.0f * kC3c * x * y; gy = -kC3c * (4.0f * zz - xx - 3.0f * yy);
+                 gz = -8.0f * kC3c * y * z; break;
+        case 12: Y = kC3d * z * (2.0f * zz - 3.0f * xx - 3.0f * yy);
+                 gx = -6.0f * kC3d * x * z; gy = -6.0f * kC3d * y * z;
+                 gz = kC3d * (6.0f * zz - 3.0f * xx - 3.0f * yy); break;
+        case 13: Y = -kC3c * x * (4.0f * zz - xx - yy);
+                 gx = -kC3c * (4.0f * zz - 3.0f * xx - yy); gy = 2.0f * kC3c * x * y;
+                 gz = -8.0f * kC3c * x * z; break;
+        case 14: Y = kC3e * z * (xx - yy); gx = 2.0f * kC3e * x * z; gy = -2.0f * kC3e * y * z;
+                 gz = kC3e * (xx - yy); break;
+        default: Y = -kC3a * x * (xx - 3.0f * yy); gx = -kC3a * (3.0f * xx - 3.0f * yy);
+                 gy = 6.0f * kC3a * x * y; break;
     }
 }
 
@@ -263,27 +264,79 @@ struct BwdOut {
     float* sh;
 };
 
-__global__ __launch_bounds__(256) void k_preprocess_bwd(ss_camera cam, BwdIn in, int64_t n,
-                                                        const float4* __restrict__ conic_rec,
-                                                        const float4* __restrict__ rgb_rec,
-                                                        const float* __restrict__ g2d,
-                                                        BwdOut out) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+constexpr int kPbBlock = 64;               // one wave per workgroup
+constexpr int kShRow = 48;                 // SH floats per Gaussian staged (degree 3)
+constexpr int kShPitchB = kShRow + 1;      // odd LDS pitch
+
+// Stage 8.  One lane per Gaussian, one wave per workgroup.  The SH part runs
+// in FP32 (the forward colour is FP32): the workgroup's SH rows are staged
+// through LDS with coalesced loads, each lane overwrites its row in place with
+// dL/dh, and the rows are written back coalesced.  The geometry chain is FP64.
+__global__ __launch_bounds__(kPbBlock) void k_preprocess_bwd(ss_camera cam, BwdIn in, int64_t n,
+                                                            const float4* __restrict__ conic_rec,
+                                                            const float4* __restrict__ rgb_rec,
+                                                            const float* __restrict__ g2d,
+                                                            BwdOut out) {
+    __shared__ float s_h[kPbBlock * kShPitchB];
+    const int64_t first = (int64_t)blockIdx.x * kPbBlock;
+    const int64_t i = first + threadIdx.x;
+    const int cnt = n - first < kPbBlock ? (int)(n - first) : kPbBlock;
     const int nb = (in.sh_degree + 1) * (in.sh_degree + 1);
-    float* osh = out.sh + (int64_t)3 * in.sh_stride * i;
-    const float4 rec = conic_rec[i];
+    const int need = 3 * nb, row = 3 * in.sh_stride;
+    const bool real = i < n;
+    const float4 rec = real ? conic_rec[i] : make_float4(0.f, 0.f, 0.f, 0.f);
     const bool alive = rec.x != 0.0f || rec.y != 0.0f || rec.z != 0.0f;
+    const float* G = g2d + (size_t)(real ? i : 0) * 12;
+    const float4 col = real ? rgb_rec[i] : make_float4(0.f, 0.f, 0.f, 0.f);
+    // a channel the forward clamped to 0, as its stored colour shows, passes no gradient
+    const float gs0 = alive && col.x > 0.0f ? G[8] : 0.0f;
+    const float gs1 = alive && col.y > 0.0f ? G[9] : 0.0f;
+    const float gs2 = alive && col.z > 0.0f ? G[10] : 0.0f;
+
+    // ---- colour -> SH and view direction (FP32)
+    for (int e = threadIdx.x; e < cnt * need; e += kPbBlock) {
+        const int g = e / need, j = e - g * need;
+        s_h[g * kShPitchB + j] = in.sh[(first + g) * row + j];
+    }
+    __syncthreads();
+    float gdx = 0.0f, gdy = 0.0f, gdz = 0.0f, dirx = 0.0f, diry = 0.0f, dirz = 0.0f, len = 1.0f;
+    if (real) {
+        const float cpx = -((cam.R[0] * cam.t[0] + cam.R[3] * cam.t[1]) + cam.R[6] * cam.t[2]);
+        const float cpy = -((cam.R[1] * cam.t[0] + cam.R[4] * cam.t[1]) + cam.R[7] * cam.t[2]);
+        const float cpz = -((cam.R[2] * cam.t[0] + cam.R[5] * cam.t[1]) + cam.R[8] * cam.t[2]);
+        const float dvx = in.means[3 * i] - cpx, dvy = in.means[3 * i + 1] - cpy,
+                    dvz = in.means[3 * i + 2] - cpz;
+        len = sqrtf(dvx * dvx + dvy * dvy + dvz * dvz);
+        dirx = dvx / len; diry = dvy / len; dirz = dvz / len;
+        float* h = s_h + threadIdx.x * kShPitchB;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            if (k < nb) {
+                float Y, tx, ty, tz;
+                sh_term(k, dirx, diry, dirz, Y, tx, ty, tz);
+                const float gy = (h[3 * k] * gs0 + h[3 * k + 1] * gs1) + h[3 * k + 2] * gs2;
+                gdx = fmaf(gy, tx, gdx);
+                gdy = fmaf(gy, ty, gdy);
+                gdz = fmaf(gy, tz, gdz);
+                h[3 * k] = Y * gs0;            // dL/dh replaces h in this lane's own row
+                h[3 * k + 1] = Y * gs1;
+                h[3 * k + 2] = Y * gs2;
+            }
+        }
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < cnt * row; e += kPbBlock) {
+        const int g = e / row, j = e - g * row;
+        out.sh[(first + g) * row + j] = j < need ? s_h[g * kShPitchB + j] : 0.0f;
+    }
+    if (!real) return;
     if (!alive) {
         for (int k = 0; k < 3; ++k) { out.means[3 * i + k] = 0.f; out.scales[3 * i + k] = 0.f; }
         for (int k = 0; k < 4; ++k) out.quats[4 * i + k] = 0.f;
         out.opacity[i] = 0.f;
-        for (int k = 0; k < 3 * in.sh_stride; ++k) osh[k] = 0.f;
         return;
     }
-    const float* G = g2d + (size_t)i * 12;
     const double gu = G[0], gv = G[1], ga = G[4], gb = G[5], gc = G[6];
-    const double grgb[3] = {G[8], G[9], G[10]};
     out.opacity[i] = G[7];
 
     const double Rc[9] = {cam.R[0], cam.R[1], cam.R[2], cam.R[3], cam.R[4],
@@ -293,37 +346,13 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(ss_camera cam, BwdIn in,
     const double y = ((Rc[3] * mx + Rc[4] * my) + Rc[5] * mz) + (double)cam.t[1];
     const double z = ((Rc[6] * mx + Rc[7] * my) + Rc[8] * mz) + (double)cam.t[2];
     const double fx = cam.fx, fy = cam.fy;
-
-    // ---- colour -> SH and view direction (a channel the forward clamped to 0,
-    // as its stored colour shows, passes no gradient)
     double gpos[3] = {0.0, 0.0, 0.0};   // gradient w.r.t. the camera-space point
-    double gmean[3] = {0.0, 0.0, 0.0};  // gradient w.r.t. the world mean
-    {
-        const float cpx = -((cam.R[0] * cam.t[0] + cam.R[3] * cam.t[1]) + cam.R[6] * cam.t[2]);
-        const float cpy = -((cam.R[1] * cam.t[0] + cam.R[4] * cam.t[1]) + cam.R[7] * cam.t[2]);
-        const float cpz = -((cam.R[2] * cam.t[0] + cam.R[5] * cam.t[1]) + cam.R[8] * cam.t[2]);
-        const float m0 = in.means[3 * i], m1 = in.means[3 * i + 1], m2 = in.means[3 * i + 2];
-        const double dvx = (double)m0 - cpx, dvy = (double)m1 - cpy, dvz = (double)m2 - cpz;
-        const double len = sqrt(dvx * dvx + dvy * dvy + dvz * dvz);
-        const double dx = dvx / len, dy = dvy / len, dz = dvz / len;
-        double Y[16], dY[16][3];
-        sh_basis_grad(dx, dy, dz, nb, Y, dY);
-        const float* h = in.sh + (int64_t)3 * in.sh_stride * i;
-        const float4 col = rgb_rec[i];
-        const double gsum[3] = {col.x > 0.0f ? grgb[0] : 0.0, col.y > 0.0f ? grgb[1] : 0.0,
-                                col.z > 0.0f ? grgb[2] : 0.0};
-        double gd[3] = {0.0, 0.0, 0.0};
-        for (int k = 0; k < nb; ++k) {
-            const double gy = (double)h[3 * k] * gsum[0] + (double)h[3 * k + 1] * gsum[1] +
-                              (double)h[3 * k + 2] * gsum[2];
-            for (int a = 0; a < 3; ++a) gd[a] += gy * dY[k][a];
-            for (int ch = 0; ch < 3; ++ch) osh[3 * k + ch] = (float)(Y[k] * gsum[ch]);
-        }
-        for (int k = 3 * nb; k < 3 * in.sh_stride; ++k) osh[k] = 0.f;
-        const double dd = gd[0] * dx + gd[1] * dy + gd[2] * dz;
-        gmean[0] += (gd[0] - dx * dd) / len;
-        gmean[1] += (gd[1] - dy * dd) / len;
-        gmean[2] += (gd[2] - dz * dd) / len;
+    double gmean[3];                    // gradient w.r.t. the world mean
+    {   // the view direction d = v / |v|, v = mean - camera centre
+        const float dd = (gdx * dirx + gdy * diry) + gdz * dirz;
+        gmean[0] = (double)((gdx - dirx * dd) / len);
+        gmean[1] = (double)((gdy - diry * dd) / len);
+        gmean[2] = (double)((gdz - dirz * dd) / len);
     }
 
     // ---- projection of the mean
@@ -468,7 +497,7 @@ hipError_t launch_backward(const ss_camera& cam, const ss_gaussians& g, const ss
                                out.score, g.n);
     }
     const int grid = 8 * ((n_tiles + 7) / 8);
-    hipLaunchKernelGGL(k_blend_bwd<1>, dim3(grid), dim3(256), 0, s, tx_n, n_tiles, cam.width,
+    hipLaunchKernelGGL(k_blend_bwd<4>, dim3(grid), dim3(64), 0, s, tx_n, n_tiles, cam.width,
                        cam.height, cam.bg[0], cam.bg[1], cam.bg[2], f.ranges, values,
                        reinterpret_cast<const float4*>(f.geom),
                        reinterpret_cast<const float4*>(f.conic),
@@ -477,8 +506,9 @@ hipError_t launch_backward(const ss_camera& cam, const ss_gaussians& g, const ss
     if (g.n > 0) {
         BwdIn in{g.means, g.scales, g.quats, g.opacity, g.sh, g.sh_degree, g.sh_stride};
         BwdOut o{out.means, out.scales, out.quats, out.opacity, out.sh};
-        hipLaunchKernelGGL(k_preprocess_bwd, dim3((unsigned)((g.n + 255) / 256)), dim3(256), 0, s,
-                           cam, in, g.n, reinterpret_cast<const float4*>(f.conic),
+        hipLaunchKernelGGL(k_preprocess_bwd, dim3((unsigned)((g.n + kPbBlock - 1) / kPbBlock)),
+                           dim3(kPbBlock), 0, s, cam, in, g.n,
+                           reinterpret_cast<const float4*>(f.conic),
                            reinterpret_cast<const float4*>(f.rgb), out.g2d, o);
     }
     return hipGetLastError();
