@@ -35,19 +35,26 @@ struct Rec {
     float4 c;   // (r, g, b, -)
 };
 
-__device__ __forceinline__ Rec load_rec(const uint32_t* __restrict__ values,
-                                        const float4* __restrict__ geom,
-                                        const float4* __restrict__ conic,
-                                        const float4* __restrict__ rgb, uint32_t j, uint32_t end) {
+__device__ __forceinline__ Rec make_rec0() {
     Rec r;
-    if (j < end) {
-        const uint32_t gi = values[j];
-        r.g = geom[gi];
-        r.q = conic[gi];
-        r.c = rgb[gi];
-    } else {
-        r.g = r.q = r.c = make_float4(0.f, 0.f, 0.f, 0.f);
-    }
+    r.g = r.q = r.c = make_float4(0.f, 0.f, 0.f, 0.f);
+    return r;
+}
+
+// The record of list entry min(j, last): loads with no condition, so the
+// compiler keeps them in flight until the values are used.
+__device__ __forceinline__ uint32_t entry_gid(const uint32_t* __restrict__ values, uint32_t j,
+                                              uint32_t last) {
+    return values[j < last ? j : last];
+}
+
+__device__ __forceinline__ Rec load_rec(const float4* __restrict__ geom,
+                                        const float4* __restrict__ conic,
+                                        const float4* __restrict__ rgb, uint32_t gi) {
+    Rec r;
+    r.g = geom[gi];
+    r.q = conic[gi];
+    r.c = rgb[gi];
     return r;
 }
 
@@ -99,18 +106,33 @@ __global__ __launch_bounds__(64) void k_blend(const Item* __restrict__ items, Ba
 #pragma unroll
     for (int s = 0; s < 4; ++s) sl |= (__ballot(fy[s] < kDone) != 0ull ? 1u : 0u) << s;
     const uint32_t start = ranges[2 * tile], end = ranges[2 * tile + 1];
-    Rec nxt = load_rec(values, geom, conic, rgb, start + lane, end);
+    // Batch b's records are fetched during batch b - 1 and their list entries
+    // during batch b - 2, so neither load stalls a batch.  Entries past the
+    // list end repeat its last entry (in bounds, never read from LDS).
+    const uint32_t e_last = end > start ? end - 1 : start;
+    Rec nxt = make_rec0();
+    uint32_t gid_nx = 0;
+    if (start < end) {
+        nxt = load_rec(geom, conic, rgb, entry_gid(values, start + lane, e_last));
+        gid_nx = entry_gid(values, start + kBatch + lane, e_last);
+    }
     for (uint32_t base = start; base < end && sl; base += kBatch) {
         s_geo[lane] = nxt.g;
         s_con[lane] = make_float4(nxt.q.x, 2.0f * nxt.q.y, nxt.q.z, nxt.q.w);
         s_col[lane] = nxt.c;
         __syncthreads();
-        if (base + kBatch < end) nxt = load_rec(values, geom, conic, rgb, base + kBatch + lane, end);
+        nxt = load_rec(geom, conic, rgb, gid_nx);
+        gid_nx = entry_gid(values, base + 2 * kBatch + lane, e_last);
         const uint32_t nb = end - base < (uint32_t)kBatch ? end - base : (uint32_t)kBatch;
+        // LDS reads run one entry ahead of their use, so their latency overlaps
+        // the current entry's arithmetic
+        float4 g_nx = s_geo[0], q_nx = s_con[0], c_nx = s_col[0];
         for (uint32_t k = 0; k < nb; ++k) {
-            const float4 g = s_geo[k];
-            const float4 q = s_con[k];
-            const float4 c = s_col[k];
+            const float4 g = g_nx, q = q_nx, c = c_nx;
+            const uint32_t kn = k + 1 < nb ? k + 1 : k;
+            g_nx = s_geo[kn];
+            q_nx = s_con[kn];
+            c_nx = s_col[kn];
             const float dx = fx - g.x;
             const float adx2 = (q.x * dx) * dx;
             const float b2dx = q.y * dx;

@@ -58,20 +58,36 @@ __device__ __forceinline__ void stage_sh(const float* __restrict__ sh, int64_t f
         // (row is a multiple of 4); floats past `need` are not kept
         const unsigned q = (unsigned)(need + 3) >> 2, urow4 = (unsigned)row >> 2;
         const float4* src4 = reinterpret_cast<const float4*>(src);
-        for (unsigned e = threadIdx.x; e < (unsigned)cnt * q; e += kBlock) {
-            const unsigned g = e / q, j = e - g * q;
-            if (!s_vis[g]) continue;
-            const float4 v = src4[g * urow4 + j];
-            float* d = s_sh + g * kShPitch + 4 * j;
-            d[0] = v.x;
-            if ((int)(4 * j) + 1 < need) d[1] = v.y;
-            if ((int)(4 * j) + 2 < need) d[2] = v.z;
-            if ((int)(4 * j) + 3 < need) d[3] = v.w;
+        // kUnroll loads are issued before the first LDS store, so their
+        // latencies overlap instead of adding up
+        constexpr unsigned kUnroll = 6;
+        const unsigned total = (unsigned)cnt * q;
+        for (unsigned e0 = threadIdx.x; e0 < total; e0 += kUnroll * kBlock) {
+            float4 v[kUnroll];
+            unsigned g[kUnroll], j[kUnroll];
+            bool ok[kUnroll];
+#pragma unroll
+            for (unsigned u = 0; u < kUnroll; ++u) {
+                const unsigned e = e0 + u * kBlock;
+                g[u] = e / q;
+                j[u] = e - g[u] * q;
+                ok[u] = e < total && s_vis[g[u]];
+                v[u] = ok[u] ? ld_global(src4 + g[u] * urow4 + j[u]) : make_float4(0.f, 0.f, 0.f, 0.f);
+            }
+#pragma unroll
+            for (unsigned u = 0; u < kUnroll; ++u) {
+                if (!ok[u]) continue;
+                float* d = s_sh + g[u] * kShPitch + 4 * j[u];
+                d[0] = v[u].x;
+                if ((int)(4 * j[u]) + 1 < need) d[1] = v[u].y;
+                if ((int)(4 * j[u]) + 2 < need) d[2] = v[u].z;
+                if ((int)(4 * j[u]) + 3 < need) d[3] = v[u].w;
+            }
         }
     } else {
         for (unsigned e = threadIdx.x; e < (unsigned)(cnt * need); e += kBlock) {
             const unsigned g = e / (unsigned)need, j = e - g * (unsigned)need;
-            if (s_vis[g]) s_sh[g * kShPitch + j] = src[(int64_t)g * row + j];
+            if (s_vis[g]) s_sh[g * kShPitch + j] = ld_global(src + (int64_t)g * row + j);
         }
     }
 }
@@ -263,7 +279,8 @@ __global__ __launch_bounds__(kBlock) void k_colour(const Item* __restrict__ item
         rgb_out[o] = make_float4(0.f, 0.f, 0.f, 0.f);
         return;
     }
-    const float m0 = it.means[3 * i], m1 = it.means[3 * i + 1], m2 = it.means[3 * i + 2];
+    const float m0 = ld_global(it.means + 3 * i), m1 = ld_global(it.means + 3 * i + 1),
+                m2 = ld_global(it.means + 3 * i + 2);
     const float cpx = -((cam.R[0] * cam.t[0] + cam.R[3] * cam.t[1]) + cam.R[6] * cam.t[2]);
     const float cpy = -((cam.R[1] * cam.t[0] + cam.R[4] * cam.t[1]) + cam.R[7] * cam.t[2]);
     const float cpz = -((cam.R[2] * cam.t[0] + cam.R[5] * cam.t[1]) + cam.R[8] * cam.t[2]);

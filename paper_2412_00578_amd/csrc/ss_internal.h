@@ -183,6 +183,15 @@ __device__ __forceinline__ uint32_t tile_set(float4 g, float4 q, int mode, int t
     Ellipse e;
     if (!ellipse_setup(g, q, mode, tx_n, ty_n, e)) return 0u;
     const bool fits = e.x1 - e.x0 < kSetSide && e.y1 - e.y0 < kSetSide;
+    if (mode != SS_TILE_ACCUTILE) {
+        // the whole rectangle: its row run repeated once per row
+        const uint32_t w = (uint32_t)(e.x1 - e.x0 + 1), h = (uint32_t)(e.y1 - e.y0 + 1);
+        if (fits) {
+            *mask = ((1ull << w) - 1ull) * (0x0101010101010101ull >> (8u * (kSetSide - h)));
+            *origin = (uint32_t)e.x0 | ((uint32_t)e.y0 << 16);
+        }
+        return w * h;
+    }
     const bool cols = span_columns(e, mode);
     uint32_t n = 0;
     uint64_t m = 0ull;
@@ -243,6 +252,21 @@ struct Item {
     int32_t tile_off;     // first global tile id
     int32_t pad_;
 };
+
+// Loads through pointers read from an item table.  The compiler cannot tell
+// that such a pointer is global and would emit flat loads, whose completion
+// is counted together with LDS and scalar loads, so that every LDS wait also
+// waits for them; these take the global path explicitly.
+typedef float ss_v4f __attribute__((ext_vector_type(4)));
+typedef const __attribute__((address_space(1))) float ss_gfloat;
+typedef const __attribute__((address_space(1))) ss_v4f ss_gv4f;
+
+__device__ __forceinline__ float ld_global(const float* p) { return *(ss_gfloat*)p; }
+
+__device__ __forceinline__ float4 ld_global(const float4* p) {
+    const ss_v4f v = *(ss_gv4f*)p;
+    return make_float4(v.x, v.y, v.z, v.w);
+}
 
 struct BatchDims {
     int32_t n_items;
