@@ -228,54 +228,82 @@ __global__ __launch_bounds__(kBigBlock) void k_emit_big(const Item* __restrict__
     const uint32_t nq = seg_off[nb];
     const uint32_t wave0 = blockIdx.x * (kBigBlock / 64) + w;
     const uint32_t waves = gridDim.x * (kBigBlock / 64);
-    for (uint32_t b = wave0; b < nq; b += waves) {
-        // the segment holding queued entry b: the last with offset <= b
-        int64_t lo = 0, hi = nb - 1;
-        while (lo < hi) {
-            const int64_t mid = (lo + hi + 1) >> 1;
-            if (seg_off[mid] <= b) lo = mid; else hi = mid - 1;
-        }
-        const uint32_t j = queue[lo * kEmitBlock + (b - seg_off[lo])];   // depth-order entry
-        const uint32_t i = order[j];
-        const Item& it = items[dims.n_items == 1 ? 0 : item_of_slot(items, dims.n_items, i)];
-        const int tx_n = it.tx_n, ty_n = it.ty_n;
-        const uint32_t tile_off = (uint32_t)it.tile_off;
-        const uint32_t pos0 = j > 0 ? offsets[j - 1] : 0u;
-        const uint32_t end = offsets[j];
+    // Each round, lane l of the wave looks up queued entry wave0 + (64 r + l)
+    // waves, so that the chains of dependent loads (segment search, entry,
+    // Gaussian, record) of 64 entries overlap; the wave then walks the 64
+    // entries' spans one entry at a time.
+    for (uint32_t r0 = 0; wave0 + (uint64_t)r0 * waves < nq; r0 += 64) {
+        const uint64_t bq = wave0 + (uint64_t)(r0 + lane) * waves;
+        const bool have = bq < nq;
+        const uint32_t b = have ? (uint32_t)bq : 0u;
         Ellipse e;
-        if (!ellipse_setup(geom[i], conic[i], mode, tx_n, ty_n, e)) continue;
-        const bool cols = span_columns(e, mode);
-        const int maj0 = cols ? e.x0 : e.y0;
-        const int nmaj = cols ? e.x1 - e.x0 + 1 : e.y1 - e.y0 + 1;
-        uint32_t done = 0;
-        for (int c0 = 0; c0 < nmaj; c0 += 64) {
-            int lo = 0, hi = -1;
-            if (c0 + lane < nmaj) one_span(e, mode, tx_n, ty_n, cols, maj0 + c0 + lane, lo, hi);
-            const uint32_t len = hi >= lo ? (uint32_t)(hi - lo + 1) : 0u;
-            const uint32_t incl = wave_incl_scan_u32(len);
-            const uint32_t total = __shfl(incl, 63, 64);
-            s_excl[w][lane] = incl - len;
-            s_lo[w][lane] = lo;
-            wave_lds_sync();
-            for (uint32_t idx = lane; idx < total; idx += 64) {
-                // the last span whose exclusive start is <= idx
-                int a = 0, z = 63;
-                while (a < z) {
-                    const int mid = (a + z + 1) >> 1;
-                    if (s_excl[w][mid] <= idx) a = mid; else z = mid - 1;
-                }
-                const int major = maj0 + c0 + a;
-                const int minor = s_lo[w][a] + (int)(idx - s_excl[w][a]);
-                const uint32_t tile = tile_off + (cols ? (uint32_t)(minor * tx_n + major)
-                                                       : (uint32_t)(major * tx_n + minor));
-                const uint32_t pos = pos0 + done + idx;
-                if (pos < end && pos < limit) {
-                    keys[pos] = tile;
-                    values[pos] = i;
-                }
+        bool ok = false;
+        uint32_t i = 0, pos0 = 0, end = 0, tile_off = 0;
+        int tx_n = 0, ty_n = 0;
+        if (have) {
+            // the segment holding queued entry b: the last with offset <= b
+            int64_t lo = 0, hi = nb - 1;
+            while (lo < hi) {
+                const int64_t mid = (lo + hi + 1) >> 1;
+                if (seg_off[mid] <= b) lo = mid; else hi = mid - 1;
             }
-            done += total;
-            wave_lds_sync();
+            const uint32_t j = queue[lo * kEmitBlock + (b - seg_off[lo])];   // depth-order entry
+            i = order[j];
+            const Item& it = items[dims.n_items == 1 ? 0 : item_of_slot(items, dims.n_items, i)];
+            tx_n = it.tx_n;
+            ty_n = it.ty_n;
+            tile_off = (uint32_t)it.tile_off;
+            pos0 = j > 0 ? offsets[j - 1] : 0u;
+            end = offsets[j];
+            ok = ellipse_setup(geom[i], conic[i], mode, tx_n, ty_n, e);
+        }
+        uint64_t todo = __ballot(ok);
+        while (todo) {
+            const int L = __builtin_ctzll(todo);
+            todo &= todo - 1ull;
+            Ellipse el;
+            el.u = __shfl(e.u, L, 64); el.v = __shfl(e.v, L, 64);
+            el.a = __shfl(e.a, L, 64); el.b = __shfl(e.b, L, 64); el.c = __shfl(e.c, L, 64);
+            el.t = __shfl(e.t, L, 64); el.det = __shfl(e.det, L, 64);
+            el.hx = __shfl(e.hx, L, 64); el.hy = __shfl(e.hy, L, 64);
+            el.x0 = __shfl(e.x0, L, 64); el.x1 = __shfl(e.x1, L, 64);
+            el.y0 = __shfl(e.y0, L, 64); el.y1 = __shfl(e.y1, L, 64);
+            const uint32_t gi = __shfl(i, L, 64), p0 = __shfl(pos0, L, 64);
+            const uint32_t pend = __shfl(end, L, 64), toff = __shfl(tile_off, L, 64);
+            const int txn = __shfl(tx_n, L, 64), tyn = __shfl(ty_n, L, 64);
+            const bool cols = span_columns(el, mode);
+            const int maj0 = cols ? el.x0 : el.y0;
+            const int nmaj = cols ? el.x1 - el.x0 + 1 : el.y1 - el.y0 + 1;
+            uint32_t done = 0;
+            for (int c0 = 0; c0 < nmaj; c0 += 64) {
+                int lo = 0, hi = -1;
+                if (c0 + lane < nmaj) one_span(el, mode, txn, tyn, cols, maj0 + c0 + lane, lo, hi);
+                const uint32_t len = hi >= lo ? (uint32_t)(hi - lo + 1) : 0u;
+                const uint32_t incl = wave_incl_scan_u32(len);
+                const uint32_t total = __shfl(incl, 63, 64);
+                s_excl[w][lane] = incl - len;
+                s_lo[w][lane] = lo;
+                wave_lds_sync();
+                for (uint32_t idx = lane; idx < total; idx += 64) {
+                    // the last span whose exclusive start is <= idx
+                    int a = 0, z = 63;
+                    while (a < z) {
+                        const int mid = (a + z + 1) >> 1;
+                        if (s_excl[w][mid] <= idx) a = mid; else z = mid - 1;
+                    }
+                    const int major = maj0 + c0 + a;
+                    const int minor = s_lo[w][a] + (int)(idx - s_excl[w][a]);
+                    const uint32_t tile = toff + (cols ? (uint32_t)(minor * txn + major)
+                                                       : (uint32_t)(major * txn + minor));
+                    const uint32_t pos = p0 + done + idx;
+                    if (pos < pend && pos < limit) {
+                        keys[pos] = tile;
+                        values[pos] = gi;
+                    }
+                }
+                done += total;
+                wave_lds_sync();
+            }
         }
     }
 }

@@ -100,6 +100,7 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(const Item* __restrict__ 
                                                        uint32_t* __restrict__ dkeys,
                                                        uint4* __restrict__ tsets,
                                                        uint32_t* __restrict__ partials) {
+    __shared__ uint32_t s_cnt[kBlock];
     const int64_t slot0 = (int64_t)blockIdx.x * kBlock;
     const Item& it = items[dims.n_items == 1 ? 0 : item_of_slot(items, dims.n_items, slot0)];
     const ss_camera cam = it.cam;
@@ -121,7 +122,10 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(const Item* __restrict__ 
     }
 
     // The record, its count and its tile set; 0 for a padding slot or a culled
-    // Gaussian (whose record is zeroed).
+    // Gaussian (whose record is zeroed), and for a record whose count is left
+    // to the wave (defer).
+    float4 g4 = make_float4(0.f, 0.f, 0.f, 0.f), q4 = g4;
+    bool defer = false;
     auto record = [&]() -> uint32_t {
         const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
         if (i >= n) {  // padding slot between items
@@ -223,19 +227,31 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(const Item* __restrict__ 
             return 0u;
         }
 
-        const float4 g4 = make_float4((float)u, (float)v, (float)z, tt);
-        const float4 q4 = make_float4(ca, cb, cc, op);
+        g4 = make_float4((float)u, (float)v, (float)z, tt);
+        q4 = make_float4(ca, cb, cc, op);
         geom[o] = g4;
         conic[o] = q4;
         uint64_t mask;
         uint32_t origin;
-        const uint32_t cnt = tile_set(g4, q4, mode, tx_n, ty_n, &mask, &origin);
+        const uint32_t cnt = tile_set(g4, q4, mode, tx_n, ty_n, &mask, &origin, &defer);
+        tsets[o] = make_uint4((uint32_t)mask, (uint32_t)(mask >> 32), origin, 0u);
+        if (defer) return 0u;
         counts[o] = cnt;
         dkeys[o] = cnt ? __float_as_uint(g4.z) : kCulledKey;
-        tsets[o] = make_uint4((uint32_t)mask, (uint32_t)(mask >> 32), origin, 0u);
         return cnt;
     };
-    const uint32_t cnt = o < dims.n_slots ? record() : 0u;
+    uint32_t cnt = o < dims.n_slots ? record() : 0u;
+
+    // Long AccuTile walks are shared out over the wave rather than left to
+    // one lane while the others wait.
+    if (__ballot(defer)) {
+        const uint32_t c = accutile_count_wave(defer, g4, q4, tx_n, ty_n, s_cnt);
+        if (defer) {
+            cnt = c;
+            counts[o] = cnt;
+            dkeys[o] = cnt ? __float_as_uint(g4.z) : kCulledKey;
+        }
+    }
 
     // This workgroup's (one wave's) share of the pair count P and of the
     // Gaussians with tiles, summed by k_totals: plain stores, since thousands

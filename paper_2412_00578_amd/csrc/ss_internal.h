@@ -163,6 +163,66 @@ __device__ __forceinline__ bool for_each_span(const Ellipse& e, int mode, int tx
     return true;
 }
 
+// Band k (0-based) of an AccuTile walk on its own: the span for_each_span
+// reports for major index x0 + k / y0 + k, from the same FP64 operations (a
+// band's lower boundary is the previous band's upper one, min(16 (y0 + k),
+// box top), recomputed here).  False when the band's span is empty.
+__device__ __forceinline__ bool accutile_band(const Ellipse& e, bool cols, int k, int tx_n,
+                                              int ty_n, int& lo, int& hi) {
+    if (!cols) {
+        const int ty = e.y0 + k;
+        const double kk = (e.b / e.c) * e.hx;
+        const double y_left = e.v + kk, y_right = e.v - kk;
+        const double box_b = e.v - e.hy, box_t = e.v + e.hy;
+        const double x_min = e.u - e.hx, x_max = e.u + e.hx;
+        double ylo;
+        if (k == 0) {
+            ylo = 16.0 * e.y0;
+            ylo = ylo < box_b ? box_b : ylo;
+        } else {
+            ylo = 16.0 * ty;
+            ylo = ylo > box_t ? box_t : ylo;
+        }
+        double yhi = 16.0 * ty + 16.0;
+        yhi = yhi > box_t ? box_t : yhi;
+        double l0, r0, l1, r1;
+        row_roots(e, ylo, l0, r0);
+        row_roots(e, yhi, l1, r1);
+        const double left = (ylo <= y_left && y_left <= yhi) ? x_min : (l0 < l1 ? l0 : l1);
+        const double right = (ylo <= y_right && y_right <= yhi) ? x_max : (r0 > r1 ? r0 : r1);
+        lo = tile_lo(left, tx_n);
+        hi = tile_hi(right, tx_n);
+        lo = lo < e.x0 ? e.x0 : lo;
+        hi = hi > e.x1 ? e.x1 : hi;
+        return lo <= hi;
+    }
+    const int tx = e.x0 + k;
+    const double m = (e.b / e.a) * e.hy;
+    const double x_top = e.u + m, x_bot = e.u - m;
+    const double box_l = e.u - e.hx, box_r = e.u + e.hx;
+    const double y_min = e.v - e.hy, y_max = e.v + e.hy;
+    double xlo;
+    if (k == 0) {
+        xlo = 16.0 * e.x0;
+        xlo = xlo < box_l ? box_l : xlo;
+    } else {
+        xlo = 16.0 * tx;
+        xlo = xlo > box_r ? box_r : xlo;
+    }
+    double xhi = 16.0 * tx + 16.0;
+    xhi = xhi > box_r ? box_r : xhi;
+    double t0, b0, t1, b1;
+    col_roots(e, xlo, t0, b0);
+    col_roots(e, xhi, t1, b1);
+    const double top = (xlo <= x_top && x_top <= xhi) ? y_min : (t0 < t1 ? t0 : t1);
+    const double bot = (xlo <= x_bot && x_bot <= xhi) ? y_max : (b0 > b1 ? b0 : b1);
+    lo = tile_lo(top, ty_n);
+    hi = tile_hi(bot, ty_n);
+    lo = lo < e.y0 ? e.y0 : lo;
+    hi = hi > e.y1 ? e.y1 : hi;
+    return lo <= hi;
+}
+
 // AccuTile walks columns when the tile extent has more rows than columns.
 __device__ __forceinline__ bool span_columns(const Ellipse& e, int mode) {
     return mode == SS_TILE_ACCUTILE && (e.y1 - e.y0 > e.x1 - e.x0);
@@ -173,11 +233,18 @@ __device__ __forceinline__ bool span_columns(const Ellipse& e, int mode) {
 // window, bit r * kSetSide + c for tile (x0 + c, y0 + r).
 constexpr int kSetSide = 8;
 
+// An AccuTile record whose walk has more bands than this and whose rectangle
+// does not fit the window is counted by its whole wave (accutile_count_wave).
+constexpr int kSerialBands = 4;
+
 // Counts the record's tiles under `mode` and, when its tile rectangle fits the
 // window, records them: *mask gets the bits, *origin = x0 | y0 << 16.
-// Otherwise *mask = 0 (the emit stage re-walks the spans).
+// Otherwise *mask = 0 (the emit stage re-walks the spans).  With `defer`
+// given, a long AccuTile walk is not done: *defer is set, 0 returned, and the
+// caller counts the record with accutile_count_wave.
 __device__ __forceinline__ uint32_t tile_set(float4 g, float4 q, int mode, int tx_n, int ty_n,
-                                             uint64_t* mask, uint32_t* origin) {
+                                             uint64_t* mask, uint32_t* origin,
+                                             bool* defer = nullptr) {
     *mask = 0ull;
     *origin = 0u;
     Ellipse e;
@@ -193,6 +260,13 @@ __device__ __forceinline__ uint32_t tile_set(float4 g, float4 q, int mode, int t
         return w * h;
     }
     const bool cols = span_columns(e, mode);
+    if (defer && !fits) {
+        const int bands = cols ? e.x1 - e.x0 + 1 : e.y1 - e.y0 + 1;
+        if (bands > kSerialBands) {
+            *defer = true;
+            return 0u;
+        }
+    }
     uint32_t n = 0;
     uint64_t m = 0ull;
     for_each_span(e, mode, tx_n, ty_n, [&](int major, int lo, int hi) {
@@ -210,6 +284,62 @@ __device__ __forceinline__ uint32_t tile_set(float4 g, float4 q, int mode, int t
         *origin = (uint32_t)e.x0 | ((uint32_t)e.y0 << 16);
     }
     return n;
+}
+
+// AccuTile tile counts of the wave's lanes with `defer` set (records g, q),
+// counted by the whole wave: the bands of all those records are dealt out to
+// the 64 lanes, each band evaluated on its own by accutile_band, and the band
+// counts summed per record in s_cnt (64 words of LDS).  Returns the lane's own
+// count (0 for a lane without `defer`).  All 64 lanes must call it.
+__device__ __forceinline__ uint32_t accutile_count_wave(bool defer, float4 g, float4 q, int tx_n,
+                                                        int ty_n, uint32_t* s_cnt) {
+    const int lane = (int)__lane_id();
+    Ellipse e;
+    bool cols = false;
+    int nb = 0;
+    if (defer) {
+        ellipse_setup(g, q, SS_TILE_ACCUTILE, tx_n, ty_n, e);
+        cols = span_columns(e, SS_TILE_ACCUTILE);
+        nb = cols ? e.x1 - e.x0 + 1 : e.y1 - e.y0 + 1;
+    } else {
+        e.u = e.v = e.a = e.b = e.c = e.t = e.det = e.hx = e.hy = 0.0;
+        e.x0 = e.x1 = e.y0 = e.y1 = 0;
+    }
+    // inclusive prefix sum of the band counts over the wave
+    int incl = nb;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int t = __shfl_up(incl, d, 64);
+        if (lane >= d) incl += t;
+    }
+    const int total = __shfl(incl, 63, 64);
+    s_cnt[lane] = 0u;
+    __syncthreads();
+    for (int j0 = 0; j0 < total; j0 += 64) {
+        const int j = j0 + lane;
+        // owner L: the first lane whose inclusive sum exceeds j
+        int L = 0;
+#pragma unroll
+        for (int step = 32; step >= 1; step >>= 1) {
+            const int v = __shfl(incl, L + step - 1, 64);
+            if (v <= j) L += step;
+        }
+        L = L > 63 ? 63 : L;
+        const int k = j - (__shfl(incl, L, 64) - __shfl(nb, L, 64));
+        Ellipse el;
+        el.u = __shfl(e.u, L, 64); el.v = __shfl(e.v, L, 64);
+        el.a = __shfl(e.a, L, 64); el.b = __shfl(e.b, L, 64); el.c = __shfl(e.c, L, 64);
+        el.t = __shfl(e.t, L, 64); el.det = __shfl(e.det, L, 64);
+        el.hx = __shfl(e.hx, L, 64); el.hy = __shfl(e.hy, L, 64);
+        el.x0 = __shfl(e.x0, L, 64); el.x1 = __shfl(e.x1, L, 64);
+        el.y0 = __shfl(e.y0, L, 64); el.y1 = __shfl(e.y1, L, 64);
+        const bool cl = __shfl((int)cols, L, 64) != 0;
+        int lo, hi;
+        if (j < total && accutile_band(el, cl, k, tx_n, ty_n, lo, hi))
+            atomicAdd(&s_cnt[L], (uint32_t)(hi - lo + 1));
+    }
+    __syncthreads();
+    return defer ? s_cnt[lane] : 0u;
 }
 
 // Workgroups are dispatched round-robin over the 8 XCDs of MI355X.  This maps
