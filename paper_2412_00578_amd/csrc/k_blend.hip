@@ -124,15 +124,11 @@ __global__ __launch_bounds__(64) void k_blend(const Item* __restrict__ items, Ba
         nxt = load_rec(geom, conic, rgb, gid_nx);
         gid_nx = entry_gid(values, base + 2 * kBatch + lane, e_last);
         const uint32_t nb = end - base < (uint32_t)kBatch ? end - base : (uint32_t)kBatch;
-        // LDS reads run one entry ahead of their use, so their latency overlaps
-        // the current entry's arithmetic
-        float4 g_nx = s_geo[0], q_nx = s_con[0], c_nx = s_col[0];
+
         for (uint32_t k = 0; k < nb; ++k) {
-            const float4 g = g_nx, q = q_nx, c = c_nx;
-            const uint32_t kn = k + 1 < nb ? k + 1 : k;
-            g_nx = s_geo[kn];
-            q_nx = s_con[kn];
-            c_nx = s_col[kn];
+            const float4 g = s_geo[k];
+            const float4 q = s_con[k];
+            const float4 c = s_col[k];
             const float dx = fx - g.x;
             const float adx2 = (q.x * dx) * dx;
             const float b2dx = q.y * dx;
