@@ -141,7 +141,8 @@ typedef struct ss_frame {
     void *table;            /* [table_bytes] 16-byte aligned: the frame's item table
                                (camera, scene pointers, offsets), written by
                                ss_preprocess / ss_forward_begin / ss_batch_begin and
-                               read by the later stages of the same frame */
+                               read by the later stages of the same frame, then the
+                               blend's tile work order (written by the blend stage) */
 } ss_frame;
 
 typedef struct ss_frame_info {
@@ -291,7 +292,9 @@ int ss_ranges(const ss_camera *cam, const ss_frame *frame, const ss_pairs *pairs
  * is included at a pixel when q <= t (alpha >= 1/255), alpha = min(0.99,
  * sigma exp(-q/2)); the walk stops before a Gaussian that would take the
  * transmittance below 1e-4.  out_rgb is planar [3, H, W] f32; also writes
- * frame->t_final and frame->n_last.
+ * frame->t_final and frame->n_last.  Tiles are processed longest list first
+ * (the order is written into frame->table after the item table); the result
+ * does not depend on the order.
  */
 int ss_blend(const ss_camera *cam, const ss_frame *frame, const ss_pairs *pairs, int32_t buf,
              float *out_rgb, void *stream);

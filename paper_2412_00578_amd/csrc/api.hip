@@ -308,7 +308,7 @@ int ss_frame_sizes(int64_t n, int32_t width, int32_t height, ss_frame_info* out)
     out->scan_tmp_words = ss::scan_tmp_words(n);
     out->order_tmp_words = ss::sort_tmp_words((uint64_t)n);
     out->emit_tmp_words = ss::emit_tmp_words(n);
-    out->table_bytes = (int64_t)((sizeof(ss::Item) + 255) / 256 * 256);
+    out->table_bytes = ss::table_bytes(1, out->n_tiles);
     return SS_OK;
 }
 
@@ -454,7 +454,7 @@ int ss_batch_sizes(const ss_batch_item* items, int32_t n_items, ss_batch_info* o
     out->scan_tmp_words = ss::scan_tmp_words(L.d.n_slots);
     out->order_tmp_words = ss::sort_tmp_words((uint64_t)L.d.n_slots);
     out->emit_tmp_words = ss::emit_tmp_words(L.d.n_slots);
-    out->table_bytes = (int64_t)((sizeof(ss::Item) * (size_t)n_items + 255) / 256 * 256);
+    out->table_bytes = ss::table_bytes(n_items, L.d.n_tiles);
     return SS_OK;
 }
 

@@ -58,8 +58,51 @@ __device__ __forceinline__ Rec load_rec(const float4* __restrict__ geom,
     return r;
 }
 
+// Tile work order: the tiles by decreasing list length (in buckets of 8
+// entries; tiles within a bucket in no particular order).  Workgroups are
+// dispatched in launch order, so the longest tiles start first and the short
+// ones fill the gaps they leave, instead of a long tile that starts late
+// running on alone at the end of the launch.  One workgroup.
+constexpr int kOrderBuckets = 1024;
+
+__device__ __forceinline__ uint32_t order_bucket(uint32_t len) {
+    const uint32_t b = len >> 3;
+    return b < (uint32_t)kOrderBuckets - 1u ? b : (uint32_t)kOrderBuckets - 1u;
+}
+
+__global__ __launch_bounds__(1024) void k_tile_order(const uint32_t* __restrict__ ranges,
+                                                     int n_tiles, uint32_t* __restrict__ order) {
+    __shared__ uint32_t h[kOrderBuckets];
+    __shared__ uint32_t s_w[1024 / 64];
+    const int t0 = (int)threadIdx.x;
+    h[t0] = 0u;
+    __syncthreads();
+    for (int t = t0; t < n_tiles; t += 1024)
+        atomicAdd(&h[order_bucket(ranges[2 * t + 1] - ranges[2 * t])], 1u);
+    __syncthreads();
+    // start of bucket b: the number of tiles in buckets above b
+    const uint32_t x = h[kOrderBuckets - 1 - t0];
+    uint32_t incl = x;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t y = __shfl_up(incl, d, 64);
+        if ((t0 & 63) >= d) incl += y;
+    }
+    if ((t0 & 63) == 63) s_w[t0 >> 6] = incl;
+    __syncthreads();
+    uint32_t before = 0;
+    for (int k = 0; k < (t0 >> 6); ++k) before += s_w[k];
+    h[kOrderBuckets - 1 - t0] = before + incl - x;
+    __syncthreads();
+    for (int t = t0; t < n_tiles; t += 1024) {
+        const uint32_t pos = atomicAdd(&h[order_bucket(ranges[2 * t + 1] - ranges[2 * t])], 1u);
+        order[pos] = (uint32_t)t;
+    }
+}
+
 template <bool STATS>
 __global__ __launch_bounds__(64) void k_blend(const Item* __restrict__ items, BatchDims dims,
+                                              const uint32_t* __restrict__ tile_order,
                                               const uint32_t* __restrict__ ranges,
                                               const uint32_t* __restrict__ values,
                                               const float4* __restrict__ geom,
@@ -73,8 +116,8 @@ __global__ __launch_bounds__(64) void k_blend(const Item* __restrict__ items, Ba
     __shared__ float4 s_geo[kBatch];
     __shared__ float4 s_con[kBatch];
     __shared__ float4 s_col[kBatch];
-    const int tile = xcd_contiguous((int)blockIdx.x, dims.n_tiles);
-    if (tile < 0) return;
+    if ((int)blockIdx.x >= dims.n_tiles) return;
+    const int tile = (int)tile_order[blockIdx.x];
     const Item& it = items[dims.n_items == 1 ? 0 : item_of_tile(items, dims.n_items, tile)];
     const int W = it.cam.width, H = it.cam.height, tx_n = it.tx_n;
     const float bg0 = it.cam.bg[0], bg1 = it.cam.bg[1], bg2 = it.cam.bg[2];
@@ -192,10 +235,12 @@ __global__ __launch_bounds__(64) void k_blend(const Item* __restrict__ items, Ba
 
 hipError_t launch_blend(const Item* items, const BatchDims& d, const ss_frame& f,
                         const uint32_t* values, float* out_rgb_single, hipStream_t s) {
-    const int grid = 8 * ((d.n_tiles + 7) / 8);
+    const int grid = d.n_tiles;
     if (grid == 0) return hipSuccess;
+    uint32_t* order = tile_order_of(f.table, d.n_items);
+    hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(1024), 0, s, f.ranges, d.n_tiles, order);
     auto go = [&](auto kernel) {
-        hipLaunchKernelGGL(kernel, dim3(grid), dim3(64), 0, s, items, d, f.ranges, values,
+        hipLaunchKernelGGL(kernel, dim3(grid), dim3(64), 0, s, items, d, order, f.ranges, values,
                            reinterpret_cast<const float4*>(f.geom),
                            reinterpret_cast<const float4*>(f.conic),
                            reinterpret_cast<const float4*>(f.rgb), out_rgb_single, f.t_final,

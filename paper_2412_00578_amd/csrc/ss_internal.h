@@ -398,6 +398,17 @@ __device__ __forceinline__ float4 ld_global(const float4* p) {
     return make_float4(v.x, v.y, v.z, v.w);
 }
 
+// The item table buffer holds the n_items items, then (from the next 256-byte
+// boundary) the blend's tile work order, one u32 per tile.
+inline int64_t table_bytes(int n_items, int n_tiles) {
+    const int64_t items = ((int64_t)sizeof(Item) * n_items + 255) / 256 * 256;
+    return items + ((int64_t)n_tiles * 4 + 255) / 256 * 256;
+}
+inline uint32_t* tile_order_of(void* table, int n_items) {
+    return reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(table) +
+                                       ((int64_t)sizeof(Item) * n_items + 255) / 256 * 256);
+}
+
 struct BatchDims {
     int32_t n_items;
     int32_t n_tiles;      // total tiles
