@@ -135,9 +135,9 @@ typedef struct ss_frame {
                                tile's list the pixel evaluated before it stopped */
     uint32_t *n_contrib;    /* optional [H, W], written only with n_eval: Gaussians
                                blended into the pixel */
-    uint32_t *emit_tmp;     /* [emit_tmp_words] scratch of the preprocess stage (partial
-                               frame counts) and the emit stage (queue of Gaussians with
-                               many tiles); contents are not an output */
+    uint32_t *emit_tmp;     /* [emit_tmp_words] 16-byte aligned: scratch of the preprocess
+                               stage (partial frame counts) and the emit stage (queue of
+                               Gaussians with many tiles); contents are not an output */
     void *table;            /* [table_bytes] 16-byte aligned: the frame's item table
                                (camera, scene pointers, offsets), written by
                                ss_preprocess / ss_forward_begin / ss_batch_begin and

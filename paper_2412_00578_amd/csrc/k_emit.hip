@@ -139,51 +139,6 @@ __global__ __launch_bounds__(kEmitBlock) void k_emit(const Item* __restrict__ it
     }
 }
 
-// Span of one row (or column) of the record's tile rectangle; the same
-// arithmetic as one step of for_each_span (the band ends are clipped to the
-// SnugBox box, so an interior band boundary is the shared tile edge).
-__device__ __forceinline__ void one_span(const Ellipse& e, int mode, int tx_n, int ty_n, bool cols,
-                                         int major, int& lo, int& hi) {
-    if (mode != SS_TILE_ACCUTILE) {
-        lo = e.x0;
-        hi = e.x1;
-        return;
-    }
-    if (!cols) {
-        const double k = (e.b / e.c) * e.hx;
-        const double y_left = e.v + k, y_right = e.v - k;
-        const double box_b = e.v - e.hy, box_t = e.v + e.hy;
-        double ylo = 16.0 * major, yhi = 16.0 * major + 16.0;
-        ylo = ylo < box_b ? box_b : ylo;
-        yhi = yhi > box_t ? box_t : yhi;
-        double l0, r0, l1, r1;
-        row_roots(e, ylo, l0, r0);
-        row_roots(e, yhi, l1, r1);
-        const double left = (ylo <= y_left && y_left <= yhi) ? e.u - e.hx : (l0 < l1 ? l0 : l1);
-        const double right = (ylo <= y_right && y_right <= yhi) ? e.u + e.hx : (r0 > r1 ? r0 : r1);
-        lo = tile_lo(left, tx_n);
-        hi = tile_hi(right, tx_n);
-        lo = lo < e.x0 ? e.x0 : lo;
-        hi = hi > e.x1 ? e.x1 : hi;
-    } else {
-        const double m = (e.b / e.a) * e.hy;
-        const double x_top = e.u + m, x_bot = e.u - m;
-        const double box_l = e.u - e.hx, box_r = e.u + e.hx;
-        double xlo = 16.0 * major, xhi = 16.0 * major + 16.0;
-        xlo = xlo < box_l ? box_l : xlo;
-        xhi = xhi > box_r ? box_r : xhi;
-        double t0, b0, t1, b1;
-        col_roots(e, xlo, t0, b0);
-        col_roots(e, xhi, t1, b1);
-        const double top = (xlo <= x_top && x_top <= xhi) ? e.v - e.hy : (t0 < t1 ? t0 : t1);
-        const double bot = (xlo <= x_bot && x_bot <= xhi) ? e.v + e.hy : (b0 > b1 ? b0 : b1);
-        lo = tile_lo(top, ty_n);
-        hi = tile_hi(bot, ty_n);
-        lo = lo < e.y0 ? e.y0 : lo;
-        hi = hi > e.y1 ? e.y1 : hi;
-    }
-}
-
 // One workgroup: exclusive offsets of the nb segment counts, total last.
 __global__ __launch_bounds__(1024) void k_emit_offsets(uint32_t* __restrict__ queue,
                                                        int64_t nb) {
@@ -277,7 +232,14 @@ __global__ __launch_bounds__(kBigBlock) void k_emit_big(const Item* __restrict__
             uint32_t done = 0;
             for (int c0 = 0; c0 < nmaj; c0 += 64) {
                 int lo = 0, hi = -1;
-                if (c0 + lane < nmaj) one_span(el, mode, txn, tyn, cols, maj0 + c0 + lane, lo, hi);
+                if (c0 + lane < nmaj) {
+                    if (mode == SS_TILE_ACCUTILE) {
+                        accutile_band(el, cols, c0 + lane, txn, tyn, lo, hi);
+                    } else {
+                        lo = el.x0;
+                        hi = el.x1;
+                    }
+                }
                 const uint32_t len = hi >= lo ? (uint32_t)(hi - lo + 1) : 0u;
                 const uint32_t incl = wave_incl_scan_u32(len);
                 const uint32_t total = __shfl(incl, 63, 64);

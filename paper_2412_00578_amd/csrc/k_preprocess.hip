@@ -101,6 +101,7 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(const Item* __restrict__ 
                                                        uint4* __restrict__ tsets,
                                                        uint32_t* __restrict__ partials) {
     __shared__ uint32_t s_cnt[kBlock];
+    __shared__ uint32_t s_mask[2 * kBlock];
     const int64_t slot0 = (int64_t)blockIdx.x * kBlock;
     const Item& it = items[dims.n_items == 1 ? 0 : item_of_slot(items, dims.n_items, slot0)];
     const ss_camera cam = it.cam;
@@ -122,8 +123,8 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(const Item* __restrict__ 
     }
 
     // The record, its count and its tile set; 0 for a padding slot or a culled
-    // Gaussian (whose record is zeroed), and for a record whose count is left
-    // to the wave (defer).
+    // Gaussian (whose record is zeroed), and for an AccuTile record, whose
+    // count and tile set the wave computes afterwards (defer).
     float4 g4 = make_float4(0.f, 0.f, 0.f, 0.f), q4 = g4;
     bool defer = false;
     auto record = [&]() -> uint32_t {
@@ -231,23 +232,28 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(const Item* __restrict__ 
         q4 = make_float4(ca, cb, cc, op);
         geom[o] = g4;
         conic[o] = q4;
+        if (mode == SS_TILE_ACCUTILE) {   // tile set computed by the wave below
+            defer = true;
+            return 0u;
+        }
         uint64_t mask;
         uint32_t origin;
-        const uint32_t cnt = tile_set(g4, q4, mode, tx_n, ty_n, &mask, &origin, &defer);
+        const uint32_t cnt = rect_tile_set(g4, q4, mode, tx_n, ty_n, &mask, &origin);
         tsets[o] = make_uint4((uint32_t)mask, (uint32_t)(mask >> 32), origin, 0u);
-        if (defer) return 0u;
         counts[o] = cnt;
         dkeys[o] = cnt ? __float_as_uint(g4.z) : kCulledKey;
         return cnt;
     };
     uint32_t cnt = o < dims.n_slots ? record() : 0u;
 
-    // Long AccuTile walks are shared out over the wave rather than left to
-    // one lane while the others wait.
-    if (__ballot(defer)) {
-        const uint32_t c = accutile_count_wave(defer, g4, q4, tx_n, ty_n, s_cnt);
+    if (mode == SS_TILE_ACCUTILE && __ballot(defer)) {   // wave-uniform
+        uint64_t mask;
+        uint32_t origin;
+        const uint32_t c = accutile_tile_set(defer, g4, q4, tx_n, ty_n, s_cnt, s_mask, &mask,
+                                             &origin);
         if (defer) {
             cnt = c;
+            tsets[o] = make_uint4((uint32_t)mask, (uint32_t)(mask >> 32), origin, 0u);
             counts[o] = cnt;
             dkeys[o] = cnt ? __float_as_uint(g4.z) : kCulledKey;
         }
@@ -342,9 +348,23 @@ __global__ __launch_bounds__(1024) void k_totals(const uint32_t* __restrict__ pa
                                                  uint64_t* __restrict__ totals) {
     __shared__ uint64_t s_p[16], s_v[16];
     uint64_t p = 0, v = 0;
-    for (int64_t b = threadIdx.x; b < nb; b += 1024) {
-        p += partials[2 * b];
-        v += partials[2 * b + 1];
+    // (P, visible) pairs as 8-byte loads, eight in flight per thread
+    const uint2* __restrict__ pv = reinterpret_cast<const uint2*>(partials);
+    int64_t b = threadIdx.x;
+    for (; b + 7 * 1024 < nb; b += 8 * 1024) {
+        uint2 x[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) x[u] = pv[b + u * 1024];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            p += x[u].x;
+            v += x[u].y;
+        }
+    }
+    for (; b < nb; b += 1024) {
+        const uint2 x = pv[b];
+        p += x.x;
+        v += x.y;
     }
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) {

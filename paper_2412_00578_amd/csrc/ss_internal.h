@@ -97,76 +97,15 @@ __device__ __forceinline__ void col_roots(const Ellipse& e, double X, double& yt
     yb = e.v + (-bd + s) / e.c;
 }
 
-// Walks the tile spans of a record in enumeration order and calls
-// span(major, lo, hi) for every non-empty span: for 3-sigma / SnugBox and for
-// AccuTile-by-rows, major = ty and [lo, hi] is a tx interval; for
-// AccuTile-by-columns (more rows than columns), major = tx and [lo, hi] is a
-// ty interval.  Returns true when the spans are column spans.
-//
-// AccuTile (Alg. 1): a band's extent along the other axis is the SnugBox
-// extremal point when it lies inside the band, else the extreme of the two
-// band-boundary intersections; consecutive bands share their boundary, so one
-// new intersection is computed per band.
-template <class Span>
-__device__ __forceinline__ bool for_each_span(const Ellipse& e, int mode, int tx_n, int ty_n,
-                                              Span&& span) {
-    if (mode != SS_TILE_ACCUTILE) {
-        for (int ty = e.y0; ty <= e.y1; ++ty) span(ty, e.x0, e.x1);
-        return false;
-    }
-    const int nrows = e.y1 - e.y0 + 1, ncols = e.x1 - e.x0 + 1;
-    if (nrows <= ncols) {
-        const double k = (e.b / e.c) * e.hx;
-        const double y_left = e.v + k, y_right = e.v - k;
-        const double box_b = e.v - e.hy, box_t = e.v + e.hy;
-        const double x_min = e.u - e.hx, x_max = e.u + e.hx;
-        double ylo = 16.0 * e.y0;
-        ylo = ylo < box_b ? box_b : ylo;
-        double l0, r0;
-        row_roots(e, ylo, l0, r0);
-        for (int ty = e.y0; ty <= e.y1; ++ty) {
-            double yhi = 16.0 * ty + 16.0;
-            yhi = yhi > box_t ? box_t : yhi;
-            double l1, r1;
-            row_roots(e, yhi, l1, r1);
-            double left = (ylo <= y_left && y_left <= yhi) ? x_min : (l0 < l1 ? l0 : l1);
-            double right = (ylo <= y_right && y_right <= yhi) ? x_max : (r0 > r1 ? r0 : r1);
-            int lo = tile_lo(left, tx_n), hi = tile_hi(right, tx_n);
-            lo = lo < e.x0 ? e.x0 : lo;
-            hi = hi > e.x1 ? e.x1 : hi;
-            if (lo <= hi) span(ty, lo, hi);
-            ylo = yhi; l0 = l1; r0 = r1;
-        }
-        return false;
-    }
-    const double m = (e.b / e.a) * e.hy;
-    const double x_top = e.u + m, x_bot = e.u - m;
-    const double box_l = e.u - e.hx, box_r = e.u + e.hx;
-    const double y_min = e.v - e.hy, y_max = e.v + e.hy;
-    double xlo = 16.0 * e.x0;
-    xlo = xlo < box_l ? box_l : xlo;
-    double t0, b0;
-    col_roots(e, xlo, t0, b0);
-    for (int tx = e.x0; tx <= e.x1; ++tx) {
-        double xhi = 16.0 * tx + 16.0;
-        xhi = xhi > box_r ? box_r : xhi;
-        double t1, b1;
-        col_roots(e, xhi, t1, b1);
-        double top = (xlo <= x_top && x_top <= xhi) ? y_min : (t0 < t1 ? t0 : t1);
-        double bot = (xlo <= x_bot && x_bot <= xhi) ? y_max : (b0 > b1 ? b0 : b1);
-        int lo = tile_lo(top, ty_n), hi = tile_hi(bot, ty_n);
-        lo = lo < e.y0 ? e.y0 : lo;
-        hi = hi > e.y1 ? e.y1 : hi;
-        if (lo <= hi) span(tx, lo, hi);
-        xlo = xhi; t0 = t1; b0 = b1;
-    }
-    return true;
-}
-
-// Band k (0-based) of an AccuTile walk on its own: the span for_each_span
-// reports for major index x0 + k / y0 + k, from the same FP64 operations (a
-// band's lower boundary is the previous band's upper one, min(16 (y0 + k),
-// box top), recomputed here).  False when the band's span is empty.
+// AccuTile (Alg. 1) walks a record's tile rectangle in bands, rows of tiles
+// (or columns, when the rectangle has more rows than columns).  A band's
+// extent along the other axis is the SnugBox extremal point when that lies
+// inside the band, else the extreme of the ellipse's intersections with the
+// two band boundaries.  accutile_band evaluates band k (0-based, major index
+// y0 + k or x0 + k) on its own; its lower boundary is the upper boundary of
+// band k - 1, min(16 (y0 + k), box top), computed with the same FP64
+// operations, so evaluating the bands independently or in order gives the
+// same spans.  False when the band's span is empty.
 __device__ __forceinline__ bool accutile_band(const Ellipse& e, bool cols, int k, int tx_n,
                                               int ty_n, int& lo, int& hi) {
     if (!cols) {
@@ -233,74 +172,47 @@ __device__ __forceinline__ bool span_columns(const Ellipse& e, int mode) {
 // window, bit r * kSetSide + c for tile (x0 + c, y0 + r).
 constexpr int kSetSide = 8;
 
-// An AccuTile record whose walk has more bands than this and whose rectangle
-// does not fit the window is counted by its whole wave (accutile_count_wave).
-constexpr int kSerialBands = 4;
-
-// Counts the record's tiles under `mode` and, when its tile rectangle fits the
-// window, records them: *mask gets the bits, *origin = x0 | y0 << 16.
-// Otherwise *mask = 0 (the emit stage re-walks the spans).  With `defer`
-// given, a long AccuTile walk is not done: *defer is set, 0 returned, and the
-// caller counts the record with accutile_count_wave.
-__device__ __forceinline__ uint32_t tile_set(float4 g, float4 q, int mode, int tx_n, int ty_n,
-                                             uint64_t* mask, uint32_t* origin,
-                                             bool* defer = nullptr) {
+// 3-sigma / SnugBox tile set: the whole rectangle.  Returns the tile count
+// and, when the rectangle fits the window, sets *mask (its row run repeated
+// once per row) and *origin = x0 | y0 << 16; otherwise *mask = 0 (the emit
+// stage re-walks the rows).
+__device__ __forceinline__ uint32_t rect_tile_set(float4 g, float4 q, int mode, int tx_n,
+                                                  int ty_n, uint64_t* mask, uint32_t* origin) {
     *mask = 0ull;
     *origin = 0u;
     Ellipse e;
     if (!ellipse_setup(g, q, mode, tx_n, ty_n, e)) return 0u;
-    const bool fits = e.x1 - e.x0 < kSetSide && e.y1 - e.y0 < kSetSide;
-    if (mode != SS_TILE_ACCUTILE) {
-        // the whole rectangle: its row run repeated once per row
-        const uint32_t w = (uint32_t)(e.x1 - e.x0 + 1), h = (uint32_t)(e.y1 - e.y0 + 1);
-        if (fits) {
-            *mask = ((1ull << w) - 1ull) * (0x0101010101010101ull >> (8u * (kSetSide - h)));
-            *origin = (uint32_t)e.x0 | ((uint32_t)e.y0 << 16);
-        }
-        return w * h;
-    }
-    const bool cols = span_columns(e, mode);
-    if (defer && !fits) {
-        const int bands = cols ? e.x1 - e.x0 + 1 : e.y1 - e.y0 + 1;
-        if (bands > kSerialBands) {
-            *defer = true;
-            return 0u;
-        }
-    }
-    uint32_t n = 0;
-    uint64_t m = 0ull;
-    for_each_span(e, mode, tx_n, ty_n, [&](int major, int lo, int hi) {
-        n += (uint32_t)(hi - lo + 1);
-        if (!fits) return;
-        if (!cols) {
-            const uint64_t run = (1ull << (hi - lo + 1)) - 1ull;
-            m |= run << ((major - e.y0) * kSetSide + (lo - e.x0));
-        } else {
-            for (int r = lo; r <= hi; ++r) m |= 1ull << ((r - e.y0) * kSetSide + (major - e.x0));
-        }
-    });
-    if (fits) {
-        *mask = m;
+    const uint32_t w = (uint32_t)(e.x1 - e.x0 + 1), h = (uint32_t)(e.y1 - e.y0 + 1);
+    if (w <= (uint32_t)kSetSide && h <= (uint32_t)kSetSide) {
+        *mask = ((1ull << w) - 1ull) * (0x0101010101010101ull >> (8u * (kSetSide - h)));
         *origin = (uint32_t)e.x0 | ((uint32_t)e.y0 << 16);
     }
-    return n;
+    return w * h;
 }
 
-// AccuTile tile counts of the wave's lanes with `defer` set (records g, q),
-// counted by the whole wave: the bands of all those records are dealt out to
-// the 64 lanes, each band evaluated on its own by accutile_band, and the band
-// counts summed per record in s_cnt (64 words of LDS).  Returns the lane's own
-// count (0 for a lane without `defer`).  All 64 lanes must call it.
-__device__ __forceinline__ uint32_t accutile_count_wave(bool defer, float4 g, float4 q, int tx_n,
-                                                        int ty_n, uint32_t* s_cnt) {
+// AccuTile tile sets of the wave's lanes with `want` set (records g, q),
+// computed by the whole wave: the bands of all those records are dealt out to
+// the 64 lanes, each band evaluated on its own (accutile_band), and the band
+// counts and, for a record whose rectangle fits the window, the band's mask
+// bits are gathered per record in LDS (s_cnt: 64 words, s_mask: 128 words).
+// A lane walking its own record's bands would leave the wave waiting on its
+// longest walk.  Returns the lane's count and sets *mask / *origin as
+// rect_tile_set does (all zero for a lane without `want`).  All 64 lanes of
+// the wave must call it.
+__device__ __forceinline__ uint32_t accutile_tile_set(bool want, float4 g, float4 q, int tx_n,
+                                                      int ty_n, uint32_t* s_cnt, uint32_t* s_mask,
+                                                      uint64_t* mask, uint32_t* origin) {
     const int lane = (int)__lane_id();
     Ellipse e;
-    bool cols = false;
+    bool cols = false, fits = false;
     int nb = 0;
-    if (defer) {
-        ellipse_setup(g, q, SS_TILE_ACCUTILE, tx_n, ty_n, e);
+    *mask = 0ull;
+    *origin = 0u;
+    if (want && ellipse_setup(g, q, SS_TILE_ACCUTILE, tx_n, ty_n, e)) {
         cols = span_columns(e, SS_TILE_ACCUTILE);
         nb = cols ? e.x1 - e.x0 + 1 : e.y1 - e.y0 + 1;
+        fits = e.x1 - e.x0 < kSetSide && e.y1 - e.y0 < kSetSide;
+        if (fits) *origin = (uint32_t)e.x0 | ((uint32_t)e.y0 << 16);
     } else {
         e.u = e.v = e.a = e.b = e.c = e.t = e.det = e.hx = e.hy = 0.0;
         e.x0 = e.x1 = e.y0 = e.y1 = 0;
@@ -314,6 +226,8 @@ __device__ __forceinline__ uint32_t accutile_count_wave(bool defer, float4 g, fl
     }
     const int total = __shfl(incl, 63, 64);
     s_cnt[lane] = 0u;
+    s_mask[2 * lane] = 0u;
+    s_mask[2 * lane + 1] = 0u;
     __syncthreads();
     for (int j0 = 0; j0 < total; j0 += 64) {
         const int j = j0 + lane;
@@ -333,13 +247,26 @@ __device__ __forceinline__ uint32_t accutile_count_wave(bool defer, float4 g, fl
         el.hx = __shfl(e.hx, L, 64); el.hy = __shfl(e.hy, L, 64);
         el.x0 = __shfl(e.x0, L, 64); el.x1 = __shfl(e.x1, L, 64);
         el.y0 = __shfl(e.y0, L, 64); el.y1 = __shfl(e.y1, L, 64);
-        const bool cl = __shfl((int)cols, L, 64) != 0;
+        const int fl = __shfl((int)cols | ((int)fits << 1), L, 64);
+        const bool cl = (fl & 1) != 0, ft = (fl & 2) != 0;
         int lo, hi;
-        if (j < total && accutile_band(el, cl, k, tx_n, ty_n, lo, hi))
-            atomicAdd(&s_cnt[L], (uint32_t)(hi - lo + 1));
+        if (j < total && accutile_band(el, cl, k, tx_n, ty_n, lo, hi)) {
+            const uint32_t len = (uint32_t)(hi - lo + 1);
+            atomicAdd(&s_cnt[L], len);
+            if (ft) {
+                // row band: a run of len bits; column band: len bits 8 apart
+                const uint64_t bits =
+                    cl ? (0x0101010101010101ull >> (8u * (kSetSide - len)))
+                             << ((lo - el.y0) * kSetSide + k)
+                       : ((1ull << len) - 1ull) << (k * kSetSide + (lo - el.x0));
+                if ((uint32_t)bits) atomicOr(&s_mask[2 * L], (uint32_t)bits);
+                if ((uint32_t)(bits >> 32)) atomicOr(&s_mask[2 * L + 1], (uint32_t)(bits >> 32));
+            }
+        }
     }
     __syncthreads();
-    return defer ? s_cnt[lane] : 0u;
+    if (fits) *mask = (uint64_t)s_mask[2 * lane] | ((uint64_t)s_mask[2 * lane + 1] << 32);
+    return nb ? s_cnt[lane] : 0u;
 }
 
 // Workgroups are dispatched round-robin over the 8 XCDs of MI355X.  This maps
