@@ -100,7 +100,18 @@ __global__ __launch_bounds__(kOrderThreads) void k_tile_order(const Item* __rest
 #pragma unroll
     for (int u = 0; u < kOrderPer; ++u) h[t0 * kOrderPer + u] = 0u;
     __syncthreads();
-    for (int t = t0; t < n; t += kOrderThreads)
+    // the keys of the first kOrderPer * 1024 tiles stay in registers for the
+    // second pass (their loads are issued together)
+    uint32_t kc[kOrderPer];
+#pragma unroll
+    for (int u = 0; u < kOrderPer; ++u) {
+        const int t = t0 + u * kOrderThreads;
+        kc[u] = t < n ? order_key(items, dims.n_items, ranges, t) : 0u;
+    }
+#pragma unroll
+    for (int u = 0; u < kOrderPer; ++u)
+        if (t0 + u * kOrderThreads < n) atomicAdd(&h[kc[u]], 1u);
+    for (int t = t0 + kOrderPer * kOrderThreads; t < n; t += kOrderThreads)
         atomicAdd(&h[order_key(items, dims.n_items, ranges, t)], 1u);
     __syncthreads();
     // exclusive scan of the key counts; thread t0 owns keys kOrderPer t0 ..
@@ -148,7 +159,8 @@ __global__ __launch_bounds__(kOrderThreads) void k_tile_order(const Item* __rest
     }
     __syncthreads();
     for (int t = t0; t < n; t += kOrderThreads) {
-        const uint32_t key = order_key(items, dims.n_items, ranges, t);
+        const int u = (t - t0) / kOrderThreads;
+        const uint32_t key = u < kOrderPer ? kc[u] : order_key(items, dims.n_items, ranges, t);
         const uint32_t x = key / kOrderBuckets;
         const uint32_t r = atomicAdd(&h[key], 1u) - s_start[x];
         if (r < s_cap[x]) {

@@ -46,6 +46,22 @@ __device__ __forceinline__ uint32_t wave_incl_scan_u32(uint32_t x) {
     return x;
 }
 
+// For two positions x0 <= x1 in a non-decreasing run of 64 LDS values s
+// (s[0] <= x0): the last index whose value is <= x0, and the same for x1.
+// Six steps of binary lifting each; the two searches are interleaved so that
+// their LDS reads overlap.
+__device__ __forceinline__ void last_le64x2(const uint32_t* s, uint32_t x0, uint32_t x1, int& a0,
+                                            int& a1) {
+    a0 = 0;
+    a1 = 0;
+#pragma unroll
+    for (int step = 32; step >= 1; step >>= 1) {
+        const uint32_t v0 = s[a0 + step], v1 = s[a1 + step];
+        a0 += v0 <= x0 ? step : 0;
+        a1 += v1 <= x1 ? step : 0;
+    }
+}
+
 // Orders the wave's LDS writes before its LDS reads by other lanes.
 __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -124,17 +140,22 @@ __global__ __launch_bounds__(kEmitBlock) void k_emit(const Item* __restrict__ it
         }
     }
     wave_lds_sync();
-    for (uint32_t idx = (uint32_t)lane; idx < total; idx += 64) {
-        // the last lane whose staged run starts at or before idx
-        int a = 0, z = 63;
-        while (a < z) {
-            const int mid = (a + z + 1) >> 1;
-            if (s_pre[w][mid] <= idx) a = mid; else z = mid - 1;
-        }
+    for (uint32_t idx = (uint32_t)lane; idx < total; idx += 128) {
+        // the last lanes whose staged runs start at or before idx, idx + 64
+        const uint32_t idx2 = idx + 64;
+        int a, a2;
+        last_le64x2(s_pre[w], idx, idx2, a, a2);
         const uint32_t pos = s_pos[w][a] + (idx - s_pre[w][a]);
         if (pos < limit) {
             keys[pos] = s_tile[w][idx];
             values[pos] = s_gid[w][a];
+        }
+        if (idx2 < total) {
+            const uint32_t pos2 = s_pos[w][a2] + (idx2 - s_pre[w][a2]);
+            if (pos2 < limit) {
+                keys[pos2] = s_tile[w][idx2];
+                values[pos2] = s_gid[w][a2];
+            }
         }
     }
 }
@@ -246,21 +267,23 @@ __global__ __launch_bounds__(kBigBlock) void k_emit_big(const Item* __restrict__
                 s_excl[w][lane] = incl - len;
                 s_lo[w][lane] = lo;
                 wave_lds_sync();
-                for (uint32_t idx = lane; idx < total; idx += 64) {
-                    // the last span whose exclusive start is <= idx
-                    int a = 0, z = 63;
-                    while (a < z) {
-                        const int mid = (a + z + 1) >> 1;
-                        if (s_excl[w][mid] <= idx) a = mid; else z = mid - 1;
-                    }
-                    const int major = maj0 + c0 + a;
-                    const int minor = s_lo[w][a] + (int)(idx - s_excl[w][a]);
-                    const uint32_t tile = toff + (cols ? (uint32_t)(minor * txn + major)
-                                                       : (uint32_t)(major * txn + minor));
-                    const uint32_t pos = p0 + done + idx;
-                    if (pos < pend && pos < limit) {
-                        keys[pos] = tile;
-                        values[pos] = gi;
+                for (uint32_t idx = lane; idx < total; idx += 128) {
+                    // the last spans whose exclusive starts are <= idx, idx + 64
+                    int ab[2];
+                    last_le64x2(s_excl[w], idx, idx + 64, ab[0], ab[1]);
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        const uint32_t ix = idx + 64u * h;
+                        const int a = ab[h];
+                        const int major = maj0 + c0 + a;
+                        const int minor = s_lo[w][a] + (int)(ix - s_excl[w][a]);
+                        const uint32_t tile = toff + (cols ? (uint32_t)(minor * txn + major)
+                                                           : (uint32_t)(major * txn + minor));
+                        const uint32_t pos = p0 + done + ix;
+                        if (ix < total && pos < pend && pos < limit) {
+                            keys[pos] = tile;
+                            values[pos] = gi;
+                        }
                     }
                 }
                 done += total;

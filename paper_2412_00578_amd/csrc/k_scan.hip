@@ -5,13 +5,13 @@
 // [offsets[j] - order_counts[j], offsets[j]) and the emitted pairs come out
 // sorted by depth.
 //
-// Reduce-then-scan in three launches, so no workgroup ever waits on another:
+// Reduce-then-scan in two launches, so no workgroup ever waits on another:
 //   1. each workgroup sums its 4096 counts into a 64-bit partial;
-//   2. one workgroup turns the partials into exclusive 64-bit block offsets
-//      and writes the grand total P to scan_tmp[0];
-//   3. each workgroup rescans its counts (wave prefix sums with DPP-backed
-//      shuffles, wave totals through LDS) and writes uint32 offsets.
-// scan_tmp layout: [0] = P, [1 + b] = exclusive offset of block b.
+//   2. each workgroup sums the partials of the workgroups before it (a few
+//      hundred 8-byte reads from L2), rescans its counts (wave prefix sums,
+//      wave totals through LDS) and writes uint32 offsets; the last one writes
+//      the grand total P to scan_tmp[0].
+// scan_tmp layout: [0] = P, [1 + b] = the partial of block b.
 #include "ss_internal.h"
 
 namespace ss {
@@ -51,32 +51,16 @@ __global__ __launch_bounds__(kBlock) void k_block_sums(const uint32_t* __restric
     }
 }
 
-// One workgroup of 1024 lanes: exclusive scan of nb partials in place.
-__global__ __launch_bounds__(1024) void k_scan_partials(uint64_t* __restrict__ tmp, int64_t nb) {
-    __shared__ uint64_t wsum[16];
-    __shared__ uint64_t carry;
-    if (threadIdx.x == 0) carry = 0;
-    __syncthreads();
-    for (int64_t base = 0; base < nb; base += 1024) {
-        const int64_t i = base + threadIdx.x;
-        const uint64_t x = i < nb ? tmp[1 + i] : 0;
-        uint64_t inc = wave_incl_scan(x);
-        const int w = threadIdx.x >> 6;
-        if (__lane_id() == 63) wsum[w] = inc;
-        __syncthreads();
-        uint64_t before = carry;
-        for (int k = 0; k < w; ++k) before += wsum[k];
-        if (i < nb) tmp[1 + i] = before + inc - x;
-        __syncthreads();
-        if (threadIdx.x == 1023) carry = before + inc;
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) tmp[0] = carry;
-}
-
 __global__ __launch_bounds__(kBlock) void k_block_scan(const uint32_t* __restrict__ counts,
-                                                       int64_t n, const uint64_t* __restrict__ tmp,
+                                                       int64_t n, uint64_t* __restrict__ tmp,
                                                        uint32_t* __restrict__ offsets) {
+    // this block's offset: the partials of the blocks before it
+    __shared__ uint64_t osum[kBlock / 64];
+    uint64_t o = 0;
+    for (int64_t k = threadIdx.x; k < (int64_t)blockIdx.x; k += kBlock) o += tmp[1 + k];
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) o += __shfl_xor(o, d, 64);
+    if (__lane_id() == 0) osum[threadIdx.x >> 6] = o;
     // Lane l of the workgroup owns entries [base + l*16, base + l*16 + 16).
     const int64_t base = (int64_t)blockIdx.x * kPerBlock;
     const int64_t first = base + (int64_t)threadIdx.x * kItems;
@@ -91,13 +75,15 @@ __global__ __launch_bounds__(kBlock) void k_block_scan(const uint32_t* __restric
     const int w = threadIdx.x >> 6;
     if (__lane_id() == 63) wsum[w] = inc;
     __syncthreads();
-    uint64_t run = tmp[1 + blockIdx.x] + inc - s;
-    for (int k = 0; k < w; ++k) run += wsum[k];
+    uint64_t run = inc - s;
+#pragma unroll
+    for (int k = 0; k < kBlock / 64; ++k) run += osum[k] + (k < w ? wsum[k] : 0u);
 #pragma unroll
     for (int k = 0; k < kItems; ++k) {
         run += c[k];
         if (first + k < n) offsets[first + k] = (uint32_t)run;
     }
+    if (blockIdx.x + 1 == gridDim.x && threadIdx.x + 1 == kBlock) tmp[0] = run;
 }
 
 }  // namespace
@@ -110,11 +96,9 @@ hipError_t launch_scan(int64_t n, const ss_frame& f, hipStream_t s) {
         hipLaunchKernelGGL(k_block_sums, dim3((unsigned)nb), dim3(kBlock), 0, s,
                            f.order_counts, n, f.scan_tmp);
     }
-    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, s, f.scan_tmp, nb);
-    if (nb > 0) {
-        hipLaunchKernelGGL(k_block_scan, dim3((unsigned)nb), dim3(kBlock), 0, s,
-                           f.order_counts, n, f.scan_tmp, f.offsets);
-    }
+    // one workgroup when n == 0, to write P = 0
+    hipLaunchKernelGGL(k_block_scan, dim3((unsigned)(nb > 0 ? nb : 1)), dim3(kBlock), 0, s,
+                       f.order_counts, n, f.scan_tmp, f.offsets);
     return hipGetLastError();
 }
 

@@ -273,15 +273,32 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const K* __restrict__ keys_i
 
 // One lane per boundary position i in [0, n]: every tile whose run starts at i
 // gets start = i, every tile whose run ends at i gets end = i.
+// Thread t covers the pair boundaries i = 4t .. 4t + 3 (i <= n): where the
+// tile id changes between pair i - 1 and pair i (pair -1 counting as tile -1
+// and pair n as tile n_tiles), the tiles in between end and start at i.
+// Empty tiles get an empty range.
 __global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ keys, uint64_t n,
                                                 int n_tiles, uint32_t* __restrict__ ranges) {
-    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i > n) return;
-    const int prev = i == 0 ? -1 : (int)keys[i - 1];
-    const int cur = i == n ? n_tiles : (int)keys[i];
-    if (prev == cur) return;
-    for (int t = prev + 1; t <= cur && t < n_tiles; ++t) ranges[2 * t] = (uint32_t)i;
-    for (int t = prev < 0 ? 0 : prev; t < cur && t < n_tiles; ++t) ranges[2 * t + 1] = (uint32_t)i;
+    const uint64_t i0 = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4u;
+    if (i0 > n) return;
+    int k[5];
+    k[0] = i0 == 0 ? -1 : (int)keys[i0 - 1];
+    if (i0 + 4 <= n) {
+        const uint4 v = *reinterpret_cast<const uint4*>(keys + i0);
+        k[1] = (int)v.x; k[2] = (int)v.y; k[3] = (int)v.z; k[4] = (int)v.w;
+    } else {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) k[1 + u] = i0 + u < n ? (int)keys[i0 + u] : n_tiles;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const uint64_t i = i0 + u;
+        const int prev = k[u], cur = k[u + 1];
+        if (i > n || prev == cur) continue;
+        for (int t = prev + 1; t <= cur && t < n_tiles; ++t) ranges[2 * t] = (uint32_t)i;
+        for (int t = prev < 0 ? 0 : prev; t < cur && t < n_tiles; ++t)
+            ranges[2 * t + 1] = (uint32_t)i;
+    }
 }
 
 // Sorts (key, value) pairs on the low `bits` key bits, ping-ponging between
@@ -353,8 +370,8 @@ hipError_t launch_sort(const ss_pairs& p, int buf, uint64_t n, int bits, int* ou
 
 hipError_t launch_ranges(const uint32_t* keys, uint64_t n, int n_tiles, uint32_t* ranges,
                          hipStream_t s) {
-    const uint64_t items = n + 1;
-    const uint64_t grid = (items + 255) / 256;
+    const uint64_t threads = n / 4 + 1;           // boundaries 0 .. n, four per thread
+    const uint64_t grid = (threads + 255) / 256;
     hipLaunchKernelGGL(k_ranges, dim3((unsigned)grid), dim3(256), 0, s, keys, n, n_tiles, ranges);
     return hipGetLastError();
 }
