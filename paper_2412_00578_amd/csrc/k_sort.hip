@@ -64,9 +64,11 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid) {
     uint64_t m = __ballot(valid);
 #pragma unroll
     for (int bit = 0; bit < 8; ++bit) {
-        const bool set = (d >> bit) & 1u;
-        const uint64_t bb = __ballot(set);
-        m &= set ? bb : ~bb;
+        const uint32_t set = (d >> bit) & 1u;
+        const uint64_t bb = __ballot(set != 0u);
+        // lanes agreeing on this bit: bb where it is set, ~bb where it is not
+        const uint32_t flip = set - 1u;
+        m &= bb ^ (((uint64_t)flip << 32) | flip);
     }
     return m;
 }
@@ -170,7 +172,7 @@ __global__ __launch_bounds__(kBlock) void k_dscan(uint32_t* __restrict__ hist, u
 // drop: keys equal to kCulledKey are left out, as in k_hist.  A workgroup
 // walks its chunk in sub-tiles of kBlock * ITEMS keys.
 template <class K, int ITEMS>
-__global__ __launch_bounds__(kBlock) void k_scatter(const K* __restrict__ keys_in,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_scatter(const K* __restrict__ keys_in,
                                                     const uint32_t* __restrict__ vals_in,
                                                     K* __restrict__ keys_out,
                                                     uint32_t* __restrict__ vals_out, uint64_t n,
