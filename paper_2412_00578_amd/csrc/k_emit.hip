@@ -16,8 +16,7 @@
 //               consecutive addresses.  Each workgroup lists its other entries
 //               in its own segment of the scratch (no atomics: thousands on one
 //               counter would serialise), and one workgroup turns the
-//               per-segment counts into offsets and packs the segments into
-//               one list;
+//               per-segment counts into offsets;
 //   k_emit_big  one wave per queued entry re-walks the FP64 tile spans of the
 //               record: lanes compute up to 64 spans (rows, or columns for
 //               AccuTile on tall extents) at once, a wave prefix sum places
@@ -34,8 +33,7 @@ constexpr int kBigGrid = 1024;
 
 // Scratch layout for n entries, nb = ceil(n / 256) workgroups: segments of
 // queued entries [0, 256 nb), their counts [256 nb, 257 nb), exclusive segment
-// offsets with the total last [257 nb, 258 nb + 1), and the queued entries
-// packed in segment order [258 nb + 1, 258 nb + 1 + n).
+// offsets with the total last [257 nb, 258 nb + 1).
 __host__ __device__ __forceinline__ int64_t queue_blocks(int64_t n) { return (n + 255) / 256; }
 
 __device__ __forceinline__ uint32_t wave_incl_scan_u32(uint32_t x) {
@@ -162,16 +160,13 @@ __global__ __launch_bounds__(kEmitBlock) void k_emit(const Item* __restrict__ it
     }
 }
 
-// One workgroup: exclusive offsets of the nb segment counts, total last,
-// and the segments' entries packed one after another (each thread copies the
-// segments it scanned; the copies' loads are independent, so they overlap).
+// One workgroup: exclusive offsets of the nb segment counts, total last.
 __global__ __launch_bounds__(1024) void k_emit_offsets(uint32_t* __restrict__ queue,
                                                        int64_t nb) {
     __shared__ uint32_t s_w[16];
     __shared__ uint32_t s_carry;
     const uint32_t* cnt = queue + nb * kEmitBlock;
     uint32_t* off = queue + nb * kEmitBlock + nb;
-    uint32_t* packed = queue + nb * kEmitBlock + 2 * nb + 1;
     if (threadIdx.x == 0) s_carry = 0u;
     __syncthreads();
     for (int64_t base = 0; base < nb; base += 1024) {
@@ -183,11 +178,7 @@ __global__ __launch_bounds__(1024) void k_emit_offsets(uint32_t* __restrict__ qu
         __syncthreads();
         uint32_t before = s_carry;
         for (int k = 0; k < w; ++k) before += s_w[k];
-        if (b < nb) {
-            const uint32_t o = before + inc - x;
-            off[b] = o;
-            for (uint32_t e = 0; e < x; ++e) packed[o + e] = queue[b * kEmitBlock + e];
-        }
+        if (b < nb) off[b] = before + inc - x;
         __syncthreads();
         if (threadIdx.x == 1023) s_carry = before + inc;
         __syncthreads();
@@ -209,14 +200,14 @@ __global__ __launch_bounds__(kBigBlock) void k_emit_big(const Item* __restrict__
     __shared__ int s_lo[kBigBlock / 64][64];
     const int w = threadIdx.x >> 6;
     const int lane = (int)__lane_id();
-    const uint32_t nq = queue[nb * kEmitBlock + 2 * nb];
-    const uint32_t* packed = queue + nb * kEmitBlock + 2 * nb + 1;
+    const uint32_t* seg_off = queue + nb * kEmitBlock + nb;
+    const uint32_t nq = seg_off[nb];
     const uint32_t wave0 = blockIdx.x * (kBigBlock / 64) + w;
     const uint32_t waves = gridDim.x * (kBigBlock / 64);
     // Each round, lane l of the wave looks up queued entry wave0 + (64 r + l)
-    // waves, so that the chains of dependent loads (entry, Gaussian, record)
-    // of 64 entries overlap; the wave then walks the 64 entries' spans one
-    // entry at a time.
+    // waves, so that the chains of dependent loads (segment search, entry,
+    // Gaussian, record) of 64 entries overlap; the wave then walks the 64
+    // entries' spans one entry at a time.
     for (uint32_t r0 = 0; wave0 + (uint64_t)r0 * waves < nq; r0 += 64) {
         const uint64_t bq = wave0 + (uint64_t)(r0 + lane) * waves;
         const bool have = bq < nq;
@@ -226,7 +217,13 @@ __global__ __launch_bounds__(kBigBlock) void k_emit_big(const Item* __restrict__
         uint32_t i = 0, pos0 = 0, end = 0, tile_off = 0;
         int tx_n = 0, ty_n = 0;
         if (have) {
-            const uint32_t j = packed[b];                                   // depth-order entry
+            // the segment holding queued entry b: the last with offset <= b
+            int64_t lo = 0, hi = nb - 1;
+            while (lo < hi) {
+                const int64_t mid = (lo + hi + 1) >> 1;
+                if (seg_off[mid] <= b) lo = mid; else hi = mid - 1;
+            }
+            const uint32_t j = queue[lo * kEmitBlock + (b - seg_off[lo])];   // depth-order entry
             i = order[j];
             const Item& it = items[dims.n_items == 1 ? 0 : item_of_slot(items, dims.n_items, i)];
             tx_n = it.tx_n;
@@ -300,7 +297,7 @@ __global__ __launch_bounds__(kBigBlock) void k_emit_big(const Item* __restrict__
 
 int64_t emit_tmp_words(int64_t n) {
     const int64_t nb = queue_blocks(n);
-    const int64_t q = 2 * nb * kEmitBlock + 2 * nb + 1;
+    const int64_t q = nb * kEmitBlock + 2 * nb + 1;
     const int64_t pre = 2 * ((n + 63) / 64);     // the preprocess stage's partial counts
     return q > pre ? q : pre;
 }

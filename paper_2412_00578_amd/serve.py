@@ -219,11 +219,10 @@ class GpuBackend:
         n = self.scenes[r.scene].n
         px = int(r.cam.width) * int(r.cam.height)
         est = self.pairs_per.get(self._key(r), 4 * n)
-        # records 48, counts 4, tile sets 16, depth keys 8, order 8, counts in
-        # depth order 4, offsets 4, emit queue 8: 100 B per slot (104 with the
-        # sort and scan scratch); image and per-pixel state 20 B per pixel; 16 B
-        # per pair (two buffers) with the 1.25 growth; sort scratch
-        return int(104 * n + 32 * px + 16 * 1.25 * est + (3 << 20))
+        # records, counts, tile sets, depth keys, order, offsets and queue: 92 B
+        # per slot; image and per-pixel state 20 B per pixel; 16 B per pair (two
+        # buffers) with the 1.25 growth; sort scratch
+        return int(96 * n + 32 * px + 16 * 1.25 * est + (3 << 20))
 
     def sync_reference(self, clock):
         """Ties GPU event times to the scheduler clock."""
