@@ -172,7 +172,7 @@ __global__ __launch_bounds__(kBlock) void k_dscan(uint32_t* __restrict__ hist, u
 // drop: keys equal to kCulledKey are left out, as in k_hist.  A workgroup
 // walks its chunk in sub-tiles of kBlock * ITEMS keys.
 template <class K, int ITEMS>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_scatter(const K* __restrict__ keys_in,
+__global__ __launch_bounds__(kBlock) void k_scatter(const K* __restrict__ keys_in,
                                                     const uint32_t* __restrict__ vals_in,
                                                     K* __restrict__ keys_out,
                                                     uint32_t* __restrict__ vals_out, uint64_t n,
@@ -216,6 +216,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
             key[k] = valid ? keys_in[idx] : (K)0;
             val[k] = valid ? (vals_in ? vals_in[idx] : (uint32_t)idx) : 0u;
         }
+        // Rank = keys of the same digit in earlier items (the wave's running
+        // count, advanced by each group's lowest lane with an LDS add that
+        // returns the old count) + lanes below in the same group.  The adds
+        // are issued back to back (a wave's LDS operations complete in order)
+        // and their results read afterwards, so their latencies overlap.
+        uint32_t pre[kItems];
 #pragma unroll
         for (int k = 0; k < kItems; ++k) {
             const uint64_t idx = sub + (uint64_t)w * (64 * kItems) + (uint64_t)k * 64 + lane;
@@ -223,10 +229,14 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
             const uint32_t d = digit_of(key[k], shift);
             const uint64_t m = match_digit(d, valid);
             const uint32_t below = lanes_below(m);
-            const uint32_t pre = wcnt[w][d];
-            rank[k] = pre + below;
-            if (valid && below == 0u) wcnt[w][d] = pre + (uint32_t)__popcll(m);
+            pre[k] = 0u;
+            if (valid && below == 0u) pre[k] = atomicAdd(&wcnt[w][d], (uint32_t)__popcll(m));
+            // the group's lowest lane, and this lane's place in the group
+            rank[k] = (m ? (uint32_t)__builtin_ctzll(m) : 0u) << 8 | below;
         }
+#pragma unroll
+        for (int k = 0; k < kItems; ++k)
+            rank[k] = (uint32_t)__shfl((int)pre[k], (int)(rank[k] >> 8), 64) + (rank[k] & 255u);
         __syncthreads();
         {   // per digit: prefix over waves, sub-tile total, sub-tile digit start
             uint32_t s = 0;
@@ -256,15 +266,29 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
         __syncthreads();
         // keys kept in this sub-tile: the end of the last digit's run
         const uint32_t n_sub = lstart[kRadix - 1] + tot[kRadix - 1];
-        for (uint32_t i = t; i < n_sub; i += kBlock) {
-            const K kk = s_key[i];
-            const uint32_t d = digit_of(kk, shift);
-            const uint32_t pos = base[d] + (i - lstart[d]);
-            if (pos < n) {
-                if (keys_out) keys_out[pos] = kk;
-                const uint32_t v = s_val[i];
-                vals_out[pos] = v;
-                if (gather_out) gather_out[pos] = gather[v];
+        // four staged keys per lane and step: their LDS reads overlap
+        for (uint32_t i0 = t; i0 < n_sub; i0 += 4 * kBlock) {
+            K kk[4];
+            uint32_t v[4], pos[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const uint32_t i = i0 + u * kBlock;
+                const uint32_t ii = i < n_sub ? i : i0;
+                kk[u] = s_key[ii];
+                v[u] = s_val[ii];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const uint32_t d = digit_of(kk[u], shift);
+                pos[u] = base[d] + (i0 + u * kBlock - lstart[d]);
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (i0 + u * kBlock < n_sub && pos[u] < n) {
+                    if (keys_out) keys_out[pos[u]] = kk[u];
+                    vals_out[pos[u]] = v[u];
+                    if (gather_out) gather_out[pos[u]] = gather[v[u]];
+                }
             }
         }
         __syncthreads();
