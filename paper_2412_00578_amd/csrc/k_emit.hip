@@ -71,7 +71,10 @@ __device__ __forceinline__ void wave_lds_sync() {
 
 constexpr int kEmitBlock = 256;
 constexpr int kEmitWaves = kEmitBlock / 64;
-constexpr int kStage = 64 * (int)kSmall;     // tile ids one wave can stage
+// Tile ids one wave can stage.  A wave's masked entries average a few tiles
+// each; entries past the stage's end go to the queue instead, which keeps
+// the kernel's LDS (and so its occupancy) small.
+constexpr int kStage = 1024;
 
 __global__ __launch_bounds__(kEmitBlock) void k_emit(const Item* __restrict__ items,
                                                      BatchDims dims, uint32_t n_entries,
@@ -98,7 +101,11 @@ __global__ __launch_bounds__(kEmitBlock) void k_emit(const Item* __restrict__ it
     uint4 ts = make_uint4(0u, 0u, 0u, 0u);
     if (cnt) ts = tsets[gid];
     const uint64_t mask = (uint64_t)ts.x | ((uint64_t)ts.y << 32);
-    const bool big = cnt > kSmall || (cnt && mask == 0ull);
+    const bool masked = cnt && cnt <= kSmall && mask != 0ull;
+    // staged runs in lane order; the lanes whose run would pass the stage's
+    // end (a suffix of the masked lanes) join the queue
+    const bool fit = wave_incl_scan_u32(masked ? cnt : 0u) <= (uint32_t)kStage;
+    const bool big = cnt && !(masked && fit);
     {   // list the big entries in this workgroup's segment
         __shared__ uint32_t s_nbig[kEmitWaves];
         const uint64_t bigs = __ballot(big);
