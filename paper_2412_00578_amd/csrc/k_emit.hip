@@ -11,9 +11,10 @@
 // near the camera thousands), so the work is split in two launches:
 //   k_emit      one lane per entry whose tile set the preprocess stage stored
 //               as a mask (tile rectangle within 8 x 8) with <= 32 tiles: each
-//               lane expands its mask into its wave's LDS stage, then the wave
-//               copies the stage to the pair buffers with consecutive lanes on
-//               consecutive addresses.  Each workgroup lists its other entries
+//               lane expands its mask into its wave's LDS stage (1024 tile
+//               ids; entries past its end are handled as the others), then
+//               the wave copies the stage to the pair buffers with consecutive
+//               lanes on consecutive addresses.  Each workgroup lists its other entries
 //               in its own segment of the scratch (no atomics: thousands on one
 //               counter would serialise), and one workgroup turns the
 //               per-segment counts into offsets;
