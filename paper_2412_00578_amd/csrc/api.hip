@@ -127,6 +127,13 @@ struct Layout {
     ss::BatchDims d{};
 };
 
+// Every item's SH rows start 16-byte aligned.
+bool sh_rows16(const Layout& L) {
+    for (const ss::Item& it : L.items)
+        if (((uintptr_t)it.sh & 15u) != 0 || ((3 * it.sh_stride) & 3) != 0) return false;
+    return true;
+}
+
 ss::Item make_item(const ss_camera& cam, const ss_gaussians& g, float* out) {
     ss::Item it{};
     it.cam = cam;
@@ -208,7 +215,7 @@ int begin_impl(const Layout& L, int32_t mode, const ss_frame* f, ss_frame_counts
     ss::Item* table = reinterpret_cast<ss::Item*>(f->table);
     record(ev, 0, s);
     SS_TRY(hip_status(ss::write_items(table, L.items.data(), L.d.n_items, s), "item table"));
-    SS_TRY(hip_status(ss::launch_preprocess(table, L.d, mode, *f, s), "preprocess"));
+    SS_TRY(hip_status(ss::launch_preprocess(table, L.d, mode, *f, sh_rows16(L), s), "preprocess"));
     record(ev, 1, s);
     static_assert(sizeof(ss_frame_counts) == 2 * sizeof(uint64_t), "counts layout");
     if (!sync)
@@ -329,7 +336,7 @@ int ss_preprocess(const ss_camera* cam, const ss_gaussians* g, int32_t mode, con
     hipStream_t s = (hipStream_t)stream;
     ss::Item* table = reinterpret_cast<ss::Item*>(f->table);
     SS_TRY(hip_status(ss::write_items(table, L.items.data(), 1, s), "item table"));
-    return hip_status(ss::launch_preprocess(table, L.d, mode, *f, s), "preprocess");
+    return hip_status(ss::launch_preprocess(table, L.d, mode, *f, sh_rows16(L), s), "preprocess");
 }
 
 int ss_depth_order(int64_t n, int64_t n_visible, const ss_frame* f, void* stream) {

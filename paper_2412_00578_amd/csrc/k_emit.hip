@@ -94,11 +94,13 @@ __global__ __launch_bounds__(kEmitBlock) void k_emit(const Item* __restrict__ it
     const int lane = (int)__lane_id();
     const int64_t j = (int64_t)blockIdx.x * kEmitBlock + threadIdx.x;   // depth-order entry
     const bool valid = j < n_entries;
+    // offsets and order are independent loads, issued together
     const uint32_t end = valid ? offsets[j] : 0u;
+    const uint32_t gid_j = valid ? order[j] : 0u;
     uint32_t prev = __shfl_up(end, 1, 64);
     if (lane == 0) prev = (valid && j > 0) ? offsets[j - 1] : 0u;
     const uint32_t cnt = valid ? end - prev : 0u;
-    const uint32_t gid = cnt ? order[j] : 0u;
+    const uint32_t gid = cnt ? gid_j : 0u;
     uint4 ts = make_uint4(0u, 0u, 0u, 0u);
     if (cnt) ts = tsets[gid];
     const uint64_t mask = (uint64_t)ts.x | ((uint64_t)ts.y << 32);

@@ -274,10 +274,92 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(const Item* __restrict__ 
     }
 }
 
+// Real SH basis up to `degree` at the unit direction from the camera centre
+// (-R^T t) to the mean (Sec. 3.2.1; the standard 3DGS constants).
+__device__ __forceinline__ void sh_basis(const ss_camera& cam, float m0, float m1, float m2,
+                                         int degree, float Y[16]) {
+    const float cpx = -((cam.R[0] * cam.t[0] + cam.R[3] * cam.t[1]) + cam.R[6] * cam.t[2]);
+    const float cpy = -((cam.R[1] * cam.t[0] + cam.R[4] * cam.t[1]) + cam.R[7] * cam.t[2]);
+    const float cpz = -((cam.R[2] * cam.t[0] + cam.R[5] * cam.t[1]) + cam.R[8] * cam.t[2]);
+    float dx = m0 - cpx, dy = m1 - cpy, dz = m2 - cpz;
+    const float inv = 1.0f / sqrtf(dx * dx + dy * dy + dz * dz);
+    dx *= inv; dy *= inv; dz *= inv;
+    Y[0] = kSH0;
+    if (degree >= 1) {
+        Y[1] = -kSH1 * dy; Y[2] = kSH1 * dz; Y[3] = -kSH1 * dx;
+    }
+    if (degree >= 2) {
+        const float xx = dx * dx, yy = dy * dy, zz = dz * dz;
+        Y[4] = kSH2a * (dx * dy);
+        Y[5] = -kSH2a * (dy * dz);
+        Y[6] = kSH2b * (2.0f * zz - xx - yy);
+        Y[7] = -kSH2a * (dx * dz);
+        Y[8] = kSH2c * (xx - yy);
+        if (degree >= 3) {
+            Y[9] = -kSH3a * dy * (3.0f * xx - yy);
+            Y[10] = kSH3b * (dx * dy * dz);
+            Y[11] = -kSH3c * dy * (4.0f * zz - xx - yy);
+            Y[12] = kSH3d * dz * (2.0f * zz - 3.0f * xx - 3.0f * yy);
+            Y[13] = -kSH3c * dx * (4.0f * zz - xx - yy);
+            Y[14] = kSH3e * dz * (xx - yy);
+            Y[15] = -kSH3a * dx * (xx - 3.0f * yy);
+        }
+    }
+}
+
+__device__ __forceinline__ float4 colour_of(float cr, float cg, float cb) {
+    return make_float4(fmaxf(cr + 0.5f, 0.0f), fmaxf(cg + 0.5f, 0.0f), fmaxf(cb + 0.5f, 0.0f),
+                       0.0f);
+}
+
 // View-dependent colour from SH (FP32), for the Gaussians with tiles (the
-// others get rgb = 0).  One wave per workgroup; the workgroup's SH rows are
-// staged through LDS with coalesced loads, skipping the rows of Gaussians
-// without tiles.
+// others get rgb = 0), when every SH row starts 16-byte aligned (a row of a
+// multiple of 4 floats from an aligned base): each lane loads its own row
+// with up to 12 16-byte loads, all issued before the first use, and keeps it
+// in registers.  No LDS, so the kernel runs at the occupancy its registers
+// allow; a row's 1.5 cache lines are read once.
+__global__ __launch_bounds__(kBlock) void k_colour_rows(const Item* __restrict__ items,
+                                                        BatchDims dims,
+                                                        const uint32_t* __restrict__ counts,
+                                                        float4* __restrict__ rgb_out) {
+    const int64_t slot0 = (int64_t)blockIdx.x * kBlock;
+    const Item& it = items[dims.n_items == 1 ? 0 : item_of_slot(items, dims.n_items, slot0)];
+    const int64_t i = slot0 - it.g_off + threadIdx.x;
+    const int64_t o = slot0 + threadIdx.x;
+    if (o >= dims.n_slots) return;
+    if (i >= it.n || counts[o] == 0u) {
+        rgb_out[o] = make_float4(0.f, 0.f, 0.f, 0.f);
+        return;
+    }
+    const int nb = (it.sh_degree + 1) * (it.sh_degree + 1);
+    const int q = (3 * nb + 3) / 4;                   // 16-byte pieces holding the nb coefficients
+    const float4* src = reinterpret_cast<const float4*>(it.sh + i * (3 * (int64_t)it.sh_stride));
+    float4 v[12];
+#pragma unroll
+    for (int j = 0; j < 12; ++j)
+        v[j] = j < q ? ld_global(src + j) : make_float4(0.f, 0.f, 0.f, 0.f);
+    float Y[16];
+    sh_basis(it.cam, ld_global(it.means + 3 * i), ld_global(it.means + 3 * i + 1),
+             ld_global(it.means + 3 * i + 2), it.sh_degree, Y);
+    float h[48];
+#pragma unroll
+    for (int j = 0; j < 12; ++j) {
+        h[4 * j] = v[j].x; h[4 * j + 1] = v[j].y; h[4 * j + 2] = v[j].z; h[4 * j + 3] = v[j].w;
+    }
+    float cr = 0.f, cg = 0.f, cbl = 0.f;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        if (k < nb) {
+            cr = fmaf(Y[k], h[3 * k], cr);
+            cg = fmaf(Y[k], h[3 * k + 1], cg);
+            cbl = fmaf(Y[k], h[3 * k + 2], cbl);
+        }
+    }
+    rgb_out[o] = colour_of(cr, cg, cbl);
+}
+
+// The same for any row layout: one wave per workgroup stages the SH rows of
+// its visible Gaussians through LDS with coalesced loads.
 __global__ __launch_bounds__(kBlock) void k_colour(const Item* __restrict__ items, BatchDims dims,
                                                    const uint32_t* __restrict__ counts,
                                                    float4* __restrict__ rgb_out) {
@@ -285,7 +367,6 @@ __global__ __launch_bounds__(kBlock) void k_colour(const Item* __restrict__ item
     __shared__ uint32_t s_vis[kBlock];
     const int64_t slot0 = (int64_t)blockIdx.x * kBlock;
     const Item& it = items[dims.n_items == 1 ? 0 : item_of_slot(items, dims.n_items, slot0)];
-    const ss_camera cam = it.cam;
     const int64_t n = it.n;
     const int64_t first = slot0 - it.g_off;
     const int64_t i = first + threadIdx.x;
@@ -301,36 +382,9 @@ __global__ __launch_bounds__(kBlock) void k_colour(const Item* __restrict__ item
         rgb_out[o] = make_float4(0.f, 0.f, 0.f, 0.f);
         return;
     }
-    const float m0 = ld_global(it.means + 3 * i), m1 = ld_global(it.means + 3 * i + 1),
-                m2 = ld_global(it.means + 3 * i + 2);
-    const float cpx = -((cam.R[0] * cam.t[0] + cam.R[3] * cam.t[1]) + cam.R[6] * cam.t[2]);
-    const float cpy = -((cam.R[1] * cam.t[0] + cam.R[4] * cam.t[1]) + cam.R[7] * cam.t[2]);
-    const float cpz = -((cam.R[2] * cam.t[0] + cam.R[5] * cam.t[1]) + cam.R[8] * cam.t[2]);
-    float dx = m0 - cpx, dy = m1 - cpy, dz = m2 - cpz;
-    const float inv = 1.0f / sqrtf(dx * dx + dy * dy + dz * dz);
-    dx *= inv; dy *= inv; dz *= inv;
     float Y[16];
-    Y[0] = kSH0;
-    if (it.sh_degree >= 1) {
-        Y[1] = -kSH1 * dy; Y[2] = kSH1 * dz; Y[3] = -kSH1 * dx;
-    }
-    if (it.sh_degree >= 2) {
-        const float xx = dx * dx, yy = dy * dy, zz = dz * dz;
-        Y[4] = kSH2a * (dx * dy);
-        Y[5] = -kSH2a * (dy * dz);
-        Y[6] = kSH2b * (2.0f * zz - xx - yy);
-        Y[7] = -kSH2a * (dx * dz);
-        Y[8] = kSH2c * (xx - yy);
-        if (it.sh_degree >= 3) {
-            Y[9] = -kSH3a * dy * (3.0f * xx - yy);
-            Y[10] = kSH3b * (dx * dy * dz);
-            Y[11] = -kSH3c * dy * (4.0f * zz - xx - yy);
-            Y[12] = kSH3d * dz * (2.0f * zz - 3.0f * xx - 3.0f * yy);
-            Y[13] = -kSH3c * dx * (4.0f * zz - xx - yy);
-            Y[14] = kSH3e * dz * (xx - yy);
-            Y[15] = -kSH3a * dx * (xx - 3.0f * yy);
-        }
-    }
+    sh_basis(it.cam, ld_global(it.means + 3 * i), ld_global(it.means + 3 * i + 1),
+             ld_global(it.means + 3 * i + 2), it.sh_degree, Y);
     const float* h = s_sh + threadIdx.x * kShPitch;
     float cr = 0.f, cg = 0.f, cbl = 0.f;
     for (int k = 0; k < nb; ++k) {
@@ -338,8 +392,7 @@ __global__ __launch_bounds__(kBlock) void k_colour(const Item* __restrict__ item
         cg = fmaf(Y[k], h[3 * k + 1], cg);
         cbl = fmaf(Y[k], h[3 * k + 2], cbl);
     }
-    rgb_out[o] = make_float4(fmaxf(cr + 0.5f, 0.0f), fmaxf(cg + 0.5f, 0.0f),
-                             fmaxf(cbl + 0.5f, 0.0f), 0.0f);
+    rgb_out[o] = colour_of(cr, cg, cbl);
 }
 
 // One workgroup: totals = (sum of the pair-count partials, sum of the
@@ -390,7 +443,7 @@ __global__ __launch_bounds__(1024) void k_totals(const uint32_t* __restrict__ pa
 }  // namespace
 
 hipError_t launch_preprocess(const Item* items, const BatchDims& d, int mode, const ss_frame& f,
-                             hipStream_t s) {
+                             bool sh_rows16, hipStream_t s) {
     // per-workgroup partial counts go to the emit stage's scratch, free until then
     const int64_t grid = (d.n_slots + kBlock - 1) / kBlock;
     if (grid > 0) {
@@ -398,7 +451,8 @@ hipError_t launch_preprocess(const Item* items, const BatchDims& d, int mode, co
                            mode, reinterpret_cast<float4*>(f.geom),
                            reinterpret_cast<float4*>(f.conic), f.counts, f.depth_keys,
                            reinterpret_cast<uint4*>(f.tile_sets), f.emit_tmp);
-        hipLaunchKernelGGL(k_colour, dim3((unsigned)grid), dim3(kBlock), 0, s, items, d, f.counts,
+        hipLaunchKernelGGL(sh_rows16 ? k_colour_rows : k_colour, dim3((unsigned)grid),
+                           dim3(kBlock), 0, s, items, d, f.counts,
                            reinterpret_cast<float4*>(f.rgb));
     }
     hipLaunchKernelGGL(k_totals, dim3(1), dim3(1024), 0, s, f.emit_tmp, grid, f.totals);

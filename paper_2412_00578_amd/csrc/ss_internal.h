@@ -366,8 +366,10 @@ __device__ __forceinline__ int item_of_tile(const Item* items, int n_items, int 
 // (each returns hipSuccess or the launch error)
 
 hipError_t write_items(Item* table, const Item* host_items, int n_items, hipStream_t s);
+// sh_rows16: every item's SH rows start 16-byte aligned (base aligned and a
+// row of a multiple of 4 floats), so the colour kernel can load rows whole.
 hipError_t launch_preprocess(const Item* items, const BatchDims& d, int mode, const ss_frame& f,
-                             hipStream_t s);
+                             bool sh_rows16, hipStream_t s);
 hipError_t launch_depth_order(int64_t n, int64_t n_visible, const ss_frame& f, hipStream_t s);
 hipError_t launch_scan(int64_t n, const ss_frame& f, hipStream_t s);
 int64_t scan_tmp_words(int64_t n);
