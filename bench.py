@@ -51,12 +51,14 @@ PEAK_HBM_GBS = 8000.0
 # T (1 - alpha), alpha T, the stop compare and three colour FMAs.
 OPS_PER_EVAL = 8
 OPS_PER_CONTRIB = 11
-# Algorithmic HBM bytes: preprocess reads 236 B (SH-3 inputs) and writes a 56 B
-# record (geom, conic, rgb, count, depth key, tile set: 72 B) per Gaussian;
-# the depth order moves 8 B per slot in its compacting first pass plus 60 B
-# per Gaussian with tiles over all four passes; the tile sort moves 20 B per
-# pair per 8-bit pass.
-PRE_BYTES_PER_G = 236 + 72
+# Algorithmic HBM bytes: the geometry kernel reads 44 B (mean, scale,
+# quaternion, opacity) and writes 56 B (geom, conic, count, depth key, tile
+# set) per Gaussian, the colour kernel reads the count and writes rgb (20 B) per
+# Gaussian and reads the mean and the SH-3 row (204 B) of each Gaussian with
+# tiles; the depth order moves 8 B per slot in its compacting first pass plus
+# 60 B per Gaussian with tiles over all four passes; the tile sort moves 20 B
+# per pair per 8-bit pass.
+PRE_BYTES_PER_G, PRE_BYTES_PER_VISIBLE = 44 + 56 + 20, 204
 DEPTH_ORDER_BYTES_PER_SLOT, DEPTH_ORDER_BYTES_PER_VISIBLE = 8, 60
 SORT_BYTES_PER_PAIR_PASS = 20
 
@@ -254,7 +256,8 @@ def main():
             "blended_pairs_per_frame": int(i_mean), "gaussians_with_tiles": int(v_mean),
             "blend_ops_per_frame": int(blend_ops),
             "blend_tops": round(blend_ops / (stages["blend"] * 1e-3) / 1e12, 3),
-            "preprocess_gbs": round(args.n * PRE_BYTES_PER_G / (stages["preprocess"] * 1e-3) / 1e9,
+            "preprocess_gbs": round((args.n * PRE_BYTES_PER_G + v_mean * PRE_BYTES_PER_VISIBLE) /
+                                    (stages["preprocess"] * 1e-3) / 1e9,
                                     1),
             "depth_order_gbs": round((args.n * DEPTH_ORDER_BYTES_PER_SLOT +
                                       v_mean * DEPTH_ORDER_BYTES_PER_VISIBLE) /
