@@ -27,6 +27,7 @@ at 0.5 and 0.8 of the saturation request rate over four resident scenes.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import platform
@@ -65,6 +66,28 @@ SORT_BYTES_PER_PAIR_PASS = 20
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def blend_traffic():
+    """HBM bytes (read + written) per launch of the blend (k_blend<false>,
+    AccuTile frame) from the committed FETCH_SIZE / WRITE_SIZE counter summary,
+    calibrated against a plain copy; None when that summary was taken on
+    another version of the blend source (its sha256 differs) or is missing."""
+    root = os.path.dirname(os.path.abspath(__file__))
+    src = os.path.join(root, "paper_2412_00578_amd", "csrc", "k_blend.hip")
+    summary = os.path.join(root, "profiles", "forward_c1_hbm_traffic.txt")
+    try:
+        text = open(summary).read().splitlines()
+        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    if not any(line.strip() == f"k_blend source sha256: {digest}" for line in text):
+        return None
+    for line in text:
+        f = line.split()
+        if f and f[0] == "k_blend<false>" and len(f) >= 4:
+            return int(round((float(f[2]) + float(f[3])) * 2**20))
+    return None
 
 
 def cpu_model():
@@ -310,7 +333,9 @@ def main():
         "roofline": {"bound": "alu", "kernel": "blend (k_blend)",
                      "achieved": round(achieved, 3), "peak": round(PEAK_VALU_TOPS, 1),
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK_VALU_TOPS, 4),
-                     "traffic": None,
+                     "traffic": blend_traffic(),
+                     "traffic_unit": "bytes per launch (FETCH_SIZE + WRITE_SIZE, calibrated; "
+                                     "profiles/forward_c1_hbm_traffic.txt)",
                      "work": f"{acc['evaluated_pairs_per_frame']} evaluated pixel-Gaussian pairs "
                              f"x {OPS_PER_EVAL} FP32 ops + {acc['blended_pairs_per_frame']} "
                              f"blended pairs x {OPS_PER_CONTRIB} FP32 ops per launch",
