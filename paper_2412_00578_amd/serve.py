@@ -219,9 +219,11 @@ class GpuBackend:
         n = self.scenes[r.scene].n
         px = int(r.cam.width) * int(r.cam.height)
         est = self.pairs_per.get(self._key(r), 4 * n)
-        # records, counts, tile sets, depth keys, order, offsets and queue: 92 B
-        # per slot; image and per-pixel state 20 B per pixel; 16 B per pair (two
-        # buffers) with the 1.25 growth; sort scratch
+        # records 48, counts 4, tile sets 16, depth keys 8, order 8, counts in
+        # depth order 4, offsets 4 and emit queue 4: 96 B per slot; image and
+        # per-pixel state 20 B per pixel (budgeted at 32 with the per-tile
+        # ranges and order); 16 B per pair (two buffers) with the 1.25 growth;
+        # sort scratch
         return int(96 * n + 32 * px + 16 * 1.25 * est + (3 << 20))
 
     def sync_reference(self, clock):
