@@ -34,7 +34,9 @@ constexpr int kBigGrid = 1024;
 
 // Scratch layout for n entries, nb = ceil(n / 256) workgroups: segments of
 // queued entries [0, 256 nb), their counts [256 nb, 257 nb), exclusive segment
-// offsets with the total last [257 nb, 258 nb + 1).
+// offsets with the total last [257 nb, 258 nb + 1), and a coarse index
+// [258 nb + 1, 262 nb + 2): entry g names the segment holding queued entry
+// 64 g.
 __host__ __device__ __forceinline__ int64_t queue_blocks(int64_t n) { return (n + 255) / 256; }
 
 __device__ __forceinline__ uint32_t wave_incl_scan_u32(uint32_t x) {
@@ -170,13 +172,15 @@ __global__ __launch_bounds__(kEmitBlock) void k_emit(const Item* __restrict__ it
     }
 }
 
-// One workgroup: exclusive offsets of the nb segment counts, total last.
+// One workgroup: exclusive offsets of the nb segment counts, total last, and
+// the coarse index of every 64th queued entry.
 __global__ __launch_bounds__(1024) void k_emit_offsets(uint32_t* __restrict__ queue,
                                                        int64_t nb) {
     __shared__ uint32_t s_w[16];
     __shared__ uint32_t s_carry;
     const uint32_t* cnt = queue + nb * kEmitBlock;
     uint32_t* off = queue + nb * kEmitBlock + nb;
+    uint32_t* coarse = queue + nb * kEmitBlock + 2 * nb + 1;
     if (threadIdx.x == 0) s_carry = 0u;
     __syncthreads();
     for (int64_t base = 0; base < nb; base += 1024) {
@@ -188,7 +192,11 @@ __global__ __launch_bounds__(1024) void k_emit_offsets(uint32_t* __restrict__ qu
         __syncthreads();
         uint32_t before = s_carry;
         for (int k = 0; k < w; ++k) before += s_w[k];
-        if (b < nb) off[b] = before + inc - x;
+        if (b < nb) {
+            const uint32_t o = before + inc - x;
+            off[b] = o;
+            for (uint32_t m = (o + 63u) & ~63u; m < o + x; m += 64u) coarse[m >> 6] = (uint32_t)b;
+        }
         __syncthreads();
         if (threadIdx.x == 1023) s_carry = before + inc;
         __syncthreads();
@@ -211,6 +219,7 @@ __global__ __launch_bounds__(kBigBlock) void k_emit_big(const Item* __restrict__
     const int w = threadIdx.x >> 6;
     const int lane = (int)__lane_id();
     const uint32_t* seg_off = queue + nb * kEmitBlock + nb;
+    const uint32_t* coarse = queue + nb * kEmitBlock + 2 * nb + 1;
     const uint32_t nq = seg_off[nb];
     const uint32_t wave0 = blockIdx.x * (kBigBlock / 64) + w;
     const uint32_t waves = gridDim.x * (kBigBlock / 64);
@@ -227,8 +236,11 @@ __global__ __launch_bounds__(kBigBlock) void k_emit_big(const Item* __restrict__
         uint32_t i = 0, pos0 = 0, end = 0, tile_off = 0;
         int tx_n = 0, ty_n = 0;
         if (have) {
-            // the segment holding queued entry b: the last with offset <= b
-            int64_t lo = 0, hi = nb - 1;
+            // the segment holding queued entry b: the last with offset <= b,
+            // between the segments holding entries 64 g and 64 (g + 1)
+            const uint32_t g = b >> 6;
+            int64_t lo = coarse[g];
+            int64_t hi = (uint64_t)(g + 1) * 64u < nq ? (int64_t)coarse[g + 1] : nb - 1;
             while (lo < hi) {
                 const int64_t mid = (lo + hi + 1) >> 1;
                 if (seg_off[mid] <= b) lo = mid; else hi = mid - 1;
@@ -307,7 +319,7 @@ __global__ __launch_bounds__(kBigBlock) void k_emit_big(const Item* __restrict__
 
 int64_t emit_tmp_words(int64_t n) {
     const int64_t nb = queue_blocks(n);
-    const int64_t q = nb * kEmitBlock + 2 * nb + 1;
+    const int64_t q = nb * kEmitBlock + 6 * nb + 2;
     const int64_t pre = 2 * ((n + 63) / 64);     // the preprocess stage's partial counts
     return q > pre ? q : pre;
 }

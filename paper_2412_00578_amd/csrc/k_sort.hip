@@ -94,16 +94,26 @@ __global__ __launch_bounds__(kBlock) void k_hist(const K* __restrict__ keys, uin
     const uint64_t lo = (uint64_t)blockIdx.x * chunk;
     const uint64_t hi = lo + chunk < n ? lo + chunk : n;
     const int w = threadIdx.x >> 6;
-    for (uint64_t base = lo; base < hi; base += kBlock) {   // uniform trip count
-        const uint64_t i = base + threadIdx.x;
-        const K key = i < hi ? keys[i] : (K)0;
-        const bool valid = i < hi && !(drop && key == (K)kCulledKey);
-        const uint32_t d = valid ? digit_of(key, shift) : 0u;
-        if (match) {
-            const uint64_t m = match_digit(d, valid);
-            if (valid && lanes_below(m) == 0u) atomicAdd(&h[w][d], (uint32_t)__popcll(m));
-        } else if (valid) {
-            atomicAdd(&h[w][d], 1u);
+    // kHistUnroll keys per lane and step, their loads issued together
+    constexpr int kHistUnroll = 8;
+    for (uint64_t base = lo; base < hi; base += kBlock * kHistUnroll) {   // uniform trip count
+        K key[kHistUnroll];
+#pragma unroll
+        for (int u = 0; u < kHistUnroll; ++u) {
+            const uint64_t i = base + (uint64_t)u * kBlock + threadIdx.x;
+            key[u] = i < hi ? keys[i] : (K)0;
+        }
+#pragma unroll
+        for (int u = 0; u < kHistUnroll; ++u) {
+            const uint64_t i = base + (uint64_t)u * kBlock + threadIdx.x;
+            const bool valid = i < hi && !(drop && key[u] == (K)kCulledKey);
+            const uint32_t d = valid ? digit_of(key[u], shift) : 0u;
+            if (match) {
+                const uint64_t m = match_digit(d, valid);
+                if (valid && lanes_below(m) == 0u) atomicAdd(&h[w][d], (uint32_t)__popcll(m));
+            } else if (valid) {
+                atomicAdd(&h[w][d], 1u);
+            }
         }
     }
     __syncthreads();
