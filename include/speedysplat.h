@@ -127,7 +127,8 @@ typedef struct ss_frame {
     uint64_t *scan_tmp;     /* [scan_tmp_words]; word 0 receives the pair count P */
     uint64_t *totals;       /* [2] the frame counts (ss_frame_counts: P, Gaussians with
                                tiles), zeroed and accumulated by the preprocess stage */
-    uint32_t *ranges;       /* [n_tiles, 2] per-tile [start, end) into the sorted pairs */
+    uint32_t *ranges;       /* [n_tiles, 2] 8-byte aligned: per-tile [start, end) into the
+                               sorted pairs */
     float *t_final;         /* [H, W] final transmittance per pixel */
     uint32_t *n_last;       /* [H, W] 1 + position (within its tile) of the last
                                Gaussian blended into the pixel, 0 if none */

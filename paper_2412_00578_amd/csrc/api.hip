@@ -89,6 +89,8 @@ int check_frame_records(const ss_frame* f, int64_t n) {
 int check_frame_pixels(const ss_frame* f) {
     if (!f->ranges || !f->t_final || !f->n_last)
         return fail(SS_ERR_INVALID_ARG, "a per-tile or per-pixel frame buffer is NULL");
+    if (((uintptr_t)f->ranges & 7u) != 0)
+        return fail(SS_ERR_INVALID_ARG, "frame ranges must be 8-byte aligned");
     return SS_OK;
 }
 

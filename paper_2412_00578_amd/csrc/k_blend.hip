@@ -74,15 +74,21 @@ constexpr int kOrderKeys = 8 * kOrderBuckets;     // (XCD, bucket) pairs
 constexpr int kOrderThreads = 1024;
 constexpr int kOrderPer = kOrderKeys / kOrderThreads;
 
-// XCD-major, longest bucket first within an XCD.
+// XCD-major, longest bucket first within an XCD.  tx_single: the tile grid
+// width when the batch has one item (whose tiles start at 0).
 __device__ __forceinline__ uint32_t order_key(const Item* __restrict__ items, int n_items,
-                                              const uint32_t* __restrict__ ranges, int t) {
-    const int k = n_items == 1 ? 0 : item_of_tile(items, n_items, t);
-    const int tx_n = items[k].tx_n;
-    const int lt = t - items[k].tile_off;
+                                              int tx_single, const uint32_t* __restrict__ ranges,
+                                              int t) {
+    int k = 0, tx_n = tx_single, lt = t;
+    if (n_items != 1) {
+        k = item_of_tile(items, n_items, t);
+        tx_n = items[k].tx_n;
+        lt = t - items[k].tile_off;
+    }
     const int bx = (lt % tx_n) >> 2, by = (lt / tx_n) >> 2;
     const uint32_t x = (uint32_t)(by * ((tx_n + 3) >> 2) + bx + 3 * k) & 7u;
-    const uint32_t len = ranges[2 * t + 1] - ranges[2 * t];
+    const uint2 r = *reinterpret_cast<const uint2*>(ranges + 2 * t);
+    const uint32_t len = r.y - r.x;
     const uint32_t b = len >> 3 < (uint32_t)kOrderBuckets - 1u ? len >> 3
                                                                : (uint32_t)kOrderBuckets - 1u;
     return x * kOrderBuckets + (kOrderBuckets - 1u - b);
@@ -97,6 +103,7 @@ __global__ __launch_bounds__(kOrderThreads) void k_tile_order(const Item* __rest
     __shared__ uint32_t s_start[9], s_cap[8], s_over[9], s_free[9];
     const int t0 = (int)threadIdx.x;
     const int n = dims.n_tiles;
+    const int tx1 = items[0].tx_n;
 #pragma unroll
     for (int u = 0; u < kOrderPer; ++u) h[t0 * kOrderPer + u] = 0u;
     __syncthreads();
@@ -106,13 +113,13 @@ __global__ __launch_bounds__(kOrderThreads) void k_tile_order(const Item* __rest
 #pragma unroll
     for (int u = 0; u < kOrderPer; ++u) {
         const int t = t0 + u * kOrderThreads;
-        kc[u] = t < n ? order_key(items, dims.n_items, ranges, t) : 0u;
+        kc[u] = t < n ? order_key(items, dims.n_items, tx1, ranges, t) : 0u;
     }
 #pragma unroll
     for (int u = 0; u < kOrderPer; ++u)
         if (t0 + u * kOrderThreads < n) atomicAdd(&h[kc[u]], 1u);
     for (int t = t0 + kOrderPer * kOrderThreads; t < n; t += kOrderThreads)
-        atomicAdd(&h[order_key(items, dims.n_items, ranges, t)], 1u);
+        atomicAdd(&h[order_key(items, dims.n_items, tx1, ranges, t)], 1u);
     __syncthreads();
     // exclusive scan of the key counts; thread t0 owns keys kOrderPer t0 ..
     uint32_t c[kOrderPer], sum = 0;
@@ -160,7 +167,7 @@ __global__ __launch_bounds__(kOrderThreads) void k_tile_order(const Item* __rest
     __syncthreads();
     for (int t = t0; t < n; t += kOrderThreads) {
         const int u = (t - t0) / kOrderThreads;
-        const uint32_t key = u < kOrderPer ? kc[u] : order_key(items, dims.n_items, ranges, t);
+        const uint32_t key = u < kOrderPer ? kc[u] : order_key(items, dims.n_items, tx1, ranges, t);
         const uint32_t x = key / kOrderBuckets;
         const uint32_t r = atomicAdd(&h[key], 1u) - s_start[x];
         if (r < s_cap[x]) {
