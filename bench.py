@@ -57,10 +57,11 @@ OPS_PER_CONTRIB = 11
 # set) per Gaussian, the colour kernel reads the count and writes rgb (20 B) per
 # Gaussian and reads the mean and the SH-3 row (204 B) of each Gaussian with
 # tiles; the depth order moves 8 B per slot in its compacting first pass plus
-# 60 B per Gaussian with tiles over all four passes; the tile sort moves 20 B
-# per pair per 8-bit pass.
+# 100 B per Gaussian with tiles over all four passes (keys, values, and the
+# last pass's gather of the tile sets into depth order); the tile sort moves
+# 20 B per pair per 8-bit pass.
 PRE_BYTES_PER_G, PRE_BYTES_PER_VISIBLE = 44 + 56 + 20, 204
-DEPTH_ORDER_BYTES_PER_SLOT, DEPTH_ORDER_BYTES_PER_VISIBLE = 8, 60
+DEPTH_ORDER_BYTES_PER_SLOT, DEPTH_ORDER_BYTES_PER_VISIBLE = 8, 100
 SORT_BYTES_PER_PAIR_PASS = 20
 
 

@@ -117,12 +117,14 @@ typedef struct ss_frame {
     uint32_t *order;        /* [2n]  after ss_depth_order, [0, n_visible) holds the
                                Gaussians with tiles sorted by (depth key, index);
                                [n, 2n) is scratch */
-    uint32_t *order_counts; /* [n]   after ss_depth_order: counts[order[j]], j < n_visible */
+    uint32_t *order_counts; /* [n]   after ss_depth_order: the tile count of order[j]
+                               (tile_sets[order[j]] word 3), j < n_visible */
     uint32_t *order_tmp;    /* [order_tmp_words] scratch of ss_depth_order */
     uint32_t *tile_sets;    /* [n,4] per Gaussian, written by the preprocess stage: when
                                its tile rectangle fits 8 x 8 tiles, the 64-bit mask
                                (words 0-1, bit r * 8 + c = tile (x0 + c, y0 + r)) and
-                               x0 | y0 << 16 (word 2); mask 0 otherwise */
+                               x0 | y0 << 16 (word 2); mask 0 otherwise; word 3 is the
+                               tile count */
     uint32_t *offsets;      /* [n]   inclusive prefix sum of counts in depth order */
     uint64_t *scan_tmp;     /* [scan_tmp_words]; word 0 receives the pair count P */
     uint64_t *totals;       /* [2] the frame counts (ss_frame_counts: P, Gaussians with
@@ -137,8 +139,10 @@ typedef struct ss_frame {
     uint32_t *n_contrib;    /* optional [H, W], written only with n_eval: Gaussians
                                blended into the pixel */
     uint32_t *emit_tmp;     /* [emit_tmp_words] 16-byte aligned: scratch of the preprocess
-                               stage (partial frame counts) and the emit stage (queue of
-                               Gaussians with many tiles); contents are not an output */
+                               stage (partial frame counts), the depth order (which
+                               leaves the tile sets in depth order at its start for the
+                               emit stage) and the emit stage (queue of Gaussians with
+                               many tiles); contents are not an output */
     void *table;            /* [table_bytes] 16-byte aligned: the frame's item table
                                (camera, scene pointers, offsets), written by
                                ss_preprocess / ss_forward_begin / ss_batch_begin and
@@ -245,10 +249,11 @@ int ss_preprocess(const ss_camera *cam, const ss_gaussians *g, int32_t mode,
  * Stage 2a, depth order (the depth half of the Sec. 3.2.2 sort key): stable LSD
  * radix sort of the Gaussians with tiles on frame->depth_keys (the n keys the
  * preprocess stage wrote, of which n_visible differ from 0xffffffff);
- * frame->order[0, n_visible) receives their indices by (bits(depth), index)
- * and frame->order_counts[j] = counts[order[j]].  The first pass drops the
- * Gaussians without tiles, so later passes sort n_visible keys.  Uses
- * depth_keys[0, 2n), order[n, 2n) and order_tmp as scratch.
+ * frame->order[0, n_visible) receives their indices by (bits(depth), index),
+ * frame->order_counts[j] the tile count of order[j] and emit_tmp (as [n, 4])
+ * the tile set of order[j], both read from tile_sets[order[j]].  The first
+ * pass drops the Gaussians without tiles, so later passes sort n_visible keys.
+ * Uses depth_keys[0, 2n), order[n, 2n) and order_tmp as scratch.
  */
 int ss_depth_order(int64_t n, int64_t n_visible, const ss_frame *frame, void *stream);
 
@@ -263,7 +268,8 @@ int ss_scan(int64_t n_visible, const ss_frame *frame, void *stream);
  * Stage 3, key emission (Sec. 3.2.2, "duplicateWithKeys"; Alg. 1 "Process"):
  * for each depth-order entry j < n_visible, Gaussian i = order[j] writes its
  * tiles (in an unspecified order) at [offsets[j] - counts[i], offsets[j]) of
- * pairs->keys[buf] (tile id) / values[buf] (i).  n is the number of
+ * pairs->keys[buf] (tile id) / values[buf] (i), reading its tile set from the
+ * depth-ordered copy ss_depth_order left in emit_tmp.  n is the number of
  * Gaussians; n_pairs must be the P the scan produced and <= pairs->capacity.
  */
 int ss_emit(const ss_camera *cam, int64_t n, int64_t n_visible, int32_t mode,

@@ -10,7 +10,9 @@
 // Tile counts are heavy-tailed (most Gaussians touch a few tiles, a Gaussian
 // near the camera thousands), so the work is split in two launches:
 //   k_emit      one lane per entry whose tile set the preprocess stage stored
-//               as a mask (tile rectangle within 8 x 8) with <= 32 tiles: each
+//               as a mask (tile rectangle within 8 x 8) with <= 32 tiles (the
+//               depth order left the sets in entry order, so these reads are
+//               coalesced): each
 //               lane expands its mask into its wave's LDS stage (1024 tile
 //               ids; entries past its end are handled as the others), then
 //               the wave copies the stage to the pair buffers with consecutive
@@ -82,7 +84,7 @@ constexpr int kStage = 1024;
 __global__ __launch_bounds__(kEmitBlock) void k_emit(const Item* __restrict__ items,
                                                      BatchDims dims, uint32_t n_entries,
                                                      uint32_t limit,
-                                                     const uint4* __restrict__ tsets,
+                                                     const uint4* __restrict__ tsets,   // by entry
                                                      const uint32_t* __restrict__ order,
                                                      const uint32_t* __restrict__ offsets,
                                                      uint32_t* __restrict__ keys,
@@ -104,7 +106,7 @@ __global__ __launch_bounds__(kEmitBlock) void k_emit(const Item* __restrict__ it
     const uint32_t cnt = valid ? end - prev : 0u;
     const uint32_t gid = cnt ? gid_j : 0u;
     uint4 ts = make_uint4(0u, 0u, 0u, 0u);
-    if (cnt) ts = tsets[gid];
+    if (cnt) ts = tsets[j];                       // the tile sets in depth order
     const uint64_t mask = (uint64_t)ts.x | ((uint64_t)ts.y << 32);
     const bool masked = cnt && cnt <= kSmall && mask != 0ull;
     // staged runs in lane order; the lanes whose run would pass the stage's
@@ -319,7 +321,8 @@ __global__ __launch_bounds__(kBigBlock) void k_emit_big(const Item* __restrict__
 
 int64_t emit_tmp_words(int64_t n) {
     const int64_t nb = queue_blocks(n);
-    const int64_t q = nb * kEmitBlock + 6 * nb + 2;
+    // the depth-ordered tile sets (4 words per entry), then the queue
+    const int64_t q = 4 * n + nb * kEmitBlock + 6 * nb + 2;
     const int64_t pre = 2 * ((n + 63) / 64);     // the preprocess stage's partial counts
     return q > pre ? q : pre;
 }
@@ -329,15 +332,17 @@ hipError_t launch_emit(const Item* items, const BatchDims& d, int mode, const ss
                        hipStream_t s) {
     if (n_entries <= 0) return hipSuccess;
     const int64_t nb = queue_blocks(n_entries);
+    // emit_tmp: the depth-ordered tile sets the depth order left, then the queue
+    const uint4* sets = reinterpret_cast<const uint4*>(f.emit_tmp);
+    uint32_t* queue = f.emit_tmp + 4 * n_entries;
     hipLaunchKernelGGL(k_emit, dim3((unsigned)nb), dim3(kEmitBlock), 0, s, items, d,
-                       (uint32_t)n_entries, (uint32_t)n_pairs,
-                       reinterpret_cast<const uint4*>(f.tile_sets), f.order, f.offsets, keys,
-                       values, f.emit_tmp);
-    hipLaunchKernelGGL(k_emit_offsets, dim3(1), dim3(1024), 0, s, f.emit_tmp, nb);
+                       (uint32_t)n_entries, (uint32_t)n_pairs, sets, f.order, f.offsets, keys,
+                       values, queue);
+    hipLaunchKernelGGL(k_emit_offsets, dim3(1), dim3(1024), 0, s, queue, nb);
     hipLaunchKernelGGL(k_emit_big, dim3(kBigGrid), dim3(kBigBlock), 0, s, items, d, mode,
                        (uint32_t)n_pairs, nb, reinterpret_cast<const float4*>(f.geom),
                        reinterpret_cast<const float4*>(f.conic), f.order, f.offsets, keys,
-                       values, f.emit_tmp);
+                       values, queue);
     return hipGetLastError();
 }
 

@@ -239,7 +239,7 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(const Item* __restrict__ 
         uint64_t mask;
         uint32_t origin;
         const uint32_t cnt = rect_tile_set(g4, q4, mode, tx_n, ty_n, &mask, &origin);
-        tsets[o] = make_uint4((uint32_t)mask, (uint32_t)(mask >> 32), origin, 0u);
+        tsets[o] = make_uint4((uint32_t)mask, (uint32_t)(mask >> 32), origin, cnt);
         counts[o] = cnt;
         dkeys[o] = cnt ? __float_as_uint(g4.z) : kCulledKey;
         return cnt;
@@ -253,7 +253,7 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(const Item* __restrict__ 
                                              &origin);
         if (defer) {
             cnt = c;
-            tsets[o] = make_uint4((uint32_t)mask, (uint32_t)(mask >> 32), origin, 0u);
+            tsets[o] = make_uint4((uint32_t)mask, (uint32_t)(mask >> 32), origin, cnt);
             counts[o] = cnt;
             dkeys[o] = cnt ? __float_as_uint(g4.z) : kCulledKey;
         }
@@ -399,13 +399,24 @@ __global__ __launch_bounds__(kBlock) void k_colour(const Item* __restrict__ item
     sh_basis(it.cam, ld_global(it.means + 3 * i), ld_global(it.means + 3 * i + 1),
              ld_global(it.means + 3 * i + 2), it.sh_degree, Y);
     const float* h = s_sh + threadIdx.x * kShPitch;
-    float cr = 0.f, cg = 0.f, cbl = 0.f;
-    for (int k = 0; k < nb; ++k) {
-        cr = fmaf(Y[k], h[3 * k], cr);
-        cg = fmaf(Y[k], h[3 * k + 1], cg);
-        cbl = fmaf(Y[k], h[3 * k + 2], cbl);
+    // the same sums, in the same order, as k_colour_rows: an FMA chain over
+    // each group of four coefficients, then (g0 + g1) + (g2 + g3)
+    float pr[4], pg[4], pb[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        pr[q] = pg[q] = pb[q] = 0.f;
+#pragma unroll
+        for (int mm = 0; mm < 4; ++mm) {
+            const int k = 4 * q + mm;
+            if (k < nb) {
+                pr[q] = fmaf(Y[k], h[3 * k], pr[q]);
+                pg[q] = fmaf(Y[k], h[3 * k + 1], pg[q]);
+                pb[q] = fmaf(Y[k], h[3 * k + 2], pb[q]);
+            }
+        }
     }
-    rgb_out[o] = colour_of(cr, cg, cbl);
+    rgb_out[o] = colour_of((pr[0] + pr[1]) + (pr[2] + pr[3]), (pg[0] + pg[1]) + (pg[2] + pg[3]),
+                           (pb[0] + pb[1]) + (pb[2] + pb[3]));
 }
 
 // One workgroup: totals = (sum of the pair-count partials, sum of the

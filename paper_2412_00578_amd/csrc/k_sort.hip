@@ -178,7 +178,8 @@ __global__ __launch_bounds__(kBlock) void k_dscan(uint32_t* __restrict__ hist, u
 
 // vals_in == nullptr stands for the identity (value = input position);
 // keys_out == nullptr skips the key writes (a last pass whose keys are unused);
-// with gather_out, gather_out[p] = gather[value] for every output position p;
+// with gather_out, gather_out[p] = gather[value].w and sets_out[p] =
+// gather[value] for every output position p (one 16-byte read per key);
 // drop: keys equal to kCulledKey are left out, as in k_hist.  A workgroup
 // walks its chunk in sub-tiles of kBlock * ITEMS keys.
 template <class K, int ITEMS>
@@ -189,8 +190,9 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const K* __restrict__ keys_i
                                                     int shift, uint64_t chunk, uint32_t grid,
                                                     bool drop,
                                                     const uint32_t* __restrict__ hist,
-                                                    const uint32_t* __restrict__ gather,
-                                                    uint32_t* __restrict__ gather_out) {
+                                                    const uint4* __restrict__ gather,
+                                                    uint32_t* __restrict__ gather_out,
+                                                    uint4* __restrict__ sets_out) {
     constexpr int kItems = ITEMS;
     constexpr int kSub = kBlock * ITEMS;
     __shared__ K s_key[kSub];
@@ -297,7 +299,11 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const K* __restrict__ keys_i
                 if (i0 + u * kBlock < n_sub && pos[u] < n) {
                     if (keys_out) keys_out[pos[u]] = kk[u];
                     vals_out[pos[u]] = v[u];
-                    if (gather_out) gather_out[pos[u]] = gather[v[u]];
+                    if (gather_out) {
+                        const uint4 ts = gather[v[u]];
+                        gather_out[pos[u]] = ts.w;
+                        sets_out[pos[u]] = ts;
+                    }
                 }
             }
         }
@@ -343,11 +349,12 @@ __global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ key
 // equal to kCulledKey, of which there must be n0 - n, and every later pass
 // sorts the n kept pairs (without drop, n0 == n).  identity: the input values
 // are 0..n0-1 and are not read.  With last_keys false the final pass writes
-// values only; with gather_out it also writes gather[value] in sorted order.
+// values only; with gather_out it also writes gather[value].w and (to
+// sets_out) gather[value] in sorted order.
 template <class K>
 hipError_t radix_sort(K* keys[2], uint32_t* vals[2], int cur, uint64_t n0, uint64_t n, int bits,
                       uint32_t* tmp, bool drop, bool identity, bool last_keys,
-                      const uint32_t* gather, uint32_t* gather_out, int* out_buf,
+                      const uint4* gather, uint32_t* gather_out, uint4* sets_out, int* out_buf,
                       hipStream_t s) {
     const int passes = (bits + 7) / 8;
     for (int pass = 0; pass < passes; ++pass) {
@@ -367,7 +374,7 @@ hipError_t radix_sort(K* keys[2], uint32_t* vals[2], int cur, uint64_t n0, uint6
                                                  : k_scatter<K, kItemsLarge>;
         hipLaunchKernelGGL(scatter, dim3(plan.grid), dim3(kBlock), 0, s, keys[cur], vin, kout,
                            vals[1 - cur], m, shift, plan.chunk, plan.grid, dr, tmp, gather,
-                           last ? gather_out : nullptr);
+                           last ? gather_out : nullptr, last ? sets_out : nullptr);
         cur = 1 - cur;
     }
     *out_buf = cur;
@@ -387,9 +394,11 @@ hipError_t launch_depth_order(int64_t n, int64_t n_visible, const ss_frame& f, h
     int out = 0;
     // 4 passes from buffer 0 end in buffer 0: the first drops the Gaussians
     // without tiles, the order lands in f.order[0, n_visible) and the last pass
-    // writes the tile counts in that order.
+    // writes the tile counts and the tile sets (to the start of emit_tmp) in
+    // that order.
     return radix_sort<uint32_t>(keys, vals, 0, (uint64_t)n, (uint64_t)n_visible, 32, f.order_tmp,
-                                true, true, false, f.counts, f.order_counts, &out, s);
+                                true, true, false, reinterpret_cast<const uint4*>(f.tile_sets),
+                                f.order_counts, reinterpret_cast<uint4*>(f.emit_tmp), &out, s);
 }
 
 hipError_t launch_sort(const ss_pairs& p, int buf, uint64_t n, int bits, int* out_buf,
@@ -401,7 +410,7 @@ hipError_t launch_sort(const ss_pairs& p, int buf, uint64_t n, int bits, int* ou
         return hipSuccess;
     }
     return radix_sort<uint32_t>(keys, vals, buf, n, n, bits, p.sort_tmp, false, false, true,
-                                nullptr, nullptr, out_buf, s);
+                                nullptr, nullptr, nullptr, out_buf, s);
 }
 
 hipError_t launch_ranges(const uint32_t* keys, uint64_t n, int n_tiles, uint32_t* ranges,

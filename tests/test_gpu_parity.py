@@ -194,10 +194,13 @@ def test_depth_order_random_keys(ss, gpu_device, n):
     keys = rng.integers(0x3e4ccccd, 0x3e4ccccd + 20000, size=n).astype(np.uint32)
     keys[rng.random(n) < 0.2] = np.uint32(0xFFFFFFFF)
     counts = rng.integers(0, 50, size=n).astype(np.uint32)
+    # tile sets: arbitrary mask and origin words, the count in word 3
+    sets = rng.integers(0, 2**32, size=(n, 4), dtype=np.uint64).astype(np.uint32)
+    sets[:, 3] = counts
     f = ss.Frame(n, 16, 16, gpu_device, stats=False)
     if n:
         f.depth_keys[:n].copy_(torch.from_numpy(keys.view(np.int32)))
-        f.counts.copy_(torch.from_numpy(counts.view(np.int32)))
+        f.tile_sets.copy_(torch.from_numpy(sets.view(np.int32)).reshape(f.tile_sets.shape))
     r = ss.Renderer(gpu_device)
     nv = int((keys != np.uint32(0xFFFFFFFF)).sum())
     got = u32(r.depth_order(f, nv))
@@ -205,6 +208,8 @@ def test_depth_order_random_keys(ss, gpu_device, n):
     want = np.argsort(keys, kind="stable").astype(np.uint32)[:nv]   # all-ones keys dropped
     assert np.array_equal(got, want)
     assert np.array_equal(u32(f.order_counts[:nv]), counts[want])
+    # the tile sets in depth order, left at the start of the emit scratch
+    assert np.array_equal(u32(f.emit_tmp[:4 * nv]).reshape(nv, 4), sets[want])
 
 
 @pytest.mark.parametrize("n", [0, 1, 2, 4095, 4097, 70_001, 5_000_003])
