@@ -27,9 +27,24 @@ namespace {
 
 constexpr int kBatch = 64;
 
-__device__ __forceinline__ float wave_sum(float x) {
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) x += __shfl_xor(x, m, 64);
+// x + (x of the lane the DPP control names); rows outside ROWS add 0.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ float dpp_add(float x) {
+    return x + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROWS, 0xf,
+                                                          false));
+}
+
+// Sum over the wave, complete in lane 63, with DPP row operations (VALU, no
+// LDS traffic): quad sums, 8-lane sums (row_half_mirror), 16-lane row sums
+// (row_mirror), then row 0 into row 1 and row 2 into row 3 (row_bcast:15),
+// then rows 0-1 into row 3 (row_bcast:31).
+__device__ __forceinline__ float wave_sum63(float x) {
+    x = dpp_add<0xB1, 0xf>(x);    // quad_perm [1, 0, 3, 2]
+    x = dpp_add<0x4E, 0xf>(x);    // quad_perm [2, 3, 0, 1]
+    x = dpp_add<0x141, 0xf>(x);   // row_half_mirror
+    x = dpp_add<0x140, 0xf>(x);   // row_mirror
+    x = dpp_add<0x142, 0xa>(x);   // row_bcast:15 into rows 1 and 3
+    x = dpp_add<0x143, 0xc>(x);   // row_bcast:31 into rows 2 and 3
     return x;
 }
 
@@ -170,11 +185,11 @@ __global__ __launch_bounds__(64 * (4 / SPW)) void k_blend_bwd(
                 }
             }
             if (__ballot(any) == 0ull) continue;
-            gu = wave_sum(gu); gv = wave_sum(gv); ga = wave_sum(ga); gb = wave_sum(gb);
-            gc = wave_sum(gc); gs = wave_sum(gs); gr = wave_sum(gr); gg = wave_sum(gg);
-            gbl = wave_sum(gbl);
-            if (score) sc = wave_sum(sc);
-            if (lane == 0) {
+            gu = wave_sum63(gu); gv = wave_sum63(gv); ga = wave_sum63(ga);
+            gb = wave_sum63(gb); gc = wave_sum63(gc); gs = wave_sum63(gs);
+            gr = wave_sum63(gr); gg = wave_sum63(gg); gbl = wave_sum63(gbl);
+            if (score) sc = wave_sum63(sc);
+            if (lane == 63) {
                 float* o = g2d + (size_t)s_idx[w][k] * 12;
                 atomicAdd(o + 0, gu);
                 atomicAdd(o + 1, gv);

@@ -318,10 +318,12 @@ __device__ __forceinline__ float4 colour_of(float cr, float cg, float cb) {
 // lane q of the four loads coefficients 4q .. 4q + 3 (three 16-byte loads,
 // consecutive lanes on consecutive addresses, so a load instruction of the
 // wave touches 16 rows' lines rather than 64) and sums their terms; two lane
-// exchanges add the four partial sums.  No LDS.
-constexpr int kColourPer = kBlock / 4;     // Gaussians per workgroup
+// exchanges add the four partial sums.  No LDS.  Workgroups of 256 lanes (64
+// Gaussians), so the grid has no more workgroups than the other kernels.
+constexpr int kColourBlock = 256;
+constexpr int kColourPer = kColourBlock / 4;     // Gaussians per workgroup
 
-__global__ __launch_bounds__(kBlock) void k_colour_rows(const Item* __restrict__ items,
+__global__ __launch_bounds__(kColourBlock) void k_colour_rows(const Item* __restrict__ items,
                                                         BatchDims dims,
                                                         const uint32_t* __restrict__ counts,
                                                         float4* __restrict__ rgb_out) {
@@ -477,8 +479,8 @@ hipError_t launch_preprocess(const Item* items, const BatchDims& d, int mode, co
                            reinterpret_cast<uint4*>(f.tile_sets), f.emit_tmp);
         if (sh_rows16) {
             const int64_t cgrid = (d.n_slots + kColourPer - 1) / kColourPer;
-            hipLaunchKernelGGL(k_colour_rows, dim3((unsigned)cgrid), dim3(kBlock), 0, s, items, d,
-                               f.counts, reinterpret_cast<float4*>(f.rgb));
+            hipLaunchKernelGGL(k_colour_rows, dim3((unsigned)cgrid), dim3(kColourBlock), 0, s,
+                               items, d, f.counts, reinterpret_cast<float4*>(f.rgb));
         } else {
             hipLaunchKernelGGL(k_colour, dim3((unsigned)grid), dim3(kBlock), 0, s, items, d,
                                f.counts, reinterpret_cast<float4*>(f.rgb));
