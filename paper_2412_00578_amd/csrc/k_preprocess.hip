@@ -355,7 +355,11 @@ __global__ __launch_bounds__(kColourBlock) void k_colour_rows(const Item* __rest
 #pragma unroll
         for (int mm = 0; mm < 4; ++mm) {
             // coefficient 4q + mm of this lane's four
-            const float y = q == 0 ? Y[mm] : q == 1 ? Y[4 + mm] : q == 2 ? Y[8 + mm] : Y[12 + mm];
+            // selected with compares, not an index (which would put Y in scratch)
+            float y = Y[mm];
+            y = q == 1 ? Y[4 + mm] : y;
+            y = q == 2 ? Y[8 + mm] : y;
+            y = q == 3 ? Y[12 + mm] : y;
             if (4 * q + mm < nb) {
                 cr = fmaf(y, h[3 * mm], cr);
                 cg = fmaf(y, h[3 * mm + 1], cg);
