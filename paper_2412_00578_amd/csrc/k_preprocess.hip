@@ -314,67 +314,48 @@ __device__ __forceinline__ float4 colour_of(float cr, float cg, float cb) {
 
 // View-dependent colour from SH (FP32), for the Gaussians with tiles (the
 // others get rgb = 0), when every SH row starts 16-byte aligned (a row of a
-// multiple of 4 floats from an aligned base).  Four lanes share a Gaussian:
-// lane q of the four loads coefficients 4q .. 4q + 3 (three 16-byte loads,
-// consecutive lanes on consecutive addresses, so a load instruction of the
-// wave touches 16 rows' lines rather than 64) and sums their terms; two lane
-// exchanges add the four partial sums.  No LDS.  Workgroups of 256 lanes (64
-// Gaussians), so the grid has no more workgroups than the other kernels.
-constexpr int kColourBlock = 256;
-constexpr int kColourPer = kColourBlock / 4;     // Gaussians per workgroup
-
-__global__ __launch_bounds__(kColourBlock) void k_colour_rows(const Item* __restrict__ items,
+// multiple of 4 floats from an aligned base): each lane loads its own row
+// with up to 12 16-byte loads, all issued before the first use, and keeps it
+// in registers.  No LDS, so the kernel runs at the occupancy its registers
+// allow; a row's 1.5 cache lines are read once.
+__global__ __launch_bounds__(kBlock) void k_colour_rows(const Item* __restrict__ items,
                                                         BatchDims dims,
                                                         const uint32_t* __restrict__ counts,
                                                         float4* __restrict__ rgb_out) {
-    const int64_t slot0 = (int64_t)blockIdx.x * kColourPer;
+    const int64_t slot0 = (int64_t)blockIdx.x * kBlock;
     const Item& it = items[dims.n_items == 1 ? 0 : item_of_slot(items, dims.n_items, slot0)];
-    const int q = (int)(threadIdx.x & 3u);
-    const int64_t o = slot0 + (threadIdx.x >> 2);
-    const int64_t i = o - it.g_off;
-    const bool in = o < dims.n_slots;
-    const bool vis = in && i < it.n && counts[o] > 0u;
+    const int64_t i = slot0 - it.g_off + threadIdx.x;
+    const int64_t o = slot0 + threadIdx.x;
+    if (o >= dims.n_slots) return;
+    if (i >= it.n || counts[o] == 0u) {
+        rgb_out[o] = make_float4(0.f, 0.f, 0.f, 0.f);
+        return;
+    }
     const int nb = (it.sh_degree + 1) * (it.sh_degree + 1);
-    float4 v[3];
+    const int q = (3 * nb + 3) / 4;                   // 16-byte pieces holding the nb coefficients
+    const float4* src = reinterpret_cast<const float4*>(it.sh + i * (3 * (int64_t)it.sh_stride));
+    float4 v[12];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) v[k] = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (vis) {
-        const float4* src =
-            reinterpret_cast<const float4*>(it.sh + i * (3 * (int64_t)it.sh_stride)) + 3 * q;
+    for (int j = 0; j < 12; ++j)
+        v[j] = j < q ? ld_global(src + j) : make_float4(0.f, 0.f, 0.f, 0.f);
+    float Y[16];
+    sh_basis(it.cam, ld_global(it.means + 3 * i), ld_global(it.means + 3 * i + 1),
+             ld_global(it.means + 3 * i + 2), it.sh_degree, Y);
+    float h[48];
 #pragma unroll
-        for (int k = 0; k < 3; ++k)
-            if (12 * q + 4 * k < 3 * nb) v[k] = ld_global(src + k);
+    for (int j = 0; j < 12; ++j) {
+        h[4 * j] = v[j].x; h[4 * j + 1] = v[j].y; h[4 * j + 2] = v[j].z; h[4 * j + 3] = v[j].w;
     }
     float cr = 0.f, cg = 0.f, cbl = 0.f;
-    if (vis) {
-        float Y[16];
-        sh_basis(it.cam, ld_global(it.means + 3 * i), ld_global(it.means + 3 * i + 1),
-                 ld_global(it.means + 3 * i + 2), it.sh_degree, Y);
-        const float h[12] = {v[0].x, v[0].y, v[0].z, v[0].w, v[1].x, v[1].y,
-                             v[1].z, v[1].w, v[2].x, v[2].y, v[2].z, v[2].w};
 #pragma unroll
-        for (int mm = 0; mm < 4; ++mm) {
-            // coefficient 4q + mm of this lane's four
-            // selected with compares, not an index (which would put Y in scratch)
-            float y = Y[mm];
-            y = q == 1 ? Y[4 + mm] : y;
-            y = q == 2 ? Y[8 + mm] : y;
-            y = q == 3 ? Y[12 + mm] : y;
-            if (4 * q + mm < nb) {
-                cr = fmaf(y, h[3 * mm], cr);
-                cg = fmaf(y, h[3 * mm + 1], cg);
-                cbl = fmaf(y, h[3 * mm + 2], cbl);
-            }
+    for (int k = 0; k < 16; ++k) {
+        if (k < nb) {
+            cr = fmaf(Y[k], h[3 * k], cr);
+            cg = fmaf(Y[k], h[3 * k + 1], cg);
+            cbl = fmaf(Y[k], h[3 * k + 2], cbl);
         }
     }
-#pragma unroll
-    for (int d = 1; d <= 2; d <<= 1) {
-        cr += __shfl_xor(cr, d, 64);
-        cg += __shfl_xor(cg, d, 64);
-        cbl += __shfl_xor(cbl, d, 64);
-    }
-    if (in && q == 0)
-        rgb_out[o] = vis ? colour_of(cr, cg, cbl) : make_float4(0.f, 0.f, 0.f, 0.f);
+    rgb_out[o] = colour_of(cr, cg, cbl);
 }
 
 // The same for any row layout: one wave per workgroup stages the SH rows of
@@ -405,24 +386,13 @@ __global__ __launch_bounds__(kBlock) void k_colour(const Item* __restrict__ item
     sh_basis(it.cam, ld_global(it.means + 3 * i), ld_global(it.means + 3 * i + 1),
              ld_global(it.means + 3 * i + 2), it.sh_degree, Y);
     const float* h = s_sh + threadIdx.x * kShPitch;
-    // the same sums, in the same order, as k_colour_rows: an FMA chain over
-    // each group of four coefficients, then (g0 + g1) + (g2 + g3)
-    float pr[4], pg[4], pb[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        pr[q] = pg[q] = pb[q] = 0.f;
-#pragma unroll
-        for (int mm = 0; mm < 4; ++mm) {
-            const int k = 4 * q + mm;
-            if (k < nb) {
-                pr[q] = fmaf(Y[k], h[3 * k], pr[q]);
-                pg[q] = fmaf(Y[k], h[3 * k + 1], pg[q]);
-                pb[q] = fmaf(Y[k], h[3 * k + 2], pb[q]);
-            }
-        }
+    float cr = 0.f, cg = 0.f, cbl = 0.f;
+    for (int k = 0; k < nb; ++k) {
+        cr = fmaf(Y[k], h[3 * k], cr);
+        cg = fmaf(Y[k], h[3 * k + 1], cg);
+        cbl = fmaf(Y[k], h[3 * k + 2], cbl);
     }
-    rgb_out[o] = colour_of((pr[0] + pr[1]) + (pr[2] + pr[3]), (pg[0] + pg[1]) + (pg[2] + pg[3]),
-                           (pb[0] + pb[1]) + (pb[2] + pb[3]));
+    rgb_out[o] = colour_of(cr, cg, cbl);
 }
 
 // One workgroup: totals = (sum of the pair-count partials, sum of the
@@ -481,14 +451,9 @@ hipError_t launch_preprocess(const Item* items, const BatchDims& d, int mode, co
                            mode, reinterpret_cast<float4*>(f.geom),
                            reinterpret_cast<float4*>(f.conic), f.counts, f.depth_keys,
                            reinterpret_cast<uint4*>(f.tile_sets), f.emit_tmp);
-        if (sh_rows16) {
-            const int64_t cgrid = (d.n_slots + kColourPer - 1) / kColourPer;
-            hipLaunchKernelGGL(k_colour_rows, dim3((unsigned)cgrid), dim3(kColourBlock), 0, s,
-                               items, d, f.counts, reinterpret_cast<float4*>(f.rgb));
-        } else {
-            hipLaunchKernelGGL(k_colour, dim3((unsigned)grid), dim3(kBlock), 0, s, items, d,
-                               f.counts, reinterpret_cast<float4*>(f.rgb));
-        }
+        hipLaunchKernelGGL(sh_rows16 ? k_colour_rows : k_colour, dim3((unsigned)grid),
+                           dim3(kBlock), 0, s, items, d, f.counts,
+                           reinterpret_cast<float4*>(f.rgb));
     }
     hipLaunchKernelGGL(k_totals, dim3(1), dim3(1024), 0, s, f.emit_tmp, grid, f.totals);
     return hipGetLastError();
