@@ -16,7 +16,7 @@
 //   dscan    256 workgroups, one per digit: exclusive scan of that digit's
 //            per-workgroup counts, and the digit's total
 //   scatter  workgroup b turns the digit totals into digit starts, re-reads its
-//            chunk in 4096-key (or, for short sorts, 1024-key) sub-tiles, ranks
+//            chunk in 2048-key (or, for short sorts, 1024-key) sub-tiles, ranks
 //            each key stably (each wave
 //            matches 64 digits at a time with 8 ballots; per-wave running
 //            counts live in LDS), reorders the sub-tile by digit in LDS and
@@ -29,7 +29,7 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / 64;
-constexpr int kItemsLarge = 16;               // keys per lane per sub-tile: 4096 keys
+constexpr int kItemsLarge = 8;                // keys per lane per sub-tile: 2048 keys
 constexpr int kItemsSmall = 4;                // 1024 keys, for sorts of < 2M keys
 constexpr int kRadix = 256;
 constexpr int kMaxGrid = 1024;
@@ -40,8 +40,9 @@ struct Plan {
     int items;            // keys per lane per sub-tile
 };
 
-// Sub-tiles of 4096 keys, or of 1024 when that leaves fewer than 512
-// workgroups (a CU would otherwise sit idle or walk one long chunk).
+// Sub-tiles of 2048 keys, or of 1024 for short sorts (fewer than 512 x 4096
+// keys), where larger sub-tiles would leave CUs idle or one workgroup walking
+// a long chunk.
 Plan make_plan(uint64_t n) {
     const int items = (n + 4095) / 4096 < 512 ? kItemsSmall : kItemsLarge;
     const uint64_t kSub = (uint64_t)kBlock * items;
