@@ -30,7 +30,7 @@ namespace {
 constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / 64;
 constexpr int kItemsLarge = 8;                // keys per lane per sub-tile: 2048 keys
-constexpr int kItemsSmall = 4;                // 1024 keys, for sorts of < 2M keys
+constexpr int kItemsSmall = 4;                // 1024 keys, for sorts of < 512k keys
 constexpr int kRadix = 256;
 constexpr int kMaxGrid = 1024;
 
@@ -40,11 +40,10 @@ struct Plan {
     int items;            // keys per lane per sub-tile
 };
 
-// Sub-tiles of 2048 keys, or of 1024 for short sorts (fewer than 512 x 4096
-// keys), where larger sub-tiles would leave CUs idle or one workgroup walking
-// a long chunk.
+// Sub-tiles of 2048 keys, or of 1024 for short sorts (fewer than 128 x 4096
+// keys), where larger sub-tiles would leave CUs idle.
 Plan make_plan(uint64_t n) {
-    const int items = (n + 4095) / 4096 < 512 ? kItemsSmall : kItemsLarge;
+    const int items = (n + 4095) / 4096 < 128 ? kItemsSmall : kItemsLarge;
     const uint64_t kSub = (uint64_t)kBlock * items;
     const uint64_t subs = (n + kSub - 1) / kSub;
     uint64_t g = subs < (uint64_t)kMaxGrid ? subs : (uint64_t)kMaxGrid;
