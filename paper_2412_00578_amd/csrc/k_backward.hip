@@ -284,18 +284,20 @@ constexpr int kShRow = 48;                 // SH floats per Gaussian staged (deg
 constexpr int kShPitchB = kShRow + 1;      // odd LDS pitch
 
 // Stage 8.  One lane per Gaussian, one wave per workgroup.  The SH part runs
-// in FP32 (the forward colour is FP32): the workgroup's SH rows are staged
+// in FP32 (the forward colour is FP32).  ROWS (every SH row 16-byte aligned):
+// a lane whose colour passes a gradient loads its own row into registers with
+// up to 12 16-byte loads and writes dL/dh back the same way; the others read
+// nothing and write zeros.  Otherwise the workgroup's SH rows are staged
 // through LDS with coalesced loads, each lane overwrites its row in place with
 // dL/dh, and the rows are written back coalesced.  The geometry chain is FP64.
+template <bool ROWS>
 __global__ __launch_bounds__(kPbBlock) void k_preprocess_bwd(ss_camera cam, BwdIn in, int64_t n,
                                                             const float4* __restrict__ conic_rec,
                                                             const float4* __restrict__ rgb_rec,
                                                             const float* __restrict__ g2d,
                                                             BwdOut out) {
-    __shared__ float s_h[kPbBlock * kShPitchB];
     const int64_t first = (int64_t)blockIdx.x * kPbBlock;
     const int64_t i = first + threadIdx.x;
-    const int cnt = n - first < kPbBlock ? (int)(n - first) : kPbBlock;
     const int nb = (in.sh_degree + 1) * (in.sh_degree + 1);
     const int need = 3 * nb, row = 3 * in.sh_stride;
     const bool real = i < n;
@@ -309,11 +311,6 @@ __global__ __launch_bounds__(kPbBlock) void k_preprocess_bwd(ss_camera cam, BwdI
     const float gs2 = alive && col.z > 0.0f ? G[10] : 0.0f;
 
     // ---- colour -> SH and view direction (FP32)
-    for (int e = threadIdx.x; e < cnt * need; e += kPbBlock) {
-        const int g = e / need, j = e - g * need;
-        s_h[g * kShPitchB + j] = in.sh[(first + g) * row + j];
-    }
-    __syncthreads();
     float gdx = 0.0f, gdy = 0.0f, gdz = 0.0f, dirx = 0.0f, diry = 0.0f, dirz = 0.0f, len = 1.0f;
     if (real) {
         const float cpx = -((cam.R[0] * cam.t[0] + cam.R[3] * cam.t[1]) + cam.R[6] * cam.t[2]);
@@ -323,26 +320,81 @@ __global__ __launch_bounds__(kPbBlock) void k_preprocess_bwd(ss_camera cam, BwdI
                     dvz = in.means[3 * i + 2] - cpz;
         len = sqrtf(dvx * dvx + dvy * dvy + dvz * dvz);
         dirx = dvx / len; diry = dvy / len; dirz = dvz / len;
-        float* h = s_h + threadIdx.x * kShPitchB;
+    }
+    if constexpr (ROWS) {
+        const int q = (need + 3) / 4;            // 16-byte pieces holding the coefficients
+        const bool grad = real && (gs0 != 0.0f || gs1 != 0.0f || gs2 != 0.0f);
+        float h[48];
 #pragma unroll
-        for (int k = 0; k < 16; ++k) {
-            if (k < nb) {
-                float Y, tx, ty, tz;
-                sh_term(k, dirx, diry, dirz, Y, tx, ty, tz);
-                const float gy = (h[3 * k] * gs0 + h[3 * k + 1] * gs1) + h[3 * k + 2] * gs2;
-                gdx = fmaf(gy, tx, gdx);
-                gdy = fmaf(gy, ty, gdy);
-                gdz = fmaf(gy, tz, gdz);
-                h[3 * k] = Y * gs0;            // dL/dh replaces h in this lane's own row
-                h[3 * k + 1] = Y * gs1;
-                h[3 * k + 2] = Y * gs2;
+        for (int k = 0; k < 48; ++k) h[k] = 0.0f;
+        if (grad) {
+            const float4* src = reinterpret_cast<const float4*>(in.sh + i * row);
+            float4 v[12];
+#pragma unroll
+            for (int j = 0; j < 12; ++j) v[j] = j < q ? src[j] : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+            for (int j = 0; j < 12; ++j) {
+                h[4 * j] = v[j].x; h[4 * j + 1] = v[j].y; h[4 * j + 2] = v[j].z;
+                h[4 * j + 3] = v[j].w;
+            }
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                if (k < nb) {
+                    float Y, tx, ty, tz;
+                    sh_term(k, dirx, diry, dirz, Y, tx, ty, tz);
+                    const float gy = (h[3 * k] * gs0 + h[3 * k + 1] * gs1) + h[3 * k + 2] * gs2;
+                    gdx = fmaf(gy, tx, gdx);
+                    gdy = fmaf(gy, ty, gdy);
+                    gdz = fmaf(gy, tz, gdz);
+                    h[3 * k] = Y * gs0;
+                    h[3 * k + 1] = Y * gs1;
+                    h[3 * k + 2] = Y * gs2;
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < 48; ++k)
+                if (k >= need) h[k] = 0.0f;          // the row's floats past the coefficients
+        }
+        if (real) {
+            float4* dst = reinterpret_cast<float4*>(out.sh + i * row);
+#pragma unroll
+            for (int j = 0; j < 12; ++j)
+                if (4 * j < row)
+                    dst[j] = make_float4(h[4 * j], h[4 * j + 1], h[4 * j + 2], h[4 * j + 3]);
+            for (int j = 12; 4 * j < row; ++j) dst[j] = make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+    } else {
+        __shared__ float s_h[kPbBlock * kShPitchB];
+        const int cnt = n - first < kPbBlock ? (int)(n - first) : kPbBlock;
+        for (int e = threadIdx.x; e < cnt * need; e += kPbBlock) {
+            const int g = e / need, j = e - g * need;
+            s_h[g * kShPitchB + j] = in.sh[(first + g) * row + j];
+        }
+        __syncthreads();
+        float* h = s_h + threadIdx.x * kShPitchB;
+        if (real && !(gs0 != 0.0f || gs1 != 0.0f || gs2 != 0.0f)) {
+            for (int k = 0; k < need; ++k) h[k] = 0.0f;   // no colour gradient: dL/dh = 0
+        } else if (real) {
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                if (k < nb) {
+                    float Y, tx, ty, tz;
+                    sh_term(k, dirx, diry, dirz, Y, tx, ty, tz);
+                    const float gy = (h[3 * k] * gs0 + h[3 * k + 1] * gs1) + h[3 * k + 2] * gs2;
+                    gdx = fmaf(gy, tx, gdx);
+                    gdy = fmaf(gy, ty, gdy);
+                    gdz = fmaf(gy, tz, gdz);
+                    h[3 * k] = Y * gs0;            // dL/dh replaces h in this lane's own row
+                    h[3 * k + 1] = Y * gs1;
+                    h[3 * k + 2] = Y * gs2;
+                }
             }
         }
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < cnt * row; e += kPbBlock) {
-        const int g = e / row, j = e - g * row;
-        out.sh[(first + g) * row + j] = j < need ? s_h[g * kShPitchB + j] : 0.0f;
+        __syncthreads();
+        for (int e = threadIdx.x; e < cnt * row; e += kPbBlock) {
+            const int g = e / row, j = e - g * row;
+            out.sh[(first + g) * row + j] = j < need ? s_h[g * kShPitchB + j] : 0.0f;
+        }
     }
     if (!real) return;
     if (!alive) {
@@ -521,7 +573,10 @@ hipError_t launch_backward(const ss_camera& cam, const ss_gaussians& g, const ss
     if (g.n > 0) {
         BwdIn in{g.means, g.scales, g.quats, g.opacity, g.sh, g.sh_degree, g.sh_stride};
         BwdOut o{out.means, out.scales, out.quats, out.opacity, out.sh};
-        hipLaunchKernelGGL(k_preprocess_bwd, dim3((unsigned)((g.n + kPbBlock - 1) / kPbBlock)),
+        const bool rows = ((uintptr_t)g.sh & 15u) == 0 && ((3 * g.sh_stride) & 3) == 0 &&
+                          g.sh_stride <= 16;
+        hipLaunchKernelGGL(rows ? k_preprocess_bwd<true> : k_preprocess_bwd<false>,
+                           dim3((unsigned)((g.n + kPbBlock - 1) / kPbBlock)),
                            dim3(kPbBlock), 0, s, cam, in, g.n,
                            reinterpret_cast<const float4*>(f.conic),
                            reinterpret_cast<const float4*>(f.rgb), out.g2d, o);
