@@ -157,9 +157,7 @@ __global__ __launch_bounds__(64 * (4 / SPW)) void k_blend_bwd(
                     const float gval = __expf(-0.5f * qq);
                     const float araw = q.w * gval;
                     const float al = fminf(kAlphaMax, araw);
-                    // the hardware reciprocal (about 1 ulp) instead of a correctly
-                    // rounded division: the gradients carry a 1e-4 tolerance
-                    const float tb = T[s] * __builtin_amdgcn_rcpf(1.0f - al);
+                    const float tb = T[s] / (1.0f - al);
                     const float wgt = al * tb;
                     gr = fmaf(wgt, dC[s][0], gr);
                     gg = fmaf(wgt, dC[s][1], gg);
