@@ -73,6 +73,27 @@ def test_backward_matches_oracle_small(ss, gpu_device):
     _compare(got, want)
 
 
+def test_backward_sh_rows_of_odd_length(ss, gpu_device):
+    # 17 stored coefficients per Gaussian (51-float rows): the preprocess
+    # adjoint stages SH through LDS; the padding coefficient gets no gradient.
+    import dataclasses
+    sc, cam = scenegen.scene_c3_fd(), scenegen.camera_fd()
+    pad = np.full((sc.n, 1, 3), 0.7, np.float32)
+    sc = dataclasses.replace(sc, sh=np.ascontiguousarray(np.concatenate([sc.sh, pad], axis=1)))
+    fr = oracle.render(sc, cam, "accutile")
+    w = _weights(cam, fr, 6)
+    pix = oracle.all_pixels(cam)
+    want = _oracle_grad_linear(sc, cam, pix, w.reshape(3, -1).T, fr)
+    g = ss.Gaussians.from_scene(sc, gpu_device)
+    out = ss.Renderer(gpu_device).render(g, cam, "accutile", full=True)
+    gr = ss.backward(g, cam, out, torch.as_tensor(w, dtype=torch.float32, device=gpu_device))
+    torch.cuda.synchronize()
+    got = {k: getattr(gr, k).cpu().numpy() for k in GROUPS}
+    got["opacity"] = got["opacity"].reshape(-1)
+    assert np.all(got["sh"][:, 16, :] == 0.0)
+    _compare(got, want)
+
+
 def test_autograd_function_l1_loss(ss, gpu_device):
     # torch autograd through the activations: scales = exp(log_s), opacity = sigmoid(logit).
     sc, cam = scenegen.scene_c3_fd(), scenegen.camera_fd()

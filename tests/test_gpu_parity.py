@@ -73,6 +73,19 @@ def test_odd_sizes_and_sh_degrees(ss, gpu_device):
             assert_pipeline_equal(gpu, oracle.render(sc, cam, mode))
 
 
+def test_sh_rows_of_odd_length(ss, gpu_device):
+    # SH degree 3 stored with 17 coefficients per Gaussian: 51-float rows are
+    # not 16-byte aligned, so the colour takes the LDS-staged path.
+    import dataclasses
+    cam = scenegen.Camera(200, 120, 180.0, 180.0, 100.0, 60.0, np.eye(3), np.zeros(3))
+    sc = scenegen.scene_c0(n=5000, seed=41, sh_degree=3, log_s=(-3.0, 0.8))
+    pad = np.zeros((sc.n, 1, 3), np.float32) + np.float32(0.7)   # never read (degree 3)
+    sc = dataclasses.replace(sc, sh=np.ascontiguousarray(np.concatenate([sc.sh, pad], axis=1)))
+    for mode in MODES:
+        gpu = _run(ss, gpu_device, sc, cam, mode)
+        assert_pipeline_equal(gpu, oracle.render(sc, cam, mode))
+
+
 def test_degenerate_fixtures(ss, gpu_device):
     # near plane, behind the camera, non-finite, zero quaternion, sigma < 1/255,
     # a huge screen-filling Gaussian, Gaussians straddling the image edges.
