@@ -7,16 +7,19 @@
 // a strip's included-pixel work is skipped as a unit when none of its 64
 // pixels lies inside the ellipse.  The tile's sorted Gaussians are staged
 // through LDS 64 at a time (one gathered record per lane); the next batch's
-// records are loaded into registers while the current batch is blended.
+// records are loaded into registers while the current batch is blended.  A
+// batch is walked in fully unrolled groups of 8 entries, the last group padded
+// with records that include no pixel, so loop control is paid once per group.
 //
 // A pixel that has finished (the next Gaussian would take its transmittance
 // below 1e-4) moves its sample row to y = 1e30, so its q <= t test fails from
-// then on; every 8 Gaussians a ballot per strip marks strips whose 64 pixels
-// have all finished, which then skip their work, and the wave stops once
-// every pixel has finished.  The quadratic form is evaluated with two fused
-// multiply-adds as q = fma(dy, fma(c, dy, (2b) dx), (a dx) dx) and compared
-// with the record's t, so the inclusion test (alpha >= 1/255) is exact and
-// reproducible.  An included strip takes a short path when none of its
+// then on, and after every group a ballot stops the wave once every pixel has
+// finished.  Strips are not tested for liveness one by one: the scalar test
+// and branch per strip and Gaussian cost more issue slots than the four
+// vector operations a finished strip's failing q <= t test takes.  The
+// quadratic form is evaluated with two fused multiply-adds as
+// q = fma(dy, fma(c, dy, (2b) dx), (a dx) dx) and compared with the record's
+// t, so the inclusion test (alpha >= 1/255) is exact and reproducible.  An included strip takes a short path when none of its
 // pixels stops at this Gaussian (wave-uniform test) and the full path, which
 // freezes the stopping pixels, otherwise.  Nothing on this path is a dense
 // contraction, so it runs on the FP32 VALU.
@@ -34,6 +37,10 @@ struct Rec {
     float4 q;   // (a, 2b, c, sigma)
     float4 c;   // (r, g, b, -)
 };
+
+__device__ __forceinline__ bool unfinished(const float (&fy)[4]) {
+    return fy[0] < kDone || fy[1] < kDone || fy[2] < kDone || fy[3] < kDone;
+}
 
 __device__ __forceinline__ Rec make_rec0() {
     Rec r;
@@ -228,9 +235,7 @@ __global__ __launch_bounds__(64) void k_blend(const Item* __restrict__ items, Ba
         stop[s] = 0u;
         ncon[s] = 0u;
     }
-    uint32_t sl = 0;                              // bit s: strip s has an unfinished pixel
-#pragma unroll
-    for (int s = 0; s < 4; ++s) sl |= (__ballot(fy[s] < kDone) != 0ull ? 1u : 0u) << s;
+    bool live = __ballot(unfinished(fy)) != 0ull;  // some pixel of the tile is unfinished
     const uint32_t start = ranges[2 * tile], end = ranges[2 * tile + 1];
     // Batch b's records are fetched during batch b - 1 and their list entries
     // during batch b - 2, so neither load stalls a batch.  Entries past the
@@ -242,58 +247,64 @@ __global__ __launch_bounds__(64) void k_blend(const Item* __restrict__ items, Ba
         nxt = load_rec(geom, conic, rgb, entry_gid(values, start + lane, e_last));
         gid_nx = entry_gid(values, start + kBatch + lane, e_last);
     }
-    for (uint32_t base = start; base < end && sl; base += kBatch) {
-        s_geo[lane] = nxt.g;
-        s_con[lane] = make_float4(nxt.q.x, 2.0f * nxt.q.y, nxt.q.z, nxt.q.w);
+    for (uint32_t base = start; base < end && live; base += kBatch) {
+        // slots past the list end hold a record whose q is 0 at every pixel
+        // and whose t is -1, so it includes no pixel
+        const bool real = base + (uint32_t)lane < end;
+        s_geo[lane] = real ? nxt.g : make_float4(0.0f, 0.0f, 0.0f, -1.0f);
+        s_con[lane] = real ? make_float4(nxt.q.x, 2.0f * nxt.q.y, nxt.q.z, nxt.q.w)
+                           : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         s_col[lane] = nxt.c;
         __syncthreads();
         nxt = load_rec(geom, conic, rgb, gid_nx);
         gid_nx = entry_gid(values, base + 2 * kBatch + lane, e_last);
         const uint32_t nb = end - base < (uint32_t)kBatch ? end - base : (uint32_t)kBatch;
 
-        for (uint32_t k = 0; k < nb; ++k) {
-            const float4 g = s_geo[k];
-            const float4 q = s_con[k];
-            const float4 c = s_col[k];
-            const float dx = fx - g.x;
-            const float adx2 = (q.x * dx) * dx;
-            const float b2dx = q.y * dx;
-            const uint32_t pos = base + k - start + 1u;
+        // groups of 8 entries, the last one padded; the tile stops once every
+        // pixel has finished
+        const uint32_t nb8 = (nb + 7u) & ~7u;
+        for (uint32_t k0 = 0; k0 < nb8; k0 += 8u) {
 #pragma unroll
-            for (int s = 0; s < 4; ++s) {
-                if (!(sl & (1u << s))) continue;      // wave-uniform
-                const float dy = fy[s] - g.y;
-                const float qq = fmaf(dy, fmaf(q.z, dy, b2dx), adx2);
-                if (qq <= g.w) {
-                    const float al = fminf(kAlphaMax, q.w * __builtin_amdgcn_exp2f(qq * kNegHalfLog2e));
-                    float tn = T[s] * (1.0f - al);
-                    float wgt = al * T[s];
-                    uint32_t lp = pos;
-                    uint32_t blended = 1u;
-                    if (__ballot(tn < kTMin) != 0ull) {   // some included pixel stops here
-                        const bool ok = tn >= kTMin;
-                        wgt = ok ? wgt : 0.0f;
-                        tn = ok ? tn : T[s];
-                        lp = ok ? pos : last[s];
-                        fy[s] = ok ? fy[s] : kDone;
-                        if (STATS) stop[s] = ok ? stop[s] : pos;
-                        blended = ok ? 1u : 0u;
+            for (uint32_t u = 0; u < 8u; ++u) {
+                const uint32_t k = k0 + u;
+                const float4 g = s_geo[k];
+                const float4 q = s_con[k];
+                const float4 c = s_col[k];
+                const float dx = fx - g.x;
+                const float adx2 = (q.x * dx) * dx;
+                const float b2dx = q.y * dx;
+                const uint32_t pos = base + k - start + 1u;
+#pragma unroll
+                for (int s = 0; s < 4; ++s) {
+                    const float dy = fy[s] - g.y;
+                    const float qq = fmaf(dy, fmaf(q.z, dy, b2dx), adx2);
+                    if (qq <= g.w) {
+                        const float al =
+                            fminf(kAlphaMax, q.w * __builtin_amdgcn_exp2f(qq * kNegHalfLog2e));
+                        float tn = T[s] * (1.0f - al);
+                        float wgt = al * T[s];
+                        uint32_t lp = pos;
+                        uint32_t blended = 1u;
+                        if (__ballot(tn < kTMin) != 0ull) {  // an included pixel stops here
+                            const bool ok = tn >= kTMin;
+                            wgt = ok ? wgt : 0.0f;
+                            tn = ok ? tn : T[s];
+                            lp = ok ? pos : last[s];
+                            fy[s] = ok ? fy[s] : kDone;
+                            if (STATS) stop[s] = ok ? stop[s] : pos;
+                            blended = ok ? 1u : 0u;
+                        }
+                        if (STATS) ncon[s] += blended;
+                        C[s][0] = fmaf(c.x, wgt, C[s][0]);
+                        C[s][1] = fmaf(c.y, wgt, C[s][1]);
+                        C[s][2] = fmaf(c.z, wgt, C[s][2]);
+                        T[s] = tn;
+                        last[s] = lp;
                     }
-                    if (STATS) ncon[s] += blended;
-                    C[s][0] = fmaf(c.x, wgt, C[s][0]);
-                    C[s][1] = fmaf(c.y, wgt, C[s][1]);
-                    C[s][2] = fmaf(c.z, wgt, C[s][2]);
-                    T[s] = tn;
-                    last[s] = lp;
                 }
             }
-            if ((k & 7u) == 7u) {
-                uint32_t now = 0;
-#pragma unroll
-                for (int s = 0; s < 4; ++s) now |= (__ballot(fy[s] < kDone) != 0ull ? 1u : 0u) << s;
-                sl &= now;
-                if (!sl) break;
-            }
+            live = __ballot(unfinished(fy)) != 0ull;
+            if (!live) break;
         }
         __syncthreads();
     }
