@@ -27,25 +27,54 @@ namespace {
 
 constexpr int kBatch = 64;
 
-// x + (x of the lane the DPP control names); rows outside ROWS add 0.
-template <int CTRL, int ROWS>
-__device__ __forceinline__ float dpp_add(float x) {
-    return x + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROWS, 0xf,
-                                                          false));
+// The value x of the lane the DPP control names (within a row of 16 lanes).
+template <int CTRL>
+__device__ __forceinline__ float dpp_pull(float x) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xf, 0xf,
+                                                      false));
 }
 
-// Sum over the wave, complete in lane 63, with DPP row operations (VALU, no
-// LDS traffic): quad sums, 8-lane sums (row_half_mirror), 16-lane row sums
-// (row_mirror), then row 0 into row 1 and row 2 into row 3 (row_bcast:15),
-// then rows 0-1 into row 3 (row_bcast:31).
-__device__ __forceinline__ float wave_sum63(float x) {
-    x = dpp_add<0xB1, 0xf>(x);    // quad_perm [1, 0, 3, 2]
-    x = dpp_add<0x4E, 0xf>(x);    // quad_perm [2, 3, 0, 1]
-    x = dpp_add<0x141, 0xf>(x);   // row_half_mirror
-    x = dpp_add<0x140, 0xf>(x);   // row_mirror
-    x = dpp_add<0x142, 0xa>(x);   // row_bcast:15 into rows 1 and 3
-    x = dpp_add<0x143, 0xc>(x);   // row_bcast:31 into rows 2 and 3
+// One halving step of a transposing reduction: lanes pair up through the DPP
+// control CTRL, the lane whose bit is set keeps the upper half of the slots,
+// its partner the lower half, and each adds the partner's copy of the half it
+// keeps.  Slots past N are zero.
+template <int CTRL, int N>
+__device__ __forceinline__ void halve(const float (&in)[N], float (&out)[(N + 1) / 2], bool up) {
+    constexpr int H = (N + 1) / 2;
+#pragma unroll
+    for (int j = 0; j < H; ++j) {
+        const float lo = in[j];
+        const float hi = j + H < N ? in[j + H] : 0.0f;
+        out[j] = (up ? hi : lo) + dpp_pull<CTRL>(up ? lo : hi);
+    }
+}
+
+// Wave sums of 10 per-lane values with 35 vector operations instead of 10
+// separate 6-step sums.  Within each 16-lane row, four halving steps pair lane
+// i with 15 - i (row_mirror), then with its mirror inside the 8-lane half
+// (row_half_mirror), then with i ^ 2 and i ^ 1 (quad_perm): partners always
+// hold the same slots, and every step halves the slots a lane keeps, so lane
+// i ends with the row sum of one value.  Two cross-row swaps (lanes i ^ 16,
+// i ^ 32) complete the sums.  Lane l then holds the wave sum of value
+// sum10_slot(l & 15), or nothing when that is negative.
+__device__ __forceinline__ float wave_sum10(const float (&v)[10], int lane) {
+    float a[5], b[3], c[2], d[1];
+    halve<0x140, 10>(v, a, (lane & 8) != 0);   // row_mirror
+    halve<0x141, 5>(a, b, (lane & 4) != 0);    // row_half_mirror
+    halve<0x4E, 3>(b, c, (lane & 2) != 0);     // quad_perm [2, 3, 0, 1]
+    halve<0xB1, 2>(c, d, (lane & 1) != 0);     // quad_perm [1, 0, 3, 2]
+    float x = d[0];
+    x += __shfl_xor(x, 16, 64);
+    x += __shfl_xor(x, 32, 64);
     return x;
+}
+
+// The value whose sum wave_sum10 leaves in lanes with (l & 15) == r, or -1.
+__host__ __device__ constexpr int sum10_slot(int r) {
+    const int s3 = r & 1;
+    const int s2 = (r & 2) ? s3 + 2 : s3;
+    const int s1 = (r & 4) ? s2 + 3 : s2;
+    return s2 >= 3 || s1 >= 5 ? -1 : ((r & 8) ? s1 + 5 : s1);
 }
 
 __device__ __forceinline__ uint32_t wave_max_u32(uint32_t x) {
@@ -119,6 +148,10 @@ __global__ __launch_bounds__(64 * (4 / SPW)) void k_blend_bwd(
         jmax = nl[s] > jmax ? nl[s] : jmax;
     }
     jmax = wave_max_u32(jmax);
+    // the per-Gaussian sums land one per lane in lanes 0..15 (wave_sum10)
+    const int red_slot = lane < 16 ? sum10_slot(lane) : -1;
+    // g2d row offsets of (u, v, a, b, c, sigma, r, g, b): 0, 1, 4 .. 10
+    const int red_off = red_slot < 2 ? red_slot : red_slot + 2;
     const uint32_t start = ranges[2 * tile];
     for (uint32_t hi = jmax; hi > 0u;) {
         const uint32_t lo = hi > (uint32_t)kBatch ? hi - kBatch : 0u;
@@ -185,22 +218,12 @@ __global__ __launch_bounds__(64 * (4 / SPW)) void k_blend_bwd(
                 }
             }
             if (__ballot(any) == 0ull) continue;
-            gu = wave_sum63(gu); gv = wave_sum63(gv); ga = wave_sum63(ga);
-            gb = wave_sum63(gb); gc = wave_sum63(gc); gs = wave_sum63(gs);
-            gr = wave_sum63(gr); gg = wave_sum63(gg); gbl = wave_sum63(gbl);
-            if (score) sc = wave_sum63(sc);
-            if (lane == 63) {
-                float* o = g2d + (size_t)s_idx[w][k] * 12;
-                atomicAdd(o + 0, gu);
-                atomicAdd(o + 1, gv);
-                atomicAdd(o + 4, ga);
-                atomicAdd(o + 5, gb);
-                atomicAdd(o + 6, gc);
-                atomicAdd(o + 7, gs);
-                atomicAdd(o + 8, gr);
-                atomicAdd(o + 9, gg);
-                atomicAdd(o + 10, gbl);
-                if (score) atomicAdd(score + s_idx[w][k], sc);
+            const float part[10] = {gu, gv, ga, gb, gc, gs, gr, gg, gbl, sc};
+            const float tot = wave_sum10(part, lane);
+            if (red_slot >= 0) {
+                const uint32_t gi = s_idx[w][k];
+                if (red_slot < 9) atomicAdd(g2d + (size_t)gi * 12 + red_off, tot);
+                else if (score) atomicAdd(score + gi, tot);
             }
         }
         __builtin_amdgcn_wave_barrier();
