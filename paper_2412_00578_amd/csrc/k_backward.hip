@@ -107,7 +107,7 @@ __device__ __forceinline__ uint32_t strip_mask_b(float4 g, float4 q, int tx, int
     return m;
 }
 
-template <int SPW>
+template <int SPW, bool SCORE>
 __global__ __launch_bounds__(64 * (4 / SPW)) void k_blend_bwd(
     int tx_n, int n_tiles, int W, int H, float bg0, float bg1, float bg2,
     const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ values,
@@ -182,7 +182,6 @@ __global__ __launch_bounds__(64 * (4 / SPW)) void k_blend_bwd(
             bool any = false;
 #pragma unroll
             for (int s = 0; s < SPW; ++s) {
-                if (!(m & (1u << (strip0 + s)))) continue;
                 const float dy = fy[s] - g.y;
                 const float qq = fmaf(dy, fmaf(q.z, dy, b2dx), adx2);
                 if (j < nl[s] && qq <= g.w) {
@@ -201,19 +200,19 @@ __global__ __launch_bounds__(64 * (4 / SPW)) void k_blend_bwd(
                     R[s][1] = fmaf(al, c.y, (1.0f - al) * R[s][1]);
                     R[s][2] = fmaf(al, c.z, (1.0f - al) * R[s][2]);
                     T[s] = tb;
-                    if (araw < kAlphaMax) {
-                        gs = fmaf(dal, gval, gs);
-                        const float dq = -0.5f * al * dal;
-                        // q = a dx^2 + 2b dx dy + c dy^2 with dx = px - u, dy = py - v
-                        gu += dq * -(2.0f * q.x * dx + q.y * dy);
-                        gv += dq * -(q.y * dx + 2.0f * q.z * dy);
-                        ga = fmaf(dq, dx * dx, ga);
-                        gb = fmaf(dq, 2.0f * dx * dy, gb);
-                        gc = fmaf(dq, dy * dy, gc);
-                        if (score) {
-                            const float k0 = q.w * tb;
-                            sc += k0 * k0 * (e0 * e0 + e1 * e1 + e2 * e2);
-                        }
+                    // a clamped alpha passes no gradient to q and sigma
+                    const float dau = araw < kAlphaMax ? dal : 0.0f;
+                    gs = fmaf(dau, gval, gs);
+                    const float dq = -0.5f * al * dau;
+                    // q = a dx^2 + 2b dx dy + c dy^2 with dx = px - u, dy = py - v
+                    gu += dq * -(2.0f * q.x * dx + q.y * dy);
+                    gv += dq * -(q.y * dx + 2.0f * q.z * dy);
+                    ga = fmaf(dq, dx * dx, ga);
+                    gb = fmaf(dq, 2.0f * dx * dy, gb);
+                    gc = fmaf(dq, dy * dy, gc);
+                    if (SCORE) {
+                        const float k0 = araw < kAlphaMax ? q.w * tb : 0.0f;
+                        sc += k0 * k0 * (e0 * e0 + e1 * e1 + e2 * e2);
                     }
                 }
             }
@@ -223,7 +222,7 @@ __global__ __launch_bounds__(64 * (4 / SPW)) void k_blend_bwd(
             if (red_slot >= 0) {
                 const uint32_t gi = s_idx[w][k];
                 if (red_slot < 9) atomicAdd(g2d + (size_t)gi * 12 + red_off, tot);
-                else if (score) atomicAdd(score + gi, tot);
+                else if (SCORE) atomicAdd(score + gi, tot);
             }
         }
         __builtin_amdgcn_wave_barrier();
@@ -587,8 +586,9 @@ hipError_t launch_backward(const ss_camera& cam, const ss_gaussians& g, const ss
                                out.score, g.n);
     }
     const int grid = 8 * ((n_tiles + 7) / 8);
-    hipLaunchKernelGGL(k_blend_bwd<4>, dim3(grid), dim3(64), 0, s, tx_n, n_tiles, cam.width,
-                       cam.height, cam.bg[0], cam.bg[1], cam.bg[2], f.ranges, values,
+    hipLaunchKernelGGL((out.score ? k_blend_bwd<4, true> : k_blend_bwd<4, false>), dim3(grid),
+                       dim3(64), 0, s, tx_n, n_tiles, cam.width, cam.height, cam.bg[0],
+                       cam.bg[1], cam.bg[2], f.ranges, values,
                        reinterpret_cast<const float4*>(f.geom),
                        reinterpret_cast<const float4*>(f.conic),
                        reinterpret_cast<const float4*>(f.rgb), f.t_final, f.n_last, dl_drgb,
