@@ -12,8 +12,8 @@
 //   dC/dc_i     = alpha_i T_i
 //   dC/dalpha_i = T_i (c_i - R),   R <- alpha_i c_i + (1 - alpha_i) R.
 // The per-pixel gradients with respect to (u, v, a, b, c, sigma, r, g, b) are
-// summed over the wave and added with one set of atomics per wave and
-// Gaussian.  An optional per-Gaussian score accumulates sum over pixels and
+// summed over the wave by one transposing reduction that leaves each sum in
+// its own lane, and added with one atomic instruction per wave and Gaussian.  An optional per-Gaussian score accumulates sum over pixels and
 // channels of (dC/dg_i)^2, g_i the 2D Gaussian's value at the pixel (the
 // efficient pruning score of Sec. 4.2).
 //
@@ -86,8 +86,10 @@ __device__ __forceinline__ uint32_t wave_max_u32(uint32_t x) {
     return x;
 }
 
-// Same strip mask as the forward blend (pixel centres outside a 1% widened
-// ellipse box never pass q <= t).
+// Bit s: the Gaussian's ellipse box, widened by 1% (more than the FP32
+// rounding of q for a conic whose eigenvalue ratio is bounded as tested), meets
+// strip s of tile (tx, ty).  Pixel centres outside the box never pass q <= t,
+// so a Gaussian whose mask misses every strip of the wave is skipped whole.
 __device__ __forceinline__ uint32_t strip_mask_b(float4 g, float4 q, int tx, int ty) {
     const double a = q.x, b = q.y, c = q.z, t = g.w;
     const double det = a * c - b * b;
