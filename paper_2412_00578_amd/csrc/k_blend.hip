@@ -19,10 +19,14 @@
 // vector operations a finished strip's failing q <= t test takes.  The
 // quadratic form is evaluated with two fused multiply-adds as
 // q = fma(dy, fma(c, dy, (2b) dx), (a dx) dx) and compared with the record's
-// t, so the inclusion test (alpha >= 1/255) is exact and reproducible.  An included strip takes a short path when none of its
-// pixels stops at this Gaussian (wave-uniform test) and the full path, which
-// freezes the stopping pixels, otherwise.  Nothing on this path is a dense
-// contraction, so it runs on the FP32 VALU.
+// t, so the inclusion test (alpha >= 1/255) is exact and reproducible.
+// alpha = sigma exp(-q/2) is evaluated as exp2(fma(q, -log2(e)/2, log2 sigma))
+// with log2 sigma taken once per staged record: one multiply fewer per
+// included strip, within the few-ulp error any faithful exp has.  An included
+// strip takes a short path when none of its pixels stops at this Gaussian
+// (wave-uniform test) and the full path, which freezes the stopping pixels,
+// otherwise.  Nothing on this path is a dense contraction, so it runs on the
+// FP32 VALU.
 #include "ss_internal.h"
 
 namespace ss {
@@ -34,7 +38,7 @@ constexpr float kNegHalfLog2e = -0.72134752044448170368f;  // -log2(e) / 2
 
 struct Rec {
     float4 g;   // (u, v, -, t)
-    float4 q;   // (a, 2b, c, sigma)
+    float4 q;   // (a, 2b, c, sigma); staged in LDS as (a, 2b, c, log2 sigma)
     float4 c;   // (r, g, b, -)
 };
 
@@ -252,7 +256,8 @@ __global__ __launch_bounds__(64) void k_blend(const Item* __restrict__ items, Ba
         // and whose t is -1, so it includes no pixel
         const bool real = base + (uint32_t)lane < end;
         s_geo[lane] = real ? nxt.g : make_float4(0.0f, 0.0f, 0.0f, -1.0f);
-        s_con[lane] = real ? make_float4(nxt.q.x, 2.0f * nxt.q.y, nxt.q.z, nxt.q.w)
+        s_con[lane] = real ? make_float4(nxt.q.x, 2.0f * nxt.q.y, nxt.q.z,
+                                         __builtin_amdgcn_logf(nxt.q.w))
                            : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         s_col[lane] = nxt.c;
         __syncthreads();
@@ -280,7 +285,7 @@ __global__ __launch_bounds__(64) void k_blend(const Item* __restrict__ items, Ba
                     const float qq = fmaf(dy, fmaf(q.z, dy, b2dx), adx2);
                     if (qq <= g.w) {
                         const float al =
-                            fminf(kAlphaMax, q.w * __builtin_amdgcn_exp2f(qq * kNegHalfLog2e));
+                            fminf(kAlphaMax, __builtin_amdgcn_exp2f(fmaf(qq, kNegHalfLog2e, q.w)));
                         float tn = T[s] * (1.0f - al);
                         float wgt = al * T[s];
                         uint32_t lp = pos;
