@@ -290,7 +290,8 @@ __global__ __launch_bounds__(64) void k_blend(const Item* __restrict__ items, Ba
                         float wgt = al * T[s];
                         uint32_t lp = pos;
                         uint32_t blended = 1u;
-                        if (__builtin_expect(__ballot(tn < kTMin) != 0ull, 0)) {  // a pixel stops here
+                        // rare: an included pixel stops here
+                        if (__builtin_expect(__ballot(tn < kTMin) != 0ull, 0)) {
                             const bool ok = tn >= kTMin;
                             wgt = ok ? wgt : 0.0f;
                             tn = ok ? tn : T[s];
