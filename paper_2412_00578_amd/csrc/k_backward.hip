@@ -13,9 +13,10 @@
 //   dC/dalpha_i = T_i (c_i - R),   R <- alpha_i c_i + (1 - alpha_i) R.
 // The per-pixel gradients with respect to (u, v, a, b, c, sigma, r, g, b) are
 // summed over the wave by one transposing reduction that leaves each sum in
-// its own lane, and added with one atomic instruction per wave and Gaussian.  An optional per-Gaussian score accumulates sum over pixels and
-// channels of (dC/dg_i)^2, g_i the 2D Gaussian's value at the pixel (the
-// efficient pruning score of Sec. 4.2).
+// its own lane, and added with one atomic instruction per wave and Gaussian.
+// An optional per-Gaussian score accumulates sum over pixels and channels of
+// (dC/dg_i)^2, g_i the 2D Gaussian's value at the pixel (the efficient
+// pruning score of Sec. 4.2).
 //
 // Stage 8, preprocess backward.  One lane per Gaussian: the chain rule from
 // (u, v, conic, sigma, colour) back to means, scales, quaternions, opacity and
@@ -26,6 +27,7 @@ namespace ss {
 namespace {
 
 constexpr int kBatch = 64;
+constexpr float kNegHalfLog2e = -0.72134752044448170368f;  // -log2(e) / 2
 
 // The value x of the lane the DPP control names (within a row of 16 lanes).
 template <int CTRL>
@@ -188,10 +190,12 @@ __global__ __launch_bounds__(64 * (4 / SPW)) void k_blend_bwd(
                 const float qq = fmaf(dy, fmaf(q.z, dy, b2dx), adx2);
                 if (j < nl[s] && qq <= g.w) {
                     any = true;
-                    const float gval = __expf(-0.5f * qq);
+                    const float gval = __builtin_amdgcn_exp2f(qq * kNegHalfLog2e);  // exp(-q/2)
                     const float araw = q.w * gval;
                     const float al = fminf(kAlphaMax, araw);
-                    const float tb = T[s] / (1.0f - al);
+                    // hardware reciprocal (about 1 ulp): the recurrence runs over the
+                    // pixel's blended Gaussians only, well inside the gradients' tolerance
+                    const float tb = T[s] * __builtin_amdgcn_rcpf(1.0f - al);
                     const float wgt = al * tb;
                     gr = fmaf(wgt, dC[s][0], gr);
                     gg = fmaf(wgt, dC[s][1], gg);
