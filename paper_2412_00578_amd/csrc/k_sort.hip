@@ -10,7 +10,9 @@
 //                ceil(log2(n_tiles)) bits, 2 passes at 1600x1040,
 // which moves about a third of the bytes of six passes over 12-byte pairs.
 //
-// Both are LSD radix sorts with 8-bit digits.  Each pass is reduce-then-scan,
+// Both are LSD radix sorts with digits of at most 8 bits, the key bits split
+// evenly over the passes (the tile sort's 13 bits as 7 + 6).  Each pass is
+// reduce-then-scan,
 // so no workgroup ever waits on another:
 //   hist     workgroup b counts the digits of its contiguous key chunk
 //   dscan    256 workgroups, one per digit: exclusive scan of that digit's
@@ -54,8 +56,8 @@ Plan make_plan(uint64_t n) {
 }
 
 template <class K>
-__device__ __forceinline__ uint32_t digit_of(K key, int shift) {
-    return (uint32_t)(key >> shift) & (kRadix - 1);
+__device__ __forceinline__ uint32_t digit_of(K key, int shift, uint32_t dmask) {
+    return (uint32_t)(key >> shift) & dmask;
 }
 
 // Lanes of the wave holding the same digit as this lane (among `valid` lanes),
@@ -86,7 +88,8 @@ __device__ __forceinline__ uint32_t lanes_below(uint64_t m) {
 // the depth order).
 template <class K>
 __global__ __launch_bounds__(kBlock) void k_hist(const K* __restrict__ keys, uint64_t n, int shift,
-                                                 uint64_t chunk, uint32_t grid, bool drop,
+                                                 uint32_t dmask, uint64_t chunk, uint32_t grid,
+                                                 bool drop,
                                                  bool match, uint32_t* __restrict__ hist) {
     __shared__ uint32_t h[kWaves][kRadix];
     for (int k = threadIdx.x; k < kWaves * kRadix; k += kBlock) (&h[0][0])[k] = 0u;
@@ -107,7 +110,7 @@ __global__ __launch_bounds__(kBlock) void k_hist(const K* __restrict__ keys, uin
         for (int u = 0; u < kHistUnroll; ++u) {
             const uint64_t i = base + (uint64_t)u * kBlock + threadIdx.x;
             const bool valid = i < hi && !(drop && key[u] == (K)kCulledKey);
-            const uint32_t d = valid ? digit_of(key[u], shift) : 0u;
+            const uint32_t d = valid ? digit_of(key[u], shift, dmask) : 0u;
             if (match) {
                 const uint64_t m = match_digit(d, valid);
                 if (valid && lanes_below(m) == 0u) atomicAdd(&h[w][d], (uint32_t)__popcll(m));
@@ -187,8 +190,8 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const K* __restrict__ keys_i
                                                     const uint32_t* __restrict__ vals_in,
                                                     K* __restrict__ keys_out,
                                                     uint32_t* __restrict__ vals_out, uint64_t n,
-                                                    int shift, uint64_t chunk, uint32_t grid,
-                                                    bool drop,
+                                                    int shift, uint32_t dmask, uint64_t chunk,
+                                                    uint32_t grid, bool drop,
                                                     const uint32_t* __restrict__ hist,
                                                     const uint4* __restrict__ gather,
                                                     uint32_t* __restrict__ gather_out,
@@ -238,7 +241,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const K* __restrict__ keys_i
         for (int k = 0; k < kItems; ++k) {
             const uint64_t idx = sub + (uint64_t)w * (64 * kItems) + (uint64_t)k * 64 + lane;
             const bool valid = idx < hi && !(drop && key[k] == (K)kCulledKey);
-            const uint32_t d = digit_of(key[k], shift);
+            const uint32_t d = digit_of(key[k], shift, dmask);
             const uint64_t m = match_digit(d, valid);
             const uint32_t below = lanes_below(m);
             pre[k] = 0u;
@@ -267,7 +270,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const K* __restrict__ keys_i
         for (int k = 0; k < kItems; ++k) {
             const uint64_t idx = sub + (uint64_t)w * (64 * kItems) + (uint64_t)k * 64 + lane;
             if (idx < hi && !(drop && key[k] == (K)kCulledKey)) {
-                const uint32_t d = digit_of(key[k], shift);
+                const uint32_t d = digit_of(key[k], shift, dmask);
                 const uint32_t lp = lstart[d] + wcnt[w][d] + rank[k];
                 if (lp < (uint32_t)kSub) {
                     s_key[lp] = key[k];
@@ -291,7 +294,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const K* __restrict__ keys_i
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                const uint32_t d = digit_of(kk[u], shift);
+                const uint32_t d = digit_of(kk[u], shift, dmask);
                 pos[u] = base[d] + (i0 + u * kBlock - lstart[d]);
             }
 #pragma unroll
@@ -356,11 +359,16 @@ hipError_t radix_sort(K* keys[2], uint32_t* vals[2], int cur, uint64_t n0, uint6
                       uint32_t* tmp, bool drop, bool identity, bool last_keys,
                       const uint4* gather, uint32_t* gather_out, uint4* sets_out, int* out_buf,
                       hipStream_t s) {
+    // the bits are split as evenly as the passes allow (13 bits: 7 + 6), so
+    // no pass scatters into more buckets than it must: the fewer the buckets,
+    // the longer each sub-tile's runs of equal digits and its coalesced writes
     const int passes = (bits + 7) / 8;
+    int shift = 0;
     for (int pass = 0; pass < passes; ++pass) {
         const uint64_t m = pass == 0 ? n0 : n;       // pairs this pass reads
         const Plan plan = make_plan(m);
-        const int shift = pass * 8;
+        const int width = bits / passes + (pass < bits % passes ? 1 : 0);
+        const uint32_t dmask = (1u << width) - 1u;
         const bool last = pass + 1 == passes;
         const bool dr = pass == 0 && drop;
         K* kout = (last && !last_keys) ? nullptr : keys[1 - cur];
@@ -368,14 +376,15 @@ hipError_t radix_sort(K* keys[2], uint32_t* vals[2], int cur, uint64_t n0, uint6
         // the depth keys' top byte (sign and exponent) takes few values
         const bool match = drop && shift == 24;
         hipLaunchKernelGGL(k_hist<K>, dim3(plan.grid), dim3(kBlock), 0, s, keys[cur], m, shift,
-                           plan.chunk, plan.grid, dr, match, tmp);
+                           dmask, plan.chunk, plan.grid, dr, match, tmp);
         hipLaunchKernelGGL(k_dscan, dim3(kRadix), dim3(kBlock), 0, s, tmp, plan.grid);
         auto scatter = plan.items == kItemsSmall ? k_scatter<K, kItemsSmall>
                                                  : k_scatter<K, kItemsLarge>;
         hipLaunchKernelGGL(scatter, dim3(plan.grid), dim3(kBlock), 0, s, keys[cur], vin, kout,
-                           vals[1 - cur], m, shift, plan.chunk, plan.grid, dr, tmp, gather,
+                           vals[1 - cur], m, shift, dmask, plan.chunk, plan.grid, dr, tmp, gather,
                            last ? gather_out : nullptr, last ? sets_out : nullptr);
         cur = 1 - cur;
+        shift += width;
     }
     *out_buf = cur;
     return hipGetLastError();
