@@ -12,8 +12,7 @@
 //
 // Both are LSD radix sorts with digits of at most 8 bits, the key bits split
 // evenly over the passes (the tile sort's 13 bits as 7 + 6).  Each pass is
-// reduce-then-scan,
-// so no workgroup ever waits on another:
+// reduce-then-scan, so no workgroup ever waits on another:
 //   hist     workgroup b counts the digits of its contiguous key chunk
 //   dscan    256 workgroups, one per digit: exclusive scan of that digit's
 //            per-workgroup counts, and the digit's total
