@@ -241,13 +241,16 @@ class Renderer:
 
     def render_many(self, g: Gaussians, cams, mode="accutile", outs=None) -> list:
         """Renders one frame per camera as a pipeline over two HIP streams and
-        three frame buffers: frame k+1's preprocess and frame-count read-back run
-        on a side stream while frame k's depth order, scan, emit, sort, ranges
-        and blend run on the current stream.  The preprocess is bound by memory
-        latency and the blend by the vector ALUs, so the two overlap on the GPU,
-        and the counts come back by asynchronous copies, so the GPU never waits
-        for the host.  Every frame is rendered completely and identically to
-        render(); the images are valid once the current stream syncs."""
+        three frame buffers.  A side stream runs each frame's front half
+        (preprocess, frame-count read-back, depth order, scan) while the
+        current stream runs the back half (emit, sort, ranges, blend) of the
+        frame before it: the front half is bound by memory latency and FP64
+        work, the blend by the FP32 vector ALUs, so the two overlap on the GPU.
+        The counts come back by asynchronous copies; the host waits for a
+        frame's counts (it sizes the depth order and the pair buffer with them)
+        only after it has queued the back half of the frame before.  Every
+        frame is rendered completely and identically to render(); the images
+        are valid once the current stream syncs."""
         m = mode_id(mode)
         cs = [make_camera(c) for c in cams]
         if outs is None:
@@ -268,10 +271,12 @@ class Renderer:
             self._host_p = torch.zeros((R, 2), dtype=torch.int64, pin_memory=True)
         host = self._host_p
         ready = [torch.cuda.Event() for _ in range(R)]   # counts copied (side stream)
+        front = [torch.cuda.Event() for _ in range(R)]   # depth order and scan done (side)
         free = [torch.cuda.Event() for _ in range(R)]    # frame buffer released (main)
         fss = [None] * R
+        counts = [None] * len(cs)
 
-        def begin(k):
+        def preprocess(k):
             r = k % R
             if k >= R:
                 side.wait_event(free[r])
@@ -289,20 +294,46 @@ class Renderer:
                                                sside), "ss_forward_begin_async")
             ready[r].record(side)
 
-        begin(0)
-        buf = ctypes.c_int32()
-        for k in range(len(cs)):
-            if k + 1 < len(cs):
-                begin(k + 1)
+        def order(k):                      # waits for frame k's counts
             r = k % R
             ready[r].synchronize()
-            counts = _lib.SSFrameCounts(int(host[r, 0]), int(host[r, 1]))
-            main.wait_event(ready[r])
-            ps = self.pairs_for(counts.n_pairs).struct()
-            check(lib().ss_forward_finish(ctypes.byref(cs[k]), g.n, m, ctypes.byref(fss[r]),
-                                          ctypes.byref(ps), ctypes.byref(counts), _ptr(outs[k]),
-                                          ctypes.byref(buf), None, smain), "ss_forward_finish")
+            c = counts[k] = _lib.SSFrameCounts(int(host[r, 0]), int(host[r, 1]))
+            if c.n_pairs >= 0xffffffff:
+                raise RuntimeError(f"{c.n_pairs} pairs do not fit 32-bit offsets")
+            check(lib().ss_depth_order(g.n, c.n_visible, ctypes.byref(fss[r]), sside),
+                  "ss_depth_order")
+            check(lib().ss_scan(c.n_visible, ctypes.byref(fss[r]), sside), "ss_scan")
+            front[r].record(side)
+
+        def back(k):
+            r = k % R
+            c = counts[k]
+            main.wait_event(front[r])
+            pairs = self.pairs_for(c.n_pairs)
+            ps = pairs.struct()
+            check(lib().ss_emit(ctypes.byref(cs[k]), g.n, c.n_visible, m, ctypes.byref(fss[r]),
+                                ctypes.byref(ps), 0, c.n_pairs, smain), "ss_emit")
+            buf = ctypes.c_int32()
+            check(lib().ss_sort(ctypes.byref(cs[k]), ctypes.byref(ps), 0, c.n_pairs,
+                                ctypes.byref(buf), smain), "ss_sort")
+            check(lib().ss_ranges(ctypes.byref(cs[k]), ctypes.byref(fss[r]), ctypes.byref(ps),
+                                  buf.value, c.n_pairs, smain), "ss_ranges")
+            check(lib().ss_blend(ctypes.byref(cs[k]), ctypes.byref(fss[r]), ctypes.byref(ps),
+                                 buf.value, _ptr(outs[k]), smain), "ss_blend")
             free[r].record(main)
+
+        # side stream: preprocess k + 2 is queued before the depth order of
+        # k + 1, so the side stream never idles while the host waits for counts
+        preprocess(0)
+        if len(cs) > 1:
+            preprocess(1)
+        order(0)
+        for k in range(len(cs)):
+            back(k)
+            if k + 2 < len(cs):
+                preprocess(k + 2)
+            if k + 1 < len(cs):
+                order(k + 1)
         return outs
 
     # ---- single stages (for tests and profiling) ---------------------------
