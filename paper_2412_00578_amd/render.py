@@ -195,7 +195,7 @@ class Renderer:
         self._pairs: Pairs | None = None
         self._ring: list = [None] * self.RING    # frames of render_many
         self._host_p: torch.Tensor | None = None
-        self._side = None                        # side stream of render_many
+        self._side = None                        # side streams of render_many
 
     def frame_for(self, n, width, height) -> Frame:
         if self._frame is None or not self._frame.fits(n, width, height, self.stats):
@@ -240,12 +240,12 @@ class Renderer:
     RING = 3   # frame buffers of render_many
 
     def render_many(self, g: Gaussians, cams, mode="accutile", outs=None) -> list:
-        """Renders one frame per camera as a pipeline over two HIP streams and
-        three frame buffers.  A side stream runs each frame's front half
-        (preprocess, frame-count read-back, depth order, scan) while the
-        current stream runs the back half (emit, sort, ranges, blend) of the
-        frame before it: the front half is bound by memory latency and FP64
-        work, the blend by the FP32 vector ALUs, so the two overlap on the GPU.
+        """Renders one frame per camera as a pipeline over three HIP streams and
+        three frame buffers: a side stream runs frame k + 2's preprocess and
+        frame-count read-back, a second one frame k + 1's depth order and scan,
+        and the current stream frame k's emit, sort, ranges and blend.  The
+        preprocess is bound by FP64 work and memory latency, the depth order by
+        latency, the blend by the FP32 vector ALUs, so they overlap on the GPU.
         The counts come back by asynchronous copies; the host waits for a
         frame's counts (it sizes the depth order and the pair buffer with them)
         only after it has queued the back half of the frame before.  Every
@@ -259,19 +259,21 @@ class Renderer:
         if not cs:
             return outs
         main = torch.cuda.current_stream(self.device)
-        if self._side is None:
-            self._side = torch.cuda.Stream(self.device)     # default priority
-        side = self._side
+        if self._side is None:            # default priority, like every stream here
+            self._side = (torch.cuda.Stream(self.device), torch.cuda.Stream(self.device))
+        side, mid = self._side
         side.wait_stream(main)             # earlier work on the ring buffers is done
+        mid.wait_stream(main)
         smain = ctypes.c_void_p(main.cuda_stream)
         sside = ctypes.c_void_p(side.cuda_stream)
+        smid = ctypes.c_void_p(mid.cuda_stream)
         gs = g.struct()
         R = self.RING
         if self._host_p is None:           # one ss_frame_counts per frame buffer
             self._host_p = torch.zeros((R, 2), dtype=torch.int64, pin_memory=True)
         host = self._host_p
         ready = [torch.cuda.Event() for _ in range(R)]   # counts copied (side stream)
-        front = [torch.cuda.Event() for _ in range(R)]   # depth order and scan done (side)
+        front = [torch.cuda.Event() for _ in range(R)]   # depth order and scan done (mid)
         free = [torch.cuda.Event() for _ in range(R)]    # frame buffer released (main)
         fss = [None] * R
         counts = [None] * len(cs)
@@ -283,6 +285,7 @@ class Renderer:
             f = self._ring[r]
             if f is None or not f.fits(g.n, cs[k].width, cs[k].height, self.stats):
                 side.synchronize()         # a resize: nothing may still use the old buffers
+                mid.synchronize()
                 main.synchronize()
                 self._ring[r] = None
                 self._ring[r] = f = Frame(g.n, cs[k].width, cs[k].height, self.device,
@@ -300,10 +303,11 @@ class Renderer:
             c = counts[k] = _lib.SSFrameCounts(int(host[r, 0]), int(host[r, 1]))
             if c.n_pairs >= 0xffffffff:
                 raise RuntimeError(f"{c.n_pairs} pairs do not fit 32-bit offsets")
-            check(lib().ss_depth_order(g.n, c.n_visible, ctypes.byref(fss[r]), sside),
+            mid.wait_event(ready[r])
+            check(lib().ss_depth_order(g.n, c.n_visible, ctypes.byref(fss[r]), smid),
                   "ss_depth_order")
-            check(lib().ss_scan(c.n_visible, ctypes.byref(fss[r]), sside), "ss_scan")
-            front[r].record(side)
+            check(lib().ss_scan(c.n_visible, ctypes.byref(fss[r]), smid), "ss_scan")
+            front[r].record(mid)
 
         def back(k):
             r = k % R
@@ -322,8 +326,8 @@ class Renderer:
                                  buf.value, _ptr(outs[k]), smain), "ss_blend")
             free[r].record(main)
 
-        # side stream: preprocess k + 2 is queued before the depth order of
-        # k + 1, so the side stream never idles while the host waits for counts
+        # preprocess k + 2 is queued before the host waits for frame k + 1's
+        # counts, so the side stream never idles while the host waits
         preprocess(0)
         if len(cs) > 1:
             preprocess(1)
