@@ -9,7 +9,8 @@ order, scan, pair count read-back, key emission, tile sort, tile ranges and
 blend.  Each of the three tile assignments (3-sigma, SnugBox, AccuTile) is
 timed over the same steps on the same scene twice: frame by frame with
 per-stage events (the host waits for each frame's pair count), and as one
-sequence with the host one frame ahead (Renderer.render_many), which is how a
+sequence (Renderer.render_many): the host runs ahead, and consecutive frames'
+preprocess, depth order and blend overlap on three streams, which is how a
 fly-through or video renderer runs; `value` is the AccuTile frame rate of the
 latter, `fps_sequential` the former.
 
@@ -289,8 +290,9 @@ def main():
             "sort_gbs": round(p_mean * SORT_BYTES_PER_PAIR_PASS * passes /
                               (stages["sort"] * 1e-3) / 1e9, 1),
         }
-        # The same frames with the host one frame ahead (Renderer.render_many):
-        # the pair-count read-back no longer leaves the GPU idle.
+        # The same frames as one sequence (Renderer.render_many): the host runs
+        # ahead, so the pair-count read-back leaves the GPU idle no longer, and
+        # consecutive frames' stages overlap on three streams.
         outs = [torch.empty((3, cams[0].height, cams[0].width), dtype=torch.float32, device=dev)
                 for _ in range(2)]
         seq = [cams[k % len(cams)] for k in range(args.steps)]
