@@ -215,7 +215,8 @@ typedef struct ss_grads {
  *   [0] before preprocess  [1] after preprocess  [2] before the depth order
  *   (after the frame counts were read back)  [3] after the depth order
  *   [4] after the scan  [5] after emit  [6] after the sort  [7] after the ranges
- *   [8] after the blend. */
+ *   and the tiles' work order  [8] after the blend, so [7]..[8] brackets the
+ *   blend kernel alone. */
 typedef struct ss_stage_events {
     void *ev[9];
 } ss_stage_events;

@@ -269,8 +269,10 @@ int finish_impl(const ss::BatchDims& d, int32_t mode, const ss_frame* f, const s
     record(ev, 6, s);
     SS_TRY(hip_status(ss::launch_ranges(p->keys[cur], n_pairs, d.n_tiles, f->ranges, s),
                       "ranges"));
+    SS_TRY(hip_status(ss::launch_tile_order(table, d, *f, s), "tile order"));
     record(ev, 7, s);
-    SS_TRY(hip_status(ss::launch_blend(table, d, *f, p->values[cur], out_single, s), "blend"));
+    SS_TRY(hip_status(ss::launch_blend_tiles(table, d, *f, p->values[cur], out_single, s),
+                      "blend"));
     record(ev, 8, s);
     if (out_buf) *out_buf = cur;
     return SS_OK;

@@ -333,13 +333,19 @@ __global__ __launch_bounds__(64) void k_blend(const Item* __restrict__ items, Ba
 
 }  // namespace
 
-hipError_t launch_blend(const Item* items, const BatchDims& d, const ss_frame& f,
-                        const uint32_t* values, float* out_rgb_single, hipStream_t s) {
+hipError_t launch_tile_order(const Item* items, const BatchDims& d, const ss_frame& f,
+                             hipStream_t s) {
+    if (d.n_tiles == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(kOrderThreads), 0, s, items, d, f.ranges,
+                       tile_order_of(f.table, d.n_items));
+    return hipGetLastError();
+}
+
+hipError_t launch_blend_tiles(const Item* items, const BatchDims& d, const ss_frame& f,
+                              const uint32_t* values, float* out_rgb_single, hipStream_t s) {
     const int grid = d.n_tiles;
     if (grid == 0) return hipSuccess;
-    uint32_t* order = tile_order_of(f.table, d.n_items);
-    hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(kOrderThreads), 0, s, items, d, f.ranges,
-                       order);
+    const uint32_t* order = tile_order_of(f.table, d.n_items);
     auto go = [&](auto kernel) {
         hipLaunchKernelGGL(kernel, dim3(grid), dim3(64), 0, s, items, d, order, f.ranges, values,
                            reinterpret_cast<const float4*>(f.geom),
@@ -350,6 +356,13 @@ hipError_t launch_blend(const Item* items, const BatchDims& d, const ss_frame& f
     if (f.n_eval) go(k_blend<true>);
     else go(k_blend<false>);
     return hipGetLastError();
+}
+
+hipError_t launch_blend(const Item* items, const BatchDims& d, const ss_frame& f,
+                        const uint32_t* values, float* out_rgb_single, hipStream_t s) {
+    const hipError_t e = launch_tile_order(items, d, f, s);
+    if (e != hipSuccess) return e;
+    return launch_blend_tiles(items, d, f, values, out_rgb_single, s);
 }
 
 }  // namespace ss

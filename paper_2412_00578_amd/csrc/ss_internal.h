@@ -383,6 +383,12 @@ hipError_t launch_sort(const ss_pairs& p, int buf, uint64_t n_pairs, int bits, i
                        hipStream_t s);
 hipError_t launch_ranges(const uint32_t* keys, uint64_t n_pairs, int n_tiles, uint32_t* ranges,
                          hipStream_t s);
+// launch_blend = launch_tile_order (the tiles' work order, from the ranges)
+// followed by launch_blend_tiles.
+hipError_t launch_tile_order(const Item* items, const BatchDims& d, const ss_frame& f,
+                             hipStream_t s);
+hipError_t launch_blend_tiles(const Item* items, const BatchDims& d, const ss_frame& f,
+                              const uint32_t* values, float* out_rgb_single, hipStream_t s);
 hipError_t launch_blend(const Item* items, const BatchDims& d, const ss_frame& f,
                         const uint32_t* values, float* out_rgb_single, hipStream_t s);
 hipError_t launch_backward(const ss_camera& cam, const ss_gaussians& g, const ss_frame& f,

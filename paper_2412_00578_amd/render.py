@@ -144,6 +144,8 @@ class Pairs:
         return p
 
 
+# "ranges" covers the tile ranges and the blend's tile work order, so that
+# "blend" is the blend kernel alone
 STAGES = ("preprocess", "readback", "depth_order", "scan", "emit", "sort", "ranges", "blend")
 
 
