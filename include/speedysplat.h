@@ -340,6 +340,18 @@ int ss_forward_finish(const ss_camera *cam, int64_t n, int32_t mode, const ss_fr
                       int32_t *out_buf, const ss_stage_events *events, void *stream);
 
 /*
+ * Stages 3-6 (emit, sort, ranges, blend) of ss_forward_finish, for a frame
+ * whose stage 2a and 2 the caller has already run (ss_depth_order with the
+ * frame's n and counts->n_visible, then ss_scan), possibly on another stream
+ * ordered before this one: a pipeline can then run frame k + 1's depth order
+ * beside frame k's blend.  Same arguments, results and errors as
+ * ss_forward_finish; events [2]..[4] are recorded together at the start.
+ */
+int ss_forward_back(const ss_camera *cam, int64_t n, int32_t mode, const ss_frame *frame,
+                    const ss_pairs *pairs, const ss_frame_counts *counts, float *out_rgb,
+                    int32_t *out_buf, const ss_stage_events *events, void *stream);
+
+/*
  * SYNC.  The whole forward render (stages 1-6).  *counts_out (may be NULL)
  * receives the frame counts.  If pairs->capacity < P, returns SS_ERR_WORKSPACE
  * after stage 1 without touching the pair buffers; the caller grows them to P
@@ -374,6 +386,15 @@ int ss_batch_finish(const ss_batch_item *items, int32_t n_items, int32_t mode,
                     const ss_frame *frame, const ss_pairs *pairs,
                     const ss_frame_counts *counts, int32_t *out_buf,
                     const ss_stage_events *events, void *stream);
+
+/*
+ * ss_batch_finish without stages 2a and 2, which the caller has run on the
+ * batch frame (ss_depth_order with n = the batch's n_slots and
+ * counts->n_visible, then ss_scan), as ss_forward_back does for one frame.
+ */
+int ss_batch_back(const ss_batch_item *items, int32_t n_items, int32_t mode,
+                  const ss_frame *frame, const ss_pairs *pairs, const ss_frame_counts *counts,
+                  int32_t *out_buf, const ss_stage_events *events, void *stream);
 
 /*
  * Adjoint of the forward render (the gradient flow of Sec. 4.2: per-pixel

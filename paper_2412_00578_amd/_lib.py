@@ -110,6 +110,9 @@ PROTOTYPES = {
     "ss_forward_finish": [_P(SSCamera), ctypes.c_int64, ctypes.c_int32, _P(SSFrame),
                           _P(SSPairs), _P(SSFrameCounts), _vp, _P(ctypes.c_int32),
                           _P(SSStageEvents), _vp],
+    "ss_forward_back": [_P(SSCamera), ctypes.c_int64, ctypes.c_int32, _P(SSFrame),
+                        _P(SSPairs), _P(SSFrameCounts), _vp, _P(ctypes.c_int32),
+                        _P(SSStageEvents), _vp],
     "ss_render": [_P(SSCamera), _P(SSGaussians), ctypes.c_int32, _P(SSFrame), _P(SSPairs), _vp,
                   _P(SSFrameCounts), _P(ctypes.c_int32), _P(SSStageEvents), _vp],
     "ss_batch_sizes": [_P(SSBatchItem), ctypes.c_int32, _P(SSBatchInfo)],
@@ -118,6 +121,9 @@ PROTOTYPES = {
     "ss_batch_finish": [_P(SSBatchItem), ctypes.c_int32, ctypes.c_int32, _P(SSFrame),
                         _P(SSPairs), _P(SSFrameCounts), _P(ctypes.c_int32), _P(SSStageEvents),
                         _vp],
+    "ss_batch_back": [_P(SSBatchItem), ctypes.c_int32, ctypes.c_int32, _P(SSFrame),
+                      _P(SSPairs), _P(SSFrameCounts), _P(ctypes.c_int32), _P(SSStageEvents),
+                      _vp],
     "ss_render_backward": [_P(SSCamera), _P(SSGaussians), _P(SSFrame), _P(SSPairs),
                            ctypes.c_int32, _vp, _P(SSGrads), _vp],
 }

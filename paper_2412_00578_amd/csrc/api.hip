@@ -235,10 +235,11 @@ int begin_impl(const Layout& L, int32_t mode, const ss_frame* f, ss_frame_counts
     return SS_OK;
 }
 
-// Stages 2a-6 for the counts begin_impl returned.
+// Stages 2a-6 for the counts begin_impl returned; with order false, stages
+// 3-6 only (the caller ran the depth order and the scan).
 int finish_impl(const ss::BatchDims& d, int32_t mode, const ss_frame* f, const ss_pairs* p,
                 const ss_frame_counts* c, float* out_single, int32_t* out_buf,
-                const ss_stage_events* ev, hipStream_t s) {
+                const ss_stage_events* ev, hipStream_t s, bool order = true) {
     SS_TRY(check_mode(mode));
     SS_TRY(check_frame_records(f, d.n_slots));
     SS_TRY(check_frame_pixels(f));
@@ -256,9 +257,9 @@ int finish_impl(const ss::BatchDims& d, int32_t mode, const ss_frame* f, const s
     const int passes = n_pairs > 1 ? ss::sort_passes(bits) : 0;
     const int first = passes & 1;
     record(ev, 2, s);
-    SS_TRY(hip_status(ss::launch_depth_order(d.n_slots, n_vis, *f, s), "depth order"));
+    if (order) SS_TRY(hip_status(ss::launch_depth_order(d.n_slots, n_vis, *f, s), "depth order"));
     record(ev, 3, s);
-    SS_TRY(hip_status(ss::launch_scan(n_vis, *f, s), "scan"));
+    if (order) SS_TRY(hip_status(ss::launch_scan(n_vis, *f, s), "scan"));
     record(ev, 4, s);
     SS_TRY(hip_status(ss::launch_emit(table, d, mode, *f, n_vis, p->keys[first],
                                       p->values[first], n_pairs, s),
@@ -441,6 +442,16 @@ int ss_forward_finish(const ss_camera* cam, int64_t n, int32_t mode, const ss_fr
                        (hipStream_t)stream);
 }
 
+int ss_forward_back(const ss_camera* cam, int64_t n, int32_t mode, const ss_frame* f,
+                    const ss_pairs* p, const ss_frame_counts* counts, float* out_rgb,
+                    int32_t* out_buf, const ss_stage_events* ev, void* stream) {
+    SS_TRY(check_camera(cam));
+    if (n < 0) return fail(SS_ERR_INVALID_ARG, "n < 0");
+    if (!out_rgb) return fail(SS_ERR_INVALID_ARG, "out_rgb is NULL");
+    return finish_impl(single_dims(*cam, n), mode, f, p, counts, out_rgb, out_buf, ev,
+                       (hipStream_t)stream, false);
+}
+
 int ss_render(const ss_camera* cam, const ss_gaussians* g, int32_t mode, const ss_frame* f,
               const ss_pairs* p, float* out_rgb, ss_frame_counts* counts_out, int32_t* out_buf,
               const ss_stage_events* ev, void* stream) {
@@ -484,6 +495,15 @@ int ss_batch_finish(const ss_batch_item* items, int32_t n_items, int32_t mode, c
     Layout L;
     SS_TRY(lay_out(items, n_items, L));
     return finish_impl(L.d, mode, f, p, counts, nullptr, out_buf, ev, (hipStream_t)stream);
+}
+
+int ss_batch_back(const ss_batch_item* items, int32_t n_items, int32_t mode, const ss_frame* f,
+                  const ss_pairs* p, const ss_frame_counts* counts, int32_t* out_buf,
+                  const ss_stage_events* ev, void* stream) {
+    Layout L;
+    SS_TRY(lay_out(items, n_items, L));
+    return finish_impl(L.d, mode, f, p, counts, nullptr, out_buf, ev, (hipStream_t)stream,
+                       false);
 }
 
 int ss_render_backward(const ss_camera* cam, const ss_gaussians* g, const ss_frame* f,

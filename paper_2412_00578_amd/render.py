@@ -317,15 +317,10 @@ class Renderer:
             main.wait_event(front[r])
             pairs = self.pairs_for(c.n_pairs)
             ps = pairs.struct()
-            check(lib().ss_emit(ctypes.byref(cs[k]), g.n, c.n_visible, m, ctypes.byref(fss[r]),
-                                ctypes.byref(ps), 0, c.n_pairs, smain), "ss_emit")
             buf = ctypes.c_int32()
-            check(lib().ss_sort(ctypes.byref(cs[k]), ctypes.byref(ps), 0, c.n_pairs,
-                                ctypes.byref(buf), smain), "ss_sort")
-            check(lib().ss_ranges(ctypes.byref(cs[k]), ctypes.byref(fss[r]), ctypes.byref(ps),
-                                  buf.value, c.n_pairs, smain), "ss_ranges")
-            check(lib().ss_blend(ctypes.byref(cs[k]), ctypes.byref(fss[r]), ctypes.byref(ps),
-                                 buf.value, _ptr(outs[k]), smain), "ss_blend")
+            check(lib().ss_forward_back(ctypes.byref(cs[k]), g.n, m, ctypes.byref(fss[r]),
+                                        ctypes.byref(ps), ctypes.byref(c), _ptr(outs[k]),
+                                        ctypes.byref(buf), None, smain), "ss_forward_back")
             free[r].record(main)
 
         # preprocess k + 2 is queued before the host waits for frame k + 1's
@@ -572,6 +567,30 @@ class BatchRenderer:
         check(lib().ss_batch_finish(h.items, h.n, h.mode, ctypes.byref(fs), ctypes.byref(ps),
                                     ctypes.byref(h.counts), ctypes.byref(buf), None, h.stream),
               "ss_batch_finish")
+        return h.outs
+
+    def finish_split(self, h: "_BatchHandle", stream, mid):
+        """finish() with the depth order and scan on the torch stream `mid`,
+        ordered after `stream` (the one h was begun on) and before h's
+        remaining stages there, so that they can run beside another batch's
+        emit, sort and blend."""
+        h.pairs = Pairs(int(max(h.n_pairs, 1) * self.growth) + 1024, self.device)
+        fs, ps = h.frame.struct(), h.pairs.struct()
+        front = torch.cuda.Event()
+        front.record(stream)
+        mid.wait_event(front)
+        smid = ctypes.c_void_p(mid.cuda_stream)
+        n_vis = int(h.counts.n_visible)
+        check(lib().ss_depth_order(int(h.frame.info.n_slots), n_vis, ctypes.byref(fs), smid),
+              "ss_depth_order")
+        check(lib().ss_scan(n_vis, ctypes.byref(fs), smid), "ss_scan")
+        ordered = torch.cuda.Event()
+        ordered.record(mid)
+        stream.wait_event(ordered)
+        buf = ctypes.c_int32()
+        check(lib().ss_batch_back(h.items, h.n, h.mode, ctypes.byref(fs), ctypes.byref(ps),
+                                  ctypes.byref(h.counts), ctypes.byref(buf), None, h.stream),
+              "ss_batch_back")
         return h.outs
 
     def render(self, requests, mode="accutile", outs=None, stream=None):
