@@ -388,15 +388,6 @@ int ss_batch_finish(const ss_batch_item *items, int32_t n_items, int32_t mode,
                     const ss_stage_events *events, void *stream);
 
 /*
- * ss_batch_finish without stages 2a and 2, which the caller has run on the
- * batch frame (ss_depth_order with n = the batch's n_slots and
- * counts->n_visible, then ss_scan), as ss_forward_back does for one frame.
- */
-int ss_batch_back(const ss_batch_item *items, int32_t n_items, int32_t mode,
-                  const ss_frame *frame, const ss_pairs *pairs, const ss_frame_counts *counts,
-                  int32_t *out_buf, const ss_stage_events *events, void *stream);
-
-/*
  * Adjoint of the forward render (the gradient flow of Sec. 4.2: per-pixel
  * gradients aggregated to the 2D parameters, then per Gaussian to the 3D
  * ones).  Inputs: the same camera and Gaussians as the forward call, its

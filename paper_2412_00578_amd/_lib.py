@@ -121,9 +121,6 @@ PROTOTYPES = {
     "ss_batch_finish": [_P(SSBatchItem), ctypes.c_int32, ctypes.c_int32, _P(SSFrame),
                         _P(SSPairs), _P(SSFrameCounts), _P(ctypes.c_int32), _P(SSStageEvents),
                         _vp],
-    "ss_batch_back": [_P(SSBatchItem), ctypes.c_int32, ctypes.c_int32, _P(SSFrame),
-                      _P(SSPairs), _P(SSFrameCounts), _P(ctypes.c_int32), _P(SSStageEvents),
-                      _vp],
     "ss_render_backward": [_P(SSCamera), _P(SSGaussians), _P(SSFrame), _P(SSPairs),
                            ctypes.c_int32, _vp, _P(SSGrads), _vp],
 }

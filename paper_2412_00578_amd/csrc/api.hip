@@ -497,15 +497,6 @@ int ss_batch_finish(const ss_batch_item* items, int32_t n_items, int32_t mode, c
     return finish_impl(L.d, mode, f, p, counts, nullptr, out_buf, ev, (hipStream_t)stream);
 }
 
-int ss_batch_back(const ss_batch_item* items, int32_t n_items, int32_t mode, const ss_frame* f,
-                  const ss_pairs* p, const ss_frame_counts* counts, int32_t* out_buf,
-                  const ss_stage_events* ev, void* stream) {
-    Layout L;
-    SS_TRY(lay_out(items, n_items, L));
-    return finish_impl(L.d, mode, f, p, counts, nullptr, out_buf, ev, (hipStream_t)stream,
-                       false);
-}
-
 int ss_render_backward(const ss_camera* cam, const ss_gaussians* g, const ss_frame* f,
                        const ss_pairs* p, int32_t buf, const float* dl_drgb, const ss_grads* out,
                        void* stream) {

@@ -569,30 +569,6 @@ class BatchRenderer:
               "ss_batch_finish")
         return h.outs
 
-    def finish_split(self, h: "_BatchHandle", stream, mid):
-        """finish() with the depth order and scan on the torch stream `mid`,
-        ordered after `stream` (the one h was begun on) and before h's
-        remaining stages there, so that they can run beside another batch's
-        emit, sort and blend."""
-        h.pairs = Pairs(int(max(h.n_pairs, 1) * self.growth) + 1024, self.device)
-        fs, ps = h.frame.struct(), h.pairs.struct()
-        front = torch.cuda.Event()
-        front.record(stream)
-        mid.wait_event(front)
-        smid = ctypes.c_void_p(mid.cuda_stream)
-        n_vis = int(h.counts.n_visible)
-        check(lib().ss_depth_order(int(h.frame.info.n_slots), n_vis, ctypes.byref(fs), smid),
-              "ss_depth_order")
-        check(lib().ss_scan(n_vis, ctypes.byref(fs), smid), "ss_scan")
-        ordered = torch.cuda.Event()
-        ordered.record(mid)
-        stream.wait_event(ordered)
-        buf = ctypes.c_int32()
-        check(lib().ss_batch_back(h.items, h.n, h.mode, ctypes.byref(fs), ctypes.byref(ps),
-                                  ctypes.byref(h.counts), ctypes.byref(buf), None, h.stream),
-              "ss_batch_back")
-        return h.outs
-
     def render(self, requests, mode="accutile", outs=None, stream=None):
         return self.finish(self.begin(requests, mode, outs, stream))
 
