@@ -88,8 +88,8 @@ __device__ __forceinline__ uint32_t lanes_below(uint64_t m) {
 template <class K>
 __global__ __launch_bounds__(kBlock) void k_hist(const K* __restrict__ keys, uint64_t n, int shift,
                                                  uint32_t dmask, uint64_t chunk, uint32_t grid,
-                                                 bool drop,
-                                                 bool match, uint32_t* __restrict__ hist) {
+                                                 bool drop, bool match,
+                                                 uint32_t* __restrict__ hist) {
     __shared__ uint32_t h[kWaves][kRadix];
     for (int k = threadIdx.x; k < kWaves * kRadix; k += kBlock) (&h[0][0])[k] = 0u;
     __syncthreads();
