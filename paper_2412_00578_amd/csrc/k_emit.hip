@@ -10,9 +10,9 @@
 // Tile counts are heavy-tailed (most Gaussians touch a few tiles, a Gaussian
 // near the camera thousands), so the work is split in two launches:
 //   k_emit      one lane per entry whose tile set the preprocess stage stored
-//               as a mask (tile rectangle within 8 x 8) with <= 32 tiles (the
-//               depth order left the sets in entry order, so these reads are
-//               coalesced): each
+//               as a mask (tile rectangle within 8 x 8, so at most 64 tiles;
+//               the depth order left the sets in entry order, so these reads
+//               are coalesced): each
 //               lane expands its mask into its wave's LDS stage (1024 tile
 //               ids; entries past its end are handled as the others), then
 //               the wave copies the stage to the pair buffers with consecutive
@@ -30,7 +30,6 @@
 namespace ss {
 namespace {
 
-constexpr uint32_t kSmall = 32;
 constexpr int kBigBlock = 256;
 constexpr int kBigGrid = 1024;
 
@@ -108,7 +107,7 @@ __global__ __launch_bounds__(kEmitBlock) void k_emit(const Item* __restrict__ it
     uint4 ts = make_uint4(0u, 0u, 0u, 0u);
     if (cnt) ts = tsets[j];                       // the tile sets in depth order
     const uint64_t mask = (uint64_t)ts.x | ((uint64_t)ts.y << 32);
-    const bool masked = cnt && cnt <= kSmall && mask != 0ull;
+    const bool masked = cnt && mask != 0ull;
     // staged runs in lane order; the lanes whose run would pass the stage's
     // end (a suffix of the masked lanes) join the queue
     const bool fit = wave_incl_scan_u32(masked ? cnt : 0u) <= (uint32_t)kStage;
