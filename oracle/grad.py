@@ -117,25 +117,6 @@ def blend_masked(rec, order, pixels, incl, bg=(0.0, 0.0, 0.0)):
     return col + T_fin[:, None] * torch.as_tensor(bg, dtype=DT)[None, :]
 
 
-def fma32(a, b, c):
-    """a * b + c for FP32 values, rounded once to FP32 (a fused multiply-add).
-
-    The product of two FP32 values is exact in FP64; the sum is formed in FP64
-    with its rounding error recovered exactly (Knuth's TwoSum) and rounded to
-    odd, and rounding a round-to-odd FP64 value to FP32 gives the correctly
-    rounded FP32 result because FP64 carries at least two more bits than twice
-    FP32's precision (Boldo and Melquiond, IEEE Trans. Computers 57(4), 2008).
-    """
-    p = np.float64(a) * np.float64(b)
-    c = np.float64(c)
-    s = p + c
-    bb = s - p
-    e = (p - (s - bb)) + (c - bb)
-    if e != 0.0 and (int(np.array(s).view(np.int64)) & 1) == 0:
-        s = np.nextafter(s, np.inf if e > 0 else -np.inf)
-    return np.float32(s)
-
-
 def masks_fp64(rec, order, pixels):
     """The forward pass's decisions in FP64: include iff q <= t, stop before the
     first included Gaussian that would take T below 1e-4.  Returns (incl,
@@ -171,8 +152,8 @@ def masks_from_tiled(fr, cam, order, pixels):
             i = int(fr.sorted_values[j])
             dx = fxp - geom[i, 0]
             dy = fyp - geom[i, 1]
-            qq = fma32(dy, fma32(conic[i, 2], dy, (np.float32(2.0) * conic[i, 1]) * dx),
-                       (conic[i, 0] * dx) * dx)
+            qq = ((conic[i, 0] * dx) * dx + (conic[i, 2] * dy) * dy) + \
+                ((np.float32(2.0) * conic[i, 1]) * dx) * dy
             if qq <= geom[i, 3]:
                 incl[r, pos[i]] = True
     return incl

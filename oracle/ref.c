@@ -8,8 +8,7 @@
  *
  * Build: gcc -O2 -std=c99 -ffp-contract=off -fno-fast-math -fPIC -shared.
  * Every floating-point operation below is one IEEE operation rounded once,
- * evaluated in the written order (no contraction into FMA; the blend's
- * quadratic form calls fmaf explicitly, a fused multiply-add rounded once).
+ * evaluated in the written order (no contraction into FMA).
  *
  * Stages and where the paper defines them (Speedy-Splat, arXiv 2412.00578):
  *   preprocess   Sec. 3.2.1 "Preprocessing": projection of the mean, the 3D
@@ -375,9 +374,8 @@ int orc_tile_rect(const float *geom, const float *conic, int mode, int tx_n, int
     return ok;
 }
 
-/* Preprocess all Gaussians: records and tile counts. Returns visible count.
- * The colour is kept only for a Gaussian that touches at least one tile: one
- * without tiles is never blended, and its rgb record is zero. */
+/* Preprocess all Gaussians: records (with the colour of every surviving
+ * record) and tile counts.  Returns the visible count. */
 int64_t orc_preprocess(const float *campack, int64_t n, int sh_degree, int sh_stride,
                        const float *means, const float *scales, const float *quats,
                        const float *opacity, const float *sh, int mode,
@@ -392,7 +390,6 @@ int64_t orc_preprocess(const float *campack, int64_t n, int sh_degree, int sh_st
                             sh + (int64_t)3 * sh_stride * i, sh_degree, sh_stride, mode,
                             g, q, c);
         counts[i] = ok ? (uint32_t)orc_tile_list(g, q, mode, cam.tiles_x, cam.tiles_y, NULL) : 0u;
-        if (counts[i] == 0u) c[0] = c[1] = c[2] = c[3] = 0.0f;
         visible += ok;
     }
     return visible;
@@ -456,14 +453,24 @@ void orc_ranges(int64_t p, const uint64_t *keys, int64_t n_tiles, uint32_t *rang
 
 /*
  * Blend one tile front to back (FP32).  For each pixel centre
- * (px + 0.5, py + 0.5):  q = fma(dy, fma(c, dy, (2b) dx), (a dx) dx);
- * a Gaussian is included when q <= t (alpha >= 1/255); alpha = min(0.99,
- * sigma exp(-q/2)); the walk stops before a Gaussian that would take the
- * transmittance below 1e-4.  Output planar [3,H,W].
- * ambig[] (optional) marks pixels whose stop decision could flip under a
- * different (still faithful) exp: the relative error of T that exp can cause
- * is tracked as err, each unclamped alpha adding 16 ulp * alpha / (1 - alpha),
- * and a stop test within T_MIN * (err + 4 ulp) of the threshold is flagged.
+ * (px + 0.5, py + 0.5):  q = ((a dx) dx + (c dy) dy) + ((2b) dx) dy, each
+ * operation rounded once; a Gaussian is included when q <= t (alpha >= 1/255);
+ * alpha = min(0.99, sigma exp(-q/2)); the walk stops before a Gaussian that
+ * would take the transmittance below 1e-4.  Output planar [3,H,W].
+ *
+ * ambig[] (optional) marks the pixels where another faithful FP32
+ * implementation may decide differently:
+ *  - inclusion: q is a sum of three terms (a dx^2, c dy^2, 2b dx dy).  Any FP32
+ *    evaluation in which each term passes through at most four roundings
+ *    (this order: two products and two sums; a fused form: fewer) lies within
+ *    gamma_4 * S of the exact q, S = |a| dx^2 + |c| dy^2 + 2 |b dx dy|,
+ *    gamma_4 = 4u / (1 - 4u), u = 2^-24.  The exact q is taken in FP64 (its
+ *    own error is below 4 * 2^-53 * S, and twice that is added); when |q_64 - t| is within that band for
+ *    any pair the pixel evaluated, the q <= t decision is not fixed by the
+ *    definition and the pixel is flagged.
+ *  - stop: the relative error of T that exp can cause is tracked as err, each
+ *    unclamped alpha adding 16 ulp * alpha / (1 - alpha); a stop test within
+ *    T_MIN * (err + 4 ulp) of the threshold is flagged.
  * n_contrib (optional) counts the Gaussians blended into each pixel.
  */
 static void blend_tile(const orc_cam *cam, int tx, int ty, const uint32_t *ranges,
@@ -481,12 +488,19 @@ static void blend_tile(const orc_cam *cam, int tx, int ty, const uint32_t *range
             int amb = 0;
             double err = 0.0;
             const double ulp = ldexp(1.0, -24);
+            const double gam_q = 4.0 * ulp / (1.0 - 4.0 * ulp) + 8.0 * ldexp(1.0, -53);
             float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
             for (uint32_t j = start; j < end; ++j) {
                 uint32_t i = values[j];
                 const float *g = geom + 4 * (int64_t)i, *q = conic + 4 * (int64_t)i;
                 float dx = fx - g[0], dy = fy - g[1];
-                float qq = fmaf(dy, fmaf(q[2], dy, (2.0f * q[1]) * dx), (q[0] * dx) * dx);
+                float qq = ((q[0] * dx) * dx + (q[2] * dy) * dy) + ((2.0f * q[1]) * dx) * dy;
+                {
+                    double ddx = dx, ddy = dy, a = q[0], b = q[1], c = q[2];
+                    double q64 = (a * ddx * ddx + c * ddy * ddy) + 2.0 * b * ddx * ddy;
+                    double mag = fabs(a) * ddx * ddx + fabs(c) * ddy * ddy + 2.0 * fabs(b * ddx * ddy);
+                    if (fabs(q64 - (double)g[3]) <= gam_q * mag + 0x1p-140) amb = 1;
+                }
                 if (!(qq <= g[3])) continue;
                 float al = q[3] * expf(-0.5f * qq);
                 if (al > ORC_ALPHA_MAX) al = ORC_ALPHA_MAX;

@@ -71,13 +71,21 @@ def assert_records_equal(gpu, ref: "oracle.Records"):
     bad = np.nonzero((c32 != q32).any(axis=1))[0]
     assert len(bad) == 0, f"{len(bad)} conic mismatches, e.g. " + str(
         [(int(i), gpu["conic"][i].tolist(), ref.conic[i].tolist()) for i in bad[:3]])
-    np.testing.assert_allclose(gpu["rgb"], ref.rgb, rtol=1e-6, atol=2e-6)
+    # colours are compared where the record has tiles: the GPU evaluates the
+    # view-dependent colour only for Gaussians that can be blended
+    has = ref.counts > 0
+    np.testing.assert_allclose(gpu["rgb"][has], ref.rgb[has], rtol=1e-6, atol=2e-6)
     bad = np.nonzero(gpu["counts"] != ref.counts)[0]
     assert len(bad) == 0, f"{len(bad)} count mismatches " + str(first_diffs(gpu["counts"],
                                                                             ref.counts))
 
 
 CULLED_KEY = np.uint32(0xFFFFFFFF)
+
+# Floor on the fraction of pixels the image comparison covers: the oracle
+# excludes only pixels whose inclusion or stop decision lies inside an FP32
+# rounding band (at most 0.1 % of any tested frame).
+MIN_COMPARED = 0.999
 
 
 def expected_depth_keys(rec: "oracle.Records") -> np.ndarray:
@@ -175,4 +183,6 @@ def assert_pipeline_equal(gpu, fr, image_tol=1e-4):
         assert np.array_equal(gpu["n_last"][ok], fr.n_last[ok])
         assert np.array_equal(gpu["n_eval"][ok], fr.n_eval[ok])
         assert np.array_equal(gpu["n_contrib"][ok], fr.n_contrib[ok])
-        assert ok.mean() > 0.999
+        print(f"[parity] compared pixels {ok.mean():.6f} "
+              f"({int((~ok).sum())} flagged ambiguous of {ok.size})", flush=True)
+        assert ok.mean() >= MIN_COMPARED
