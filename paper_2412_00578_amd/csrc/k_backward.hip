@@ -611,8 +611,9 @@ hipError_t launch_backward(const ss_camera& cam, const ss_gaussians& g, const ss
     if (g.n > 0) {
         BwdIn in{g.means, g.scales, g.quats, g.opacity, g.sh, g.sh_degree, g.sh_stride};
         BwdOut o{out.means, out.scales, out.quats, out.opacity, out.sh};
-        const bool rows = ((uintptr_t)g.sh & 15u) == 0 && ((3 * g.sh_stride) & 3) == 0 &&
-                          g.sh_stride <= 16;
+        // float4 row loads and stores need both SH arrays 16-byte aligned
+        const bool rows = ((uintptr_t)g.sh & 15u) == 0 && ((uintptr_t)out.sh & 15u) == 0 &&
+                          ((3 * g.sh_stride) & 3) == 0 && g.sh_stride <= 16;
         hipLaunchKernelGGL(rows ? k_preprocess_bwd<true> : k_preprocess_bwd<false>,
                            dim3((unsigned)((g.n + kPbBlock - 1) / kPbBlock)),
                            dim3(kPbBlock), 0, s, cam, in, g.n,

@@ -413,16 +413,21 @@ class Grads:
 
 
 def backward(g: Gaussians, cam, out: RenderOutput, dl_drgb: torch.Tensor,
-             want_score: bool = False) -> Grads:
-    """Adjoint of a forward render `out` (from Renderer.render(..., full=True))."""
+             want_score: bool = False, sh_out: torch.Tensor | None = None) -> Grads:
+    """Adjoint of a forward render `out` (from Renderer.render(..., full=True)).
+    sh_out: optional caller-owned [n, K, 3] float32 buffer (any 4-byte
+    alignment) that receives dL/dh."""
     c = make_camera(cam)
     dev = g.device
     dl = dl_drgb.contiguous().to(torch.float32)
+    if sh_out is not None and (tuple(sh_out.shape) != tuple(g.sh.shape) or
+                               not sh_out.is_contiguous() or sh_out.dtype != torch.float32):
+        raise ValueError("sh_out must be a contiguous float32 tensor shaped like the SH")
     if tuple(dl.shape) != (3, c.height, c.width):
         raise ValueError(f"dl_drgb must be [3, {c.height}, {c.width}]")
     n = g.n
     gr = Grads(torch.empty_like(g.means), torch.empty_like(g.scales), torch.empty_like(g.quats),
-               torch.empty_like(g.opacity), torch.empty_like(g.sh),
+               torch.empty_like(g.opacity), torch.empty_like(g.sh) if sh_out is None else sh_out,
                torch.empty((n, 12), dtype=torch.float32, device=dev),
                torch.empty(n, dtype=torch.float32, device=dev) if want_score else None)
     st = _lib.SSGrads()

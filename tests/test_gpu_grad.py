@@ -94,6 +94,27 @@ def test_backward_sh_rows_of_odd_length(ss, gpu_device):
     _compare(got, want)
 
 
+def test_backward_into_misaligned_sh_gradient(ss, gpu_device):
+    # dL/dh written into a view 4 bytes past a 16-byte boundary: the adjoint
+    # takes its scalar-store path and must give the same gradients.
+    sc, cam = scenegen.scene_c3_fd(), scenegen.camera_fd()
+    g = ss.Gaussians.from_scene(sc, gpu_device)
+    out = ss.Renderer(gpu_device).render(g, cam, "accutile", full=True)
+    w = torch.as_tensor(np.random.default_rng(8).standard_normal((3, cam.height, cam.width)),
+                        dtype=torch.float32, device=gpu_device)
+    ref = ss.backward(g, cam, out, w)
+    buf = torch.zeros(g.sh.numel() + 4, dtype=torch.float32, device=gpu_device)
+    view = buf[1:1 + g.sh.numel()].view(g.sh.shape)
+    assert view.data_ptr() % 16 == 4
+    got = ss.backward(g, cam, out, w, sh_out=view)
+    torch.cuda.synchronize()
+    # the per-Gaussian sums are atomics, so two runs agree to rounding only
+    for k in ("sh", "means"):
+        a, b = getattr(got, k).double(), getattr(ref, k).double()
+        assert float((a - b).norm() / b.norm()) <= 1e-6, k
+    assert float(buf[0]) == 0.0 and float(buf[-3]) == 0.0
+
+
 def test_autograd_function_l1_loss(ss, gpu_device):
     # torch autograd through the activations: scales = exp(log_s), opacity = sigmoid(logit).
     sc, cam = scenegen.scene_c3_fd(), scenegen.camera_fd()
