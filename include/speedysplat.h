@@ -60,7 +60,7 @@
 extern "C" {
 #endif
 
-#define SS_ABI_VERSION 3
+#define SS_ABI_VERSION 4
 
 enum ss_status {
     SS_OK = 0,
@@ -397,11 +397,13 @@ int ss_batch_finish(const ss_batch_item *items, int32_t n_items, int32_t mode,
  * transmittance from the stored final T.  out->g2d and out->score are
  * zeroed and accumulated with FP32 atomics (their summation order varies
  * between runs); the parameter gradients are then written per Gaussian.
- * Culled Gaussians get zero gradients.
+ * Culled Gaussians get zero gradients.  `events` (may be NULL) are recorded
+ * at [0] the start, [1] after zeroing g2d and score, [2] after the blend
+ * adjoint (stage 7), [3] after the preprocess adjoint (stage 8).
  */
 int ss_render_backward(const ss_camera *cam, const ss_gaussians *g, const ss_frame *frame,
                        const ss_pairs *pairs, int32_t buf, const float *dl_drgb,
-                       const ss_grads *out, void *stream);
+                       const ss_grads *out, const ss_stage_events *events, void *stream);
 
 #ifdef __cplusplus
 }

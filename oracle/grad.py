@@ -137,9 +137,10 @@ def masks_fp64(rec, order, pixels):
 
 
 def masks_from_tiled(fr, cam, order, pixels):
-    """Contribution masks from the FP32 tiled oracle frame `fr` (the decisions
-    the GPU makes): Gaussian i contributes at pixel p iff it sits in p's tile
-    list before n_last and passes the FP32 q <= t test."""
+    """Contribution masks from the tiled oracle frame `fr` (the decisions the
+    GPU makes): Gaussian i contributes at pixel p iff it sits in p's tile list
+    before n_last and passes the q <= t test, q the record's quadratic form in
+    FP64 at the pixel centre."""
     pos = {int(g): k for k, g in enumerate(order)}
     incl = np.zeros((len(pixels), len(order)), bool)
     geom, conic = fr.records.geom, fr.records.conic
@@ -147,14 +148,14 @@ def masks_from_tiled(fr, cam, order, pixels):
         tile = (py // 16) * cam.tiles_x + (px // 16)
         s, e = fr.ranges[tile]
         nl = int(fr.n_last[py, px])
-        fxp, fyp = np.float32(px) + np.float32(0.5), np.float32(py) + np.float32(0.5)
+        fxp, fyp = px + 0.5, py + 0.5
         for j in range(s, s + nl):
             i = int(fr.sorted_values[j])
-            dx = fxp - geom[i, 0]
-            dy = fyp - geom[i, 1]
-            qq = ((conic[i, 0] * dx) * dx + (conic[i, 2] * dy) * dy) + \
-                ((np.float32(2.0) * conic[i, 1]) * dx) * dy
-            if qq <= geom[i, 3]:
+            dx = fxp - float(geom[i, 0])
+            dy = fyp - float(geom[i, 1])
+            a, b, c = (float(x) for x in conic[i, :3])
+            qq = (a * dx * dx + c * dy * dy) + 2.0 * b * dx * dy
+            if qq <= float(geom[i, 3]):
                 incl[r, pos[i]] = True
     return incl
 

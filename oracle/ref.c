@@ -452,25 +452,28 @@ void orc_ranges(int64_t p, const uint64_t *keys, int64_t n_tiles, uint32_t *rang
 }
 
 /*
- * Blend one tile front to back (FP32).  For each pixel centre
- * (px + 0.5, py + 0.5):  q = ((a dx) dx + (c dy) dy) + ((2b) dx) dy, each
- * operation rounded once; a Gaussian is included when q <= t (alpha >= 1/255);
- * alpha = min(0.99, sigma exp(-q/2)); the walk stops before a Gaussian that
- * would take the transmittance below 1e-4.  Output planar [3,H,W].
+ * Blend one tile front to back.  For each pixel centre (px + 0.5, py + 0.5),
+ * with dx, dy its offsets from the record's centre (one FP64 subtraction
+ * each), the quadratic form q = (a dx^2 + c dy^2) + 2b dx dy of the stored
+ * record is evaluated in FP64 and a Gaussian is included when q <= t
+ * (alpha >= 1/255): the same inequality, on the same record and in the same
+ * precision, as the tile geometry, so a pixel is included only where its
+ * tile was assigned.  alpha = min(0.99, sigma exp(-q/2)) in FP32 from q
+ * rounded to FP32; the walk stops before a Gaussian that would take the
+ * transmittance below 1e-4; colours accumulate in FP32.  Output planar [3,H,W].
  *
- * ambig[] (optional) marks the pixels where another faithful FP32
- * implementation may decide differently:
- *  - inclusion: q is a sum of three terms (a dx^2, c dy^2, 2b dx dy).  Any FP32
- *    evaluation in which each term passes through at most four roundings
- *    (this order: two products and two sums; a fused form: fewer) lies within
- *    gamma_4 * S of the exact q, S = |a| dx^2 + |c| dy^2 + 2 |b dx dy|,
- *    gamma_4 = 4u / (1 - 4u), u = 2^-24.  The exact q is taken in FP64 (its
- *    own error is below 4 * 2^-53 * S, and twice that is added); when |q_64 - t| is within that band for
- *    any pair the pixel evaluated, the q <= t decision is not fixed by the
- *    definition and the pixel is flagged.
- *  - stop: the relative error of T that exp can cause is tracked as err, each
- *    unclamped alpha adding 16 ulp * alpha / (1 - alpha); a stop test within
- *    T_MIN * (err + 4 ulp) of the threshold is flagged.
+ * ambig[] (optional) marks the pixels where another faithful implementation
+ * may decide differently:
+ *  - inclusion: any FP64 evaluation of q with at most four roundings per term
+ *    lies within gamma_4 * S of the exact q (S = |a| dx^2 + |c| dy^2 +
+ *    2 |b dx dy|, gamma_4 = 4v / (1 - 4v), v = 2^-53); a pair whose q lies
+ *    within twice that of t is flagged.
+ *  - stop: the relative error of T that another faithful alpha can cause is
+ *    tracked as err.  alpha may differ by 16 FP32 ulp through exp and, where
+ *    two FP64 values of q round to neighbouring FP32 values, by half an ulp of
+ *    q times q; each alpha not clamped on both sides adds that relative error
+ *    times alpha / (1 - alpha), and a stop test within T_MIN * (err + 4 ulp)
+ *    of the threshold is flagged.
  * n_contrib (optional) counts the Gaussians blended into each pixel.
  */
 static void blend_tile(const orc_cam *cam, int tx, int ty, const uint32_t *ranges,
@@ -487,26 +490,25 @@ static void blend_tile(const orc_cam *cam, int tx, int ty, const uint32_t *range
             uint32_t last = 0, evals = end - start, contrib = 0;
             int amb = 0;
             double err = 0.0;
-            const double ulp = ldexp(1.0, -24);
-            const double gam_q = 4.0 * ulp / (1.0 - 4.0 * ulp) + 8.0 * ldexp(1.0, -53);
-            float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
+            const double ulp = ldexp(1.0, -24), v = ldexp(1.0, -53);
+            const double gam_q = 2.0 * (4.0 * v / (1.0 - 4.0 * v));
+            double fx = (double)px + 0.5, fy = (double)py + 0.5;
             for (uint32_t j = start; j < end; ++j) {
                 uint32_t i = values[j];
                 const float *g = geom + 4 * (int64_t)i, *q = conic + 4 * (int64_t)i;
-                float dx = fx - g[0], dy = fy - g[1];
-                float qq = ((q[0] * dx) * dx + (q[2] * dy) * dy) + ((2.0f * q[1]) * dx) * dy;
-                {
-                    double ddx = dx, ddy = dy, a = q[0], b = q[1], c = q[2];
-                    double q64 = (a * ddx * ddx + c * ddy * ddy) + 2.0 * b * ddx * ddy;
-                    double mag = fabs(a) * ddx * ddx + fabs(c) * ddy * ddy + 2.0 * fabs(b * ddx * ddy);
-                    if (fabs(q64 - (double)g[3]) <= gam_q * mag + 0x1p-140) amb = 1;
-                }
-                if (!(qq <= g[3])) continue;
-                float al = q[3] * expf(-0.5f * qq);
-                if (al > ORC_ALPHA_MAX) al = ORC_ALPHA_MAX;
+                double dx = fx - (double)g[0], dy = fy - (double)g[1];
+                double a = q[0], b = q[1], c = q[2], t = g[3];
+                double q64 = (a * dx * dx + c * dy * dy) + 2.0 * b * dx * dy;
+                double mag = fabs(a) * dx * dx + fabs(c) * dy * dy + 2.0 * fabs(b * dx * dy);
+                if (fabs(q64 - t) <= gam_q * mag + 0x1p-1000) amb = 1;
+                if (!(q64 <= t)) continue;
+                float qq = (float)q64;
+                float raw = q[3] * expf(-0.5f * qq);
+                float al = raw > ORC_ALPHA_MAX ? ORC_ALPHA_MAX : raw;
                 float tn = T * (1.0f - al);
-                if (q[3] * expf(-0.5f * qq) <= ORC_ALPHA_MAX * (1.0f + 32.0f * (float)ulp))
-                    err += 16.0 * ulp * (double)al / (1.0 - (double)al);
+                double rel_al = 16.0 * ulp + 0.5 * ulp * fabs((double)qq);
+                if ((double)raw <= (double)ORC_ALPHA_MAX * (1.0 + 2.0 * rel_al))
+                    err += rel_al * (double)al / (1.0 - (double)al);
                 if (fabs((double)tn - (double)ORC_T_MIN) <= (double)ORC_T_MIN * (err + 4.0 * ulp))
                     amb = 1;
                 if (tn < ORC_T_MIN) {
@@ -562,8 +564,9 @@ void orc_blend(const float *campack, const uint32_t *ranges, const uint32_t *val
  * considered at pixels whose tile lies in its tile rectangle for that mode
  * (the 3-sigma restricted reference); rect_mode < 0 considers every record.
  * ambig[k] is set when an inclusion or stop decision lay in its rounding band
- * (inclusion: |q - t| within 8 ulp32 of the magnitude of q's terms; stop: a
- * relative 1e-3 of the threshold).  Output rgb[k*3 + ch].
+ * (inclusion: |q - t| within 16 FP64 ulp of the magnitude of q's terms, which
+ * covers two FP64 evaluations of q in different orders; stop: a relative 1e-3
+ * of the threshold).  Output rgb[k*3 + ch].
  */
 void orc_brute_pixels(const float *campack, int64_t n, const float *geom, const float *conic,
                       const float *rgb, const int64_t *order, int64_t n_order, int rect_mode,
@@ -578,7 +581,7 @@ void orc_brute_pixels(const float *campack, int64_t n, const float *geom, const 
             orc_tile_rect(geom + 4 * i, conic + 4 * i, rect_mode, cam.tiles_x, cam.tiles_y,
                           rects + 4 * i);
     }
-    const double gam = 8.0 * ldexp(1.0, -24);
+    const double gam = 16.0 * ldexp(1.0, -53);
     for (int64_t k = 0; k < n_pix; ++k) {
         int px = pix[2 * k], py = pix[2 * k + 1];
         int tx = px / ORC_TILE, ty = py / ORC_TILE;

@@ -122,7 +122,7 @@ PROTOTYPES = {
                         _P(SSPairs), _P(SSFrameCounts), _P(ctypes.c_int32), _P(SSStageEvents),
                         _vp],
     "ss_render_backward": [_P(SSCamera), _P(SSGaussians), _P(SSFrame), _P(SSPairs),
-                           ctypes.c_int32, _vp, _P(SSGrads), _vp],
+                           ctypes.c_int32, _vp, _P(SSGrads), _P(SSStageEvents), _vp],
 }
 RESTYPES = {"ss_status_string": ctypes.c_char_p, "ss_last_error": ctypes.c_char_p}
 

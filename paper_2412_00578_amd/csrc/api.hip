@@ -499,7 +499,7 @@ int ss_batch_finish(const ss_batch_item* items, int32_t n_items, int32_t mode, c
 
 int ss_render_backward(const ss_camera* cam, const ss_gaussians* g, const ss_frame* f,
                        const ss_pairs* p, int32_t buf, const float* dl_drgb, const ss_grads* out,
-                       void* stream) {
+                       const ss_stage_events* events, void* stream) {
     SS_TRY(check_camera(cam));
     SS_TRY(check_gaussians(g));
     SS_TRY(check_frame_records(f, g->n));
@@ -511,7 +511,8 @@ int ss_render_backward(const ss_camera* cam, const ss_gaussians* g, const ss_fra
                      !out->g2d))
         return fail(SS_ERR_INVALID_ARG, "a gradient buffer is NULL");
     return hip_status(
-        ss::launch_backward(*cam, *g, *f, p->values[buf], dl_drgb, *out, (hipStream_t)stream),
+        ss::launch_backward(*cam, *g, *f, p->values[buf], dl_drgb, *out,
+                            events ? events->ev : nullptr, (hipStream_t)stream),
         "backward");
 }
 

@@ -88,7 +88,7 @@ __device__ __forceinline__ uint32_t wave_max_u32(uint32_t x) {
     return x;
 }
 
-// Bit s: the Gaussian's ellipse box, widened by 1% (more than the FP32
+// Bit s: the Gaussian's ellipse box, widened by 1% (far more than the FP64
 // rounding of q for a conic whose eigenvalue ratio is bounded as tested), meets
 // strip s of tile (tx, ty).  Pixel centres outside the box never pass q <= t,
 // so a Gaussian whose mask misses every strip of the wave is skipped whole.
@@ -120,9 +120,11 @@ __global__ __launch_bounds__(64 * (4 / SPW)) void k_blend_bwd(
     const uint32_t* __restrict__ n_last, const float* __restrict__ dl_drgb,
     float* __restrict__ g2d, float* __restrict__ score) {
     constexpr int kWaves = 4 / SPW;
-    __shared__ float4 s_geo[kWaves][kBatch];   // (u, v, strip mask bits, t)
-    __shared__ float4 s_con[kWaves][kBatch];   // (a, 2b, c, sigma)
-    __shared__ float4 s_col[kWaves][kBatch];   // (r, g, b, -)
+    __shared__ double2 s_uv[kWaves][kBatch];   // (u, v)
+    __shared__ double2 s_ab[kWaves][kBatch];   // (a, 2b)
+    __shared__ double2 s_ct[kWaves][kBatch];   // (c, t)
+    __shared__ float4 s_col[kWaves][kBatch];   // (r, g, b, sigma)
+    __shared__ uint32_t s_mask[kWaves][kBatch];  // strip mask bits
     __shared__ uint32_t s_idx[kWaves][kBatch];
     const int tile = xcd_contiguous((int)blockIdx.x, n_tiles);
     if (tile < 0) return;
@@ -132,15 +134,16 @@ __global__ __launch_bounds__(64 * (4 / SPW)) void k_blend_bwd(
     const int tx = tile % tx_n, ty = tile / tx_n;
     const int px = tx * kTile + (lane & 15);
     const int py0 = ty * kTile + 4 * strip0 + (lane >> 4);
-    const float fx = (float)px + 0.5f;
+    const double fx = (double)px + 0.5;
     const size_t hw = (size_t)W * (size_t)H;
-    float fy[SPW], T[SPW], R[SPW][3], dC[SPW][3];
+    double fy[SPW];
+    float T[SPW], R[SPW][3], dC[SPW][3];
     uint32_t nl[SPW];
     uint32_t jmax = 0u;
 #pragma unroll
     for (int s = 0; s < SPW; ++s) {
         const int py = py0 + 4 * s;
-        fy[s] = (float)py + 0.5f;
+        fy[s] = (double)py + 0.5;
         const bool in = px < W && py < H;
         const size_t p = in ? (size_t)py * W + px : 0;
         nl[s] = in ? n_last[p] : 0u;
@@ -162,10 +165,12 @@ __global__ __launch_bounds__(64 * (4 / SPW)) void k_blend_bwd(
         const uint32_t cnt = hi - lo;
         if ((uint32_t)lane < cnt) {
             const uint32_t gi = values[start + lo + lane];
-            const float4 g = geom[gi], q = conic[gi];
-            s_geo[w][lane] = make_float4(g.x, g.y, __uint_as_float(strip_mask_b(g, q, tx, ty)), g.w);
-            s_con[w][lane] = make_float4(q.x, 2.0f * q.y, q.z, q.w);
-            s_col[w][lane] = rgb[gi];
+            const float4 g = geom[gi], q = conic[gi], c = rgb[gi];
+            s_uv[w][lane] = make_double2(g.x, g.y);
+            s_ab[w][lane] = make_double2(q.x, 2.0 * (double)q.y);
+            s_ct[w][lane] = make_double2(q.z, g.w);
+            s_col[w][lane] = make_float4(c.x, c.y, c.z, q.w);
+            s_mask[w][lane] = strip_mask_b(g, q, tx, ty);
             s_idx[w][lane] = gi;
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -173,25 +178,30 @@ __global__ __launch_bounds__(64 * (4 / SPW)) void k_blend_bwd(
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         for (int k = (int)cnt - 1; k >= 0; --k) {
             const uint32_t j = lo + (uint32_t)k;
-            const float4 g = s_geo[w][k];
-            uint32_t m = __builtin_amdgcn_readfirstlane(__float_as_uint(g.z));
+            uint32_t m = __builtin_amdgcn_readfirstlane(s_mask[w][k]);
             if (!(m & (((1u << SPW) - 1u) << strip0))) continue;
-            const float4 q = s_con[w][k];
+            const double2 uv = s_uv[w][k];
+            const double2 ab = s_ab[w][k];
+            const double2 ct = s_ct[w][k];
             const float4 c = s_col[w][k];
-            const float dx = fx - g.x;
-            const float adx2 = (q.x * dx) * dx;
-            const float b2dx = q.y * dx;
+            // the forward's inclusion test, bit for bit (FP64 on the record)
+            const double dx64 = fx - uv.x;
+            const double adx2 = (ab.x * dx64) * dx64;
+            const double b2dx = ab.y * dx64;
+            const float dx = (float)dx64;
+            const float qa = (float)ab.x, qb2 = (float)ab.y, qc = (float)ct.x, sig = c.w;
             float gu = 0.f, gv = 0.f, ga = 0.f, gb = 0.f, gc = 0.f, gs = 0.f;
             float gr = 0.f, gg = 0.f, gbl = 0.f, sc = 0.f;
             bool any = false;
 #pragma unroll
             for (int s = 0; s < SPW; ++s) {
-                const float dy = fy[s] - g.y;
-                const float qq = fmaf(dy, fmaf(q.z, dy, b2dx), adx2);
-                if (j < nl[s] && qq <= g.w) {
+                const double dy64 = fy[s] - uv.y;
+                const double q64 = fma(fma(ct.x, dy64, b2dx), dy64, adx2);
+                if (j < nl[s] && q64 <= ct.y) {
                     any = true;
+                    const float qq = (float)q64, dy = (float)dy64;
                     const float gval = __builtin_amdgcn_exp2f(qq * kNegHalfLog2e);  // exp(-q/2)
-                    const float araw = q.w * gval;
+                    const float araw = sig * gval;
                     const float al = fminf(kAlphaMax, araw);
                     // hardware reciprocal (about 1 ulp): the recurrence runs over the
                     // pixel's blended Gaussians only, well inside the gradients' tolerance
@@ -211,13 +221,13 @@ __global__ __launch_bounds__(64 * (4 / SPW)) void k_blend_bwd(
                     gs = fmaf(dau, gval, gs);
                     const float dq = -0.5f * al * dau;
                     // q = a dx^2 + 2b dx dy + c dy^2 with dx = px - u, dy = py - v
-                    gu += dq * -(2.0f * q.x * dx + q.y * dy);
-                    gv += dq * -(q.y * dx + 2.0f * q.z * dy);
+                    gu += dq * -(2.0f * qa * dx + qb2 * dy);
+                    gv += dq * -(qb2 * dx + 2.0f * qc * dy);
                     ga = fmaf(dq, dx * dx, ga);
                     gb = fmaf(dq, 2.0f * dx * dy, gb);
                     gc = fmaf(dq, dy * dy, gc);
                     if (SCORE) {
-                        const float k0 = araw < kAlphaMax ? q.w * tb : 0.0f;
+                        const float k0 = araw < kAlphaMax ? sig * tb : 0.0f;
                         sc += k0 * k0 * (e0 * e0 + e1 * e1 + e2 * e2);
                     }
                 }
@@ -589,9 +599,13 @@ __global__ __launch_bounds__(kPbBlock) void k_preprocess_bwd(ss_camera cam, BwdI
 
 hipError_t launch_backward(const ss_camera& cam, const ss_gaussians& g, const ss_frame& f,
                            const uint32_t* values, const float* dl_drgb, const ss_grads& out,
-                           hipStream_t s) {
+                           void* const* ev, hipStream_t s) {
     const int tx_n = (cam.width + kTile - 1) / kTile, ty_n = (cam.height + kTile - 1) / kTile;
     const int n_tiles = tx_n * ty_n;
+    auto mark = [&](int k) {
+        if (ev && ev[k]) (void)hipEventRecord((hipEvent_t)ev[k], s);
+    };
+    mark(0);
     if (g.n > 0) {
         const int64_t m = g.n * 12;
         hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s,
@@ -600,6 +614,7 @@ hipError_t launch_backward(const ss_camera& cam, const ss_gaussians& g, const ss
             hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)((g.n + 255) / 256)), dim3(256), 0, s,
                                out.score, g.n);
     }
+    mark(1);
     const int grid = 8 * ((n_tiles + 7) / 8);
     hipLaunchKernelGGL((out.score ? k_blend_bwd<4, true> : k_blend_bwd<4, false>), dim3(grid),
                        dim3(64), 0, s, tx_n, n_tiles, cam.width, cam.height, cam.bg[0],
@@ -608,6 +623,7 @@ hipError_t launch_backward(const ss_camera& cam, const ss_gaussians& g, const ss
                        reinterpret_cast<const float4*>(f.conic),
                        reinterpret_cast<const float4*>(f.rgb), f.t_final, f.n_last, dl_drgb,
                        out.g2d, out.score);
+    mark(2);
     if (g.n > 0) {
         BwdIn in{g.means, g.scales, g.quats, g.opacity, g.sh, g.sh_degree, g.sh_stride};
         BwdOut o{out.means, out.scales, out.quats, out.opacity, out.sh};
@@ -620,6 +636,7 @@ hipError_t launch_backward(const ss_camera& cam, const ss_gaussians& g, const ss
                            reinterpret_cast<const float4*>(f.conic),
                            reinterpret_cast<const float4*>(f.rgb), out.g2d, o);
     }
+    mark(3);
     return hipGetLastError();
 }
 

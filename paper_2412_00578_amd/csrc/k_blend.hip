@@ -17,12 +17,17 @@
 // finished.  Strips are not tested for liveness one by one: the scalar test
 // and branch per strip and Gaussian cost more issue slots than the four
 // vector operations a finished strip's failing q <= t test takes.  The
-// quadratic form is evaluated with two fused multiply-adds as
-// q = fma(dy, fma(c, dy, (2b) dx), (a dx) dx) and compared with the record's
-// t, so the inclusion test (alpha >= 1/255) is exact and reproducible.
-// alpha = sigma exp(-q/2) is evaluated as exp2(fma(q, -log2(e)/2, log2 sigma))
-// with log2 sigma taken once per staged record: one multiply fewer per
-// included strip, within the few-ulp error any faithful exp has.  An included
+// quadratic form of the stored record is evaluated in FP64, with dx and dy
+// from one subtraction each and q = fma(fma(c, dy, (2b) dx), dy, (a dx) dx),
+// and compared with the record's t: the inclusion test (alpha >= 1/255) is the
+// inequality the tile geometry decides in FP64 on the same record, so a pixel
+// is included only where its tile was assigned, and an ill-conditioned q (a
+// needle-like Gaussian seen along its long axis) keeps its accuracy.  FP64
+// adds and FMAs issue at the rate of FP32 ones, and the record is staged in
+// LDS already widened.  alpha = sigma exp(-q/2) is evaluated in FP32 as
+// exp2(fma(q, -log2(e)/2, log2 sigma)) with log2 sigma taken once per staged
+// record: one multiply fewer per included strip, within the few-ulp error any
+// faithful exp has.  An included
 // strip takes a short path when none of its pixels stops at this Gaussian
 // (wave-uniform test) and the full path, which freezes the stopping pixels,
 // otherwise.  Nothing on this path is a dense contraction, so it runs on the
@@ -33,7 +38,7 @@ namespace ss {
 namespace {
 
 constexpr int kBatch = 64;
-constexpr float kDone = 1e30f;                    // sample row of a finished pixel
+constexpr double kDone = 1e30;                    // sample row of a finished pixel
 constexpr float kNegHalfLog2e = -0.72134752044448170368f;  // -log2(e) / 2
 
 struct Rec {
@@ -42,7 +47,7 @@ struct Rec {
     float4 c;   // (r, g, b, -)
 };
 
-__device__ __forceinline__ bool unfinished(const float (&fy)[4]) {
+__device__ __forceinline__ bool unfinished(const double (&fy)[4]) {
     return fy[0] < kDone || fy[1] < kDone || fy[2] < kDone || fy[3] < kDone;
 }
 
@@ -207,9 +212,10 @@ __global__ __launch_bounds__(64) void k_blend(const Item* __restrict__ items, Ba
                                               uint32_t* __restrict__ n_last_all,
                                               uint32_t* __restrict__ n_eval_all,
                                               uint32_t* __restrict__ n_contrib_all) {
-    __shared__ float4 s_geo[kBatch];
-    __shared__ float4 s_con[kBatch];
-    __shared__ float4 s_col[kBatch];
+    __shared__ double2 s_uv[kBatch];     // (u, v)
+    __shared__ double2 s_ab[kBatch];     // (a, 2b)
+    __shared__ double2 s_ct[kBatch];     // (c, t)
+    __shared__ float4 s_col[kBatch];     // (r, g, b, log2 sigma)
     if ((int)blockIdx.x >= dims.n_tiles) return;
     const int tile = (int)tile_order[blockIdx.x];
     const Item& it = items[dims.n_items == 1 ? 0 : item_of_tile(items, dims.n_items, tile)];
@@ -226,13 +232,14 @@ __global__ __launch_bounds__(64) void k_blend(const Item* __restrict__ items, Ba
     const int tx = lt % tx_n, ty = lt / tx_n;
     const int px = tx * kTile + (lane & 15);
     const int py0 = ty * kTile + (lane >> 4);
-    const float fx = (float)px + 0.5f;
-    float fy[4], T[4], C[4][3];
+    const double fx = (double)px + 0.5;
+    double fy[4];
+    float T[4], C[4][3];
     uint32_t last[4], stop[4], ncon[4];
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
         const bool in = px < W && (py0 + 4 * s) < H;
-        fy[s] = in ? (float)(py0 + 4 * s) + 0.5f : kDone;
+        fy[s] = in ? (double)(py0 + 4 * s) + 0.5 : kDone;
         T[s] = 1.0f;
         C[s][0] = C[s][1] = C[s][2] = 0.0f;
         last[s] = 0u;
@@ -255,11 +262,11 @@ __global__ __launch_bounds__(64) void k_blend(const Item* __restrict__ items, Ba
         // slots past the list end hold a record whose q is 0 at every pixel
         // and whose t is -1, so it includes no pixel
         const bool real = base + (uint32_t)lane < end;
-        s_geo[lane] = real ? nxt.g : make_float4(0.0f, 0.0f, 0.0f, -1.0f);
-        s_con[lane] = real ? make_float4(nxt.q.x, 2.0f * nxt.q.y, nxt.q.z,
-                                         __builtin_amdgcn_logf(nxt.q.w))
-                           : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        s_col[lane] = nxt.c;
+        s_uv[lane] = real ? make_double2(nxt.g.x, nxt.g.y) : make_double2(0.0, 0.0);
+        s_ab[lane] = real ? make_double2(nxt.q.x, 2.0 * (double)nxt.q.y) : make_double2(0.0, 0.0);
+        s_ct[lane] = real ? make_double2(nxt.q.z, nxt.g.w) : make_double2(0.0, -1.0);
+        s_col[lane] = make_float4(nxt.c.x, nxt.c.y, nxt.c.z,
+                                  real ? __builtin_amdgcn_logf(nxt.q.w) : 0.0f);
         __syncthreads();
         nxt = load_rec(geom, conic, rgb, gid_nx);
         gid_nx = entry_gid(values, base + 2 * kBatch + lane, e_last);
@@ -272,20 +279,21 @@ __global__ __launch_bounds__(64) void k_blend(const Item* __restrict__ items, Ba
 #pragma unroll
             for (uint32_t u = 0; u < 8u; ++u) {
                 const uint32_t k = k0 + u;
-                const float4 g = s_geo[k];
-                const float4 q = s_con[k];
+                const double2 uv = s_uv[k];
+                const double2 ab = s_ab[k];
+                const double2 ct = s_ct[k];
                 const float4 c = s_col[k];
-                const float dx = fx - g.x;
-                const float adx2 = (q.x * dx) * dx;
-                const float b2dx = q.y * dx;
+                const double dx = fx - uv.x;
+                const double adx2 = (ab.x * dx) * dx;
+                const double b2dx = ab.y * dx;
                 const uint32_t pos = base + k - start + 1u;
 #pragma unroll
                 for (int s = 0; s < 4; ++s) {
-                    const float dy = fy[s] - g.y;
-                    const float qq = fmaf(dy, fmaf(q.z, dy, b2dx), adx2);
-                    if (qq <= g.w) {
-                        const float al =
-                            fminf(kAlphaMax, __builtin_amdgcn_exp2f(fmaf(qq, kNegHalfLog2e, q.w)));
+                    const double dy = fy[s] - uv.y;
+                    const double qq = fma(fma(ct.x, dy, b2dx), dy, adx2);
+                    if (qq <= ct.y) {
+                        const float al = fminf(kAlphaMax, __builtin_amdgcn_exp2f(
+                                                              fmaf((float)qq, kNegHalfLog2e, c.w)));
                         float tn = T[s] * (1.0f - al);
                         float wgt = al * T[s];
                         uint32_t lp = pos;

@@ -393,6 +393,6 @@ hipError_t launch_blend(const Item* items, const BatchDims& d, const ss_frame& f
                         const uint32_t* values, float* out_rgb_single, hipStream_t s);
 hipError_t launch_backward(const ss_camera& cam, const ss_gaussians& g, const ss_frame& f,
                            const uint32_t* values, const float* dl_drgb, const ss_grads& out,
-                           hipStream_t s);
+                           void* const* ev, hipStream_t s);
 
 }  // namespace ss

@@ -149,6 +149,29 @@ class Pairs:
 STAGES = ("preprocess", "readback", "depth_order", "scan", "emit", "sort", "ranges", "blend")
 
 
+class BackwardEvents:
+    """Four timing events ss_render_backward records: start, after zeroing the
+    accumulators, after the blend adjoint, after the preprocess adjoint."""
+
+    def __init__(self, device):
+        self.events = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        s = torch.cuda.current_stream(device)
+        for e in self.events:  # creates the underlying hipEvent_t
+            e.record(s)
+        s.synchronize()
+
+    def struct(self) -> _lib.SSStageEvents:
+        st = _lib.SSStageEvents()
+        for k, e in enumerate(self.events):
+            st.ev[k] = e.cuda_event
+        return st
+
+    def ms(self) -> dict:
+        e = self.events
+        return {"zero": e[0].elapsed_time(e[1]), "blend_bwd": e[1].elapsed_time(e[2]),
+                "preprocess_bwd": e[2].elapsed_time(e[3])}
+
+
 class StageEvents:
     """Nine timing events recorded by the library at stage boundaries."""
 
@@ -413,10 +436,12 @@ class Grads:
 
 
 def backward(g: Gaussians, cam, out: RenderOutput, dl_drgb: torch.Tensor,
-             want_score: bool = False, sh_out: torch.Tensor | None = None) -> Grads:
+             want_score: bool = False, sh_out: torch.Tensor | None = None,
+             events: "BackwardEvents | None" = None) -> Grads:
     """Adjoint of a forward render `out` (from Renderer.render(..., full=True)).
     sh_out: optional caller-owned [n, K, 3] float32 buffer (any 4-byte
-    alignment) that receives dL/dh."""
+    alignment) that receives dL/dh.  events: optional BackwardEvents that time
+    the blend adjoint and the preprocess adjoint."""
     c = make_camera(cam)
     dev = g.device
     dl = dl_drgb.contiguous().to(torch.float32)
@@ -437,6 +462,7 @@ def backward(g: Gaussians, cam, out: RenderOutput, dl_drgb: torch.Tensor,
     gs, fs, ps = g.struct(), out.frame.struct(), out.pairs.struct()
     check(lib().ss_render_backward(ctypes.byref(c), ctypes.byref(gs), ctypes.byref(fs),
                                    ctypes.byref(ps), out.buf, _ptr(dl), ctypes.byref(st),
+                                   ctypes.byref(events.struct()) if events else None,
                                    _stream(dev)), "ss_render_backward")
     return gr
 

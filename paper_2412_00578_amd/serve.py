@@ -97,7 +97,11 @@ class Scheduler:
         self.sleep = sleep
         self.max_retries = max_retries
 
-    def run(self, requests: list[Request]) -> ServeStats:
+    def run(self, requests: list[Request], skip: int = 0) -> ServeStats:
+        """Serves every request; the statistics cover the requests after the
+        first `skip` arrivals (a warm-up that still loads the server), with the
+        rate taken from the first counted arrival to the last counted
+        completion."""
         reqs = sorted(requests, key=lambda r: r.arrival)
         t0 = self.clock()
         now = lambda: self.clock() - t0
@@ -175,8 +179,13 @@ class Scheduler:
                 self.sleep(max(0.0, min(t_next - now(), 1e-4)))
             elif nxt < len(reqs):
                 self.sleep(max(0.0, reqs[nxt].arrival - now()))
-        lat = np.array([(r.t_done - r.arrival) * 1e3 for r in reqs if r.status == "done"])
-        return ServeStats(len(reqs), now(), lat, sizes, peak, failed, requeued)
+        counted = reqs[skip:]
+        lat = np.array([(r.t_done - r.arrival) * 1e3 for r in counted if r.status == "done"])
+        wall = now()
+        if skip and counted:
+            wall = max(r.t_done for r in counted) - counted[0].arrival
+        n_failed = sum(r.status == "failed" for r in counted)
+        return ServeStats(len(counted), wall, lat, sizes, peak, n_failed, requeued)
 
 
 class WorkspaceTooSmall(RuntimeError):
@@ -274,9 +283,10 @@ class GpuBackend:
 
 
 def serve(scenes, requests, device="cuda", mode="accutile", pool_bytes=16 << 30, max_batch=8,
-          slots=2, keep_images=False) -> ServeStats:
-    """Runs the request stream against resident scenes in real time."""
+          slots=2, keep_images=False, skip=0) -> ServeStats:
+    """Runs the request stream against resident scenes in real time; the
+    statistics leave out the first `skip` arrivals."""
     backend = GpuBackend(scenes, device, mode, keep_images)
     sched = Scheduler(backend, pool_bytes, max_batch, slots)
     backend.sync_reference(sched.clock)
-    return sched.run(requests)
+    return sched.run(requests, skip)

@@ -109,55 +109,53 @@ def test_autograd_equals_finite_differences():
     print(f"checked {checked}, skipped {skipped}, worst relative error {worst:.2e}")
 
 
-def _fma32_exact(a, b, c):
-    """Correctly rounded (to nearest, ties to even) FP32 value of a*b + c,
-    from exact rational arithmetic."""
+def _fma64_exact(a, b, c):
+    """Correctly rounded FP64 value of a*b + c: exact rational arithmetic, then
+    CPython's correctly rounded integer division."""
     from fractions import Fraction
-    x = Fraction(float(a)) * Fraction(float(b)) + Fraction(float(c))
-    guess = np.float32(float(x))
-    cands = [np.nextafter(guess, np.float32(-np.inf)), guess,
-             np.nextafter(guess, np.float32(np.inf))]
-    best = min(cands, key=lambda v: (abs(Fraction(float(v)) - x),
-                                     int(np.array(v).view(np.int32)) & 1))
-    return np.float32(best)
+    x = Fraction(a) * Fraction(b) + Fraction(c)
+    return x.numerator / x.denominator
 
 
-def test_inclusion_band_covers_faithful_fp32_orders():
-    """The blend's inclusion-ambiguity band: any FP32 evaluation of
-    q = a dx^2 + 2b dx dy + c dy^2 in which each term passes through at most
-    four roundings lies within gamma_4 * S of the exact q (S = the sum of the
-    terms' magnitudes, gamma_4 = 4u/(1-4u), u = 2^-24).  Checked against exact
-    rationals for the unfused order the oracle uses and for a fused
-    multiply-add order (correctly rounded FMAs from exact arithmetic), on
-    random forms and on forms built to sit next to a threshold."""
+def test_inclusion_band_covers_faithful_fp64_orders():
+    """The blend's inclusion-ambiguity band: the quadratic form of an FP32
+    record, q = a dx^2 + 2b dx dy + c dy^2 with dx, dy FP64 offsets of an FP32
+    pixel centre, evaluated in FP64 in any order with at most four roundings
+    per term, lies within gamma_4 * S of the exact q (S = the sum of the terms'
+    magnitudes, gamma_4 = 4v/(1-4v), v = 2^-53).  Checked against exact
+    rationals for the oracle's unfused order and for a fused multiply-add
+    order, on random forms (including needle-like, ill-conditioned ones) and
+    on thresholds placed just outside the band, where both orders must decide
+    as the exact q does."""
     from fractions import Fraction as F
-    u = 2.0 ** -24
-    gam = 4 * u / (1 - 4 * u)
+    v = 2.0 ** -53
+    gam = 4 * v / (1 - 4 * v)
     rng = np.random.default_rng(12)
     worst = 0.0
     for k in range(3000):
         a, c = np.abs(rng.standard_normal(2)).astype(np.float32) * np.float32(rng.choice([1e-3, 0.1, 3]))
-        b = np.float32(rng.uniform(-0.99, 0.99) * np.sqrt(float(a) * float(c)))
-        dx, dy = (rng.standard_normal(2) * rng.choice([0.5, 5, 40])).astype(np.float32)
-        q_o14 = ((a * dx) * dx + (c * dy) * dy) + ((np.float32(2) * b) * dx) * dy
-        q_fma = _fma32_exact(dy, _fma32_exact(c, dy, (np.float32(2) * b) * dx), (a * dx) * dx)
-        exact = (F(float(a)) * F(float(dx)) ** 2 + 2 * F(float(b)) * F(float(dx)) * F(float(dy))
-                 + F(float(c)) * F(float(dy)) ** 2)
-        S = (abs(F(float(a))) * F(float(dx)) ** 2 + 2 * abs(F(float(b)) * F(float(dx)) * F(float(dy)))
-             + abs(F(float(c))) * F(float(dy)) ** 2)
-        for q in (q_o14, q_fma):
-            err = abs(F(float(q)) - exact)
+        rho = rng.choice([rng.uniform(-0.99, 0.99), 1.0 - 10.0 ** -rng.uniform(3, 7)])
+        b = np.float32(rho * np.sqrt(float(a) * float(c)))
+        u, vv = (rng.uniform(-50, 1650, 2)).astype(np.float32)
+        px, py = rng.integers(0, 1600, 2)
+        dx, dy = (px + 0.5) - float(u), (py + 0.5) - float(vv)   # exact in FP64
+        A, B, C = float(a), float(b), float(c)
+        q_o = (A * dx * dx + C * dy * dy) + 2.0 * B * dx * dy
+        q_f = _fma64_exact(_fma64_exact(C, dy, (2.0 * B) * dx), dy, (A * dx) * dx)
+        exact = F(A) * F(dx) ** 2 + 2 * F(B) * F(dx) * F(dy) + F(C) * F(dy) ** 2
+        S = abs(F(A)) * F(dx) ** 2 + 2 * abs(F(B) * F(dx) * F(dy)) + abs(F(C)) * F(dy) ** 2
+        for q in (q_o, q_f):
+            err = abs(F(q) - exact)
             assert err <= F(gam) * S, (k, a, b, c, dx, dy, q)
             if S > 0:
-                worst = max(worst, float(err / S) / u)
-        # a threshold just beyond the band on either side: both orders decide as exact
-        t_in = np.float32(float(exact) + 1.01 * gam * float(S))
-        t_out = np.float32(float(exact) - 1.01 * gam * float(S))
-        if F(float(t_in)) - exact > F(gam) * S:
-            assert q_o14 <= t_in and q_fma <= t_in
-        if exact - F(float(t_out)) > F(gam) * S:
-            assert not (q_o14 <= t_out) and not (q_fma <= t_out)
-    print(f"worst |fl(q) - q| / S = {worst:.2f} u (bound {gam / u:.2f} u)")
+                worst = max(worst, float(err / S) / v)
+        t_in = float(exact) + 2.01 * gam * float(S)
+        t_out = float(exact) - 2.01 * gam * float(S)
+        if F(t_in) - exact > F(gam) * S:
+            assert q_o <= t_in and q_f <= t_in
+        if exact - F(t_out) > F(gam) * S:
+            assert not (q_o <= t_out) and not (q_f <= t_out)
+    print(f"worst |fl(q) - q| / S = {worst:.2f} ulp64 (bound {gam / v:.2f})")
 
 
 def test_oracle_flags_a_pixel_on_the_inclusion_threshold():

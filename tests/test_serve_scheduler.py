@@ -174,3 +174,16 @@ def test_idle_server_sleeps_until_arrivals():
     st = _sched(be, clock).run(reqs)
     assert reqs[0].t_start >= 5.0 and reqs[1].t_start >= 10.0
     assert math.isclose(st.pct(50), 1.5, rel_tol=0.01)  # each alone: 1 ms + 0.5 ms
+
+
+def test_warmup_arrivals_are_served_but_not_counted():
+    clock = FakeClock()
+    be = MockBackend(clock, {0: 10})
+    arr = np.arange(60) * 2e-3
+    reqs = _reqs(arr, [0] * 60)
+    st = _sched(be, clock).run(reqs, skip=20)
+    assert all(r.status == "done" for r in reqs)     # the warm-up is still served
+    assert st.n == 40 and len(st.latencies_ms) == 40
+    want = np.array([(r.t_done - r.arrival) * 1e3 for r in reqs[20:]])
+    assert np.allclose(np.sort(st.latencies_ms), np.sort(want))
+    assert st.wall_s == pytest.approx(max(r.t_done for r in reqs[20:]) - reqs[20].arrival)
