@@ -12,8 +12,8 @@
  * --------------------------------
  * - Every array argument is DEVICE memory owned by the caller, C-contiguous,
  *   at least 16-byte aligned (torch allocations are).  The library never
- *   allocates, frees or keeps device memory and keeps no state between calls
- *   other than its loaded kernels.
+ *   allocates or frees device memory and keeps no state between calls other
+ *   than its loaded kernels and the static scratch array of ss_sort_noalloc.
  * - `stream` is a hipStream_t (NULL = the null stream).  Every call only
  *   enqueues work on it and returns; outputs are valid once the stream has
  *   been synchronised.  The exceptions, which synchronise `stream` to read the
@@ -285,6 +285,23 @@ int ss_emit(const ss_camera *cam, int64_t n, int64_t n_visible, int32_t mode,
  */
 int ss_sort(const ss_camera *cam, const ss_pairs *pairs, int32_t buf, uint64_t n_pairs,
             int32_t *out_buf, void *stream);
+
+/*
+ * ss_sort for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * sort, arguments, result and errors, but the sort's scratch (one pass's
+ * per-workgroup digit counts and digit totals) lives in a static device array
+ * of the library, 1 MiB + 1 KiB on each GPU it runs on, held until the
+ * process ends; pairs->sort_tmp is not read and may be NULL.  The keys and
+ * values buffers are still the caller's.  The scratch needed does not grow
+ * with the pair count (at most 2^32 - 2 pairs, as for ss_sort); a larger need
+ * would return SS_ERR_WORKSPACE.  The first call on a device looks up the
+ * array's address for that device (the current device, which must be the
+ * stream's).  Calls that overlap on one GPU share the array and race:
+ * serialise them (one stream, or events).  Allocates nothing.
+ */
+int ss_sort_noalloc(const ss_camera *cam, const ss_pairs *pairs, int32_t buf, uint64_t n_pairs,
+                    int32_t *out_buf, void *stream);
 
 /*
  * Stage 5, per-tile ranges of the sorted keys (Sec. 3.2.2, "identifyTileRanges"):

@@ -101,6 +101,8 @@ PROTOTYPES = {
                 _P(SSPairs), ctypes.c_int32, ctypes.c_uint64, _vp],
     "ss_sort": [_P(SSCamera), _P(SSPairs), ctypes.c_int32, ctypes.c_uint64,
                 _P(ctypes.c_int32), _vp],
+    "ss_sort_noalloc": [_P(SSCamera), _P(SSPairs), ctypes.c_int32, ctypes.c_uint64,
+                        _P(ctypes.c_int32), _vp],
     "ss_ranges": [_P(SSCamera), _P(SSFrame), _P(SSPairs), ctypes.c_int32, ctypes.c_uint64, _vp],
     "ss_blend": [_P(SSCamera), _P(SSFrame), _P(SSPairs), ctypes.c_int32, _vp, _vp],
     "ss_forward_begin": [_P(SSCamera), _P(SSGaussians), ctypes.c_int32, _P(SSFrame),

@@ -386,6 +386,28 @@ int ss_sort(const ss_camera* cam, const ss_pairs* p, int32_t buf, uint64_t n_pai
     return st;
 }
 
+int ss_sort_noalloc(const ss_camera* cam, const ss_pairs* p, int32_t buf, uint64_t n_pairs,
+                    int32_t* out_buf, void* stream) {
+    SS_TRY(check_camera(cam));
+    if (!p) return fail(SS_ERR_INVALID_ARG, "pairs is NULL");
+    ss_pairs q = *p;
+    q.sort_tmp = reinterpret_cast<uint32_t*>(q.keys[0]);   // unused; satisfies the NULL check
+    SS_TRY(check_pairs(&q, buf, n_pairs));
+    if (!out_buf) return fail(SS_ERR_INVALID_ARG, "out_buf is NULL");
+    if (ss::sort_tmp_words(n_pairs) > ss::static_sort_tmp_words())
+        return fail(SS_ERR_WORKSPACE,
+                    "sorting %llu pairs needs %lld scratch words; the static scratch holds %lld",
+                    (unsigned long long)n_pairs, (long long)ss::sort_tmp_words(n_pairs),
+                    (long long)ss::static_sort_tmp_words());
+    int tx, ty;
+    const int bits = sort_bits_for(tiles_of(cam, &tx, &ty));
+    int ob = buf;
+    int st = hip_status(ss::launch_sort_static(q, buf, n_pairs, bits, &ob, (hipStream_t)stream),
+                        "sort (static scratch)");
+    *out_buf = ob;
+    return st;
+}
+
 int ss_ranges(const ss_camera* cam, const ss_frame* f, const ss_pairs* p, int32_t buf,
               uint64_t n_pairs, void* stream) {
     SS_TRY(check_camera(cam));

@@ -23,6 +23,8 @@
 //            counts live in LDS), reorders the sub-tile by digit in LDS and
 //            writes every digit run to its global offset with consecutive
 //            lanes on consecutive addresses.
+#include <mutex>
+
 #include "ss_internal.h"
 
 namespace ss {
@@ -389,11 +391,44 @@ hipError_t radix_sort(K* keys[2], uint32_t* vals[2], int cur, uint64_t n0, uint6
     return hipGetLastError();
 }
 
+// Scratch of ss_sort_noalloc: one pass's per-workgroup digit counts and digit
+// totals (kRadix x kMaxGrid + kRadix words, 1 MiB + 1 KiB, whatever the pair
+// count), held on every GPU the library runs on until the process ends.  Every
+// word a pass reads is written by that pass's k_hist and k_dscan first, so
+// nothing needs clearing between calls; calls that overlap on one GPU share
+// it and race.  In host code `scratch` names a host-side stand-in: kernels
+// receive the device address hipGetSymbolAddress returns for the current
+// device, looked up once per device.
+constexpr int64_t kStaticSortWords = (int64_t)kRadix * kMaxGrid + kRadix;
+static __device__ __align__(256) uint32_t scratch[kStaticSortWords];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+uint32_t* g_scratch_ptr[kMaxDevices] = {};
+
+hipError_t static_sort_scratch(uint32_t** out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = static_cast<uint32_t*>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+
 }  // namespace
 
 int sort_passes(int bits) { return (bits + 7) / 8; }
 
 int64_t sort_tmp_words(uint64_t) { return (int64_t)kRadix * kMaxGrid + kRadix; }
+
+int64_t static_sort_tmp_words() { return kStaticSortWords; }
 
 hipError_t launch_depth_order(int64_t n, int64_t n_visible, const ss_frame& f, hipStream_t s) {
     if (n <= 0 || n_visible <= 0) return hipSuccess;
@@ -419,6 +454,15 @@ hipError_t launch_sort(const ss_pairs& p, int buf, uint64_t n, int bits, int* ou
     }
     return radix_sort<uint32_t>(keys, vals, buf, n, n, bits, p.sort_tmp, false, false, true,
                                 nullptr, nullptr, nullptr, out_buf, s);
+}
+
+hipError_t launch_sort_static(const ss_pairs& p, int buf, uint64_t n, int bits, int* out_buf,
+                              hipStream_t s) {
+    if (sort_tmp_words(n) > kStaticSortWords) return hipErrorInvalidValue;
+    ss_pairs q = p;
+    const hipError_t e = static_sort_scratch(&q.sort_tmp);
+    if (e != hipSuccess) return e;
+    return launch_sort(q, buf, n, bits, out_buf, s);
 }
 
 hipError_t launch_ranges(const uint32_t* keys, uint64_t n, int n_tiles, uint32_t* ranges,

@@ -381,6 +381,12 @@ int64_t sort_tmp_words(uint64_t capacity);
 int sort_passes(int bits);
 hipError_t launch_sort(const ss_pairs& p, int buf, uint64_t n_pairs, int bits, int* out_buf,
                        hipStream_t s);
+// launch_sort with the sort scratch in the library's static device array (the
+// caller's p.sort_tmp is not used): hipErrorInvalidValue if the pass needs more
+// than static_sort_tmp_words(), or the runtime's error looking it up.
+hipError_t launch_sort_static(const ss_pairs& p, int buf, uint64_t n_pairs, int bits,
+                              int* out_buf, hipStream_t s);
+int64_t static_sort_tmp_words();
 hipError_t launch_ranges(const uint32_t* keys, uint64_t n_pairs, int n_tiles, uint32_t* ranges,
                          hipStream_t s);
 // launch_blend = launch_tile_order (the tiles' work order, from the ranges)
