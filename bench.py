@@ -277,6 +277,39 @@ def frame_bytes(n, v, p, tiles, width, height):
             "ranges": p * RANGES_BYTES_PER_PAIR + tiles * RANGES_BYTES_PER_TILE}
 
 
+def band_bench(ss, g, cams, steps, warmup, n_bands=8):
+    """The benchmark frame split into n_bands bands of tile rows, as n_bands
+    GPUs would render it (ss_render_band: every Gaussian preprocessed, only
+    the band's tiles rendered), each band timed one by one on this GPU with
+    stage events: the per-band ms, the slowest band (the split frame's
+    critical path, before the image gather) and the per-stage times of the
+    middle band."""
+    import numpy as np
+    import torch
+    cam0 = cams[0]
+    bounds = np.linspace(0, cam0.tiles_y, n_bands + 1).round().astype(int)
+    r = ss.Renderer(g.device)
+    res = {"workload": f"the AccuTile benchmark frame split into {n_bands} bands of tile rows "
+                       f"{bounds.tolist()}, each rendered alone over the 8 cameras",
+           "band_ms": []}
+    for b, (b0, b1) in enumerate(zip(bounds[:-1], bounds[1:])):
+        for w in range(warmup):
+            r.render_band(g, cams[w % len(cams)], "accutile", int(b0), int(b1 - b0))
+        evs = [ss.StageEvents(g.device) for _ in range(steps)]
+        torch.cuda.synchronize()
+        for k in range(steps):
+            r.render_band(g, cams[k % len(cams)], "accutile", int(b0), int(b1 - b0),
+                          events=evs[k])
+        torch.cuda.synchronize()
+        st = {s: statistics.mean(e.stage_ms()[s] for e in evs) for s in ss.STAGES}
+        res["band_ms"].append(round(sum(st.values()), 4))
+        if b == n_bands // 2:
+            res["middle_band_stage_ms"] = {k: round(v, 4) for k, v in st.items()}
+    res["slowest_band_ms"] = max(res["band_ms"])
+    log(f"bands: {res}")
+    return res
+
+
 def c2_bench(ss, dev, modes, warmup):
     """The 150k-Gaussian scene over 64 random orbit cameras, frames one by one:
     ms per frame and the cost per Gaussian-tile pair and per evaluated
@@ -586,6 +619,7 @@ def main():
     }
     if not args.no_extra:
         line["backward"] = backward_bench(ss, g, cams, max(args.steps // 3, 5), args.warmup)
+        line["bands_8"] = band_bench(ss, g, cams, max(args.steps // 3, 5), args.warmup)
         line["c2_150k_64_cameras"] = c2_bench(ss, dev, modes, args.warmup)
         line["c3_forward_backward"] = c3_bench(ss, dev, max(args.steps // 3, 5), args.warmup)
     if not args.no_serve:

@@ -378,6 +378,28 @@ int ss_render(const ss_camera *cam, const ss_gaussians *g, int32_t mode, const s
               const ss_pairs *pairs, float *out_rgb, ss_frame_counts *counts_out,
               int32_t *out_buf, const ss_stage_events *events, void *stream);
 
+/*
+ * SYNC.  The forward render of one band of tile rows [tile_row0, tile_row0 +
+ * tile_rows) of the camera's image: the piece of a frame one GPU renders
+ * when a frame is split across GPUs by screen-space bands (the tile pipeline
+ * of Sec. 3.2 restricted to a viewport).  Every Gaussian is preprocessed for
+ * the whole camera, exactly as by ss_render; only tiles in the band's rows
+ * are counted, emitted, sorted, given ranges and blended, and the band's
+ * tile ids, per-pixel buffers and image are relative to its first row:
+ * tile id = (ty - tile_row0) * tiles_x + tx, pixel row py - 16 tile_row0.
+ * The band's pairs, ranges and pixels equal the whole frame's restricted to
+ * the band, bit for bit.  `frame` is sized by ss_frame_sizes(n, width,
+ * band_height), band_height = min(height, 16 (tile_row0 + tile_rows)) -
+ * 16 tile_row0, and out_rgb is [3, band_height, width].  Errors as for
+ * ss_render (SS_ERR_WORKSPACE with *counts_out set when the pair workspace is
+ * too small), and SS_ERR_INVALID_ARG for a band outside the image.  The
+ * adjoint (ss_render_backward) takes whole frames only.
+ */
+int ss_render_band(const ss_camera *cam, const ss_gaussians *g, int32_t mode, int32_t tile_row0,
+                   int32_t tile_rows, const ss_frame *frame, const ss_pairs *pairs,
+                   float *out_rgb, ss_frame_counts *counts_out, int32_t *out_buf,
+                   const ss_stage_events *events, void *stream);
+
 /* Sizes for a batch of n_items (1 .. 4096) items. */
 int ss_batch_sizes(const ss_batch_item *items, int32_t n_items, ss_batch_info *out);
 

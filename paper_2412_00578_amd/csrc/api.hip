@@ -145,6 +145,8 @@ ss::Item make_item(const ss_camera& cam, const ss_gaussians& g, float* out) {
     it.sh_degree = g.sh_degree; it.sh_stride = g.sh_stride;
     it.tx_n = (cam.width + ss::kTile - 1) / ss::kTile;
     it.ty_n = (cam.height + ss::kTile - 1) / ss::kTile;
+    it.by0 = 0;
+    it.by1 = it.ty_n;
     return it;
 }
 
@@ -184,6 +186,20 @@ Layout single_layout(const ss_camera& cam, const ss_gaussians& g) {
     L.d.n_tiles = L.items[0].tx_n * L.items[0].ty_n;
     L.d.n_slots = g.n;
     L.d.n_pixels = (int64_t)cam.width * cam.height;
+    return L;
+}
+
+// A single frame restricted to the tile rows [row0, row0 + rows): every
+// Gaussian is preprocessed, but only the band's tiles get pairs, and the
+// per-tile and per-pixel buffers and the image cover the band's rows.
+Layout band_layout(const ss_camera& cam, const ss_gaussians& g, int row0, int rows) {
+    Layout L = single_layout(cam, g);
+    ss::Item& it = L.items[0];
+    it.by0 = row0;
+    it.by1 = row0 + rows;
+    const int y_end = cam.height < it.by1 * ss::kTile ? cam.height : it.by1 * ss::kTile;
+    L.d.n_tiles = it.tx_n * rows;
+    L.d.n_pixels = (int64_t)cam.width * (y_end - row0 * ss::kTile);
     return L;
 }
 
@@ -485,6 +501,30 @@ int ss_render(const ss_camera* cam, const ss_gaussians* g, int32_t mode, const s
         return fail(SS_ERR_WORKSPACE, "%llu pairs exceed the workspace capacity %llu",
                     (unsigned long long)c.n_pairs, (unsigned long long)p->capacity);
     return ss_forward_finish(cam, g->n, mode, f, p, &c, out_rgb, out_buf, ev, stream);
+}
+
+int ss_render_band(const ss_camera* cam, const ss_gaussians* g, int32_t mode, int32_t tile_row0,
+                   int32_t tile_rows, const ss_frame* f, const ss_pairs* p, float* out_rgb,
+                   ss_frame_counts* counts_out, int32_t* out_buf, const ss_stage_events* ev,
+                   void* stream) {
+    SS_TRY(check_camera(cam));
+    SS_TRY(check_gaussians(g));
+    if (!p) return fail(SS_ERR_INVALID_ARG, "pairs is NULL");
+    if (!out_rgb) return fail(SS_ERR_INVALID_ARG, "out_rgb is NULL");
+    int tx, ty;
+    tiles_of(cam, &tx, &ty);
+    if (tile_row0 < 0 || tile_row0 >= ty || tile_rows < 1 || tile_rows > ty - tile_row0)
+        return fail(SS_ERR_INVALID_ARG, "band rows [%d, %d) outside the %d tile rows",
+                    tile_row0, tile_row0 + tile_rows, ty);
+    const Layout L = band_layout(*cam, *g, tile_row0, tile_rows);
+    const hipStream_t s = (hipStream_t)stream;
+    ss_frame_counts c{};
+    SS_TRY(begin_impl(L, mode, f, &c, ev, true, s));
+    if (counts_out) *counts_out = c;
+    if (c.n_pairs > p->capacity)
+        return fail(SS_ERR_WORKSPACE, "%llu pairs exceed the workspace capacity %llu",
+                    (unsigned long long)c.n_pairs, (unsigned long long)p->capacity);
+    return finish_impl(L.d, mode, f, p, &c, out_rgb, out_buf, ev, s);
 }
 
 int ss_batch_sizes(const ss_batch_item* items, int32_t n_items, ss_batch_info* out) {

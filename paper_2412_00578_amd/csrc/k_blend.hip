@@ -227,9 +227,10 @@ __global__ __launch_bounds__(64) void k_blend(const Item* __restrict__ items, Ba
     uint32_t* __restrict__ n_eval = STATS ? n_eval_all + it.pix_off : nullptr;
     uint32_t* __restrict__ n_contrib =
         STATS && n_contrib_all ? n_contrib_all + it.pix_off : nullptr;
-    const int lt = tile - it.tile_off;      // tile within the item's image
+    const int lt = tile - it.tile_off;      // tile within the item's band of tile rows
     const int lane = (int)threadIdx.x;
-    const int tx = lt % tx_n, ty = lt / tx_n;
+    const int tx = lt % tx_n, ty = lt / tx_n + it.by0;
+    const int row0 = it.by0 * kTile;        // first image row of the band
     const int px = tx * kTile + (lane & 15);
     const int py0 = ty * kTile + (lane >> 4);
     const double fx = (double)px + 0.5;
@@ -322,12 +323,13 @@ __global__ __launch_bounds__(64) void k_blend(const Item* __restrict__ items, Ba
         }
         __syncthreads();
     }
-    const size_t hw = (size_t)W * (size_t)H;
+    const int rows = (H < it.by1 * kTile ? H : it.by1 * kTile) - row0;   // the band's rows
+    const size_t hw = (size_t)W * (size_t)rows;
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
         const int py = py0 + 4 * s;
         if (px < W && py < H) {
-            const size_t p = (size_t)py * W + px;
+            const size_t p = (size_t)(py - row0) * W + px;
             out[p] = C[s][0] + T[s] * bg0;
             out[hw + p] = C[s][1] + T[s] * bg1;
             out[2 * hw + p] = C[s][2] + T[s] * bg2;

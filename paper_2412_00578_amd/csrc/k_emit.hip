@@ -235,7 +235,7 @@ __global__ __launch_bounds__(kBigBlock) void k_emit_big(const Item* __restrict__
         Ellipse e;
         bool ok = false;
         uint32_t i = 0, pos0 = 0, end = 0, tile_off = 0;
-        int tx_n = 0, ty_n = 0;
+        int tx_n = 0, ty_n = 0, by0 = 0, by1 = 0;
         if (have) {
             // the segment holding queued entry b: the last with offset <= b,
             // between the segments holding entries 64 g and 64 (g + 1)
@@ -251,10 +251,12 @@ __global__ __launch_bounds__(kBigBlock) void k_emit_big(const Item* __restrict__
             const Item& it = items[dims.n_items == 1 ? 0 : item_of_slot(items, dims.n_items, i)];
             tx_n = it.tx_n;
             ty_n = it.ty_n;
+            by0 = it.by0;
+            by1 = it.by1;
             tile_off = (uint32_t)it.tile_off;
             pos0 = j > 0 ? offsets[j - 1] : 0u;
             end = offsets[j];
-            ok = ellipse_setup(geom[i], conic[i], mode, tx_n, ty_n, e);
+            ok = ellipse_setup(geom[i], conic[i], mode, tx_n, ty_n, by0, by1, e);
         }
         uint64_t todo = __ballot(ok);
         while (todo) {
@@ -267,6 +269,8 @@ __global__ __launch_bounds__(kBigBlock) void k_emit_big(const Item* __restrict__
             el.hx = __shfl(e.hx, L, 64); el.hy = __shfl(e.hy, L, 64);
             el.x0 = __shfl(e.x0, L, 64); el.x1 = __shfl(e.x1, L, 64);
             el.y0 = __shfl(e.y0, L, 64); el.y1 = __shfl(e.y1, L, 64);
+            el.cols = __shfl((int)e.cols, L, 64) != 0;
+            const int row0 = __shfl(by0, L, 64);    // the band's first tile row
             const uint32_t gi = __shfl(i, L, 64), p0 = __shfl(pos0, L, 64);
             const uint32_t pend = __shfl(end, L, 64), toff = __shfl(tile_off, L, 64);
             const int txn = __shfl(tx_n, L, 64), tyn = __shfl(ty_n, L, 64);
@@ -300,8 +304,9 @@ __global__ __launch_bounds__(kBigBlock) void k_emit_big(const Item* __restrict__
                         const int a = ab[h];
                         const int major = maj0 + c0 + a;
                         const int minor = s_lo[w][a] + (int)(ix - s_excl[w][a]);
-                        const uint32_t tile = toff + (cols ? (uint32_t)(minor * txn + major)
-                                                           : (uint32_t)(major * txn + minor));
+                        const uint32_t tile =
+                            toff + (cols ? (uint32_t)((minor - row0) * txn + major)
+                                         : (uint32_t)((major - row0) * txn + minor));
                         const uint32_t pos = p0 + done + ix;
                         if (ix < total && pos < pend && pos < limit) {
                             keys[pos] = tile;

@@ -107,7 +107,7 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(const Item* __restrict__ 
     const ss_camera cam = it.cam;
     const Inputs in{it.means, it.scales, it.quats, it.opacity, it.sh, it.sh_degree, it.sh_stride};
     const int64_t n = it.n;
-    const int tx_n = it.tx_n, ty_n = it.ty_n;
+    const int tx_n = it.tx_n, ty_n = it.ty_n, by0 = it.by0, by1 = it.by1;
     const int64_t first = slot0 - it.g_off;       // local index of this block's first lane
     const int64_t i = first + threadIdx.x;        // Gaussian of the item
     const int64_t o = slot0 + threadIdx.x;        // its record slot
@@ -238,7 +238,7 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(const Item* __restrict__ 
         }
         uint64_t mask;
         uint32_t origin;
-        const uint32_t cnt = rect_tile_set(g4, q4, mode, tx_n, ty_n, &mask, &origin);
+        const uint32_t cnt = rect_tile_set(g4, q4, mode, tx_n, ty_n, by0, by1, &mask, &origin);
         tsets[o] = make_uint4((uint32_t)mask, (uint32_t)(mask >> 32), origin, cnt);
         counts[o] = cnt;
         dkeys[o] = cnt ? __float_as_uint(g4.z) : kCulledKey;
@@ -249,8 +249,8 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(const Item* __restrict__ 
     if (mode == SS_TILE_ACCUTILE && __ballot(defer)) {   // wave-uniform
         uint64_t mask;
         uint32_t origin;
-        const uint32_t c = accutile_tile_set(defer, g4, q4, tx_n, ty_n, s_cnt, s_mask, &mask,
-                                             &origin);
+        const uint32_t c = accutile_tile_set(defer, g4, q4, tx_n, ty_n, by0, by1, s_cnt, s_mask,
+                                             &mask, &origin);
         if (defer) {
             cnt = c;
             tsets[o] = make_uint4((uint32_t)mask, (uint32_t)(mask >> 32), origin, cnt);

@@ -29,7 +29,8 @@ constexpr uint32_t kCulledKey = 0xffffffffu;  // depth-order key of a slot with 
 
 struct Ellipse {
     double u, v, a, b, c, t, det, hx, hy;
-    int x0, x1, y0, y1;  // inclusive tile rectangle
+    int x0, x1, y0, y1;  // inclusive tile rectangle (rows clipped to the frame's band)
+    bool cols;           // AccuTile walks columns (decided on the image's rectangle)
 };
 
 // Edge -> tile index: divide by the tile size, round down, clip to the grid.
@@ -46,10 +47,14 @@ __device__ __forceinline__ int tile_hi(double x, int n) {
     return (int)f;
 }
 
-// Sets up the record ellipse and the mode's tile rectangle.  False when the
-// record cannot touch a tile (culled record or rectangle outside the image).
+// Sets up the record ellipse and the mode's tile rectangle, then clips its rows
+// to the frame's band of tile rows [by0, by1) (the whole image: 0, ty_n).
+// AccuTile's walking direction is decided on the rectangle within the image,
+// before the band clip, so a band's tiles are exactly the image's tiles in
+// those rows.  False when the record cannot touch a tile of the band (culled
+// record, or rectangle outside the image or the band).
 __device__ __forceinline__ bool ellipse_setup(float4 g, float4 q, int mode, int tx_n, int ty_n,
-                                              Ellipse& e) {
+                                              int by0, int by1, Ellipse& e) {
     e.u = g.x; e.v = g.y; e.t = g.w;
     e.a = q.x; e.b = q.y; e.c = q.z;
     e.det = e.a * e.c - e.b * e.b;
@@ -74,6 +79,13 @@ __device__ __forceinline__ bool ellipse_setup(float4 g, float4 q, int mode, int 
     }
     e.x0 = tile_lo(xl, tx_n); e.x1 = tile_hi(xh, tx_n);
     e.y0 = tile_lo(yl, ty_n); e.y1 = tile_hi(yh, ty_n);
+    e.cols = mode == SS_TILE_ACCUTILE && (e.y1 - e.y0 > e.x1 - e.x0);
+    // A row band k of a clipped rectangle is evaluated exactly as in the whole
+    // image: its lower boundary is 16 (y0 + k) whether or not it is the first
+    // (16 y0 lies in [box bottom, box top] for every row but the rectangle's
+    // first), so clipping y0 changes no span.
+    e.y0 = e.y0 < by0 ? by0 : e.y0;
+    e.y1 = e.y1 > by1 - 1 ? by1 - 1 : e.y1;
     return e.x0 <= e.x1 && e.y0 <= e.y1;
 }
 
@@ -162,9 +174,10 @@ __device__ __forceinline__ bool accutile_band(const Ellipse& e, bool cols, int k
     return lo <= hi;
 }
 
-// AccuTile walks columns when the tile extent has more rows than columns.
+// AccuTile walks columns when the tile extent within the image has more rows
+// than columns.
 __device__ __forceinline__ bool span_columns(const Ellipse& e, int mode) {
-    return mode == SS_TILE_ACCUTILE && (e.y1 - e.y0 > e.x1 - e.x0);
+    return mode == SS_TILE_ACCUTILE && e.cols;
 }
 
 // Side of the tile window a tile set records: a record whose tile rectangle
@@ -177,15 +190,16 @@ constexpr int kSetSide = 8;
 // once per row) and *origin = x0 | y0 << 16; otherwise *mask = 0 (the emit
 // stage re-walks the rows).
 __device__ __forceinline__ uint32_t rect_tile_set(float4 g, float4 q, int mode, int tx_n,
-                                                  int ty_n, uint64_t* mask, uint32_t* origin) {
+                                                  int ty_n, int by0, int by1, uint64_t* mask,
+                                                  uint32_t* origin) {
     *mask = 0ull;
     *origin = 0u;
     Ellipse e;
-    if (!ellipse_setup(g, q, mode, tx_n, ty_n, e)) return 0u;
+    if (!ellipse_setup(g, q, mode, tx_n, ty_n, by0, by1, e)) return 0u;
     const uint32_t w = (uint32_t)(e.x1 - e.x0 + 1), h = (uint32_t)(e.y1 - e.y0 + 1);
     if (w <= (uint32_t)kSetSide && h <= (uint32_t)kSetSide) {
         *mask = ((1ull << w) - 1ull) * (0x0101010101010101ull >> (8u * (kSetSide - h)));
-        *origin = (uint32_t)e.x0 | ((uint32_t)e.y0 << 16);
+        *origin = (uint32_t)e.x0 | ((uint32_t)(e.y0 - by0) << 16);
     }
     return w * h;
 }
@@ -200,22 +214,24 @@ __device__ __forceinline__ uint32_t rect_tile_set(float4 g, float4 q, int mode, 
 // rect_tile_set does (all zero for a lane without `want`).  All 64 lanes of
 // the wave must call it.
 __device__ __forceinline__ uint32_t accutile_tile_set(bool want, float4 g, float4 q, int tx_n,
-                                                      int ty_n, uint32_t* s_cnt, uint32_t* s_mask,
-                                                      uint64_t* mask, uint32_t* origin) {
+                                                      int ty_n, int by0, int by1, uint32_t* s_cnt,
+                                                      uint32_t* s_mask, uint64_t* mask,
+                                                      uint32_t* origin) {
     const int lane = (int)__lane_id();
     Ellipse e;
     bool cols = false, fits = false;
     int nb = 0;
     *mask = 0ull;
     *origin = 0u;
-    if (want && ellipse_setup(g, q, SS_TILE_ACCUTILE, tx_n, ty_n, e)) {
+    if (want && ellipse_setup(g, q, SS_TILE_ACCUTILE, tx_n, ty_n, by0, by1, e)) {
         cols = span_columns(e, SS_TILE_ACCUTILE);
         nb = cols ? e.x1 - e.x0 + 1 : e.y1 - e.y0 + 1;
         fits = e.x1 - e.x0 < kSetSide && e.y1 - e.y0 < kSetSide;
-        if (fits) *origin = (uint32_t)e.x0 | ((uint32_t)e.y0 << 16);
+        if (fits) *origin = (uint32_t)e.x0 | ((uint32_t)(e.y0 - by0) << 16);
     } else {
         e.u = e.v = e.a = e.b = e.c = e.t = e.det = e.hx = e.hy = 0.0;
         e.x0 = e.x1 = e.y0 = e.y1 = 0;
+        e.cols = false;
     }
     // inclusive prefix sum of the band counts over the wave
     int incl = nb;
@@ -307,6 +323,8 @@ struct Item {
     int32_t sh_degree, sh_stride;
     int32_t tx_n, ty_n;   // tile grid of the item's image
     int32_t tile_off;     // first global tile id
+    int32_t by0, by1;     // the item's band of tile rows [by0, by1) (the image: 0, ty_n);
+                          // its tiles, pixels and image cover these rows only
     int32_t pad_;
 };
 

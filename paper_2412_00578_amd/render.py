@@ -262,6 +262,41 @@ class Renderer:
                                 int(buf.value))
         return out
 
+    def render_band(self, g: Gaussians, cam, mode, tile_row0: int, tile_rows: int,
+                    out: torch.Tensor | None = None, full: bool = False,
+                    events: "StageEvents | None" = None):
+        """Forward render of the band of tile rows [tile_row0, tile_row0 +
+        tile_rows) of the camera's image (ss_render_band): every Gaussian is
+        preprocessed, only the band's tiles are rendered.  Returns the band's
+        image [3, band_height, W] (or a RenderOutput with the band's frame and
+        pairs if full)."""
+        m = mode_id(mode)
+        c = make_camera(cam)
+        y_end = min(c.height, 16 * (tile_row0 + tile_rows))
+        bh = max(y_end - 16 * tile_row0, 1)
+        frame = self.frame_for(g.n, c.width, bh)
+        if out is None:
+            out = torch.empty((3, bh, c.width), dtype=torch.float32, device=self.device)
+        gs, fs = g.struct(), frame.struct()
+        counts = _lib.SSFrameCounts()
+        buf = ctypes.c_int32()
+        ev = events.struct() if events is not None else None
+        evp = ctypes.byref(ev) if ev is not None else None
+        for attempt in range(2):
+            pairs = self.pairs_for(counts.n_pairs)
+            ps = pairs.struct()
+            st = lib().ss_render_band(ctypes.byref(c), ctypes.byref(gs), m, int(tile_row0),
+                                      int(tile_rows), ctypes.byref(fs), ctypes.byref(ps),
+                                      _ptr(out), ctypes.byref(counts), ctypes.byref(buf), evp,
+                                      _stream(self.device))
+            if st != _lib.SS_ERR_WORKSPACE or attempt == 1:
+                check(st, "ss_render_band")
+                break
+        if full:
+            return RenderOutput(out, int(counts.n_pairs), int(counts.n_visible), frame, pairs,
+                                int(buf.value))
+        return out
+
     RING = 3   # frame buffers of render_many
 
     def render_many(self, g: Gaussians, cams, mode="accutile", outs=None) -> list:
