@@ -310,6 +310,95 @@ def band_bench(ss, g, cams, steps, warmup, n_bands=8):
     return res
 
 
+def pruning_demo(ss, dev, iters=3000):
+    """The pruning schedule of Sec. 4.2.2-4.2.3 (80 % soft prunes at 20/30/40 %
+    of training, 30 % hard prunes every 10 % from 50 %), scaled to `iters`
+    iterations, on a synthetic fit-to-target run through the autograd
+    function: a 300k-Gaussian model fitted with Adam and an L1 loss to eight
+    800x520 views of a different 100k-Gaussian scene.  Scores are summed over
+    the eight views before each prune; the Adam moments are compacted with
+    the parameters.  After each prune: Gaussians, render FPS at the training
+    resolution and PSNR over the views."""
+    import torch
+
+    import scenegen
+    from paper_2412_00578_amd import prune as pr
+    cams = scenegen.orbit_cameras(8, 12.0, 10.0, 800, 520)
+    gt = ss.Gaussians.from_scene(scenegen.scene_blobs(100_000, 60), dev)
+    rgt = ss.Renderer(dev)
+    targets = [rgt.render(gt, c, "accutile").clone() for c in cams]
+    sc = scenegen.scene_blobs(300_000, 61)
+    op = torch.tensor(sc.opacity).clamp(1e-4, 1 - 1e-4)
+    raw = [torch.tensor(sc.means), torch.tensor(sc.scales).log(), torch.tensor(sc.quats),
+           torch.log(op / (1 - op)), torch.tensor(sc.sh)]
+    params = [t.to(dev).requires_grad_(True) for t in raw]
+    lrs = (1e-3, 5e-3, 1e-3, 5e-2, 2.5e-3)
+
+    def make_opt(ps):
+        return torch.optim.Adam([{"params": [p], "lr": lr} for p, lr in zip(ps, lrs)], eps=1e-15)
+
+    opt = make_opt(params)
+    act = lambda ps: ss.Gaussians(ps[0].detach(), ps[1].detach().exp(), ps[2].detach(),
+                                  torch.sigmoid(ps[3].detach()), ps[4].detach(), 3)
+
+    def measure():
+        g = act(params)
+        r = ss.Renderer(dev)
+        mse = 0.0
+        for c, tgt in zip(cams, targets):
+            mse += float(((r.render(g, c, "accutile") - tgt) ** 2).mean()) / len(cams)
+        for c in cams:
+            r.render(g, c, "accutile")
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record()
+        for k in range(16):
+            r.render(g, cams[k % len(cams)], "accutile")
+        b.record()
+        torch.cuda.synchronize()
+        return {"gaussians": g.n, "fps": round(16000.0 / a.elapsed_time(b), 1),
+                "psnr_db": round(-10.0 * math.log10(max(mse, 1e-12)), 2)}
+
+    events = {it: (ratio, kind) for it, ratio, kind in pr.Schedule(total=iters).events()}
+    log_rows = [dict(iteration=0, kind="start", ratio=0.0, **measure())]
+    t0 = time.perf_counter()
+    for it in range(iters):
+        if it in events:
+            ratio, kind = events[it]
+            g = act(params)
+            score = sum(ss.pruning_score(g, c, "accutile") for c in cams)
+            keep = pr.select(score, ratio)
+            packed = pr.gather(ss.Gaussians(*[p.detach() for p in params], 3), keep)
+            state = [opt.state[p] for p in params]
+            moments = {m: pr.gather(ss.Gaussians(*[st[m] for st in state], 3), keep)
+                       for m in ("exp_avg", "exp_avg_sq")}
+            steps = [st["step"] for st in state]
+            fields = ("means", "scales", "quats", "opacity", "sh")
+            params = [getattr(packed, f).reshape((-1,) + tuple(p.shape[1:])).requires_grad_(True)
+                      for f, p in zip(fields, params)]
+            opt = make_opt(params)
+            for k, p in enumerate(params):
+                opt.state[p] = {"step": steps[k],
+                                "exp_avg": getattr(moments["exp_avg"], fields[k]).reshape(p.shape),
+                                "exp_avg_sq": getattr(moments["exp_avg_sq"],
+                                                      fields[k]).reshape(p.shape)}
+            row = dict(iteration=it, kind=kind, ratio=ratio, **measure())
+            log_rows.append(row)
+            log(f"prune: {row}")
+        k = it % len(cams)
+        img = ss.render(params[0], params[1].exp(), params[2], torch.sigmoid(params[3]),
+                        params[4], cams[k], "accutile")
+        loss = (img - targets[k]).abs().mean()
+        opt.zero_grad(set_to_none=True)
+        loss.backward()
+        opt.step()
+    log_rows.append(dict(iteration=iters, kind="end", ratio=0.0, **measure()))
+    return {"workload": f"fit of a 300k-Gaussian SH-3 model to eight 800x520 AccuTile views of a "
+                        f"100k-Gaussian scene, Adam, L1 loss, {iters} iterations, the paper's "
+                        f"schedule scaled by {iters}/30000",
+            "train_s": round(time.perf_counter() - t0, 1), "after_each_prune": log_rows}
+
+
 def c2_bench(ss, dev, modes, warmup):
     """The 150k-Gaussian scene over 64 random orbit cameras, frames one by one:
     ms per frame and the cost per Gaussian-tile pair and per evaluated
@@ -622,6 +711,7 @@ def main():
         line["bands_8"] = band_bench(ss, g, cams, max(args.steps // 3, 5), args.warmup)
         line["c2_150k_64_cameras"] = c2_bench(ss, dev, modes, args.warmup)
         line["c3_forward_backward"] = c3_bench(ss, dev, max(args.steps // 3, 5), args.warmup)
+        line["pruning"] = pruning_demo(ss, dev)
     if not args.no_serve:
         line["serving"] = serving_bench(ss, dev, args.serve_scale)
         line["serving_p50_ms"] = line["serving"]["poisson_0.8X_accutile"]["p50_ms"]

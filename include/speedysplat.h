@@ -444,6 +444,31 @@ int ss_render_backward(const ss_camera *cam, const ss_gaussians *g, const ss_fra
                        const ss_pairs *pairs, int32_t buf, const float *dl_drgb,
                        const ss_grads *out, const ss_stage_events *events, void *stream);
 
+/*
+ * Pruning (Sec. 4.2.2 Soft Pruning: a fraction of the Gaussians removed at
+ * scheduled points of training; Sec. 4.2.3 Hard Pruning: a constant fraction
+ * removed at fixed intervals), ranked by the efficient pruning score of
+ * Sec. 4.2.1 (ss_grads.score, summed over the views the caller chooses).
+ *
+ * ss_prune_count: *n_keep_out = n - floor(prune_ratio * n), the product taken
+ * in double precision; prune_ratio in [0, 1].
+ * ss_prune_tmp_words: uint32 words of scratch for ss_prune_select.
+ * ss_prune_select: keep_idx[0, n_keep) receives, in ascending order, the
+ * indices of the n_keep highest scores; a score that is NaN or <= 0 ranks as
+ * 0, and among equal scores at the threshold the lower indices are kept.
+ * score [n] f32, keep_idx [n_keep] u32 and tmp are device memory; n_keep is
+ * known on the host when the call returns (no synchronisation).
+ * ss_gather_gaussians: compacts the Gaussians to the kept ones: every
+ * parameter row j of `out` (n = n_keep, the input's SH degree and stride,
+ * caller-owned device arrays) receives row keep_idx[j] of `in`.
+ */
+int ss_prune_count(int64_t n, double prune_ratio, int64_t *n_keep_out);
+int ss_prune_tmp_words(int64_t n, int64_t *out_words);
+int ss_prune_select(const float *score, int64_t n, double prune_ratio, uint32_t *keep_idx,
+                    uint32_t *tmp, int64_t *n_keep_out, void *stream);
+int ss_gather_gaussians(const ss_gaussians *in, const uint32_t *keep_idx, int64_t n_keep,
+                        const ss_gaussians *out, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

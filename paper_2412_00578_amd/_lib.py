@@ -120,6 +120,10 @@ PROTOTYPES = {
     "ss_render_band": [_P(SSCamera), _P(SSGaussians), ctypes.c_int32, ctypes.c_int32,
                        ctypes.c_int32, _P(SSFrame), _P(SSPairs), _vp, _P(SSFrameCounts),
                        _P(ctypes.c_int32), _P(SSStageEvents), _vp],
+    "ss_prune_count": [ctypes.c_int64, ctypes.c_double, _P(ctypes.c_int64)],
+    "ss_prune_tmp_words": [ctypes.c_int64, _P(ctypes.c_int64)],
+    "ss_prune_select": [_vp, ctypes.c_int64, ctypes.c_double, _vp, _vp, _P(ctypes.c_int64), _vp],
+    "ss_gather_gaussians": [_P(SSGaussians), _vp, ctypes.c_int64, _P(SSGaussians), _vp],
     "ss_batch_sizes": [_P(SSBatchItem), ctypes.c_int32, _P(SSBatchInfo)],
     "ss_batch_begin": [_P(SSBatchItem), ctypes.c_int32, ctypes.c_int32, _P(SSFrame),
                        _P(SSFrameCounts), _P(SSStageEvents), _vp],

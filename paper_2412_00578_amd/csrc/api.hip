@@ -1,5 +1,6 @@
 // C ABI of the library (declared in include/speedysplat.h): argument checks on
 // the host, then asynchronous launches on the caller's stream.
+#include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
 #include <string.h>
@@ -557,6 +558,60 @@ int ss_batch_finish(const ss_batch_item* items, int32_t n_items, int32_t mode, c
     Layout L;
     SS_TRY(lay_out(items, n_items, L));
     return finish_impl(L.d, mode, f, p, counts, nullptr, out_buf, ev, (hipStream_t)stream);
+}
+
+int ss_prune_tmp_words(int64_t n, int64_t* out_words) {
+    if (!out_words) return fail(SS_ERR_INVALID_ARG, "out is NULL");
+    if (n < 0 || n > 0x7fffffffll) return fail(SS_ERR_INVALID_ARG, "n outside 0..2^31-1");
+    *out_words = ss::prune_tmp_words(n);
+    return SS_OK;
+}
+
+int ss_prune_count(int64_t n, double prune_ratio, int64_t* n_keep_out) {
+    if (!n_keep_out) return fail(SS_ERR_INVALID_ARG, "n_keep_out is NULL");
+    if (n < 0 || n > 0x7fffffffll) return fail(SS_ERR_INVALID_ARG, "n outside 0..2^31-1");
+    if (!(prune_ratio >= 0.0 && prune_ratio <= 1.0))
+        return fail(SS_ERR_INVALID_ARG, "prune ratio %g outside [0, 1]", prune_ratio);
+    const double pruned = floor(prune_ratio * (double)n);
+    *n_keep_out = n - (int64_t)pruned;
+    return SS_OK;
+}
+
+int ss_prune_select(const float* score, int64_t n, double prune_ratio, uint32_t* keep_idx,
+                    uint32_t* tmp, int64_t* n_keep_out, void* stream) {
+    int64_t n_keep = 0;
+    SS_TRY(ss_prune_count(n, prune_ratio, &n_keep));
+    if (n > 0 && (!score || !tmp || (n_keep > 0 && !keep_idx)))
+        return fail(SS_ERR_INVALID_ARG, "a pruning buffer is NULL");
+    *n_keep_out = n_keep;
+    return hip_status(ss::launch_prune_select(score, n, n_keep, keep_idx, tmp, (hipStream_t)stream),
+                      "prune select");
+}
+
+int ss_gather_gaussians(const ss_gaussians* in, const uint32_t* keep_idx, int64_t n_keep,
+                        const ss_gaussians* out, void* stream) {
+    SS_TRY(check_gaussians(in));
+    if (!out) return fail(SS_ERR_INVALID_ARG, "out is NULL");
+    if (n_keep < 0 || n_keep > in->n)
+        return fail(SS_ERR_INVALID_ARG, "n_keep %lld outside 0..%lld", (long long)n_keep,
+                    (long long)in->n);
+    if (out->n != n_keep || out->sh_degree != in->sh_degree || out->sh_stride != in->sh_stride)
+        return fail(SS_ERR_INVALID_ARG, "out must have n = n_keep and the input's SH layout");
+    if (n_keep == 0) return SS_OK;
+    if (!keep_idx || !out->means || !out->scales || !out->quats || !out->opacity || !out->sh)
+        return fail(SS_ERR_INVALID_ARG, "a gather buffer is NULL");
+    const hipStream_t s = (hipStream_t)stream;
+    SS_TRY(hip_status(ss::launch_gather(in->means, keep_idx, n_keep, 3, (float*)out->means, s),
+                      "gather means"));
+    SS_TRY(hip_status(ss::launch_gather(in->scales, keep_idx, n_keep, 3, (float*)out->scales, s),
+                      "gather scales"));
+    SS_TRY(hip_status(ss::launch_gather(in->quats, keep_idx, n_keep, 4, (float*)out->quats, s),
+                      "gather quats"));
+    SS_TRY(hip_status(ss::launch_gather(in->opacity, keep_idx, n_keep, 1, (float*)out->opacity, s),
+                      "gather opacity"));
+    return hip_status(ss::launch_gather(in->sh, keep_idx, n_keep, 3 * in->sh_stride,
+                                        (float*)out->sh, s),
+                      "gather sh");
 }
 
 int ss_render_backward(const ss_camera* cam, const ss_gaussians* g, const ss_frame* f,

@@ -415,6 +415,13 @@ hipError_t launch_blend_tiles(const Item* items, const BatchDims& d, const ss_fr
                               const uint32_t* values, float* out_rgb_single, hipStream_t s);
 hipError_t launch_blend(const Item* items, const BatchDims& d, const ss_frame& f,
                         const uint32_t* values, float* out_rgb_single, hipStream_t s);
+int64_t prune_tmp_words(int64_t n);
+// Kept indices (ascending) of the n_keep highest scores, ties to the lower index.
+hipError_t launch_prune_select(const float* score, int64_t n, int64_t n_keep, uint32_t* keep_idx,
+                               uint32_t* tmp, hipStream_t s);
+// dst[j, :] = src[idx[j], :] for rows of w floats, j < m.
+hipError_t launch_gather(const float* src, const uint32_t* idx, int64_t m, int w, float* dst,
+                         hipStream_t s);
 hipError_t launch_backward(const ss_camera& cam, const ss_gaussians& g, const ss_frame& f,
                            const uint32_t* values, const float* dl_drgb, const ss_grads& out,
                            void* const* ev, hipStream_t s);
