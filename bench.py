@@ -5,9 +5,10 @@ Workload: a 1.5M-Gaussian SH-degree-3 clustered scene (200 anisotropic blobs
 plus 10% uniform background in a 20-unit box) rendered at 1600x1040 with 16x16
 tiles from 8 orbit cameras (radius 12, 10 degrees elevation), all synthetic and
 seeded.  One step is one forward render of one frame: preprocess, depth
-order, scan, pair count read-back, key emission, tile sort, tile ranges and
-blend, bracketed by hipEvents from before the preprocess to after the blend
-(the paper's per-frame timing).  `value` is the AccuTile frame rate measured
+order, scan, key emission, tile sort, tile ranges and blend, timed frame after
+frame (the paper's per-frame timing); the stages after the preprocess read
+the frame counts on the device (ss_render_nosync), and the same frames with
+the counts read back to the host mid-frame (ss_render) are reported beside.  `value` is the AccuTile frame rate measured
 that way; each of the three tile assignments (3-sigma, SnugBox, AccuTile) is
 timed over the same frames of the same scene, and their ratios stand beside
 the paper's (Table 2: 1.82x SnugBox, 1.99x AccuTile on an RTX A5000).  The
@@ -238,24 +239,54 @@ def work_counters(ss, g, cams, mode):
     return P, V, E, I
 
 
-def time_frames(ss, r, g, cams, mode, steps, warmup):
-    """Frames one by one, each bracketed by the library's stage events; returns
-    (mean ms per frame over the whole run, mean stage ms)."""
+def time_frames(ss, r, g, cams, mode, steps, warmup, band=None, sync=False):
+    """Frames one by one, each a complete forward render of one camera.  The
+    frame time is measured over `steps` frames rendered back to back and
+    bracketed by two events (no events inside a frame); the stage times come
+    from a second pass over the same frames in which the library records its
+    nine stage events inside every frame (each recorded event costs the
+    stream a few microseconds).  Whole frames use ss_render_nosync (the host
+    queues each frame whole; every frame is checked afterwards to have fit
+    its pair workspace), or with sync=True ss_render, which reads the frame
+    counts back mid-frame.  Returns (mean ms per frame, mean stage ms, mean ms
+    per frame of the second pass)."""
     import torch
     dev = g.device
+    c0 = cams[0]
+    outs = [torch.empty((3, c0.height, c0.width), dtype=torch.float32, device=dev)
+            for _ in range(2)]
+    queued = []
+
+    def frame(k, events=None):
+        cam = cams[k % len(cams)]
+        if band is not None:
+            r.render_band(g, cam, mode, band[0], band[1], events=events)
+        elif sync:
+            r.render(g, cam, mode, out=outs[k % 2], events=events)
+        else:
+            queued.append(r.render_nosync(g, cam, mode, out=outs[k % 2], events=events))
+
+    for c in cams:                       # sizes the pair workspace for every camera
+        r.render(g, c, mode)
     for w in range(warmup):
-        r.render(g, cams[w % len(cams)], mode)
-    evs = [ss.StageEvents(dev) for _ in range(steps)]
+        frame(w)
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     start.record()
     for k in range(steps):
-        r.render(g, cams[k % len(cams)], mode, events=evs[k])
+        frame(k)
     stop.record()
     torch.cuda.synchronize()
     ms = start.elapsed_time(stop) / steps
+    evs = [ss.StageEvents(dev) for _ in range(steps)]
+    torch.cuda.synchronize()
+    for k in range(steps):
+        frame(k, evs[k])
+    torch.cuda.synchronize()
     stages = {s: statistics.mean(e.stage_ms()[s] for e in evs) for s in ss.STAGES}
     frame_ev = statistics.mean(sum(e.stage_ms().values()) for e in evs)
+    if not all(q.ok() for q in queued):
+        raise RuntimeError("a frame did not fit its pair workspace")
     return ms, stages, frame_ev
 
 
@@ -285,7 +316,6 @@ def band_bench(ss, g, cams, steps, warmup, n_bands=8):
     critical path, before the image gather) and the per-stage times of the
     middle band."""
     import numpy as np
-    import torch
     cam0 = cams[0]
     bounds = np.linspace(0, cam0.tiles_y, n_bands + 1).round().astype(int)
     r = ss.Renderer(g.device)
@@ -293,16 +323,9 @@ def band_bench(ss, g, cams, steps, warmup, n_bands=8):
                        f"{bounds.tolist()}, each rendered alone over the 8 cameras",
            "band_ms": []}
     for b, (b0, b1) in enumerate(zip(bounds[:-1], bounds[1:])):
-        for w in range(warmup):
-            r.render_band(g, cams[w % len(cams)], "accutile", int(b0), int(b1 - b0))
-        evs = [ss.StageEvents(g.device) for _ in range(steps)]
-        torch.cuda.synchronize()
-        for k in range(steps):
-            r.render_band(g, cams[k % len(cams)], "accutile", int(b0), int(b1 - b0),
-                          events=evs[k])
-        torch.cuda.synchronize()
-        st = {s: statistics.mean(e.stage_ms()[s] for e in evs) for s in ss.STAGES}
-        res["band_ms"].append(round(sum(st.values()), 4))
+        ms, st, _ = time_frames(ss, r, g, cams, "accutile", steps, warmup,
+                                band=(int(b0), int(b1 - b0)))
+        res["band_ms"].append(round(ms, 4))
         if b == n_bands // 2:
             res["middle_band_stage_ms"] = {k: round(v, 4) for k, v in st.items()}
     res["slowest_band_ms"] = max(res["band_ms"])
@@ -618,6 +641,8 @@ def main():
     results = {}
     for mode in modes:
         ms, stages, frame_ev = time_frames(ss, r, g, cams, mode, args.steps, args.warmup)
+        ms_sync, stages_sync, _ = time_frames(ss, r, g, cams, mode, args.steps, args.warmup,
+                                              sync=True)
         P, V, E, I = work[mode]
         steps_cam = [k % len(cams) for k in range(args.steps)]
         p_mean = statistics.mean(P[c] for c in steps_cam)
@@ -631,6 +656,9 @@ def main():
         results[mode] = {
             "fps": round(1000.0 / ms, 2), "ms_per_frame": round(ms, 4),
             "stage_ms": {k: round(v, 4) for k, v in stages.items()},
+            "ms_per_frame_with_stage_events": round(frame_ev, 4),
+            "ms_per_frame_readback": round(ms_sync, 4),
+            "stage_ms_readback": {k: round(v, 4) for k, v in stages_sync.items()},
             "pairs_per_frame": int(p_mean), "evaluated_pairs_per_frame": int(e_mean),
             "blended_pairs_per_frame": int(i_mean), "gaussians_with_tiles": int(v_mean),
             "blend_rated_tslots": round(rated / (stages["blend"] * 1e-3) / 1e12, 3),
@@ -655,7 +683,8 @@ def main():
         ms_pipe = start.elapsed_time(stop) / args.steps
         results[mode].update({"fps_pipelined": round(1000.0 / ms_pipe, 2),
                               "ms_per_frame_pipelined": round(ms_pipe, 4)})
-        log(f"{mode}: {ms:.3f} ms/frame one by one ({1000 / ms:.1f} FPS), {ms_pipe:.3f} ms/frame "
+        log(f"{mode}: {ms:.3f} ms/frame one by one ({1000 / ms:.1f} FPS; {ms_sync:.3f} with the "
+            f"count read-back), {ms_pipe:.3f} ms/frame "
             f"pipelined; stages " + " ".join(f"{k}={v:.3f}" for k, v in stages.items()))
     for mode in modes:
         if "3sigma" in results and mode != "3sigma":

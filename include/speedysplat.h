@@ -379,6 +379,26 @@ int ss_render(const ss_camera *cam, const ss_gaussians *g, int32_t mode, const s
               int32_t *out_buf, const ss_stage_events *events, void *stream);
 
 /*
+ * The whole forward render (stages 1-6) with no host synchronisation: the
+ * stages after the preprocess are launched over upper bounds (the record
+ * slots, pairs->capacity) and read the frame counts the preprocess stage
+ * leaves in frame->totals on the device, so the host can queue frame after
+ * frame and the GPU never waits for a read-back.  If the frame has more pairs
+ * than pairs->capacity, no pair is written and the image is the background
+ * alone: the caller finds out from the frame counts, which are copied into
+ * *counts_host (host memory, pinned for an asynchronous copy; may be NULL)
+ * once the preprocess has run, and renders the frame again with a larger
+ * workspace.  Otherwise the results equal ss_render's bit for bit.
+ * pairs->capacity must be at least 1; *out_buf receives the pair buffer
+ * holding the sorted pairs.  Events as for ss_render (event [2] directly
+ * follows [1]: there is no read-back).
+ */
+int ss_render_nosync(const ss_camera *cam, const ss_gaussians *g, int32_t mode,
+                     const ss_frame *frame, const ss_pairs *pairs, float *out_rgb,
+                     ss_frame_counts *counts_host, int32_t *out_buf,
+                     const ss_stage_events *events, void *stream);
+
+/*
  * SYNC.  The forward render of one band of tile rows [tile_row0, tile_row0 +
  * tile_rows) of the camera's image: the piece of a frame one GPU renders
  * when a frame is split across GPUs by screen-space bands (the tile pipeline

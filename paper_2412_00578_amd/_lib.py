@@ -117,6 +117,8 @@ PROTOTYPES = {
                         _P(SSStageEvents), _vp],
     "ss_render": [_P(SSCamera), _P(SSGaussians), ctypes.c_int32, _P(SSFrame), _P(SSPairs), _vp,
                   _P(SSFrameCounts), _P(ctypes.c_int32), _P(SSStageEvents), _vp],
+    "ss_render_nosync": [_P(SSCamera), _P(SSGaussians), ctypes.c_int32, _P(SSFrame), _P(SSPairs),
+                         _vp, _vp, _P(ctypes.c_int32), _P(SSStageEvents), _vp],
     "ss_render_band": [_P(SSCamera), _P(SSGaussians), ctypes.c_int32, ctypes.c_int32,
                        ctypes.c_int32, _P(SSFrame), _P(SSPairs), _vp, _P(SSFrameCounts),
                        _P(ctypes.c_int32), _P(SSStageEvents), _vp],

@@ -230,7 +230,7 @@ int begin_impl(const Layout& L, int32_t mode, const ss_frame* f, ss_frame_counts
     SS_TRY(check_mode(mode));
     SS_TRY(check_frame_records(f, L.d.n_slots));
     SS_TRY(check_table(f));
-    if (!out) return fail(SS_ERR_INVALID_ARG, "frame counts pointer is NULL");
+    if (!out && sync) return fail(SS_ERR_INVALID_ARG, "frame counts pointer is NULL");
     ss::Item* table = reinterpret_cast<ss::Item*>(f->table);
     record(ev, 0, s);
     SS_TRY(hip_status(ss::write_items(table, L.items.data(), L.d.n_items, s), "item table"));
@@ -238,9 +238,10 @@ int begin_impl(const Layout& L, int32_t mode, const ss_frame* f, ss_frame_counts
     record(ev, 1, s);
     static_assert(sizeof(ss_frame_counts) == 2 * sizeof(uint64_t), "counts layout");
     if (!sync)
-        return hip_status(hipMemcpyAsync(out, f->totals, sizeof(ss_frame_counts),
-                                         hipMemcpyDeviceToHost, s),
-                          "copy frame counts");
+        return out ? hip_status(hipMemcpyAsync(out, f->totals, sizeof(ss_frame_counts),
+                                               hipMemcpyDeviceToHost, s),
+                                "copy frame counts")
+                   : SS_OK;
     ss_frame_counts c{};
     SS_TRY(hip_status(hipMemcpyAsync(&c, f->totals, sizeof(c), hipMemcpyDeviceToHost, s),
                       "read frame counts"));
@@ -253,7 +254,9 @@ int begin_impl(const Layout& L, int32_t mode, const ss_frame* f, ss_frame_counts
 }
 
 // Stages 2a-6 for the counts begin_impl returned; with order false, stages
-// 3-6 only (the caller ran the depth order and the scan).
+// 3-6 only (the caller ran the depth order and the scan).  With c == NULL the
+// stages read the frame counts on the device (frame->totals), launched over
+// the record slots and the pair workspace's capacity (no host read-back).
 int finish_impl(const ss::BatchDims& d, int32_t mode, const ss_frame* f, const ss_pairs* p,
                 const ss_frame_counts* c, float* out_single, int32_t* out_buf,
                 const ss_stage_events* ev, hipStream_t s, bool order = true) {
@@ -261,31 +264,44 @@ int finish_impl(const ss::BatchDims& d, int32_t mode, const ss_frame* f, const s
     SS_TRY(check_frame_records(f, d.n_slots));
     SS_TRY(check_frame_pixels(f));
     SS_TRY(check_table(f));
-    if (!c) return fail(SS_ERR_INVALID_ARG, "frame counts pointer is NULL");
-    if (c->n_visible > (uint64_t)d.n_slots)
-        return fail(SS_ERR_INVALID_ARG, "n_visible %llu exceeds the %lld record slots",
-                    (unsigned long long)c->n_visible, (long long)d.n_slots);
-    const uint64_t n_pairs = c->n_pairs;
-    const int64_t n_vis = (int64_t)c->n_visible;
-    SS_TRY(check_pairs(p, 0, n_pairs));
+    const uint64_t* totals = nullptr;
+    uint64_t n_pairs;
+    int64_t n_vis;
+    if (c) {
+        if (c->n_visible > (uint64_t)d.n_slots)
+            return fail(SS_ERR_INVALID_ARG, "n_visible %llu exceeds the %lld record slots",
+                        (unsigned long long)c->n_visible, (long long)d.n_slots);
+        n_pairs = c->n_pairs;
+        n_vis = (int64_t)c->n_visible;
+        SS_TRY(check_pairs(p, 0, n_pairs));
+    } else {
+        if (!p) return fail(SS_ERR_INVALID_ARG, "pairs is NULL");
+        if (p->capacity < 1)
+            return fail(SS_ERR_WORKSPACE, "the pair workspace has no capacity");
+        n_pairs = p->capacity;             // bounds; the counts are read on the device
+        n_vis = d.n_slots;
+        SS_TRY(check_pairs(p, 0, n_pairs));
+        totals = f->totals;
+    }
     const ss::Item* table = reinterpret_cast<const ss::Item*>(f->table);
     const int bits = sort_bits_for(d.n_tiles);
     // Emit into the buffer that makes the sorted result land in buffer 0.
-    const int passes = n_pairs > 1 ? ss::sort_passes(bits) : 0;
+    const int passes = (n_pairs > 1 || totals) ? ss::sort_passes(bits) : 0;
     const int first = passes & 1;
     record(ev, 2, s);
-    if (order) SS_TRY(hip_status(ss::launch_depth_order(d.n_slots, n_vis, *f, s), "depth order"));
+    if (order)
+        SS_TRY(hip_status(ss::launch_depth_order(d.n_slots, n_vis, *f, s, totals), "depth order"));
     record(ev, 3, s);
-    if (order) SS_TRY(hip_status(ss::launch_scan(n_vis, *f, s), "scan"));
+    if (order) SS_TRY(hip_status(ss::launch_scan(n_vis, *f, s, totals), "scan"));
     record(ev, 4, s);
     SS_TRY(hip_status(ss::launch_emit(table, d, mode, *f, n_vis, p->keys[first],
-                                      p->values[first], n_pairs, s),
+                                      p->values[first], n_pairs, s, totals),
                       "emit"));
     record(ev, 5, s);
     int cur = first;
-    SS_TRY(hip_status(ss::launch_sort(*p, first, n_pairs, bits, &cur, s), "sort"));
+    SS_TRY(hip_status(ss::launch_sort(*p, first, n_pairs, bits, &cur, s, totals), "sort"));
     record(ev, 6, s);
-    SS_TRY(hip_status(ss::launch_ranges(p->keys[cur], n_pairs, d.n_tiles, f->ranges, s),
+    SS_TRY(hip_status(ss::launch_ranges(p->keys[cur], n_pairs, d.n_tiles, f->ranges, s, totals),
                       "ranges"));
     SS_TRY(hip_status(ss::launch_tile_order(table, d, *f, s), "tile order"));
     record(ev, 7, s);
@@ -502,6 +518,19 @@ int ss_render(const ss_camera* cam, const ss_gaussians* g, int32_t mode, const s
         return fail(SS_ERR_WORKSPACE, "%llu pairs exceed the workspace capacity %llu",
                     (unsigned long long)c.n_pairs, (unsigned long long)p->capacity);
     return ss_forward_finish(cam, g->n, mode, f, p, &c, out_rgb, out_buf, ev, stream);
+}
+
+int ss_render_nosync(const ss_camera* cam, const ss_gaussians* g, int32_t mode,
+                     const ss_frame* f, const ss_pairs* p, float* out_rgb,
+                     ss_frame_counts* counts_host, int32_t* out_buf, const ss_stage_events* ev,
+                     void* stream) {
+    SS_TRY(check_camera(cam));
+    SS_TRY(check_gaussians(g));
+    if (!out_rgb) return fail(SS_ERR_INVALID_ARG, "out_rgb is NULL");
+    const Layout L = single_layout(*cam, *g);
+    const hipStream_t s = (hipStream_t)stream;
+    SS_TRY(begin_impl(L, mode, f, counts_host, ev, false, s));
+    return finish_impl(L.d, mode, f, p, nullptr, out_rgb, out_buf, ev, s);
 }
 
 int ss_render_band(const ss_camera* cam, const ss_gaussians* g, int32_t mode, int32_t tile_row0,

@@ -88,15 +88,20 @@ __global__ __launch_bounds__(kEmitBlock) void k_emit(const Item* __restrict__ it
                                                      const uint32_t* __restrict__ offsets,
                                                      uint32_t* __restrict__ keys,
                                                      uint32_t* __restrict__ values,
-                                                     uint32_t* __restrict__ queue) {
+                                                     uint32_t* __restrict__ queue,
+                                                     const uint64_t* __restrict__ totals) {
     __shared__ uint32_t s_tile[kEmitWaves][kStage];
+    // n_entries (the queue layout) and limit are bounds; the counts of this
+    // frame may be smaller (device frame counts)
+    const uint32_t n_valid = (uint32_t)frame_count(totals, 1, n_entries);
+    limit = (uint32_t)frame_count(totals, 0, limit);
     __shared__ uint32_t s_pre[kEmitWaves][64];    // exclusive prefix of the staged counts
     __shared__ uint32_t s_pos[kEmitWaves][64];    // first pair position of each lane's entry
     __shared__ uint32_t s_gid[kEmitWaves][64];
     const int w = threadIdx.x >> 6;
     const int lane = (int)__lane_id();
     const int64_t j = (int64_t)blockIdx.x * kEmitBlock + threadIdx.x;   // depth-order entry
-    const bool valid = j < n_entries;
+    const bool valid = j < n_valid;
     // offsets and order are independent loads, issued together
     const uint32_t end = valid ? offsets[j] : 0u;
     const uint32_t gid_j = valid ? order[j] : 0u;
@@ -214,8 +219,10 @@ __global__ __launch_bounds__(kBigBlock) void k_emit_big(const Item* __restrict__
                                                         const uint32_t* __restrict__ offsets,
                                                         uint32_t* __restrict__ keys,
                                                         uint32_t* __restrict__ values,
-                                                        const uint32_t* __restrict__ queue) {
+                                                        const uint32_t* __restrict__ queue,
+                                                        const uint64_t* __restrict__ totals) {
     __shared__ uint32_t s_excl[kBigBlock / 64][64];
+    limit = (uint32_t)frame_count(totals, 0, limit);
     __shared__ int s_lo[kBigBlock / 64][64];
     const int w = threadIdx.x >> 6;
     const int lane = (int)__lane_id();
@@ -333,7 +340,7 @@ int64_t emit_tmp_words(int64_t n) {
 
 hipError_t launch_emit(const Item* items, const BatchDims& d, int mode, const ss_frame& f,
                        int64_t n_entries, uint32_t* keys, uint32_t* values, uint64_t n_pairs,
-                       hipStream_t s) {
+                       hipStream_t s, const uint64_t* totals) {
     if (n_entries <= 0) return hipSuccess;
     const int64_t nb = queue_blocks(n_entries);
     // emit_tmp: the depth-ordered tile sets the depth order left, then the queue
@@ -341,12 +348,12 @@ hipError_t launch_emit(const Item* items, const BatchDims& d, int mode, const ss
     uint32_t* queue = f.emit_tmp + 4 * n_entries;
     hipLaunchKernelGGL(k_emit, dim3((unsigned)nb), dim3(kEmitBlock), 0, s, items, d,
                        (uint32_t)n_entries, (uint32_t)n_pairs, sets, f.order, f.offsets, keys,
-                       values, queue);
+                       values, queue, totals);
     hipLaunchKernelGGL(k_emit_offsets, dim3(1), dim3(1024), 0, s, queue, nb);
     hipLaunchKernelGGL(k_emit_big, dim3(kBigGrid), dim3(kBigBlock), 0, s, items, d, mode,
                        (uint32_t)n_pairs, nb, reinterpret_cast<const float4*>(f.geom),
                        reinterpret_cast<const float4*>(f.conic), f.order, f.offsets, keys,
-                       values, queue);
+                       values, queue, totals);
     return hipGetLastError();
 }
 

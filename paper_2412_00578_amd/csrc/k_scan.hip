@@ -32,7 +32,9 @@ __device__ __forceinline__ uint64_t wave_incl_scan(uint64_t x) {
 }
 
 __global__ __launch_bounds__(kBlock) void k_block_sums(const uint32_t* __restrict__ counts,
-                                                       int64_t n, uint64_t* __restrict__ tmp) {
+                                                       int64_t n, uint64_t* __restrict__ tmp,
+                                                       const uint64_t* __restrict__ totals) {
+    n = (int64_t)frame_count(totals, 1, (uint64_t)n);
     const int64_t base = (int64_t)blockIdx.x * kPerBlock;
     uint64_t s = 0;
 #pragma unroll
@@ -53,7 +55,9 @@ __global__ __launch_bounds__(kBlock) void k_block_sums(const uint32_t* __restric
 
 __global__ __launch_bounds__(kBlock) void k_block_scan(const uint32_t* __restrict__ counts,
                                                        int64_t n, uint64_t* __restrict__ tmp,
-                                                       uint32_t* __restrict__ offsets) {
+                                                       uint32_t* __restrict__ offsets,
+                                                       const uint64_t* __restrict__ totals) {
+    n = (int64_t)frame_count(totals, 1, (uint64_t)n);
     // this block's offset: the partials of the blocks before it
     __shared__ uint64_t osum[kBlock / 64];
     uint64_t o = 0;
@@ -90,15 +94,15 @@ __global__ __launch_bounds__(kBlock) void k_block_scan(const uint32_t* __restric
 
 int64_t scan_tmp_words(int64_t n) { return 1 + (n + kPerBlock - 1) / kPerBlock; }
 
-hipError_t launch_scan(int64_t n, const ss_frame& f, hipStream_t s) {
+hipError_t launch_scan(int64_t n, const ss_frame& f, hipStream_t s, const uint64_t* totals) {
     const int64_t nb = (n + kPerBlock - 1) / kPerBlock;
     if (nb > 0) {
         hipLaunchKernelGGL(k_block_sums, dim3((unsigned)nb), dim3(kBlock), 0, s,
-                           f.order_counts, n, f.scan_tmp);
+                           f.order_counts, n, f.scan_tmp, totals);
     }
     // one workgroup when n == 0, to write P = 0
     hipLaunchKernelGGL(k_block_scan, dim3((unsigned)(nb > 0 ? nb : 1)), dim3(kBlock), 0, s,
-                       f.order_counts, n, f.scan_tmp, f.offsets);
+                       f.order_counts, n, f.scan_tmp, f.offsets, totals);
     return hipGetLastError();
 }
 

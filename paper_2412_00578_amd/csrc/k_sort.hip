@@ -61,6 +61,19 @@ __device__ __forceinline__ uint32_t digit_of(K key, int shift, uint32_t dmask) {
     return (uint32_t)(key >> shift) & dmask;
 }
 
+// Keys this pass reads and each workgroup's chunk.  With device frame counts
+// the grid was planned for the bound n and the chunk is re-planned for the
+// count: the same sub-tiles spread over the same grid, every workgroup of
+// k_hist and k_scatter computing the same chunk.
+__device__ __forceinline__ void pass_extent(const uint64_t* totals, int word, uint64_t sub,
+                                            uint32_t grid, uint64_t& n, uint64_t& chunk) {
+    if (!totals) return;
+    n = frame_count(totals, word, n);
+    const uint64_t subs = (n + sub - 1) / sub;
+    const uint64_t per = (subs + grid - 1) / grid;
+    chunk = (per ? per : 1) * sub;
+}
+
 // Lanes of the wave holding the same digit as this lane (among `valid` lanes),
 // found with one ballot per digit bit.
 __device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid) {
@@ -91,8 +104,11 @@ template <class K>
 __global__ __launch_bounds__(kBlock) void k_hist(const K* __restrict__ keys, uint64_t n, int shift,
                                                  uint32_t dmask, uint64_t chunk, uint32_t grid,
                                                  bool drop, bool match,
-                                                 uint32_t* __restrict__ hist) {
+                                                 uint32_t* __restrict__ hist,
+                                                 const uint64_t* __restrict__ totals, int word,
+                                                 uint32_t sub) {
     __shared__ uint32_t h[kWaves][kRadix];
+    pass_extent(totals, word, sub, grid, n, chunk);
     for (int k = threadIdx.x; k < kWaves * kRadix; k += kBlock) (&h[0][0])[k] = 0u;
     __syncthreads();
     const uint64_t lo = (uint64_t)blockIdx.x * chunk;
@@ -196,9 +212,12 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const K* __restrict__ keys_i
                                                     const uint32_t* __restrict__ hist,
                                                     const uint4* __restrict__ gather,
                                                     uint32_t* __restrict__ gather_out,
-                                                    uint4* __restrict__ sets_out) {
+                                                    uint4* __restrict__ sets_out,
+                                                    const uint64_t* __restrict__ totals,
+                                                    int word) {
     constexpr int kItems = ITEMS;
     constexpr int kSub = kBlock * ITEMS;
+    pass_extent(totals, word, (uint64_t)kSub, grid, n, chunk);
     __shared__ K s_key[kSub];
     __shared__ uint32_t s_val[kSub];
     __shared__ uint32_t base[kRadix];     // global position of this chunk's next key per digit
@@ -324,7 +343,9 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const K* __restrict__ keys_i
 // and pair n as tile n_tiles), the tiles in between end and start at i.
 // Empty tiles get an empty range.
 __global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ keys, uint64_t n,
-                                                int n_tiles, uint32_t* __restrict__ ranges) {
+                                                int n_tiles, uint32_t* __restrict__ ranges,
+                                                const uint64_t* __restrict__ totals) {
+    n = frame_count(totals, 0, n);
     const uint64_t i0 = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4u;
     if (i0 > n) return;
     int k[5];
@@ -351,7 +372,9 @@ __global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ key
 // buffers 0 and 1 from buffer `cur`; *out_buf receives the buffer holding the
 // result.  The first pass reads n0 pairs; with drop it leaves out the keys
 // equal to kCulledKey, of which there must be n0 - n, and every later pass
-// sorts the n kept pairs (without drop, n0 == n).  identity: the input values
+// sorts the n kept pairs (without drop, n0 == n).  With `totals`, n is a
+// bound and the passes that sort n keys read their count from device word
+// `word` (and, without drop, so does the first).  identity: the input values
 // are 0..n0-1 and are not read.  With last_keys false the final pass writes
 // values only; with gather_out it also writes gather[value].w and (to
 // sets_out) gather[value] in sorted order.
@@ -359,7 +382,7 @@ template <class K>
 hipError_t radix_sort(K* keys[2], uint32_t* vals[2], int cur, uint64_t n0, uint64_t n, int bits,
                       uint32_t* tmp, bool drop, bool identity, bool last_keys,
                       const uint4* gather, uint32_t* gather_out, uint4* sets_out, int* out_buf,
-                      hipStream_t s) {
+                      hipStream_t s, const uint64_t* totals = nullptr, int word = 0) {
     // the bits are split as evenly as the passes allow (13 bits: 7 + 6), so
     // no pass scatters into more buckets than it must: the fewer the buckets,
     // the longer each sub-tile's runs of equal digits and its coalesced writes
@@ -376,14 +399,17 @@ hipError_t radix_sort(K* keys[2], uint32_t* vals[2], int cur, uint64_t n0, uint6
         const uint32_t* vin = (pass == 0 && identity) ? nullptr : vals[cur];
         // the depth keys' top byte (sign and exponent) takes few values
         const bool match = drop && shift == 24;
+        // the dropping first pass reads every slot, a host count
+        const uint64_t* dc = (pass == 0 && drop) ? nullptr : totals;
         hipLaunchKernelGGL(k_hist<K>, dim3(plan.grid), dim3(kBlock), 0, s, keys[cur], m, shift,
-                           dmask, plan.chunk, plan.grid, dr, match, tmp);
+                           dmask, plan.chunk, plan.grid, dr, match, tmp, dc, word,
+                           (uint32_t)(kBlock * plan.items));
         hipLaunchKernelGGL(k_dscan, dim3(kRadix), dim3(kBlock), 0, s, tmp, plan.grid);
         auto scatter = plan.items == kItemsSmall ? k_scatter<K, kItemsSmall>
                                                  : k_scatter<K, kItemsLarge>;
         hipLaunchKernelGGL(scatter, dim3(plan.grid), dim3(kBlock), 0, s, keys[cur], vin, kout,
                            vals[1 - cur], m, shift, dmask, plan.chunk, plan.grid, dr, tmp, gather,
-                           last ? gather_out : nullptr, last ? sets_out : nullptr);
+                           last ? gather_out : nullptr, last ? sets_out : nullptr, dc, word);
         cur = 1 - cur;
         shift += width;
     }
@@ -430,7 +456,8 @@ int64_t sort_tmp_words(uint64_t) { return (int64_t)kRadix * kMaxGrid + kRadix; }
 
 int64_t static_sort_tmp_words() { return kStaticSortWords; }
 
-hipError_t launch_depth_order(int64_t n, int64_t n_visible, const ss_frame& f, hipStream_t s) {
+hipError_t launch_depth_order(int64_t n, int64_t n_visible, const ss_frame& f, hipStream_t s,
+                              const uint64_t* totals) {
     if (n <= 0 || n_visible <= 0) return hipSuccess;
     uint32_t* keys[2] = {f.depth_keys, f.depth_keys + n};
     uint32_t* vals[2] = {f.order, f.order + n};
@@ -441,19 +468,21 @@ hipError_t launch_depth_order(int64_t n, int64_t n_visible, const ss_frame& f, h
     // that order.
     return radix_sort<uint32_t>(keys, vals, 0, (uint64_t)n, (uint64_t)n_visible, 32, f.order_tmp,
                                 true, true, false, reinterpret_cast<const uint4*>(f.tile_sets),
-                                f.order_counts, reinterpret_cast<uint4*>(f.emit_tmp), &out, s);
+                                f.order_counts, reinterpret_cast<uint4*>(f.emit_tmp), &out, s,
+                                totals, 1);
 }
 
 hipError_t launch_sort(const ss_pairs& p, int buf, uint64_t n, int bits, int* out_buf,
-                       hipStream_t s) {
+                       hipStream_t s, const uint64_t* totals) {
     uint32_t* keys[2] = {p.keys[0], p.keys[1]};
     uint32_t* vals[2] = {p.values[0], p.values[1]};
-    if (n <= 1) {
+    if (n <= 1 && !totals) {
         *out_buf = buf;
         return hipSuccess;
     }
+    if (n == 0) n = 1;      // a device count of 0 or 1 sorts nothing; the grid is one group
     return radix_sort<uint32_t>(keys, vals, buf, n, n, bits, p.sort_tmp, false, false, true,
-                                nullptr, nullptr, nullptr, out_buf, s);
+                                nullptr, nullptr, nullptr, out_buf, s, totals, 0);
 }
 
 hipError_t launch_sort_static(const ss_pairs& p, int buf, uint64_t n, int bits, int* out_buf,
@@ -466,10 +495,11 @@ hipError_t launch_sort_static(const ss_pairs& p, int buf, uint64_t n, int bits, 
 }
 
 hipError_t launch_ranges(const uint32_t* keys, uint64_t n, int n_tiles, uint32_t* ranges,
-                         hipStream_t s) {
+                         hipStream_t s, const uint64_t* totals) {
     const uint64_t threads = n / 4 + 1;           // boundaries 0 .. n, four per thread
     const uint64_t grid = (threads + 255) / 256;
-    hipLaunchKernelGGL(k_ranges, dim3((unsigned)grid), dim3(256), 0, s, keys, n, n_tiles, ranges);
+    hipLaunchKernelGGL(k_ranges, dim3((unsigned)grid), dim3(256), 0, s, keys, n, n_tiles, ranges,
+                       totals);
     return hipGetLastError();
 }
 

@@ -297,6 +297,22 @@ __device__ __forceinline__ int xcd_contiguous(int b, int n) {
 
 __device__ __forceinline__ unsigned lane_id() { return __lane_id(); }
 
+// ---------------------------------------------------------------- frame counts
+//
+// The stages after the preprocess can run without the host reading the frame
+// counts back: launched over host bounds (the record slots, the pair
+// workspace's capacity), they read the counts the preprocess stage left in
+// device memory (ss_frame.totals: word 0 the pair count P, word 1 the
+// Gaussians with tiles).  A count above its bound (a pair workspace too
+// small for the frame) reads as 0, so nothing is written past the buffers.
+// totals == nullptr: the bound is the count (the host read it back).
+__device__ __forceinline__ uint64_t frame_count(const uint64_t* totals, int word,
+                                                uint64_t bound) {
+    if (!totals) return bound;
+    const uint64_t v = totals[word];
+    return v <= bound ? v : 0u;
+}
+
 // ---------------------------------------------------------------- render items
 //
 // Every launch renders a batch of one or more items (a camera, a resident
@@ -388,17 +404,21 @@ hipError_t write_items(Item* table, const Item* host_items, int n_items, hipStre
 // row of a multiple of 4 floats), so the colour kernel can load rows whole.
 hipError_t launch_preprocess(const Item* items, const BatchDims& d, int mode, const ss_frame& f,
                              bool sh_rows16, hipStream_t s);
-hipError_t launch_depth_order(int64_t n, int64_t n_visible, const ss_frame& f, hipStream_t s);
-hipError_t launch_scan(int64_t n, const ss_frame& f, hipStream_t s);
+// With `totals` (device frame counts) non-null, n_visible, n, n_entries and
+// n_pairs below are bounds and the stages read their counts from `totals`.
+hipError_t launch_depth_order(int64_t n, int64_t n_visible, const ss_frame& f, hipStream_t s,
+                              const uint64_t* totals = nullptr);
+hipError_t launch_scan(int64_t n, const ss_frame& f, hipStream_t s,
+                       const uint64_t* totals = nullptr);
 int64_t scan_tmp_words(int64_t n);
 int64_t emit_tmp_words(int64_t n);
 hipError_t launch_emit(const Item* items, const BatchDims& d, int mode, const ss_frame& f,
                        int64_t n_entries, uint32_t* keys, uint32_t* values, uint64_t n_pairs,
-                       hipStream_t s);
+                       hipStream_t s, const uint64_t* totals = nullptr);
 int64_t sort_tmp_words(uint64_t capacity);
 int sort_passes(int bits);
 hipError_t launch_sort(const ss_pairs& p, int buf, uint64_t n_pairs, int bits, int* out_buf,
-                       hipStream_t s);
+                       hipStream_t s, const uint64_t* totals = nullptr);
 // launch_sort with the sort scratch in the library's static device array (the
 // caller's p.sort_tmp is not used): hipErrorInvalidValue if the pass needs more
 // than static_sort_tmp_words(), or the runtime's error looking it up.
@@ -406,7 +426,7 @@ hipError_t launch_sort_static(const ss_pairs& p, int buf, uint64_t n_pairs, int 
                               int* out_buf, hipStream_t s);
 int64_t static_sort_tmp_words();
 hipError_t launch_ranges(const uint32_t* keys, uint64_t n_pairs, int n_tiles, uint32_t* ranges,
-                         hipStream_t s);
+                         hipStream_t s, const uint64_t* totals = nullptr);
 // launch_blend = launch_tile_order (the tiles' work order, from the ranges)
 // followed by launch_blend_tiles.
 hipError_t launch_tile_order(const Item* items, const BatchDims& d, const ss_frame& f,

@@ -207,6 +207,28 @@ class RenderOutput:
     buf: int                 # pair buffer holding the sorted pairs
 
 
+@dataclass
+class NoSyncRender:
+    """A frame queued by Renderer.render_nosync."""
+    image: torch.Tensor
+    frame: "Frame"
+    pairs: "Pairs"
+    buf: int
+    counts: torch.Tensor     # pinned [2]: P, Gaussians with tiles (valid after the sync)
+    capacity: int
+
+    @property
+    def n_pairs(self) -> int:
+        return int(self.counts[0])
+
+    def ok(self) -> bool:
+        """True when the pair workspace held the frame (call after the sync)."""
+        p = int(self.counts[0])
+        if p < 0:
+            raise RuntimeError("frame counts not copied yet: synchronise the stream first")
+        return p <= self.capacity
+
+
 class Renderer:
     """Owns reusable frame and pair buffers; grows them on demand."""
 
@@ -221,6 +243,9 @@ class Renderer:
         self._ring: list = [None] * self.RING    # frames of render_many
         self._host_p: torch.Tensor | None = None
         self._side = None                        # side streams of render_many
+        self._max_pairs = 0                      # largest pair count seen (sizes render_nosync)
+        self._nosync_counts: torch.Tensor | None = None
+        self._nosync_next = 0
 
     def frame_for(self, n, width, height) -> Frame:
         if self._frame is None or not self._frame.fits(n, width, height, self.stats):
@@ -251,6 +276,7 @@ class Renderer:
         evp = ctypes.byref(ev) if ev is not None else None
         check(lib().ss_forward_begin(ctypes.byref(c), ctypes.byref(gs), m, ctypes.byref(fs),
                                      ctypes.byref(counts), evp, stream), "ss_forward_begin")
+        self._max_pairs = max(self._max_pairs, int(counts.n_pairs))
         pairs = self.pairs_for(counts.n_pairs)
         ps = pairs.struct()
         buf = ctypes.c_int32()
@@ -261,6 +287,41 @@ class Renderer:
             return RenderOutput(out, int(counts.n_pairs), int(counts.n_visible), frame, pairs,
                                 int(buf.value))
         return out
+
+    NOSYNC_SLOTS = 256   # frame-count slots of render_nosync (frames in flight)
+
+    def render_nosync(self, g: Gaussians, cam, mode="accutile", out: torch.Tensor | None = None,
+                      events: "StageEvents | None" = None) -> "NoSyncRender":
+        """Forward render with no host synchronisation (ss_render_nosync): every
+        stage is queued at once, the later ones reading the frame counts on the
+        device, so frames can be queued back to back without the GPU waiting for
+        a read-back.  The pair workspace is the renderer's, sized for the
+        largest frame it has seen (with growth headroom).  The frame counts land
+        in a pinned slot; once the stream has been synchronised, the returned
+        object's ok() tells whether the workspace held the frame (if not, the
+        image is the background alone: render() the frame instead, which also
+        grows the workspace).  At most NOSYNC_SLOTS frames may be checked late."""
+        m = mode_id(mode)
+        c = make_camera(cam)
+        frame = self.frame_for(g.n, c.width, c.height)
+        if out is None:
+            out = torch.empty((3, c.height, c.width), dtype=torch.float32, device=self.device)
+        if self._nosync_counts is None:
+            self._nosync_counts = torch.zeros((self.NOSYNC_SLOTS, 2), dtype=torch.int64,
+                                              pin_memory=True)
+        slot = self._nosync_next % self.NOSYNC_SLOTS
+        self._nosync_next += 1
+        host = self._nosync_counts[slot]
+        host.fill_(-1)
+        pairs = self.pairs_for(max(self._max_pairs, 1))
+        gs, fs, ps = g.struct(), frame.struct(), pairs.struct()
+        buf = ctypes.c_int32()
+        ev = events.struct() if events is not None else None
+        check(lib().ss_render_nosync(ctypes.byref(c), ctypes.byref(gs), m, ctypes.byref(fs),
+                                     ctypes.byref(ps), _ptr(out), ctypes.c_void_p(host.data_ptr()),
+                                     ctypes.byref(buf), ctypes.byref(ev) if ev is not None else None,
+                                     _stream(self.device)), "ss_render_nosync")
+        return NoSyncRender(out, frame, pairs, int(buf.value), host, pairs.capacity)
 
     def render_band(self, g: Gaussians, cam, mode, tile_row0: int, tile_rows: int,
                     out: torch.Tensor | None = None, full: bool = False,

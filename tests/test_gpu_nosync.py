@@ -1,0 +1,111 @@
+"""ss_render_nosync (no read-back of the frame counts: the stages after the
+preprocess read them on the device) against ss_render: identical sorted
+pairs, ranges, images and per-pixel state; frames queued back to back; and
+a pair workspace too small for the frame, which must write nothing past the
+workspace, leave the background image and report the overflow."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import scenegen
+from gpu_util import u32
+
+pytestmark = pytest.mark.gpu
+MODES = ["3sigma", "snugbox", "accutile"]
+
+
+@pytest.fixture(scope="module")
+def ss():
+    import paper_2412_00578_amd as ss
+    ss.lib()
+    return ss
+
+
+def _same(a, b, p):
+    assert np.array_equal(u32(a.pairs.keys[a.buf][:p]), u32(b.pairs.keys[b.buf][:p]))
+    assert np.array_equal(u32(a.pairs.values[a.buf][:p]), u32(b.pairs.values[b.buf][:p]))
+    assert np.array_equal(u32(a.frame.ranges), u32(b.frame.ranges))
+    assert np.array_equal(a.image.cpu().numpy(), b.image.cpu().numpy())
+    assert np.array_equal(a.frame.t_final.cpu().numpy(), b.frame.t_final.cpu().numpy())
+    assert np.array_equal(u32(a.frame.n_last), u32(b.frame.n_last))
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("which", ["c0", "c1", "edge"])
+def test_nosync_equals_render(ss, gpu_device, mode, which):
+    if which == "c0":
+        sc, cam = scenegen.scene_c0(), scenegen.camera_c0()
+    elif which == "c1":
+        sc, cam = scenegen.scene_c1(), scenegen.camera_c1()
+    else:
+        sc = scenegen.scene_blobs(60_000, 21, log_s=(-3.0, 1.0))
+        cam = scenegen.cameras_c1(8)[1].with_size(1920, 1080)
+    print(f"[case] nosync {which} {mode}", flush=True)
+    g = ss.Gaussians.from_scene(sc, gpu_device)
+    ref = ss.Renderer(gpu_device).render(g, cam, mode, full=True)
+    r = ss.Renderer(gpu_device)
+    r.render(g, cam, mode)                 # sizes the pair workspace
+    out = r.render_nosync(g, cam, mode)
+    torch.cuda.synchronize()
+    assert out.ok() and out.n_pairs == ref.n_pairs
+    _same(out, ref, ref.n_pairs)
+    if which == "c0":
+        fr = oracle.render(sc, cam, mode)
+        ok = ~fr.ambiguous
+        assert np.abs(out.image.cpu().numpy() - fr.image)[:, ok].max() <= 1e-4
+
+
+def test_frames_back_to_back(ss, gpu_device):
+    """Eight frames of the benchmark scene queued with no synchronisation, then
+    checked one by one against ss_render."""
+    print("[case] nosync back to back", flush=True)
+    sc, cams = scenegen.scene_c1(), scenegen.cameras_c1(8)
+    g = ss.Gaussians.from_scene(sc, gpu_device)
+    r = ss.Renderer(gpu_device)
+    for c in cams:
+        r.render(g, c, "accutile")
+    outs = [r.render_nosync(g, c, "accutile",
+                            out=torch.empty((3, c.height, c.width), device=gpu_device))
+            for c in cams]
+    imgs = [o.image.clone() for o in outs]
+    torch.cuda.synchronize()
+    ref = ss.Renderer(gpu_device)
+    for c, o, im in zip(cams, outs, imgs):
+        assert o.ok()
+        assert np.array_equal(im.cpu().numpy(), ref.render(g, c, "accutile").cpu().numpy())
+
+
+def test_workspace_overflow_is_reported(ss, gpu_device):
+    print("[case] nosync overflow", flush=True)
+    sc, cam = scenegen.scene_c1(), scenegen.camera_c1()
+    g = ss.Gaussians.from_scene(sc, gpu_device)
+    r = ss.Renderer(gpu_device)                    # no frame seen: a 1025-pair workspace
+    guard = r.pairs_for(1)
+    for t in guard.keys + guard.values:
+        t.fill_(-7)
+    out = r.render_nosync(g, cam, "accutile")
+    torch.cuda.synchronize()
+    assert not out.ok() and out.n_pairs > out.capacity
+    assert np.all(out.image.cpu().numpy() == 0.0)                 # background only
+    assert np.all(u32(out.frame.ranges) == 0)
+    for t in guard.keys + guard.values:                            # nothing written
+        assert np.all(t.cpu().numpy() == -7)
+    r.render(g, cam, "accutile")                                   # grows the workspace
+    again = r.render_nosync(g, cam, "accutile")
+    torch.cuda.synchronize()
+    assert again.ok()
+
+
+def test_empty_scene(ss, gpu_device):
+    cam = scenegen.Camera(40, 24, 40.0, 40.0, 20.0, 12.0, np.eye(3), np.zeros(3),
+                          bg=(0.25, 0.5, 1.0))
+    sc = scenegen.fixture_scene(np.zeros((0, 3)), np.zeros((0, 3)), np.zeros((0, 4)),
+                                np.zeros(0), np.zeros((0, 3)))
+    g = ss.Gaussians.from_scene(sc, gpu_device)
+    out = ss.Renderer(gpu_device).render_nosync(g, cam, "accutile")
+    torch.cuda.synchronize()
+    assert out.ok() and out.n_pairs == 0
+    img = out.image.cpu().numpy()
+    for ch, b in enumerate(cam.bg):
+        assert np.all(img[ch] == np.float32(b))
