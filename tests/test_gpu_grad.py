@@ -245,3 +245,38 @@ def test_backward_full_size_masked_tiles(ss, gpu_device):
     got = {k: getattr(gr, k).cpu().numpy() for k in GROUPS}
     got["opacity"] = got["opacity"].reshape(-1)
     _compare(got, want, "-c3")
+
+
+def test_backward_through_clamped_stacks(ss, gpu_device):
+    """Stacks of near-opaque Gaussians in front of the camera: many pixels see
+    alpha clamped at 0.99 or just below it (T_before = T_after / (1 - alpha)
+    amplifies the recurrence's rounding by up to 100 per step), mixed with
+    moderate ones, until the transmittance stops the walk at 1e-4."""
+    rng = np.random.default_rng(77)
+    n = 240
+    xy = rng.uniform(-0.25, 0.25, size=(n, 2))
+    z = rng.uniform(2.0, 3.0, size=n)
+    means = np.column_stack([xy, z])
+    scales = np.exp(rng.uniform(-2.6, -1.6, size=(n, 3)))
+    quats = rng.standard_normal((n, 4))
+    kind = rng.integers(0, 3, size=n)
+    opac = np.where(kind == 0, rng.uniform(0.995, 0.9999, n),         # clamped at the centre
+                    np.where(kind == 1, rng.uniform(0.95, 0.985, n),  # just below the clamp
+                             rng.uniform(0.2, 0.6, n)))
+    cols = rng.uniform(-0.8, 0.8, size=(n, 3))
+    sc = scenegen.fixture_scene(means, scales, quats, opac, cols)
+    cam = scenegen.camera_fd()
+    fr = oracle.render(sc, cam, "accutile")
+    stopped = int((fr.n_last < fr.n_eval).sum())
+    print(f"[case] clamped stacks: {stopped} of {fr.n_last.size} pixels stop early", flush=True)
+    assert stopped > 500                       # the walk is cut by the transmittance
+    w = _weights(cam, fr, 8)
+    pix = oracle.all_pixels(cam)
+    want = _oracle_grad_linear(sc, cam, pix, w.reshape(3, -1).T, fr)
+    g = ss.Gaussians.from_scene(sc, gpu_device)
+    out = ss.Renderer(gpu_device).render(g, cam, "accutile", full=True)
+    gr = ss.backward(g, cam, out, torch.as_tensor(w, dtype=torch.float32, device=gpu_device))
+    torch.cuda.synchronize()
+    got = {k: getattr(gr, k).cpu().numpy() for k in GROUPS}
+    got["opacity"] = got["opacity"].reshape(-1)
+    _compare(got, want, " clamped")

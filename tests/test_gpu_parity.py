@@ -46,6 +46,17 @@ def test_c1_full_size(ss, gpu_device, mode):
     assert_pipeline_equal(gpu, oracle.render(sc, cam, mode))
 
 
+@pytest.mark.parametrize("mode", ["3sigma", "accutile"])
+def test_c4_largest_scene_full_hd(ss, gpu_device, mode):
+    # the 6M-Gaussian resident scene of the serving workload at 1920x1080
+    # (half-filled last tile row), the largest pair counts of the tests
+    sc = scenegen.scene_c4(3)
+    cam = scenegen.cameras_c1(8)[5].with_size(1920, 1080)
+    gpu = _run(ss, gpu_device, sc, cam, mode)
+    print(f"[case] pairs {gpu['n_pairs']}", flush=True)
+    assert_pipeline_equal(gpu, oracle.render(sc, cam, mode))
+
+
 def test_c2_shape_other_camera(ss, gpu_device):
     sc = scenegen.scene_c2()
     cam = scenegen.cameras_c2(4)[3]
