@@ -121,6 +121,10 @@ void record(const ss_stage_events* ev, int k, hipStream_t s) {
     } while (0)
 
 constexpr int kMaxItems = 4096;
+#ifndef SS_PERSISTENT_FRAMES
+#define SS_PERSISTENT_FRAMES 0
+#endif
+constexpr bool kPersistentFrames = SS_PERSISTENT_FRAMES != 0;
 
 int64_t pad_slots(int64_t n) { return (n + ss::kSlotAlign - 1) / ss::kSlotAlign * ss::kSlotAlign; }
 
@@ -233,7 +237,8 @@ int begin_impl(const Layout& L, int32_t mode, const ss_frame* f, ss_frame_counts
     if (!out && sync) return fail(SS_ERR_INVALID_ARG, "frame counts pointer is NULL");
     ss::Item* table = reinterpret_cast<ss::Item*>(f->table);
     record(ev, 0, s);
-    SS_TRY(hip_status(ss::write_items(table, L.items.data(), L.d.n_items, s), "item table"));
+    SS_TRY(hip_status(ss::write_items(table, L.items.data(), L.d.n_items, s, f->totals),
+                      "item table"));
     SS_TRY(hip_status(ss::launch_preprocess(table, L.d, mode, *f, sh_rows16(L), s), "preprocess"));
     record(ev, 1, s);
     static_assert(sizeof(ss_frame_counts) == 2 * sizeof(uint64_t), "counts layout");
@@ -305,7 +310,11 @@ int finish_impl(const ss::BatchDims& d, int32_t mode, const ss_frame* f, const s
                       "ranges"));
     SS_TRY(hip_status(ss::launch_tile_order(table, d, *f, s), "tile order"));
     record(ev, 7, s);
-    SS_TRY(hip_status(ss::launch_blend_tiles(table, d, *f, p->values[cur], out_single, s),
+    // a batch's tiles (every item, every resolution) are served by one resident
+    // grid pulling from per-XCD work queues
+    const bool persistent = d.n_items > 1 || kPersistentFrames;
+    SS_TRY(hip_status(ss::launch_blend_tiles(table, d, *f, p->values[cur], out_single, s,
+                                             persistent),
                       "blend"));
     record(ev, 8, s);
     if (out_buf) *out_buf = cur;
@@ -373,7 +382,7 @@ int ss_preprocess(const ss_camera* cam, const ss_gaussians* g, int32_t mode, con
     const Layout L = single_layout(*cam, *g);
     hipStream_t s = (hipStream_t)stream;
     ss::Item* table = reinterpret_cast<ss::Item*>(f->table);
-    SS_TRY(hip_status(ss::write_items(table, L.items.data(), 1, s), "item table"));
+    SS_TRY(hip_status(ss::write_items(table, L.items.data(), 1, s, f->totals), "item table"));
     return hip_status(ss::launch_preprocess(table, L.d, mode, *f, sh_rows16(L), s), "preprocess");
 }
 

@@ -113,8 +113,10 @@ __device__ __forceinline__ uint32_t order_key(const Item* __restrict__ items, in
 __global__ __launch_bounds__(kOrderThreads) void k_tile_order(const Item* __restrict__ items,
                                                               BatchDims dims,
                                                               const uint32_t* __restrict__ ranges,
-                                                              uint32_t* __restrict__ order) {
+                                                              uint32_t* __restrict__ order,
+                                                              uint32_t* __restrict__ queue) {
     __shared__ uint32_t h[kOrderKeys];
+    if (threadIdx.x < 8) queue[threadIdx.x] = 0u;     // the persistent blend's counters
     __shared__ uint32_t s_w[kOrderThreads / 64];
     __shared__ uint32_t s_start[9], s_cap[8], s_over[9], s_free[9];
     const int t0 = (int)threadIdx.x;
@@ -199,25 +201,31 @@ __global__ __launch_bounds__(kOrderThreads) void k_tile_order(const Item* __rest
     }
 }
 
+// The records of a tile's list staged in LDS, kBatch at a time.
+struct Stage {
+    double2 uv[kBatch];     // (u, v)
+    double2 ab[kBatch];     // (a, 2b)
+    double2 ct[kBatch];     // (c, t)
+    float4 col[kBatch];     // (r, g, b, log2 sigma)
+};
+
 template <bool STATS>
-__global__ __launch_bounds__(64) void k_blend(const Item* __restrict__ items, BatchDims dims,
-                                              const uint32_t* __restrict__ tile_order,
-                                              const uint32_t* __restrict__ ranges,
-                                              const uint32_t* __restrict__ values,
-                                              const float4* __restrict__ geom,
-                                              const float4* __restrict__ conic,
-                                              const float4* __restrict__ rgb,
-                                              float* __restrict__ out_single,
-                                              float* __restrict__ t_final_all,
-                                              uint32_t* __restrict__ n_last_all,
-                                              uint32_t* __restrict__ n_eval_all,
-                                              uint32_t* __restrict__ n_contrib_all) {
-    __shared__ double2 s_uv[kBatch];     // (u, v)
-    __shared__ double2 s_ab[kBatch];     // (a, 2b)
-    __shared__ double2 s_ct[kBatch];     // (c, t)
-    __shared__ float4 s_col[kBatch];     // (r, g, b, log2 sigma)
-    if ((int)blockIdx.x >= dims.n_tiles) return;
-    const int tile = (int)tile_order[blockIdx.x];
+__device__ __forceinline__ void blend_tile(const int tile, Stage& st,
+                                           const Item* __restrict__ items, const BatchDims& dims,
+                                           const uint32_t* __restrict__ ranges,
+                                           const uint32_t* __restrict__ values,
+                                           const float4* __restrict__ geom,
+                                           const float4* __restrict__ conic,
+                                           const float4* __restrict__ rgb,
+                                           float* __restrict__ out_single,
+                                           float* __restrict__ t_final_all,
+                                           uint32_t* __restrict__ n_last_all,
+                                           uint32_t* __restrict__ n_eval_all,
+                                           uint32_t* __restrict__ n_contrib_all) {
+    double2* __restrict__ s_uv = st.uv;
+    double2* __restrict__ s_ab = st.ab;
+    double2* __restrict__ s_ct = st.ct;
+    float4* __restrict__ s_col = st.col;
     const Item& it = items[dims.n_items == 1 ? 0 : item_of_tile(items, dims.n_items, tile)];
     const int W = it.cam.width, H = it.cam.height, tx_n = it.tx_n;
     const float bg0 = it.cam.bg[0], bg1 = it.cam.bg[1], bg2 = it.cam.bg[2];
@@ -341,27 +349,110 @@ __global__ __launch_bounds__(64) void k_blend(const Item* __restrict__ items, Ba
     }
 }
 
+// One workgroup (one wave) per tile, tiles taken in the work order: launch
+// index b renders tile tile_order[b].
+template <bool STATS>
+__global__ __launch_bounds__(64) void k_blend(const Item* __restrict__ items, BatchDims dims,
+                                              const uint32_t* __restrict__ tile_order,
+                                              const uint32_t* __restrict__ ranges,
+                                              const uint32_t* __restrict__ values,
+                                              const float4* __restrict__ geom,
+                                              const float4* __restrict__ conic,
+                                              const float4* __restrict__ rgb,
+                                              float* __restrict__ out_single,
+                                              float* __restrict__ t_final_all,
+                                              uint32_t* __restrict__ n_last_all,
+                                              uint32_t* __restrict__ n_eval_all,
+                                              uint32_t* __restrict__ n_contrib_all) {
+    __shared__ Stage st;
+    if ((int)blockIdx.x >= dims.n_tiles) return;
+    blend_tile<STATS>((int)tile_order[blockIdx.x], st, items, dims, ranges, values, geom, conic,
+                      rgb, out_single, t_final_all, n_last_all, n_eval_all, n_contrib_all);
+}
+
+// Persistent: a grid the GPU holds at once (a multiple of 8 workgroups) pulls
+// tiles from per-XCD work queues until they are empty.  Workgroup b runs on
+// XCD b mod 8 and takes the tiles the work order gave that XCD (launch indices
+// x + 8 r, longest lists first) by incrementing the XCD's counter (zeroed by
+// k_tile_order); no workgroup waits on another.  Serves a batch's tiles of
+// every item and resolution from one resident grid.
+template <bool STATS>
+__global__ __launch_bounds__(64) void k_blend_persistent(
+    const Item* __restrict__ items, BatchDims dims, const uint32_t* __restrict__ tile_order,
+    uint32_t* __restrict__ queue, const uint32_t* __restrict__ ranges,
+    const uint32_t* __restrict__ values, const float4* __restrict__ geom,
+    const float4* __restrict__ conic, const float4* __restrict__ rgb,
+    float* __restrict__ out_single, float* __restrict__ t_final_all,
+    uint32_t* __restrict__ n_last_all, uint32_t* __restrict__ n_eval_all,
+    uint32_t* __restrict__ n_contrib_all) {
+    __shared__ Stage st;
+    const uint32_t x = blockIdx.x & 7u;
+    const uint32_t n = (uint32_t)dims.n_tiles;
+    const uint32_t cap = n > x ? (n - x + 7u) / 8u : 0u;    // launch indices of XCD x
+    for (;;) {
+        uint32_t r = 0u;
+        if (threadIdx.x == 0) r = atomicAdd(queue + x, 1u);
+        r = (uint32_t)__shfl((int)r, 0, 64);
+        if (r >= cap) break;
+        blend_tile<STATS>((int)tile_order[x + 8u * r], st, items, dims, ranges, values, geom,
+                          conic, rgb, out_single, t_final_all, n_last_all, n_eval_all,
+                          n_contrib_all);
+        __syncthreads();            // the next tile restages the LDS batch
+    }
+}
+
 }  // namespace
 
 hipError_t launch_tile_order(const Item* items, const BatchDims& d, const ss_frame& f,
                              hipStream_t s) {
     if (d.n_tiles == 0) return hipSuccess;
     hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(kOrderThreads), 0, s, items, d, f.ranges,
-                       tile_order_of(f.table, d.n_items));
+                       tile_order_of(f.table, d.n_items),
+                       tile_queue_of(f.table, d.n_items, d.n_tiles));
     return hipGetLastError();
 }
 
+namespace {
+// Workgroups of the persistent blend the GPU holds at once (per device).
+template <class K>
+int resident_groups(K kernel) {
+    static int cached[64] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+    if (!cached[dev]) {
+        int per_cu = 0, cus = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 64, 0) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            return 0;
+        cached[dev] = per_cu * cus;
+    }
+    return cached[dev];
+}
+}  // namespace
+
 hipError_t launch_blend_tiles(const Item* items, const BatchDims& d, const ss_frame& f,
-                              const uint32_t* values, float* out_rgb_single, hipStream_t s) {
+                              const uint32_t* values, float* out_rgb_single, hipStream_t s,
+                              bool persistent) {
     const int grid = d.n_tiles;
     if (grid == 0) return hipSuccess;
     const uint32_t* order = tile_order_of(f.table, d.n_items);
+    const float4* g4 = reinterpret_cast<const float4*>(f.geom);
+    const float4* c4 = reinterpret_cast<const float4*>(f.conic);
+    const float4* r4 = reinterpret_cast<const float4*>(f.rgb);
+    if (persistent) {
+        auto kernel = f.n_eval ? k_blend_persistent<true> : k_blend_persistent<false>;
+        const int held = resident_groups(kernel) / 8 * 8;
+        const int tiles8 = (grid + 7) / 8 * 8;
+        const int pg = held > 0 && held < tiles8 ? held : tiles8;
+        hipLaunchKernelGGL(kernel, dim3(pg), dim3(64), 0, s, items, d, order,
+                           tile_queue_of(f.table, d.n_items, d.n_tiles), f.ranges, values, g4,
+                           c4, r4, out_rgb_single, f.t_final, f.n_last, f.n_eval, f.n_contrib);
+        return hipGetLastError();
+    }
     auto go = [&](auto kernel) {
         hipLaunchKernelGGL(kernel, dim3(grid), dim3(64), 0, s, items, d, order, f.ranges, values,
-                           reinterpret_cast<const float4*>(f.geom),
-                           reinterpret_cast<const float4*>(f.conic),
-                           reinterpret_cast<const float4*>(f.rgb), out_rgb_single, f.t_final,
-                           f.n_last, f.n_eval, f.n_contrib);
+                           g4, c4, r4, out_rgb_single, f.t_final, f.n_last, f.n_eval,
+                           f.n_contrib);
     };
     if (f.n_eval) go(k_blend<true>);
     else go(k_blend<false>);
@@ -369,10 +460,11 @@ hipError_t launch_blend_tiles(const Item* items, const BatchDims& d, const ss_fr
 }
 
 hipError_t launch_blend(const Item* items, const BatchDims& d, const ss_frame& f,
-                        const uint32_t* values, float* out_rgb_single, hipStream_t s) {
+                        const uint32_t* values, float* out_rgb_single, hipStream_t s,
+                        bool persistent) {
     const hipError_t e = launch_tile_order(items, d, f, s);
     if (e != hipSuccess) return e;
-    return launch_blend_tiles(items, d, f, values, out_rgb_single, s);
+    return launch_blend_tiles(items, d, f, values, out_rgb_single, s, persistent);
 }
 
 }  // namespace ss

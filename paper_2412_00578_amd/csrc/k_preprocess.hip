@@ -395,26 +395,21 @@ __global__ __launch_bounds__(kBlock) void k_colour(const Item* __restrict__ item
     rgb_out[o] = colour_of(cr, cg, cbl);
 }
 
-// One workgroup: totals = (sum of the pair-count partials, sum of the
-// visible-count partials) over nb workgroups of k_preprocess.
+// totals += (sum of the pair-count partials, sum of the visible-count
+// partials) over nb workgroups of k_preprocess: each workgroup sums a
+// contiguous run of partials and adds its two sums with one atomic each
+// (a few dozen atomics on one address; the totals were zeroed by
+// k_write_items).
 __global__ __launch_bounds__(1024) void k_totals(const uint32_t* __restrict__ partials, int64_t nb,
                                                  uint64_t* __restrict__ totals) {
     __shared__ uint64_t s_p[16], s_v[16];
     uint64_t p = 0, v = 0;
-    // (P, visible) pairs as 8-byte loads, eight in flight per thread
+    const int64_t per = (nb + gridDim.x - 1) / gridDim.x;
+    const int64_t lo = (int64_t)blockIdx.x * per;
+    const int64_t hi = lo + per < nb ? lo + per : nb;
+    // (P, visible) pairs as 8-byte loads
     const uint2* __restrict__ pv = reinterpret_cast<const uint2*>(partials);
-    int64_t b = threadIdx.x;
-    for (; b + 7 * 1024 < nb; b += 8 * 1024) {
-        uint2 x[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) x[u] = pv[b + u * 1024];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            p += x[u].x;
-            v += x[u].y;
-        }
-    }
-    for (; b < nb; b += 1024) {
+    for (int64_t b = lo + threadIdx.x; b < hi; b += 1024) {
         const uint2 x = pv[b];
         p += x.x;
         v += x.y;
@@ -435,8 +430,8 @@ __global__ __launch_bounds__(1024) void k_totals(const uint32_t* __restrict__ pa
             tp += s_p[w];
             tv += s_v[w];
         }
-        totals[0] = tp;
-        totals[1] = tv;
+        if (tp) atomicAdd((unsigned long long*)&totals[0], (unsigned long long)tp);
+        if (tv) atomicAdd((unsigned long long*)&totals[1], (unsigned long long)tv);
     }
 }
 
@@ -455,21 +450,32 @@ hipError_t launch_preprocess(const Item* items, const BatchDims& d, int mode, co
                            dim3(kBlock), 0, s, items, d, f.counts,
                            reinterpret_cast<float4*>(f.rgb));
     }
-    hipLaunchKernelGGL(k_totals, dim3(1), dim3(1024), 0, s, f.emit_tmp, grid, f.totals);
+    if (grid > 0) {
+        // about 1024 partials per reducing workgroup
+        const int64_t tg = (grid + 1023) / 1024 < 64 ? (grid + 1023) / 1024 : 64;
+        hipLaunchKernelGGL(k_totals, dim3((unsigned)tg), dim3(1024), 0, s, f.emit_tmp, grid,
+                           f.totals);
+    }
     return hipGetLastError();
 }
 
-__global__ void k_write_items(Item* __restrict__ table, ItemPack pack, int first, int count) {
+// Writes items [first, first + count) of the table; with totals, also zeroes
+// the frame counts the preprocess stage accumulates.
+__global__ void k_write_items(Item* __restrict__ table, ItemPack pack, int first, int count,
+                              uint64_t* __restrict__ totals) {
     const int k = threadIdx.x;
     if (k < count) table[first + k] = pack.it[k];
+    if (totals && k < 2) totals[k] = 0u;
 }
 
-hipError_t write_items(Item* table, const Item* host_items, int n_items, hipStream_t s) {
+hipError_t write_items(Item* table, const Item* host_items, int n_items, hipStream_t s,
+                       uint64_t* totals) {
     for (int first = 0; first < n_items; first += kPack) {
         ItemPack pack;
         const int count = n_items - first < kPack ? n_items - first : kPack;
         for (int k = 0; k < count; ++k) pack.it[k] = host_items[first + k];
-        hipLaunchKernelGGL(k_write_items, dim3(1), dim3(kPack), 0, s, table, pack, first, count);
+        hipLaunchKernelGGL(k_write_items, dim3(1), dim3(kPack), 0, s, table, pack, first, count,
+                           first == 0 ? totals : nullptr);
     }
     return hipGetLastError();
 }

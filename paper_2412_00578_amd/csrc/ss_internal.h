@@ -360,14 +360,18 @@ __device__ __forceinline__ float4 ld_global(const float4* p) {
 }
 
 // The item table buffer holds the n_items items, then (from the next 256-byte
-// boundary) the blend's tile work order, one u32 per tile.
+// boundary) the blend's tile work order, one u32 per tile, then (from the next
+// 256-byte boundary) the 8 per-XCD work counters of the persistent blend.
 inline int64_t table_bytes(int n_items, int n_tiles) {
     const int64_t items = ((int64_t)sizeof(Item) * n_items + 255) / 256 * 256;
-    return items + ((int64_t)n_tiles * 4 + 255) / 256 * 256;
+    return items + ((int64_t)n_tiles * 4 + 255) / 256 * 256 + 256;
 }
 inline uint32_t* tile_order_of(void* table, int n_items) {
     return reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(table) +
                                        ((int64_t)sizeof(Item) * n_items + 255) / 256 * 256);
+}
+inline uint32_t* tile_queue_of(void* table, int n_items, int n_tiles) {
+    return tile_order_of(table, n_items) + ((int64_t)n_tiles * 4 + 255) / 256 * 64;
 }
 
 struct BatchDims {
@@ -399,7 +403,9 @@ __device__ __forceinline__ int item_of_tile(const Item* items, int n_items, int 
 // ---------------------------------------------------------------- launchers
 // (each returns hipSuccess or the launch error)
 
-hipError_t write_items(Item* table, const Item* host_items, int n_items, hipStream_t s);
+// With `totals`, also zeroes the frame counts (before launch_preprocess adds to them).
+hipError_t write_items(Item* table, const Item* host_items, int n_items, hipStream_t s,
+                       uint64_t* totals = nullptr);
 // sh_rows16: every item's SH rows start 16-byte aligned (base aligned and a
 // row of a multiple of 4 floats), so the colour kernel can load rows whole.
 hipError_t launch_preprocess(const Item* items, const BatchDims& d, int mode, const ss_frame& f,
@@ -431,10 +437,14 @@ hipError_t launch_ranges(const uint32_t* keys, uint64_t n_pairs, int n_tiles, ui
 // followed by launch_blend_tiles.
 hipError_t launch_tile_order(const Item* items, const BatchDims& d, const ss_frame& f,
                              hipStream_t s);
+// persistent: a resident grid pulling tiles from per-XCD work queues instead of
+// one workgroup per tile (the same results).
 hipError_t launch_blend_tiles(const Item* items, const BatchDims& d, const ss_frame& f,
-                              const uint32_t* values, float* out_rgb_single, hipStream_t s);
+                              const uint32_t* values, float* out_rgb_single, hipStream_t s,
+                              bool persistent = false);
 hipError_t launch_blend(const Item* items, const BatchDims& d, const ss_frame& f,
-                        const uint32_t* values, float* out_rgb_single, hipStream_t s);
+                        const uint32_t* values, float* out_rgb_single, hipStream_t s,
+                        bool persistent = false);
 int64_t prune_tmp_words(int64_t n);
 // Kept indices (ascending) of the n_keep highest scores, ties to the lower index.
 hipError_t launch_prune_select(const float* score, int64_t n, int64_t n_keep, uint32_t* keep_idx,
