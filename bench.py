@@ -541,7 +541,7 @@ def backward_bench(ss, g, cams, steps, warmup):
 
 
 def serving_bench(ss, dev, scale=1.0, n_sat=400, n_req=2000, n_warm=200, max_batch=8,
-                  pool_gib=16):
+                  pool_gib=4):
     """Continuous-batching serving over 4 resident scenes (0.3M / 1M / 3M / 6M
     Gaussians, SH-3, clustered) with random orbit cameras at 640x480,
     1280x720, 1600x1040 or 1920x1080: AccuTile's saturation rate X (every

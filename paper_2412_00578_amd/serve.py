@@ -56,6 +56,8 @@ class ServeStats:
     peak_reserved_bytes: int = 0
     failed: int = 0
     requeued: int = 0
+    admission_bound: int = 0      # batches closed because the next request did not fit the pool
+    peak_device_bytes: int = 0    # device memory the backend actually held at its peak
 
     def pct(self, q) -> float:
         return float(np.percentile(self.latencies_ms, q)) if len(self.latencies_ms) else math.nan
@@ -70,7 +72,9 @@ class ServeStats:
                 "p50_ms": round(self.pct(50), 3), "p99_ms": round(self.pct(99), 3),
                 "mean_batch": round(float(np.mean(self.batch_sizes)), 2) if self.batch_sizes
                 else 0.0,
-                "peak_reserved_gib": round(self.peak_reserved_bytes / 2**30, 3)}
+                "peak_reserved_gib": round(self.peak_reserved_bytes / 2**30, 3),
+                "admission_bound_batches": self.admission_bound,
+                "peak_device_gib": round(self.peak_device_bytes / 2**30, 3)}
 
 
 class Scheduler:
@@ -111,6 +115,7 @@ class Scheduler:
         reserved = peak = 0
         nxt = finished = failed = requeued = 0
         sizes = []
+        bound = 0
         retries = collections.Counter()
         while finished < len(reqs):
             while nxt < len(reqs) and reqs[nxt].arrival <= now():
@@ -141,6 +146,8 @@ class Scheduler:
                         if not batch and not inflight:
                             batch.append(pending.popleft())   # alone in an empty pool
                             nbytes += fb
+                        else:
+                            bound += 1
                         break
                     batch.append(pending.popleft())
                     nbytes += fb
@@ -185,7 +192,9 @@ class Scheduler:
         if skip and counted:
             wall = max(r.t_done for r in counted) - counted[0].arrival
         n_failed = sum(r.status == "failed" for r in counted)
-        return ServeStats(len(counted), wall, lat, sizes, peak, n_failed, requeued)
+        peak_dev = getattr(self.backend, "peak_device_bytes", lambda: 0)()
+        return ServeStats(len(counted), wall, lat, sizes, peak, n_failed, requeued, bound,
+                          peak_dev)
 
 
 class WorkspaceTooSmall(RuntimeError):
@@ -237,10 +246,18 @@ class GpuBackend:
         # sort scratch
         return int(112 * n + 32 * px + 16 * 1.25 * est + (3 << 20))
 
+    def peak_device_bytes(self) -> int:
+        """Device memory the batches held at the peak of the run, beyond what
+        was allocated when the run started (the resident scenes)."""
+        torch = self.torch
+        return max(0, int(torch.cuda.max_memory_allocated(self.device)) - self.base_bytes)
+
     def sync_reference(self, clock):
         """Ties GPU event times to the scheduler clock."""
         torch = self.torch
         torch.cuda.synchronize(self.device)
+        self.base_bytes = int(torch.cuda.memory_allocated(self.device))
+        torch.cuda.reset_peak_memory_stats(self.device)
         self.ref_event = torch.cuda.Event(enable_timing=True)
         self.ref_event.record(torch.cuda.current_stream(self.device))
         torch.cuda.synchronize(self.device)

@@ -187,3 +187,14 @@ def test_warmup_arrivals_are_served_but_not_counted():
     want = np.array([(r.t_done - r.arrival) * 1e3 for r in reqs[20:]])
     assert np.allclose(np.sort(st.latencies_ms), np.sort(want))
     assert st.wall_s == pytest.approx(max(r.t_done for r in reqs[20:]) - reqs[20].arrival)
+
+
+def test_admission_bound_batches_are_counted():
+    clock = FakeClock()
+    be = MockBackend(clock, {0: 30})
+    reqs = _reqs([0.0] * 12, [0] * 12)
+    st = _sched(be, clock, pool=100, max_batch=8).run(reqs)
+    # 3 x 30 fits, the 4th does not: every batch but the last closes on the pool
+    assert st.admission_bound >= 1
+    assert st.summary()["admission_bound_batches"] == st.admission_bound
+    assert st.peak_reserved_bytes <= 100
