@@ -314,48 +314,84 @@ __device__ __forceinline__ float4 colour_of(float cr, float cg, float cb) {
 
 // View-dependent colour from SH (FP32), for the Gaussians with tiles (the
 // others get rgb = 0), when every SH row starts 16-byte aligned (a row of a
-// multiple of 4 floats from an aligned base): each lane loads its own row
-// with up to 12 16-byte loads, all issued before the first use, and keeps it
-// in registers.  No LDS, so the kernel runs at the occupancy its registers
-// allow; a row's 1.5 cache lines are read once.
+// multiple of 4 floats from an aligned base).  The wave lists its lanes with
+// tiles, then copies their rows to LDS kColRows at a time with 16-byte loads,
+// consecutive lanes on consecutive pieces of a row (a row's 1.5 cache lines
+// read by one instruction, rows of Gaussians without tiles not read), and
+// each listed lane reads its own row back.  A lane loading a whole row by
+// itself would make every load instruction touch 64 cache lines.
+constexpr int kColRows = 32;               // rows staged per round
+constexpr int kColPitch = 13;              // 16-byte pieces per staged row: 12 + 1 (banks)
 __global__ __launch_bounds__(kBlock) void k_colour_rows(const Item* __restrict__ items,
                                                         BatchDims dims,
                                                         const uint32_t* __restrict__ counts,
                                                         float4* __restrict__ rgb_out) {
+    __shared__ float4 s_rows[kColRows * kColPitch];
+    __shared__ uint32_t s_lane[kBlock];
     const int64_t slot0 = (int64_t)blockIdx.x * kBlock;
     const Item& it = items[dims.n_items == 1 ? 0 : item_of_slot(items, dims.n_items, slot0)];
-    const int64_t i = slot0 - it.g_off + threadIdx.x;
-    const int64_t o = slot0 + threadIdx.x;
-    if (o >= dims.n_slots) return;
-    if (i >= it.n || counts[o] == 0u) {
-        rgb_out[o] = make_float4(0.f, 0.f, 0.f, 0.f);
-        return;
-    }
+    const int lane = (int)threadIdx.x;
+    const int64_t first = slot0 - it.g_off;
+    const int64_t i = first + lane;
+    const int64_t o = slot0 + lane;
+    const bool vis = o < dims.n_slots && i < it.n && counts[o] != 0u;
+    const uint64_t vm = __ballot(vis);
+    const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(vm >> 32),
+                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)vm, 0u));
+    if (vis) s_lane[rank] = (uint32_t)lane;
+    __syncthreads();
+    const int n_vis = __popcll(vm);
     const int nb = (it.sh_degree + 1) * (it.sh_degree + 1);
     const int q = (3 * nb + 3) / 4;                   // 16-byte pieces holding the nb coefficients
-    const float4* src = reinterpret_cast<const float4*>(it.sh + i * (3 * (int64_t)it.sh_stride));
-    float4 v[12];
-#pragma unroll
-    for (int j = 0; j < 12; ++j)
-        v[j] = j < q ? ld_global(src + j) : make_float4(0.f, 0.f, 0.f, 0.f);
+    const uint32_t urow4 = (uint32_t)(3 * it.sh_stride) / 4u;
+    const float4* base = reinterpret_cast<const float4*>(it.sh + first * (3 * (int64_t)it.sh_stride));
     float Y[16];
-    sh_basis(it.cam, ld_global(it.means + 3 * i), ld_global(it.means + 3 * i + 1),
-             ld_global(it.means + 3 * i + 2), it.sh_degree, Y);
-    float h[48];
+    if (vis)
+        sh_basis(it.cam, ld_global(it.means + 3 * i), ld_global(it.means + 3 * i + 1),
+                 ld_global(it.means + 3 * i + 2), it.sh_degree, Y);
+    float4 col = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int r0 = 0; r0 < n_vis; r0 += kColRows) {
+        const int rows = n_vis - r0 < kColRows ? n_vis - r0 : kColRows;
+        const int pieces = rows * q;
+        // all loads of the round are issued before the first LDS store
+        constexpr int kPer = kColRows * 12 / kBlock;
+        float4 v[kPer];
+        int dst[kPer];
 #pragma unroll
-    for (int j = 0; j < 12; ++j) {
-        h[4 * j] = v[j].x; h[4 * j + 1] = v[j].y; h[4 * j + 2] = v[j].z; h[4 * j + 3] = v[j].w;
-    }
-    float cr = 0.f, cg = 0.f, cbl = 0.f;
-#pragma unroll
-    for (int k = 0; k < 16; ++k) {
-        if (k < nb) {
-            cr = fmaf(Y[k], h[3 * k], cr);
-            cg = fmaf(Y[k], h[3 * k + 1], cg);
-            cbl = fmaf(Y[k], h[3 * k + 2], cbl);
+        for (int u = 0; u < kPer; ++u) {
+            const int p = u * kBlock + lane;
+            const bool ok = p < pieces;
+            const int r = ok ? p / q : 0, j = ok ? p - r * q : 0;
+            dst[u] = ok ? r * kColPitch + j : -1;
+            const uint32_t L = s_lane[r0 + r];          // r0 + r < n_vis
+            v[u] = ok ? ld_global(base + (uint64_t)L * urow4 + j) : make_float4(0.f, 0.f, 0.f, 0.f);
         }
+#pragma unroll
+        for (int u = 0; u < kPer; ++u)
+            if (dst[u] >= 0) s_rows[dst[u]] = v[u];
+        __syncthreads();
+        if (vis && (int)rank >= r0 && (int)rank < r0 + kColRows) {
+            const float4* row = s_rows + ((int)rank - r0) * kColPitch;
+            float h[48];
+#pragma unroll
+            for (int j = 0; j < 12; ++j) {
+                const float4 x = j < q ? row[j] : make_float4(0.f, 0.f, 0.f, 0.f);
+                h[4 * j] = x.x; h[4 * j + 1] = x.y; h[4 * j + 2] = x.z; h[4 * j + 3] = x.w;
+            }
+            float cr = 0.f, cg = 0.f, cbl = 0.f;
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                if (k < nb) {
+                    cr = fmaf(Y[k], h[3 * k], cr);
+                    cg = fmaf(Y[k], h[3 * k + 1], cg);
+                    cbl = fmaf(Y[k], h[3 * k + 2], cbl);
+                }
+            }
+            col = colour_of(cr, cg, cbl);
+        }
+        __syncthreads();
     }
-    rgb_out[o] = colour_of(cr, cg, cbl);
+    if (o < dims.n_slots) rgb_out[o] = col;
 }
 
 // The same for any row layout: one wave per workgroup stages the SH rows of
