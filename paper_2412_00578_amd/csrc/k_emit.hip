@@ -20,11 +20,11 @@
 //               in its own segment of the scratch (no atomics: thousands on one
 //               counter would serialise), and one workgroup turns the
 //               per-segment counts into offsets;
-//   k_emit_big  one wave per queued entry re-walks the FP64 tile spans of the
-//               record: lanes compute up to 64 spans (rows, or columns for
-//               AccuTile on tall extents) at once, a wave prefix sum places
-//               them, and the wave writes the keys with consecutive lanes on
-//               consecutive addresses.
+//   k_emit_big  each wave takes 64 queued entries at a time and re-walks the
+//               FP64 tile spans of their records: the spans (rows, or columns
+//               for AccuTile on tall extents) of all 64 are dealt out to the
+//               lanes, a wave prefix sum places them, and the wave writes the
+//               keys with consecutive lanes on consecutive addresses.
 #include "ss_internal.h"
 
 namespace ss {
@@ -221,25 +221,42 @@ __global__ __launch_bounds__(kBigBlock) void k_emit_big(const Item* __restrict__
                                                         uint32_t* __restrict__ values,
                                                         const uint32_t* __restrict__ queue,
                                                         const uint64_t* __restrict__ totals) {
-    __shared__ uint32_t s_excl[kBigBlock / 64][64];
+    constexpr int kW = kBigBlock / 64;
+    // per band of the current chunk: start of its tiles in the chunk, tile id of
+    // its first tile, tile id step along it, pair position of its first tile,
+    // end of its entry's pair range, its Gaussian
+    __shared__ uint32_t s_excl[kW][64];
+    __shared__ uint32_t s_tile[kW][64];
+    __shared__ uint32_t s_step[kW][64];
+    __shared__ uint32_t s_pos[kW][64];
+    __shared__ uint32_t s_end[kW][64];
+    __shared__ uint32_t s_gid[kW][64];
+    __shared__ uint32_t s_done[kW][64];      // tiles placed so far, per entry of the round
     limit = (uint32_t)frame_count(totals, 0, limit);
-    __shared__ int s_lo[kBigBlock / 64][64];
     const int w = threadIdx.x >> 6;
     const int lane = (int)__lane_id();
     const uint32_t* seg_off = queue + nb * kEmitBlock + nb;
     const uint32_t* coarse = queue + nb * kEmitBlock + 2 * nb + 1;
     const uint32_t nq = seg_off[nb];
-    const uint32_t wave0 = blockIdx.x * (kBigBlock / 64) + w;
-    const uint32_t waves = gridDim.x * (kBigBlock / 64);
+    const uint32_t wave0 = blockIdx.x * kW + w;
+    const uint32_t waves = gridDim.x * kW;
     // Each round, lane l of the wave looks up queued entry wave0 + (64 r + l)
     // waves, so that the chains of dependent loads (segment search, entry,
-    // Gaussian, record) of 64 entries overlap; the wave then walks the 64
-    // entries' spans one entry at a time.
+    // Gaussian, record) of 64 entries overlap.  The bands (tile rows, or
+    // columns for AccuTile on tall extents) of the round's entries are then
+    // dealt out to the lanes 64 at a time, each band's span evaluated on its
+    // own as the preprocess stage counted it, and the chunk's tiles written
+    // with consecutive lanes on consecutive pair positions.  A band takes its
+    // place in its entry's pair range with an LDS add: the order of one
+    // Gaussian's own pairs does not matter.
     for (uint32_t r0 = 0; wave0 + (uint64_t)r0 * waves < nq; r0 += 64) {
         const uint64_t bq = wave0 + (uint64_t)(r0 + lane) * waves;
         const bool have = bq < nq;
         const uint32_t b = have ? (uint32_t)bq : 0u;
         Ellipse e;
+        e.u = e.v = e.a = e.b = e.c = e.t = e.det = e.hx = e.hy = 0.0;
+        e.x0 = e.x1 = e.y0 = e.y1 = 0;
+        e.cols = false;
         bool ok = false;
         uint32_t i = 0, pos0 = 0, end = 0, tile_off = 0;
         int tx_n = 0, ty_n = 0, by0 = 0, by1 = 0;
@@ -265,10 +282,25 @@ __global__ __launch_bounds__(kBigBlock) void k_emit_big(const Item* __restrict__
             end = offsets[j];
             ok = ellipse_setup(geom[i], conic[i], mode, tx_n, ty_n, by0, by1, e);
         }
-        uint64_t todo = __ballot(ok);
-        while (todo) {
-            const int L = __builtin_ctzll(todo);
-            todo &= todo - 1ull;
+        const bool cols = ok && span_columns(e, mode);
+        const uint32_t nmaj =
+            ok ? (uint32_t)(cols ? e.x1 - e.x0 + 1 : e.y1 - e.y0 + 1) : 0u;
+        const uint32_t incl = wave_incl_scan_u32(nmaj);
+        const uint32_t n_bands = __shfl(incl, 63, 64);
+        s_done[w][lane] = 0u;
+        wave_lds_sync();
+        for (uint32_t c0 = 0; c0 < n_bands; c0 += 64) {
+            const uint32_t jb = c0 + (uint32_t)lane;
+            // owner L: the first lane whose inclusive band count exceeds jb
+            int L = 0;
+#pragma unroll
+            for (int step = 32; step >= 1; step >>= 1) {
+                const uint32_t v = (uint32_t)__shfl((int)incl, L + step - 1, 64);
+                if (v <= jb) L += step;
+            }
+            L = L > 63 ? 63 : L;
+            const int k = (int)(jb - ((uint32_t)__shfl((int)incl, L, 64) -
+                                      (uint32_t)__shfl((int)nmaj, L, 64)));
             Ellipse el;
             el.u = __shfl(e.u, L, 64); el.v = __shfl(e.v, L, 64);
             el.a = __shfl(e.a, L, 64); el.b = __shfl(e.b, L, 64); el.c = __shfl(e.c, L, 64);
@@ -276,54 +308,54 @@ __global__ __launch_bounds__(kBigBlock) void k_emit_big(const Item* __restrict__
             el.hx = __shfl(e.hx, L, 64); el.hy = __shfl(e.hy, L, 64);
             el.x0 = __shfl(e.x0, L, 64); el.x1 = __shfl(e.x1, L, 64);
             el.y0 = __shfl(e.y0, L, 64); el.y1 = __shfl(e.y1, L, 64);
-            el.cols = __shfl((int)e.cols, L, 64) != 0;
-            const int row0 = __shfl(by0, L, 64);    // the band's first tile row
+            const bool cl = __shfl((int)cols, L, 64) != 0;
+            el.cols = cl;
+            const int row0 = __shfl(by0, L, 64);    // the item's first tile row
+            const int txn = __shfl(tx_n, L, 64), tyn = __shfl(ty_n, L, 64);
             const uint32_t gi = __shfl(i, L, 64), p0 = __shfl(pos0, L, 64);
             const uint32_t pend = __shfl(end, L, 64), toff = __shfl(tile_off, L, 64);
-            const int txn = __shfl(tx_n, L, 64), tyn = __shfl(ty_n, L, 64);
-            const bool cols = span_columns(el, mode);
-            const int maj0 = cols ? el.x0 : el.y0;
-            const int nmaj = cols ? el.x1 - el.x0 + 1 : el.y1 - el.y0 + 1;
-            uint32_t done = 0;
-            for (int c0 = 0; c0 < nmaj; c0 += 64) {
-                int lo = 0, hi = -1;
-                if (c0 + lane < nmaj) {
-                    if (mode == SS_TILE_ACCUTILE) {
-                        accutile_band(el, cols, c0 + lane, txn, tyn, lo, hi);
-                    } else {
-                        lo = el.x0;
-                        hi = el.x1;
-                    }
+            int lo = 0, hi = -1;
+            if (jb < n_bands) {
+                if (mode == SS_TILE_ACCUTILE) {
+                    accutile_band(el, cl, k, txn, tyn, lo, hi);
+                } else {
+                    lo = el.x0;
+                    hi = el.x1;
                 }
-                const uint32_t len = hi >= lo ? (uint32_t)(hi - lo + 1) : 0u;
-                const uint32_t incl = wave_incl_scan_u32(len);
-                const uint32_t total = __shfl(incl, 63, 64);
-                s_excl[w][lane] = incl - len;
-                s_lo[w][lane] = lo;
-                wave_lds_sync();
-                for (uint32_t idx = lane; idx < total; idx += 128) {
-                    // the last spans whose exclusive starts are <= idx, idx + 64
-                    int ab[2];
-                    last_le64x2(s_excl[w], idx, idx + 64, ab[0], ab[1]);
-#pragma unroll
-                    for (int h = 0; h < 2; ++h) {
-                        const uint32_t ix = idx + 64u * h;
-                        const int a = ab[h];
-                        const int major = maj0 + c0 + a;
-                        const int minor = s_lo[w][a] + (int)(ix - s_excl[w][a]);
-                        const uint32_t tile =
-                            toff + (cols ? (uint32_t)((minor - row0) * txn + major)
-                                         : (uint32_t)((major - row0) * txn + minor));
-                        const uint32_t pos = p0 + done + ix;
-                        if (ix < total && pos < pend && pos < limit) {
-                            keys[pos] = tile;
-                            values[pos] = gi;
-                        }
-                    }
-                }
-                done += total;
-                wave_lds_sync();
             }
+            const uint32_t len = hi >= lo ? (uint32_t)(hi - lo + 1) : 0u;
+            const uint32_t start = len ? atomicAdd(&s_done[w][L], len) : 0u;
+            const int major = (cl ? el.x0 : el.y0) + k;
+            // tile id of the band's minor index m: rows toff + (major - row0) txn + m,
+            // columns toff + (m - row0) txn + major
+            const uint32_t t_lo = cl ? toff + (uint32_t)((lo - row0) * txn + major)
+                                     : toff + (uint32_t)((major - row0) * txn + lo);
+            const uint32_t cincl = wave_incl_scan_u32(len);
+            const uint32_t ctotal = __shfl(cincl, 63, 64);
+            s_excl[w][lane] = cincl - len;
+            s_tile[w][lane] = t_lo;
+            s_step[w][lane] = cl ? (uint32_t)txn : 1u;
+            s_pos[w][lane] = p0 + start;
+            s_end[w][lane] = pend;
+            s_gid[w][lane] = gi;
+            wave_lds_sync();
+            for (uint32_t idx = lane; idx < ctotal; idx += 128) {
+                // the last bands whose exclusive starts are <= idx, idx + 64
+                int ab[2];
+                last_le64x2(s_excl[w], idx, idx + 64, ab[0], ab[1]);
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const uint32_t ix = idx + 64u * h;
+                    const int a = ab[h];
+                    const uint32_t off = ix - s_excl[w][a];
+                    const uint32_t pos = s_pos[w][a] + off;
+                    if (ix < ctotal && pos < s_end[w][a] && pos < limit) {
+                        keys[pos] = s_tile[w][a] + off * s_step[w][a];
+                        values[pos] = s_gid[w][a];
+                    }
+                }
+            }
+            wave_lds_sync();
         }
     }
 }
