@@ -19,10 +19,13 @@
 // vector operations a finished strip's failing q <= t test takes.  The
 // quadratic form of the stored record is evaluated in FP64, with dx and dy
 // from one subtraction each and q = fma(fma(c, dy, (2b) dx), dy, (a dx) dx),
-// and compared with the record's t: the inclusion test (alpha >= 1/255) is the
-// inequality the tile geometry decides in FP64 on the same record, so a pixel
-// is included only where its tile was assigned, and an ill-conditioned q (a
-// needle-like Gaussian seen along its long axis) keeps its accuracy.  FP64
+// and compared with the record's t: the inclusion test (alpha >= 1/255) is
+// the inequality the tile geometry decides in FP64 on the same record, so a
+// pixel is included only where its tile was assigned, and an ill-conditioned
+// q (a needle-like Gaussian seen along its long axis) keeps its accuracy.
+// The four strips' q are evaluated before any of their inclusion branches, so
+// their FP64 dependency chains overlap instead of each waiting behind the
+// previous strip's branch.  FP64
 // adds and FMAs issue at the rate of FP32 ones, and the record is staged in
 // LDS already widened.  alpha = sigma exp(-q/2) is evaluated in FP32 as
 // exp2(fma(q, -log2(e)/2, log2 sigma)) with log2 sigma taken once per staged
@@ -296,10 +299,18 @@ __device__ __forceinline__ void blend_tile(const int tile, Stage& st,
                 const double adx2 = (ab.x * dx) * dx;
                 const double b2dx = ab.y * dx;
                 const uint32_t pos = base + k - start + 1u;
+                // the four strips' FP64 chains first, so their latencies overlap
+                double q4[4];
 #pragma unroll
                 for (int s = 0; s < 4; ++s) {
                     const double dy = fy[s] - uv.y;
-                    const double qq = fma(fma(ct.x, dy, b2dx), dy, adx2);
+                    q4[s] = fma(fma(ct.x, dy, b2dx), dy, adx2);
+                }
+                // keeps the compiler from sinking each chain into its branch
+                asm volatile("" : "+v"(q4[0]), "+v"(q4[1]), "+v"(q4[2]), "+v"(q4[3]));
+#pragma unroll
+                for (int s = 0; s < 4; ++s) {
+                    const double qq = q4[s];
                     if (qq <= ct.y) {
                         const float al = fminf(kAlphaMax, __builtin_amdgcn_exp2f(
                                                               fmaf((float)qq, kNegHalfLog2e, c.w)));
