@@ -385,10 +385,12 @@ int ss_render(const ss_camera *cam, const ss_gaussians *g, int32_t mode, const s
  * leaves in frame->totals on the device, so the host can queue frame after
  * frame and the GPU never waits for a read-back.  If the frame has more pairs
  * than pairs->capacity, no pair is written and the image is the background
- * alone: the caller finds out from the frame counts, which are copied into
- * *counts_host (host memory, pinned for an asynchronous copy; may be NULL)
- * once the preprocess has run, and renders the frame again with a larger
- * workspace.  Otherwise the results equal ss_render's bit for bit.
+ * alone: the caller finds out from the frame counts, which land in
+ * *counts_host (host memory; may be NULL) by the time the stream has run the
+ * frame, and renders the frame again with a larger workspace.  Page-locked
+ * host memory (hipHostMalloc, or registered with the runtime) is written by a
+ * kernel of the frame; other host memory by a copy enqueued after the
+ * preprocess stage.  Otherwise the results equal ss_render's bit for bit.
  * pairs->capacity must be at least 1; *out_buf receives the pair buffer
  * holding the sorted pairs.  Events as for ss_render (event [2] directly
  * follows [1]: there is no read-back).

@@ -262,9 +262,12 @@ int begin_impl(const Layout& L, int32_t mode, const ss_frame* f, ss_frame_counts
 // 3-6 only (the caller ran the depth order and the scan).  With c == NULL the
 // stages read the frame counts on the device (frame->totals), launched over
 // the record slots and the pair workspace's capacity (no host read-back).
+// counts_dev: host memory the device can write (or null), receives the frame
+// counts from the tile-order kernel.
 int finish_impl(const ss::BatchDims& d, int32_t mode, const ss_frame* f, const ss_pairs* p,
                 const ss_frame_counts* c, float* out_single, int32_t* out_buf,
-                const ss_stage_events* ev, hipStream_t s, bool order = true) {
+                const ss_stage_events* ev, hipStream_t s, bool order = true,
+                uint64_t* counts_dev = nullptr) {
     SS_TRY(check_mode(mode));
     SS_TRY(check_frame_records(f, d.n_slots));
     SS_TRY(check_frame_pixels(f));
@@ -308,7 +311,7 @@ int finish_impl(const ss::BatchDims& d, int32_t mode, const ss_frame* f, const s
     record(ev, 6, s);
     SS_TRY(hip_status(ss::launch_ranges(p->keys[cur], n_pairs, d.n_tiles, f->ranges, s, totals),
                       "ranges"));
-    SS_TRY(hip_status(ss::launch_tile_order(table, d, *f, s), "tile order"));
+    SS_TRY(hip_status(ss::launch_tile_order(table, d, *f, s, counts_dev), "tile order"));
     record(ev, 7, s);
     // a batch's tiles (every item, every resolution) are served by one resident
     // grid pulling from per-XCD work queues
@@ -538,8 +541,23 @@ int ss_render_nosync(const ss_camera* cam, const ss_gaussians* g, int32_t mode,
     if (!out_rgb) return fail(SS_ERR_INVALID_ARG, "out_rgb is NULL");
     const Layout L = single_layout(*cam, *g);
     const hipStream_t s = (hipStream_t)stream;
-    SS_TRY(begin_impl(L, mode, f, counts_host, ev, false, s));
-    return finish_impl(L.d, mode, f, p, nullptr, out_rgb, out_buf, ev, s);
+    // Page-locked host memory is written by the tile-order kernel (no copy on
+    // the stream); other host memory by a copy after the preprocess stage.
+    uint64_t* counts_dev = nullptr;
+    if (counts_host && L.d.n_tiles > 0) {     // the tile-order kernel runs
+        hipPointerAttribute_t attr{};
+        if (hipPointerGetAttributes(&attr, counts_host) == hipSuccess &&
+            attr.type == hipMemoryTypeHost && attr.devicePointer && attr.hostPointer)
+            // the device address of counts_host itself (the attributes may
+            // describe the start of its allocation)
+            counts_dev = reinterpret_cast<uint64_t*>(
+                static_cast<char*>(attr.devicePointer) +
+                (reinterpret_cast<char*>(counts_host) - static_cast<char*>(attr.hostPointer)));
+        else
+            (void)hipGetLastError();     // not registered with the runtime
+    }
+    SS_TRY(begin_impl(L, mode, f, counts_dev ? nullptr : counts_host, ev, false, s));
+    return finish_impl(L.d, mode, f, p, nullptr, out_rgb, out_buf, ev, s, true, counts_dev);
 }
 
 int ss_render_band(const ss_camera* cam, const ss_gaussians* g, int32_t mode, int32_t tile_row0,

@@ -113,13 +113,20 @@ __device__ __forceinline__ uint32_t order_key(const Item* __restrict__ items, in
     return x * kOrderBuckets + (kOrderBuckets - 1u - b);
 }
 
+// counts_out (host memory the device can write, or null) receives the frame
+// counts (totals[0], totals[1]).
 __global__ __launch_bounds__(kOrderThreads) void k_tile_order(const Item* __restrict__ items,
                                                               BatchDims dims,
                                                               const uint32_t* __restrict__ ranges,
                                                               uint32_t* __restrict__ order,
-                                                              uint32_t* __restrict__ queue) {
+                                                              uint32_t* __restrict__ queue,
+                                                              const uint64_t* __restrict__ totals,
+                                                              uint64_t* __restrict__ counts_out) {
     __shared__ uint32_t h[kOrderKeys];
     if (threadIdx.x < 8) queue[threadIdx.x] = 0u;     // the persistent blend's counters
+    if (counts_out && threadIdx.x < 2)
+        __hip_atomic_store(counts_out + threadIdx.x, totals[threadIdx.x], __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_SYSTEM);
     __shared__ uint32_t s_w[kOrderThreads / 64];
     __shared__ uint32_t s_start[9], s_cap[8], s_over[9], s_free[9];
     const int t0 = (int)threadIdx.x;
@@ -415,11 +422,11 @@ __global__ __launch_bounds__(64) void k_blend_persistent(
 }  // namespace
 
 hipError_t launch_tile_order(const Item* items, const BatchDims& d, const ss_frame& f,
-                             hipStream_t s) {
+                             hipStream_t s, uint64_t* counts_out) {
     if (d.n_tiles == 0) return hipSuccess;
     hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(kOrderThreads), 0, s, items, d, f.ranges,
                        tile_order_of(f.table, d.n_items),
-                       tile_queue_of(f.table, d.n_items, d.n_tiles));
+                       tile_queue_of(f.table, d.n_items, d.n_tiles), f.totals, counts_out);
     return hipGetLastError();
 }
 

@@ -435,8 +435,10 @@ hipError_t launch_ranges(const uint32_t* keys, uint64_t n_pairs, int n_tiles, ui
                          hipStream_t s, const uint64_t* totals = nullptr);
 // launch_blend = launch_tile_order (the tiles' work order, from the ranges)
 // followed by launch_blend_tiles.
+// counts_out: host memory the device can write (or null), receives the frame
+// counts f.totals[0..1] when the tile order runs.
 hipError_t launch_tile_order(const Item* items, const BatchDims& d, const ss_frame& f,
-                             hipStream_t s);
+                             hipStream_t s, uint64_t* counts_out = nullptr);
 // persistent: a resident grid pulling tiles from per-XCD work queues instead of
 // one workgroup per tile (the same results).
 hipError_t launch_blend_tiles(const Item* items, const BatchDims& d, const ss_frame& f,
