@@ -20,7 +20,7 @@ PKG = os.path.dirname(HERE)
 ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "libspeedysplat.so")
 SOURCES = ["api.hip", "k_preprocess.hip", "k_scan.hip", "k_emit.hip", "k_sort.hip",
-           "k_blend.hip", "k_backward.hip", "k_prune.hip"]
+           "k_tile_order.hip", "k_blend.hip", "k_backward.hip", "k_prune.hip"]
 ARCH = os.environ.get("SS_OFFLOAD_ARCH", "gfx950")
 
 
