@@ -109,3 +109,32 @@ def test_empty_scene(ss, gpu_device):
     img = out.image.cpu().numpy()
     for ch, b in enumerate(cam.bg):
         assert np.all(img[ch] == np.float32(b))
+
+
+def test_counts_into_pageable_memory(ss, gpu_device):
+    """The frame counts land in ordinary (pageable) host memory too: the
+    library falls back from the kernel's write to a copy on the stream."""
+    import ctypes
+    from paper_2412_00578_amd import _lib
+    from paper_2412_00578_amd.render import make_camera, mode_id
+    print("[case] nosync counts into pageable memory", flush=True)
+    sc, cam = scenegen.scene_c0(), scenegen.camera_c0()
+    g = ss.Gaussians.from_scene(sc, gpu_device)
+    r = ss.Renderer(gpu_device)
+    ref = r.render(g, cam, "accutile", full=True)
+    c = make_camera(cam)
+    frame = r.frame_for(g.n, c.width, c.height)
+    pairs = r.pairs_for(max(ref.n_pairs, 1))
+    out = torch.empty((3, c.height, c.width), dtype=torch.float32, device=gpu_device)
+    host = np.full(2, -1, dtype=np.int64)                    # pageable
+    gs, fs, ps = g.struct(), frame.struct(), pairs.struct()
+    buf = ctypes.c_int32()
+    st = ss.lib().ss_render_nosync(ctypes.byref(c), ctypes.byref(gs), mode_id("accutile"),
+                                   ctypes.byref(fs), ctypes.byref(ps),
+                                   ctypes.c_void_p(out.data_ptr()),
+                                   ctypes.c_void_p(host.ctypes.data), ctypes.byref(buf), None,
+                                   ctypes.c_void_p(torch.cuda.current_stream(gpu_device).cuda_stream))
+    assert st == _lib.SS_OK
+    torch.cuda.synchronize()
+    assert host[0] == ref.n_pairs and host[1] == ref.n_visible
+    assert np.array_equal(out.cpu().numpy(), ref.image.cpu().numpy())
