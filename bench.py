@@ -77,7 +77,8 @@ RATED_SLOTS_PER_WALKED = 42
 # sort moves 20 B per pair per pass; the ranges read 4 B per pair and write
 # 8 B per tile; the blend gathers a 44-B record per pair and writes 20 B per
 # pixel.
-PRE_BYTES_PER_G, PRE_BYTES_PER_VISIBLE = 44 + 56 + 20, 204
+PRE_BYTES_PER_G = 44 + 56
+COLOUR_BYTES_PER_G, COLOUR_BYTES_PER_VISIBLE = 20, 204
 DEPTH_ORDER_BYTES_PER_SLOT, DEPTH_ORDER_BYTES_PER_VISIBLE = 8, 100
 SCAN_BYTES_PER_VISIBLE = 12
 EMIT_BYTES_PER_VISIBLE, EMIT_BYTES_PER_PAIR = 28, 8
@@ -300,7 +301,11 @@ def stage_roofline_ms(stages_bytes, blend_slots):
 
 def frame_bytes(n, v, p, tiles, width, height):
     passes = (int(math.ceil(math.log2(max(tiles, 2)))) + 7) // 8
-    return {"preprocess": n * PRE_BYTES_PER_G + v * PRE_BYTES_PER_VISIBLE,
+    # the colour kernel runs beside the depth order .. ranges (a second
+    # stream), so it has no stage of its own; its bytes count in the roofline
+    # sum only
+    return {"preprocess": n * PRE_BYTES_PER_G,
+            "colour": n * COLOUR_BYTES_PER_G + v * COLOUR_BYTES_PER_VISIBLE,
             "depth_order": n * DEPTH_ORDER_BYTES_PER_SLOT + v * DEPTH_ORDER_BYTES_PER_VISIBLE,
             "scan": v * SCAN_BYTES_PER_VISIBLE,
             "emit": v * EMIT_BYTES_PER_VISIBLE + p * EMIT_BYTES_PER_PAIR,
@@ -663,7 +668,8 @@ def main():
             "blended_pairs_per_frame": int(i_mean), "gaussians_with_tiles": int(v_mean),
             "blend_rated_tslots": round(rated / (stages["blend"] * 1e-3) / 1e12, 3),
             "blend_counted_tslots": round(counted / (stages["blend"] * 1e-3) / 1e12, 3),
-            "stage_gbs": {k: round(fb[k] / (stages[k] * 1e-3) / 1e9, 1) for k in fb},
+            "stage_gbs": {k: round(fb[k] / (stages[k] * 1e-3) / 1e9, 1) for k in fb
+                          if k in stages},
             "stage_roofline_ms": {k: round(v, 4) for k, v in roof.items()},
             "frame_roofline_frac": round(sum(roof.values()) / ms, 4),
         }

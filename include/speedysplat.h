@@ -373,6 +373,16 @@ int ss_forward_back(const ss_camera *cam, int64_t n, int32_t mode, const ss_fram
  * receives the frame counts.  If pairs->capacity < P, returns SS_ERR_WORKSPACE
  * after stage 1 without touching the pair buffers; the caller grows them to P
  * and calls again.  `events` may be NULL.
+ *
+ * ss_render, ss_render_nosync and ss_render_band run the colour kernel on a
+ * second stream of the library's (one per device, created on first use, held
+ * until the process ends) while `stream` runs the depth order, scan, emit,
+ * sort and ranges; `stream` waits for it before the blend, and also when the
+ * call fails after it started.  Work queued on `stream` after the call is
+ * therefore ordered after every kernel of the frame, as with a single stream.
+ * Calls from several host threads on one device are serialised inside the
+ * library while they queue their work.  Stage event [1] follows the geometry
+ * kernel: the colour kernel's time falls within stages 2a-5.
  */
 int ss_render(const ss_camera *cam, const ss_gaussians *g, int32_t mode, const ss_frame *frame,
               const ss_pairs *pairs, float *out_rgb, ss_frame_counts *counts_out,

@@ -5,6 +5,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <vector>
 
 #include "ss_internal.h"
@@ -27,6 +28,37 @@ int hip_status(hipError_t e, const char* where) {
 }
 
 bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
+
+// The colour kernel's second stream and its two events, one set per device,
+// created on first use (default priority, not synchronising with the null
+// stream) and held until the process ends.  A single-call render holds its
+// device's lock from the fork to the enqueued join, so calls from several
+// host threads do not interleave the events.
+struct DeviceSide {
+    std::mutex mu;
+    ss::SideStream side{nullptr, nullptr, nullptr};
+    bool ready = false;
+};
+constexpr int kMaxSideDevices = 64;
+DeviceSide g_side[kMaxSideDevices];
+
+int side_for_device(DeviceSide** out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_status(e, "get device");
+    if (dev < 0 || dev >= kMaxSideDevices) return fail(SS_ERR_HIP, "device %d out of range", dev);
+    DeviceSide& d = g_side[dev];
+    std::lock_guard<std::mutex> lock(d.mu);
+    if (!d.ready) {
+        e = hipStreamCreateWithFlags(&d.side.stream, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&d.side.fork, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&d.side.join, hipEventDisableTiming);
+        if (e != hipSuccess) return hip_status(e, "colour stream");
+        d.ready = true;
+    }
+    *out = &d;
+    return SS_OK;
+}
 
 int tiles_of(const ss_camera* cam, int* tx, int* ty) {
     *tx = (cam->width + ss::kTile - 1) / ss::kTile;
@@ -230,7 +262,8 @@ int check_table(const ss_frame* f) {
 // sync: wait and store them in *out; otherwise enqueue their copy into the
 // host struct *out and return.
 int begin_impl(const Layout& L, int32_t mode, const ss_frame* f, ss_frame_counts* out,
-               const ss_stage_events* ev, bool sync, hipStream_t s) {
+               const ss_stage_events* ev, bool sync, hipStream_t s,
+               const ss::SideStream* side = nullptr) {
     SS_TRY(check_mode(mode));
     SS_TRY(check_frame_records(f, L.d.n_slots));
     SS_TRY(check_table(f));
@@ -239,7 +272,8 @@ int begin_impl(const Layout& L, int32_t mode, const ss_frame* f, ss_frame_counts
     record(ev, 0, s);
     SS_TRY(hip_status(ss::write_items(table, L.items.data(), L.d.n_items, s, f->totals),
                       "item table"));
-    SS_TRY(hip_status(ss::launch_preprocess(table, L.d, mode, *f, sh_rows16(L), s), "preprocess"));
+    SS_TRY(hip_status(ss::launch_preprocess(table, L.d, mode, *f, sh_rows16(L), s, side),
+                      "preprocess"));
     record(ev, 1, s);
     static_assert(sizeof(ss_frame_counts) == 2 * sizeof(uint64_t), "counts layout");
     if (!sync)
@@ -267,7 +301,7 @@ int begin_impl(const Layout& L, int32_t mode, const ss_frame* f, ss_frame_counts
 int finish_impl(const ss::BatchDims& d, int32_t mode, const ss_frame* f, const ss_pairs* p,
                 const ss_frame_counts* c, float* out_single, int32_t* out_buf,
                 const ss_stage_events* ev, hipStream_t s, bool order = true,
-                uint64_t* counts_dev = nullptr) {
+                uint64_t* counts_dev = nullptr, const ss::SideStream* side = nullptr) {
     SS_TRY(check_mode(mode));
     SS_TRY(check_frame_records(f, d.n_slots));
     SS_TRY(check_frame_pixels(f));
@@ -313,6 +347,8 @@ int finish_impl(const ss::BatchDims& d, int32_t mode, const ss_frame* f, const s
                       "ranges"));
     SS_TRY(hip_status(ss::launch_tile_order(table, d, *f, s, counts_dev), "tile order"));
     record(ev, 7, s);
+    // the colour (run on the side stream) is read from here on
+    if (side) SS_TRY(hip_status(hipStreamWaitEvent(s, side->join, 0), "join colour stream"));
     // a batch's tiles (every item, every resolution) are served by one resident
     // grid pulling from per-XCD work queues
     const bool persistent = d.n_items > 1 || kPersistentFrames;
@@ -322,6 +358,22 @@ int finish_impl(const ss::BatchDims& d, int32_t mode, const ss_frame* f, const s
     record(ev, 8, s);
     if (out_buf) *out_buf = cur;
     return SS_OK;
+}
+
+// A whole frame in one call, with the colour kernel on the device's side
+// stream while the caller's stream runs the depth order, scan, emit, sort and
+// ranges; body(side) runs begin_impl and finish_impl, which waits for the
+// colour before the blend.  If a step fails after the fork, the caller's
+// stream still waits for the colour, so nothing queued later on it can race
+// the colour kernel's writes.
+template <class Body>
+int with_colour_stream(hipStream_t s, Body body) {
+    DeviceSide* ds = nullptr;
+    SS_TRY(side_for_device(&ds));
+    std::lock_guard<std::mutex> lock(ds->mu);
+    const int st = body(static_cast<const ss::SideStream*>(&ds->side));
+    if (st != SS_OK) (void)hipStreamWaitEvent(s, ds->side.join, 0);
+    return st;
 }
 
 }  // namespace
@@ -523,13 +575,20 @@ int ss_render(const ss_camera* cam, const ss_gaussians* g, int32_t mode, const s
               const ss_pairs* p, float* out_rgb, ss_frame_counts* counts_out, int32_t* out_buf,
               const ss_stage_events* ev, void* stream) {
     if (!p) return fail(SS_ERR_INVALID_ARG, "pairs is NULL");
-    ss_frame_counts c{};
-    SS_TRY(ss_forward_begin(cam, g, mode, f, &c, ev, stream));
-    if (counts_out) *counts_out = c;
-    if (c.n_pairs > p->capacity)
-        return fail(SS_ERR_WORKSPACE, "%llu pairs exceed the workspace capacity %llu",
-                    (unsigned long long)c.n_pairs, (unsigned long long)p->capacity);
-    return ss_forward_finish(cam, g->n, mode, f, p, &c, out_rgb, out_buf, ev, stream);
+    SS_TRY(check_camera(cam));
+    SS_TRY(check_gaussians(g));
+    if (!out_rgb) return fail(SS_ERR_INVALID_ARG, "out_rgb is NULL");
+    const Layout L = single_layout(*cam, *g);
+    const hipStream_t s = (hipStream_t)stream;
+    return with_colour_stream(s, [&](const ss::SideStream* side) {
+        ss_frame_counts c{};
+        SS_TRY(begin_impl(L, mode, f, &c, ev, true, s, side));
+        if (counts_out) *counts_out = c;
+        if (c.n_pairs > p->capacity)
+            return fail(SS_ERR_WORKSPACE, "%llu pairs exceed the workspace capacity %llu",
+                        (unsigned long long)c.n_pairs, (unsigned long long)p->capacity);
+        return finish_impl(L.d, mode, f, p, &c, out_rgb, out_buf, ev, s, true, nullptr, side);
+    });
 }
 
 int ss_render_nosync(const ss_camera* cam, const ss_gaussians* g, int32_t mode,
@@ -556,8 +615,11 @@ int ss_render_nosync(const ss_camera* cam, const ss_gaussians* g, int32_t mode,
         else
             (void)hipGetLastError();     // not registered with the runtime
     }
-    SS_TRY(begin_impl(L, mode, f, counts_dev ? nullptr : counts_host, ev, false, s));
-    return finish_impl(L.d, mode, f, p, nullptr, out_rgb, out_buf, ev, s, true, counts_dev);
+    return with_colour_stream(s, [&](const ss::SideStream* side) {
+        SS_TRY(begin_impl(L, mode, f, counts_dev ? nullptr : counts_host, ev, false, s, side));
+        return finish_impl(L.d, mode, f, p, nullptr, out_rgb, out_buf, ev, s, true, counts_dev,
+                           side);
+    });
 }
 
 int ss_render_band(const ss_camera* cam, const ss_gaussians* g, int32_t mode, int32_t tile_row0,
@@ -575,13 +637,15 @@ int ss_render_band(const ss_camera* cam, const ss_gaussians* g, int32_t mode, in
                     tile_row0, tile_row0 + tile_rows, ty);
     const Layout L = band_layout(*cam, *g, tile_row0, tile_rows);
     const hipStream_t s = (hipStream_t)stream;
-    ss_frame_counts c{};
-    SS_TRY(begin_impl(L, mode, f, &c, ev, true, s));
-    if (counts_out) *counts_out = c;
-    if (c.n_pairs > p->capacity)
-        return fail(SS_ERR_WORKSPACE, "%llu pairs exceed the workspace capacity %llu",
-                    (unsigned long long)c.n_pairs, (unsigned long long)p->capacity);
-    return finish_impl(L.d, mode, f, p, &c, out_rgb, out_buf, ev, s);
+    return with_colour_stream(s, [&](const ss::SideStream* side) {
+        ss_frame_counts c{};
+        SS_TRY(begin_impl(L, mode, f, &c, ev, true, s, side));
+        if (counts_out) *counts_out = c;
+        if (c.n_pairs > p->capacity)
+            return fail(SS_ERR_WORKSPACE, "%llu pairs exceed the workspace capacity %llu",
+                        (unsigned long long)c.n_pairs, (unsigned long long)p->capacity);
+        return finish_impl(L.d, mode, f, p, &c, out_rgb, out_buf, ev, s, true, nullptr, side);
+    });
 }
 
 int ss_batch_sizes(const ss_batch_item* items, int32_t n_items, ss_batch_info* out) {

@@ -322,13 +322,12 @@ __device__ __forceinline__ float4 colour_of(float cr, float cg, float cb) {
 // itself would make every load instruction touch 64 cache lines.
 constexpr int kColRows = 32;               // rows staged per round
 constexpr int kColPitch = 13;              // 16-byte pieces per staged row: 12 + 1 (banks)
-__global__ __launch_bounds__(kBlock) void k_colour_rows(const Item* __restrict__ items,
-                                                        BatchDims dims,
-                                                        const uint32_t* __restrict__ counts,
-                                                        float4* __restrict__ rgb_out) {
-    __shared__ float4 s_rows[kColRows * kColPitch];
-    __shared__ uint32_t s_lane[kBlock];
-    const int64_t slot0 = (int64_t)blockIdx.x * kBlock;
+__device__ __forceinline__ void colour_rows_block(const Item* __restrict__ items,
+                                                  const BatchDims& dims,
+                                                  const uint32_t* __restrict__ counts,
+                                                  float4* __restrict__ rgb_out, int64_t slot0,
+                                                  float4* __restrict__ s_rows,
+                                                  uint32_t* __restrict__ s_lane) {
     const Item& it = items[dims.n_items == 1 ? 0 : item_of_slot(items, dims.n_items, slot0)];
     const int lane = (int)threadIdx.x;
     const int64_t first = slot0 - it.g_off;
@@ -392,6 +391,22 @@ __global__ __launch_bounds__(kBlock) void k_colour_rows(const Item* __restrict__
         __syncthreads();
     }
     if (o < dims.n_slots) rgb_out[o] = col;
+}
+
+// Workgroup b colours the slots of blocks b, b + grid, ...: one block each
+// when the grid covers the slots, fewer workgroups when the kernel runs beside
+// the stages that follow the geometry kernel.
+__global__ __launch_bounds__(kBlock) void k_colour_rows(const Item* __restrict__ items,
+                                                        BatchDims dims,
+                                                        const uint32_t* __restrict__ counts,
+                                                        float4* __restrict__ rgb_out) {
+    __shared__ float4 s_rows[kColRows * kColPitch];
+    __shared__ uint32_t s_lane[kBlock];
+    const int64_t blocks = (dims.n_slots + kBlock - 1) / kBlock;
+    for (int64_t b = blockIdx.x; b < blocks; b += gridDim.x) {
+        colour_rows_block(items, dims, counts, rgb_out, b * kBlock, s_rows, s_lane);
+        __syncthreads();              // the next block rewrites s_lane and s_rows
+    }
 }
 
 // The same for any row layout: one wave per workgroup stages the SH rows of
@@ -473,8 +488,30 @@ __global__ __launch_bounds__(1024) void k_totals(const uint32_t* __restrict__ pa
 
 }  // namespace
 
+namespace {
+// Waves per CU of the colour kernel when it runs beside the depth order, scan,
+// emit and sort (measured: 2, 4 and 8 per CU; a full grid slowed those stages
+// by more than it saved).
+constexpr int kColourSideWaves = 8;
+
+// Compute units of the current device (cached per device).
+int compute_units() {
+    static int cached[64] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    if (!cached[dev]) {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            cus <= 0)
+            return 256;
+        cached[dev] = cus;
+    }
+    return cached[dev];
+}
+}  // namespace
+
 hipError_t launch_preprocess(const Item* items, const BatchDims& d, int mode, const ss_frame& f,
-                             bool sh_rows16, hipStream_t s) {
+                             bool sh_rows16, hipStream_t s, const SideStream* side) {
     // per-workgroup partial counts go to the emit stage's scratch, free until then
     const int64_t grid = (d.n_slots + kBlock - 1) / kBlock;
     if (grid > 0) {
@@ -482,9 +519,30 @@ hipError_t launch_preprocess(const Item* items, const BatchDims& d, int mode, co
                            mode, reinterpret_cast<float4*>(f.geom),
                            reinterpret_cast<float4*>(f.conic), f.counts, f.depth_keys,
                            reinterpret_cast<uint4*>(f.tile_sets), f.emit_tmp);
-        hipLaunchKernelGGL(sh_rows16 ? k_colour_rows : k_colour, dim3((unsigned)grid),
-                           dim3(kBlock), 0, s, items, d, f.counts,
-                           reinterpret_cast<float4*>(f.rgb));
+        // the colour needs the counts; only the blend needs the colour
+        hipStream_t cs = s;
+        if (side) {
+            hipError_t e = hipEventRecord(side->fork, s);
+            if (e == hipSuccess) e = hipStreamWaitEvent(side->stream, side->fork, 0);
+            if (e != hipSuccess) return e;
+            cs = side->stream;
+        }
+        // beside the later stages the colour kernel takes a few waves per CU,
+        // leaving the CUs to their latency-bound kernels
+        unsigned cgrid = (unsigned)grid;
+        if (side && sh_rows16) {
+            const int64_t cap = (int64_t)kColourSideWaves * compute_units();
+            cgrid = (unsigned)(grid < cap ? grid : cap);
+        }
+        hipLaunchKernelGGL(sh_rows16 ? k_colour_rows : k_colour, dim3(cgrid), dim3(kBlock), 0, cs,
+                           items, d, f.counts, reinterpret_cast<float4*>(f.rgb));
+        if (side) {
+            const hipError_t e = hipEventRecord(side->join, side->stream);
+            if (e != hipSuccess) return e;
+        }
+    } else if (side) {
+        const hipError_t e = hipEventRecord(side->join, s);     // nothing to wait for
+        if (e != hipSuccess) return e;
     }
     if (grid > 0) {
         // about 1024 partials per reducing workgroup

@@ -406,10 +406,20 @@ __device__ __forceinline__ int item_of_tile(const Item* items, int n_items, int 
 // With `totals`, also zeroes the frame counts (before launch_preprocess adds to them).
 hipError_t write_items(Item* table, const Item* host_items, int n_items, hipStream_t s,
                        uint64_t* totals = nullptr);
+// A second stream the colour kernel can run on while the caller's stream goes
+// on with the stages that do not read the colour: `fork` is recorded on the
+// caller's stream after the geometry kernel and waited for by `stream`;
+// `join` is recorded on `stream` after the colour kernel, and the caller's
+// stream must wait for it before anything reads frame.rgb.
+struct SideStream {
+    hipStream_t stream;
+    hipEvent_t fork, join;
+};
 // sh_rows16: every item's SH rows start 16-byte aligned (base aligned and a
 // row of a multiple of 4 floats), so the colour kernel can load rows whole.
+// side: run the colour kernel there (null: on s).
 hipError_t launch_preprocess(const Item* items, const BatchDims& d, int mode, const ss_frame& f,
-                             bool sh_rows16, hipStream_t s);
+                             bool sh_rows16, hipStream_t s, const SideStream* side = nullptr);
 // With `totals` (device frame counts) non-null, n_visible, n, n_entries and
 // n_pairs below are bounds and the stages read their counts from `totals`.
 hipError_t launch_depth_order(int64_t n, int64_t n_visible, const ss_frame& f, hipStream_t s,
