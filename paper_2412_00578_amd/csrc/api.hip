@@ -346,9 +346,10 @@ int finish_impl(const ss::BatchDims& d, int32_t mode, const ss_frame* f, const s
     SS_TRY(hip_status(ss::launch_ranges(p->keys[cur], n_pairs, d.n_tiles, f->ranges, s, totals),
                       "ranges"));
     SS_TRY(hip_status(ss::launch_tile_order(table, d, *f, s, counts_dev), "tile order"));
-    record(ev, 7, s);
-    // the colour (run on the side stream) is read from here on
+    // the colour (run on the side stream) is read from here on; the blend
+    // stage's event follows the wait, so the stage times the blend alone
     if (side) SS_TRY(hip_status(hipStreamWaitEvent(s, side->join, 0), "join colour stream"));
+    record(ev, 7, s);
     // a batch's tiles (every item, every resolution) are served by one resident
     // grid pulling from per-XCD work queues
     const bool persistent = d.n_items > 1 || kPersistentFrames;
