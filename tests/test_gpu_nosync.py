@@ -138,3 +138,70 @@ def test_counts_into_pageable_memory(ss, gpu_device):
     torch.cuda.synchronize()
     assert host[0] == ref.n_pairs and host[1] == ref.n_visible
     assert np.array_equal(out.cpu().numpy(), ref.image.cpu().numpy())
+
+
+def test_two_caller_streams(ss, gpu_device):
+    """Frames queued alternately on two caller streams (two renderers, no
+    synchronisation between them) share the library's colour stream: each
+    frame's blend must still read its own frame's colours."""
+    print("[case] nosync on two caller streams", flush=True)
+    sc, cams = scenegen.scene_c1(), scenegen.cameras_c1(8)
+    g = ss.Gaussians.from_scene(sc, gpu_device)
+    rs = [ss.Renderer(gpu_device), ss.Renderer(gpu_device)]
+    streams = [torch.cuda.Stream(device=gpu_device), torch.cuda.Stream(device=gpu_device)]
+    for r in rs:
+        for c in cams[:4]:
+            r.render(g, c, "accutile")
+    torch.cuda.synchronize()
+    queued = []
+    for k in range(8):
+        c = cams[k % 4]
+        with torch.cuda.stream(streams[k % 2]):
+            out = torch.empty((3, c.height, c.width), device=gpu_device)
+            queued.append((c, rs[k % 2].render_nosync(g, c, "accutile", out=out)))
+    torch.cuda.synchronize()
+    ref = ss.Renderer(gpu_device)
+    for c, o in queued:
+        assert o.ok()
+        assert np.array_equal(o.image.cpu().numpy(), ref.render(g, c, "accutile").cpu().numpy())
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_single_call_render(ss, gpu_device, mode):
+    """ss_render (one call: colour kernel on the library's second stream)
+    equals the two-call render bit for bit; with a workspace smaller than the
+    frame it reports the counts and SS_ERR_WORKSPACE, and work queued on the
+    caller's stream afterwards still sees the frame's colours."""
+    import ctypes
+    from paper_2412_00578_amd import _lib
+    from paper_2412_00578_amd.render import Pairs, make_camera, mode_id
+    print(f"[case] single-call render {mode}", flush=True)
+    sc, cam = scenegen.scene_c1(), scenegen.camera_c1()
+    g = ss.Gaussians.from_scene(sc, gpu_device)
+    r = ss.Renderer(gpu_device)
+    ref = r.render(g, cam, mode, full=True)
+    ref_img = ref.image.cpu().numpy()
+    ref_rgb = ref.frame.rgb.cpu().numpy()
+    c = make_camera(cam)
+    frame = r.frame_for(g.n, c.width, c.height)
+    stream = ctypes.c_void_p(torch.cuda.current_stream(gpu_device).cuda_stream)
+    gs, fs = g.struct(), frame.struct()
+    for cap in (ref.n_pairs, 1024):
+        pairs = Pairs(cap, gpu_device)
+        ps = pairs.struct()
+        out = torch.zeros((3, c.height, c.width), device=gpu_device)
+        counts = _lib.SSFrameCounts()
+        buf = ctypes.c_int32(-1)
+        st = ss.lib().ss_render(ctypes.byref(c), ctypes.byref(gs), mode_id(mode), ctypes.byref(fs),
+                                ctypes.byref(ps), ctypes.c_void_p(out.data_ptr()),
+                                ctypes.byref(counts), ctypes.byref(buf), None, stream)
+        rgb = frame.rgb.clone()                      # queued on the caller's stream
+        torch.cuda.synchronize()
+        assert counts.n_pairs == ref.n_pairs and counts.n_visible == ref.n_visible
+        vis = frame.counts.cpu().numpy() > 0
+        assert np.array_equal(rgb.cpu().numpy()[vis], ref_rgb[vis])
+        if cap >= ref.n_pairs:
+            assert st == _lib.SS_OK
+            assert np.array_equal(out.cpu().numpy(), ref_img)
+        else:
+            assert st == _lib.SS_ERR_WORKSPACE
