@@ -205,3 +205,37 @@ def test_single_call_render(ss, gpu_device, mode):
             assert np.array_equal(out.cpu().numpy(), ref_img)
         else:
             assert st == _lib.SS_ERR_WORKSPACE
+
+
+def test_every_gaussian_culled(ss, gpu_device):
+    """A scene whose Gaussians are all behind the camera or outside the image:
+    no pairs, the background image, through the two-call, single-call and
+    no-read-back renders."""
+    print("[case] every Gaussian culled", flush=True)
+    cam = scenegen.Camera(96, 64, 80.0, 80.0, 48.0, 32.0, np.eye(3), np.zeros(3),
+                          bg=(0.1, 0.2, 0.3))
+    rng = np.random.default_rng(5)
+    n = 3000
+    behind = np.column_stack([rng.uniform(-1, 1, n // 2), rng.uniform(-1, 1, n // 2),
+                              rng.uniform(-5, -0.5, n // 2)])
+    aside = np.column_stack([rng.uniform(30, 40, n - n // 2), rng.uniform(-1, 1, n - n // 2),
+                             rng.uniform(2, 6, n - n // 2)])
+    means = np.vstack([behind, aside])
+    q = rng.normal(size=(n, 4))
+    sc = scenegen.fixture_scene(means, np.full((n, 3), 0.05), q / np.linalg.norm(q, axis=1)[:, None],
+                                np.full(n, 0.9), rng.uniform(0, 1, (n, 3)))
+    g = ss.Gaussians.from_scene(sc, gpu_device)
+    r = ss.Renderer(gpu_device)
+    two = r.render(g, cam, "accutile", full=True)
+    assert two.n_pairs == 0 and two.n_visible == 0
+    ns = r.render_nosync(g, cam, "accutile")
+    band = r.render_band(g, cam, "accutile", 1, 2)
+    torch.cuda.synchronize()
+    assert ns.ok() and ns.n_pairs == 0
+    for img in (two.image, ns.image):
+        im = img.cpu().numpy()
+        for ch, b in enumerate(cam.bg):
+            assert np.all(im[ch] == np.float32(b))
+    bim = band.cpu().numpy()
+    for ch, b in enumerate(cam.bg):
+        assert np.all(bim[ch] == np.float32(b))
