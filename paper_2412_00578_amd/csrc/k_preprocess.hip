@@ -92,7 +92,105 @@ __device__ __forceinline__ void stage_sh(const float* __restrict__ sh, int64_t f
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_preprocess(const Item* __restrict__ items,
+// The geometry kernel's workgroup: four waves, whose AccuTile bands are dealt
+// out together (a wave alone leaves a third of its last chunk's lanes idle).
+constexpr int kPreBlock = 256;
+static_assert(kSlotAlign % kPreBlock == 0, "a preprocess workgroup must not span two items");
+
+// A record's ellipse as the lanes evaluating its bands read it from LDS.
+struct BandRec {
+    double u, v, a, b, c, t, det, hx, hy;
+    int x0, x1, y0, y1;
+    int flags;                 // bit 0: bands are columns; bit 1: the set fits the mask window
+    int pad;
+};
+static_assert(sizeof(BandRec) == 96, "band record layout");
+
+// AccuTile tile sets of the workgroup's lanes with `want` set (records g, q):
+// the bands of all those records are dealt out to the workgroup's lanes, 64
+// to a wave at a time, each band evaluated on its own (accutile_band), and the
+// band counts and, for a record whose rectangle fits the window, the band's
+// mask bits are gathered per record with LDS atomics.  Returns the lane's
+// count and sets *mask / *origin as rect_tile_set does (all zero for a lane
+// without `want`).  Every thread of the workgroup must call it.
+__device__ __forceinline__ uint32_t accutile_tile_set_wg(bool want, float4 g, float4 q, int tx_n,
+                                                         int ty_n, int by0, int by1,
+                                                         BandRec* s_rec, uint32_t* s_incl,
+                                                         uint32_t* s_nb, uint32_t* s_cnt,
+                                                         uint32_t* s_mask, uint32_t* s_wsum,
+                                                         uint64_t* mask, uint32_t* origin) {
+    const int t = (int)threadIdx.x;
+    const int w = t >> 6, lane = t & 63;
+    Ellipse e;
+    bool fits = false;
+    uint32_t nb = 0;
+    *mask = 0ull;
+    *origin = 0u;
+    if (want && ellipse_setup(g, q, SS_TILE_ACCUTILE, tx_n, ty_n, by0, by1, e)) {
+        const bool cols = span_columns(e, SS_TILE_ACCUTILE);
+        nb = (uint32_t)(cols ? e.x1 - e.x0 + 1 : e.y1 - e.y0 + 1);
+        fits = e.x1 - e.x0 < kSetSide && e.y1 - e.y0 < kSetSide;
+        if (fits) *origin = (uint32_t)e.x0 | ((uint32_t)(e.y0 - by0) << 16);
+        BandRec& r = s_rec[t];
+        r.u = e.u; r.v = e.v; r.a = e.a; r.b = e.b; r.c = e.c; r.t = e.t; r.det = e.det;
+        r.hx = e.hx; r.hy = e.hy;
+        r.x0 = e.x0; r.x1 = e.x1; r.y0 = e.y0; r.y1 = e.y1;
+        r.flags = (cols ? 1 : 0) | (fits ? 2 : 0);
+    }
+    s_nb[t] = nb;
+    s_cnt[t] = 0u;
+    s_mask[2 * t] = 0u;
+    s_mask[2 * t + 1] = 0u;
+    // inclusive prefix sum of the band counts over the workgroup
+    uint32_t incl = nb;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t y = (uint32_t)__shfl_up((int)incl, d, 64);
+        if (lane >= d) incl += y;
+    }
+    if (lane == 63) s_wsum[w] = incl;
+    __syncthreads();
+    for (int k = 0; k < w; ++k) incl += s_wsum[k];
+    s_incl[t] = incl;
+    __syncthreads();
+    const uint32_t total = s_incl[kPreBlock - 1];
+    for (uint32_t c0 = (uint32_t)w * 64u; c0 < total; c0 += kPreBlock) {   // wave-uniform
+        const uint32_t j = c0 + (uint32_t)lane;
+        if (j >= total) continue;
+        // owner L: the first lane whose inclusive sum exceeds j
+        int L = 0;
+#pragma unroll
+        for (int step = kPreBlock / 2; step >= 1; step >>= 1)
+            if (s_incl[L + step - 1] <= j) L += step;
+        const int k = (int)(j - (s_incl[L] - s_nb[L]));
+        const BandRec& r = s_rec[L];
+        Ellipse el;
+        el.u = r.u; el.v = r.v; el.a = r.a; el.b = r.b; el.c = r.c; el.t = r.t; el.det = r.det;
+        el.hx = r.hx; el.hy = r.hy;
+        el.x0 = r.x0; el.x1 = r.x1; el.y0 = r.y0; el.y1 = r.y1;
+        const bool cl = (r.flags & 1) != 0, ft = (r.flags & 2) != 0;
+        el.cols = cl;
+        int lo, hi;
+        if (accutile_band(el, cl, k, tx_n, ty_n, lo, hi)) {
+            const uint32_t len = (uint32_t)(hi - lo + 1);
+            atomicAdd(&s_cnt[L], len);
+            if (ft) {
+                // row band: a run of len bits; column band: len bits 8 apart
+                const uint64_t bits =
+                    cl ? (0x0101010101010101ull >> (8u * (kSetSide - len)))
+                             << ((lo - el.y0) * kSetSide + k)
+                       : ((1ull << len) - 1ull) << (k * kSetSide + (lo - el.x0));
+                if ((uint32_t)bits) atomicOr(&s_mask[2 * L], (uint32_t)bits);
+                if ((uint32_t)(bits >> 32)) atomicOr(&s_mask[2 * L + 1], (uint32_t)(bits >> 32));
+            }
+        }
+    }
+    __syncthreads();
+    if (fits) *mask = (uint64_t)s_mask[2 * t] | ((uint64_t)s_mask[2 * t + 1] << 32);
+    return nb ? s_cnt[t] : 0u;
+}
+
+__global__ __launch_bounds__(kPreBlock) void k_preprocess(const Item* __restrict__ items,
                                                        BatchDims dims, int mode,
                                                        float4* __restrict__ geom,
                                                        float4* __restrict__ conic,
@@ -100,9 +198,11 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(const Item* __restrict__ 
                                                        uint32_t* __restrict__ dkeys,
                                                        uint4* __restrict__ tsets,
                                                        uint32_t* __restrict__ partials) {
-    __shared__ uint32_t s_cnt[kBlock];
-    __shared__ uint32_t s_mask[2 * kBlock];
-    const int64_t slot0 = (int64_t)blockIdx.x * kBlock;
+    __shared__ BandRec s_rec[kPreBlock];
+    __shared__ uint32_t s_incl[kPreBlock], s_nb[kPreBlock], s_cnt[kPreBlock];
+    __shared__ uint32_t s_mask[2 * kPreBlock];
+    __shared__ uint32_t s_wsum[kPreBlock / 64], s_part[2 * (kPreBlock / 64)];
+    const int64_t slot0 = (int64_t)blockIdx.x * kPreBlock;
     const Item& it = items[dims.n_items == 1 ? 0 : item_of_slot(items, dims.n_items, slot0)];
     const ss_camera cam = it.cam;
     const Inputs in{it.means, it.scales, it.quats, it.opacity, it.sh, it.sh_degree, it.sh_stride};
@@ -246,11 +346,11 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(const Item* __restrict__ 
     };
     uint32_t cnt = o < dims.n_slots ? record() : 0u;
 
-    if (mode == SS_TILE_ACCUTILE && __ballot(defer)) {   // wave-uniform
+    if (mode == SS_TILE_ACCUTILE) {   // workgroup-uniform
         uint64_t mask;
         uint32_t origin;
-        const uint32_t c = accutile_tile_set(defer, g4, q4, tx_n, ty_n, by0, by1, s_cnt, s_mask,
-                                             &mask, &origin);
+        const uint32_t c = accutile_tile_set_wg(defer, g4, q4, tx_n, ty_n, by0, by1, s_rec, s_incl,
+                                                s_nb, s_cnt, s_mask, s_wsum, &mask, &origin);
         if (defer) {
             cnt = c;
             tsets[o] = make_uint4((uint32_t)mask, (uint32_t)(mask >> 32), origin, cnt);
@@ -259,18 +359,28 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(const Item* __restrict__ 
         }
     }
 
-    // This workgroup's (one wave's) share of the pair count P and of the
-    // Gaussians with tiles, summed by k_totals: plain stores, since thousands
-    // of atomics on one address would serialise.
+    // This workgroup's share of the pair count P and of the Gaussians with
+    // tiles, summed by k_totals: plain stores, since thousands of atomics on
+    // one address would serialise.
     uint32_t sp = cnt, sv = cnt ? 1u : 0u;
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) {
         sp += __shfl_xor(sp, d, 64);
         sv += __shfl_xor(sv, d, 64);
     }
+    if ((threadIdx.x & 63) == 0) {
+        s_part[2 * (threadIdx.x >> 6)] = sp;
+        s_part[2 * (threadIdx.x >> 6) + 1] = sv;
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
-        partials[2 * blockIdx.x] = sp;
-        partials[2 * blockIdx.x + 1] = sv;
+        uint32_t p = 0, v = 0;
+        for (int k = 0; k < kPreBlock / 64; ++k) {
+            p += s_part[2 * k];
+            v += s_part[2 * k + 1];
+        }
+        partials[2 * blockIdx.x] = p;
+        partials[2 * blockIdx.x + 1] = v;
     }
 }
 
@@ -513,9 +623,10 @@ int compute_units() {
 hipError_t launch_preprocess(const Item* items, const BatchDims& d, int mode, const ss_frame& f,
                              bool sh_rows16, hipStream_t s, const SideStream* side) {
     // per-workgroup partial counts go to the emit stage's scratch, free until then
-    const int64_t grid = (d.n_slots + kBlock - 1) / kBlock;
+    const int64_t pgrid = (d.n_slots + kPreBlock - 1) / kPreBlock;
+    const int64_t grid = (d.n_slots + kBlock - 1) / kBlock;       // the colour kernels'
     if (grid > 0) {
-        hipLaunchKernelGGL(k_preprocess, dim3((unsigned)grid), dim3(kBlock), 0, s, items, d,
+        hipLaunchKernelGGL(k_preprocess, dim3((unsigned)pgrid), dim3(kPreBlock), 0, s, items, d,
                            mode, reinterpret_cast<float4*>(f.geom),
                            reinterpret_cast<float4*>(f.conic), f.counts, f.depth_keys,
                            reinterpret_cast<uint4*>(f.tile_sets), f.emit_tmp);
@@ -544,10 +655,10 @@ hipError_t launch_preprocess(const Item* items, const BatchDims& d, int mode, co
         const hipError_t e = hipEventRecord(side->join, s);     // nothing to wait for
         if (e != hipSuccess) return e;
     }
-    if (grid > 0) {
+    if (pgrid > 0) {
         // about 1024 partials per reducing workgroup
-        const int64_t tg = (grid + 1023) / 1024 < 64 ? (grid + 1023) / 1024 : 64;
-        hipLaunchKernelGGL(k_totals, dim3((unsigned)tg), dim3(1024), 0, s, f.emit_tmp, grid,
+        const int64_t tg = (pgrid + 1023) / 1024 < 64 ? (pgrid + 1023) / 1024 : 64;
+        hipLaunchKernelGGL(k_totals, dim3((unsigned)tg), dim3(1024), 0, s, f.emit_tmp, pgrid,
                            f.totals);
     }
     return hipGetLastError();

@@ -204,87 +204,6 @@ __device__ __forceinline__ uint32_t rect_tile_set(float4 g, float4 q, int mode, 
     return w * h;
 }
 
-// AccuTile tile sets of the wave's lanes with `want` set (records g, q),
-// computed by the whole wave: the bands of all those records are dealt out to
-// the 64 lanes, each band evaluated on its own (accutile_band), and the band
-// counts and, for a record whose rectangle fits the window, the band's mask
-// bits are gathered per record in LDS (s_cnt: 64 words, s_mask: 128 words).
-// A lane walking its own record's bands would leave the wave waiting on its
-// longest walk.  Returns the lane's count and sets *mask / *origin as
-// rect_tile_set does (all zero for a lane without `want`).  All 64 lanes of
-// the wave must call it.
-__device__ __forceinline__ uint32_t accutile_tile_set(bool want, float4 g, float4 q, int tx_n,
-                                                      int ty_n, int by0, int by1, uint32_t* s_cnt,
-                                                      uint32_t* s_mask, uint64_t* mask,
-                                                      uint32_t* origin) {
-    const int lane = (int)__lane_id();
-    Ellipse e;
-    bool cols = false, fits = false;
-    int nb = 0;
-    *mask = 0ull;
-    *origin = 0u;
-    if (want && ellipse_setup(g, q, SS_TILE_ACCUTILE, tx_n, ty_n, by0, by1, e)) {
-        cols = span_columns(e, SS_TILE_ACCUTILE);
-        nb = cols ? e.x1 - e.x0 + 1 : e.y1 - e.y0 + 1;
-        fits = e.x1 - e.x0 < kSetSide && e.y1 - e.y0 < kSetSide;
-        if (fits) *origin = (uint32_t)e.x0 | ((uint32_t)(e.y0 - by0) << 16);
-    } else {
-        e.u = e.v = e.a = e.b = e.c = e.t = e.det = e.hx = e.hy = 0.0;
-        e.x0 = e.x1 = e.y0 = e.y1 = 0;
-        e.cols = false;
-    }
-    // inclusive prefix sum of the band counts over the wave
-    int incl = nb;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const int t = __shfl_up(incl, d, 64);
-        if (lane >= d) incl += t;
-    }
-    const int total = __shfl(incl, 63, 64);
-    s_cnt[lane] = 0u;
-    s_mask[2 * lane] = 0u;
-    s_mask[2 * lane + 1] = 0u;
-    __syncthreads();
-    for (int j0 = 0; j0 < total; j0 += 64) {
-        const int j = j0 + lane;
-        // owner L: the first lane whose inclusive sum exceeds j
-        int L = 0;
-#pragma unroll
-        for (int step = 32; step >= 1; step >>= 1) {
-            const int v = __shfl(incl, L + step - 1, 64);
-            if (v <= j) L += step;
-        }
-        L = L > 63 ? 63 : L;
-        const int k = j - (__shfl(incl, L, 64) - __shfl(nb, L, 64));
-        Ellipse el;
-        el.u = __shfl(e.u, L, 64); el.v = __shfl(e.v, L, 64);
-        el.a = __shfl(e.a, L, 64); el.b = __shfl(e.b, L, 64); el.c = __shfl(e.c, L, 64);
-        el.t = __shfl(e.t, L, 64); el.det = __shfl(e.det, L, 64);
-        el.hx = __shfl(e.hx, L, 64); el.hy = __shfl(e.hy, L, 64);
-        el.x0 = __shfl(e.x0, L, 64); el.x1 = __shfl(e.x1, L, 64);
-        el.y0 = __shfl(e.y0, L, 64); el.y1 = __shfl(e.y1, L, 64);
-        const int fl = __shfl((int)cols | ((int)fits << 1), L, 64);
-        const bool cl = (fl & 1) != 0, ft = (fl & 2) != 0;
-        int lo, hi;
-        if (j < total && accutile_band(el, cl, k, tx_n, ty_n, lo, hi)) {
-            const uint32_t len = (uint32_t)(hi - lo + 1);
-            atomicAdd(&s_cnt[L], len);
-            if (ft) {
-                // row band: a run of len bits; column band: len bits 8 apart
-                const uint64_t bits =
-                    cl ? (0x0101010101010101ull >> (8u * (kSetSide - len)))
-                             << ((lo - el.y0) * kSetSide + k)
-                       : ((1ull << len) - 1ull) << (k * kSetSide + (lo - el.x0));
-                if ((uint32_t)bits) atomicOr(&s_mask[2 * L], (uint32_t)bits);
-                if ((uint32_t)(bits >> 32)) atomicOr(&s_mask[2 * L + 1], (uint32_t)(bits >> 32));
-            }
-        }
-    }
-    __syncthreads();
-    if (fits) *mask = (uint64_t)s_mask[2 * lane] | ((uint64_t)s_mask[2 * lane + 1] << 32);
-    return nb ? s_cnt[lane] : 0u;
-}
-
 // Workgroups are dispatched round-robin over the 8 XCDs of MI355X.  This maps
 // launch index b (grid = 8 * ceil(n/8)) to item b % 8 * ceil(n/8) + b / 8, so
 // every XCD walks a contiguous run of items and keeps their shared data in its
