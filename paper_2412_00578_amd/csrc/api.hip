@@ -51,8 +51,11 @@ int side_for_device(DeviceSide** out) {
     std::lock_guard<std::mutex> lock(d.mu);
     if (!d.ready) {
         e = hipStreamCreateWithFlags(&d.side.stream, hipStreamNonBlocking);
-        if (e == hipSuccess) e = hipEventCreateWithFlags(&d.side.fork, hipEventDisableTiming);
-        if (e == hipSuccess) e = hipEventCreateWithFlags(&d.side.join, hipEventDisableTiming);
+        // both ends of each dependency run on this device: no system-scope
+        // fence (a writeback of the L2s) when the events are recorded
+        const unsigned flags = hipEventDisableTiming | hipEventDisableSystemFence;
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&d.side.fork, flags);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&d.side.join, flags);
         if (e != hipSuccess) return hip_status(e, "colour stream");
         d.ready = true;
     }
