@@ -273,9 +273,13 @@ int begin_impl(const Layout& L, int32_t mode, const ss_frame* f, ss_frame_counts
     if (!out && sync) return fail(SS_ERR_INVALID_ARG, "frame counts pointer is NULL");
     ss::Item* table = reinterpret_cast<ss::Item*>(f->table);
     record(ev, 0, s);
-    SS_TRY(hip_status(ss::write_items(table, L.items.data(), L.d.n_items, s, f->totals),
-                      "item table"));
-    SS_TRY(hip_status(ss::launch_preprocess(table, L.d, mode, *f, sh_rows16(L), s, side),
+    // a single item travels with the geometry kernel
+    const bool single = L.d.n_items == 1;
+    if (!single)
+        SS_TRY(hip_status(ss::write_items(table, L.items.data(), L.d.n_items, s, f->totals),
+                          "item table"));
+    SS_TRY(hip_status(ss::launch_preprocess(table, L.d, mode, *f, sh_rows16(L), s, side,
+                                            single ? L.items.data() : nullptr, table),
                       "preprocess"));
     record(ev, 1, s);
     static_assert(sizeof(ss_frame_counts) == 2 * sizeof(uint64_t), "counts layout");
@@ -441,8 +445,9 @@ int ss_preprocess(const ss_camera* cam, const ss_gaussians* g, int32_t mode, con
     const Layout L = single_layout(*cam, *g);
     hipStream_t s = (hipStream_t)stream;
     ss::Item* table = reinterpret_cast<ss::Item*>(f->table);
-    SS_TRY(hip_status(ss::write_items(table, L.items.data(), 1, s, f->totals), "item table"));
-    return hip_status(ss::launch_preprocess(table, L.d, mode, *f, sh_rows16(L), s), "preprocess");
+    return hip_status(ss::launch_preprocess(table, L.d, mode, *f, sh_rows16(L), s, nullptr,
+                                            L.items.data(), table),
+                      "preprocess");
 }
 
 int ss_depth_order(int64_t n, int64_t n_visible, const ss_frame* f, void* stream) {

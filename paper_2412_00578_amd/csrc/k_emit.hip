@@ -179,7 +179,9 @@ __global__ __launch_bounds__(kEmitBlock) void k_emit(const Item* __restrict__ it
 }
 
 // One workgroup: exclusive offsets of the nb segment counts, total last, and
-// the coarse index of every 64th queued entry.
+// the coarse index of every 64th queued entry.  Each lane scans kOffPer
+// consecutive counts, so up to 4096 segments take one step.
+constexpr int kOffPer = 4;
 __global__ __launch_bounds__(1024) void k_emit_offsets(uint32_t* __restrict__ queue,
                                                        int64_t nb) {
     __shared__ uint32_t s_w[16];
@@ -189,19 +191,29 @@ __global__ __launch_bounds__(1024) void k_emit_offsets(uint32_t* __restrict__ qu
     uint32_t* coarse = queue + nb * kEmitBlock + 2 * nb + 1;
     if (threadIdx.x == 0) s_carry = 0u;
     __syncthreads();
-    for (int64_t base = 0; base < nb; base += 1024) {
-        const int64_t b = base + threadIdx.x;
-        const uint32_t x = b < nb ? cnt[b] : 0u;
-        const uint32_t inc = wave_incl_scan_u32(x);
+    for (int64_t base = 0; base < nb; base += 1024 * kOffPer) {
+        const int64_t b0 = base + (int64_t)threadIdx.x * kOffPer;
+        uint32_t x[kOffPer], sum = 0;
+#pragma unroll
+        for (int k = 0; k < kOffPer; ++k) {
+            x[k] = b0 + k < nb ? cnt[b0 + k] : 0u;
+            sum += x[k];
+        }
+        const uint32_t inc = wave_incl_scan_u32(sum);
         const int w = threadIdx.x >> 6;
         if ((threadIdx.x & 63) == 63) s_w[w] = inc;
         __syncthreads();
         uint32_t before = s_carry;
         for (int k = 0; k < w; ++k) before += s_w[k];
-        if (b < nb) {
-            const uint32_t o = before + inc - x;
-            off[b] = o;
-            for (uint32_t m = (o + 63u) & ~63u; m < o + x; m += 64u) coarse[m >> 6] = (uint32_t)b;
+        uint32_t o = before + inc - sum;
+#pragma unroll
+        for (int k = 0; k < kOffPer; ++k) {
+            if (b0 + k < nb) {
+                off[b0 + k] = o;
+                for (uint32_t m = (o + 63u) & ~63u; m < o + x[k]; m += 64u)
+                    coarse[m >> 6] = (uint32_t)(b0 + k);
+            }
+            o += x[k];
         }
         __syncthreads();
         if (threadIdx.x == 1023) s_carry = before + inc;

@@ -197,13 +197,30 @@ __global__ __launch_bounds__(kPreBlock) void k_preprocess(const Item* __restrict
                                                        uint32_t* __restrict__ counts,
                                                        uint32_t* __restrict__ dkeys,
                                                        uint4* __restrict__ tsets,
-                                                       uint32_t* __restrict__ partials) {
+                                                       uint32_t* __restrict__ partials,
+                                                       Item item0, Item* __restrict__ table_out,
+                                                       uint64_t* __restrict__ totals) {
     __shared__ BandRec s_rec[kPreBlock];
     __shared__ uint32_t s_incl[kPreBlock], s_nb[kPreBlock], s_cnt[kPreBlock];
     __shared__ uint32_t s_mask[2 * kPreBlock];
     __shared__ uint32_t s_wsum[kPreBlock / 64], s_part[2 * (kPreBlock / 64)];
     const int64_t slot0 = (int64_t)blockIdx.x * kPreBlock;
-    const Item& it = items[dims.n_items == 1 ? 0 : item_of_slot(items, dims.n_items, slot0)];
+    // With table_out, the frame's one item comes as an argument: workgroup 0
+    // writes it to the table the later stages read and zeroes the frame
+    // counts (which k_totals adds to after this kernel), so no launch of its
+    // own precedes the frame.
+    if (table_out && blockIdx.x == 0) {
+        static_assert(sizeof(Item) % 4 == 0, "item words");
+        const uint32_t* src = reinterpret_cast<const uint32_t*>(&item0);
+        uint32_t* dst = reinterpret_cast<uint32_t*>(table_out);
+        for (int k = threadIdx.x; k < (int)(sizeof(Item) / 4); k += kPreBlock) dst[k] = src[k];
+        if (threadIdx.x < 2) totals[threadIdx.x] = 0u;
+    }
+    Item it;
+    if (table_out)
+        it = item0;
+    else
+        it = items[dims.n_items == 1 ? 0 : item_of_slot(items, dims.n_items, slot0)];
     const ss_camera cam = it.cam;
     const Inputs in{it.means, it.scales, it.quats, it.opacity, it.sh, it.sh_degree, it.sh_stride};
     const int64_t n = it.n;
@@ -560,7 +577,7 @@ __global__ __launch_bounds__(kBlock) void k_colour(const Item* __restrict__ item
 // partials) over nb workgroups of k_preprocess: each workgroup sums a
 // contiguous run of partials and adds its two sums with one atomic each
 // (a few dozen atomics on one address; the totals were zeroed by
-// k_write_items).
+// k_write_items or, for a frame of one item, by k_preprocess).
 __global__ __launch_bounds__(1024) void k_totals(const uint32_t* __restrict__ partials, int64_t nb,
                                                  uint64_t* __restrict__ totals) {
     __shared__ uint64_t s_p[16], s_v[16];
@@ -621,15 +638,24 @@ int compute_units() {
 }  // namespace
 
 hipError_t launch_preprocess(const Item* items, const BatchDims& d, int mode, const ss_frame& f,
-                             bool sh_rows16, hipStream_t s, const SideStream* side) {
+                             bool sh_rows16, hipStream_t s, const SideStream* side,
+                             const Item* host_single, Item* table) {
     // per-workgroup partial counts go to the emit stage's scratch, free until then
     const int64_t pgrid = (d.n_slots + kPreBlock - 1) / kPreBlock;
     const int64_t grid = (d.n_slots + kBlock - 1) / kBlock;       // the colour kernels'
+    if (host_single && grid == 0) {
+        // no geometry kernel to carry the item: the table still needs it
+        const hipError_t e = write_items(table, host_single, 1, s, f.totals);
+        if (e != hipSuccess) return e;
+        host_single = nullptr;
+    }
     if (grid > 0) {
+        const Item item0 = host_single ? *host_single : Item{};
         hipLaunchKernelGGL(k_preprocess, dim3((unsigned)pgrid), dim3(kPreBlock), 0, s, items, d,
                            mode, reinterpret_cast<float4*>(f.geom),
                            reinterpret_cast<float4*>(f.conic), f.counts, f.depth_keys,
-                           reinterpret_cast<uint4*>(f.tile_sets), f.emit_tmp);
+                           reinterpret_cast<uint4*>(f.tile_sets), f.emit_tmp, item0,
+                           host_single ? table : nullptr, f.totals);
         // the colour needs the counts; only the blend needs the colour
         hipStream_t cs = s;
         if (side) {

@@ -336,9 +336,13 @@ struct SideStream {
 };
 // sh_rows16: every item's SH rows start 16-byte aligned (base aligned and a
 // row of a multiple of 4 floats), so the colour kernel can load rows whole.
-// side: run the colour kernel there (null: on s).
+// side: run the colour kernel there (null: on s).  host_single (a frame of one
+// item, d.n_items == 1): the item, which the geometry kernel takes as an
+// argument and writes to `table` (== items) while zeroing the frame counts,
+// in place of write_items.
 hipError_t launch_preprocess(const Item* items, const BatchDims& d, int mode, const ss_frame& f,
-                             bool sh_rows16, hipStream_t s, const SideStream* side = nullptr);
+                             bool sh_rows16, hipStream_t s, const SideStream* side = nullptr,
+                             const Item* host_single = nullptr, Item* table = nullptr);
 // With `totals` (device frame counts) non-null, n_visible, n, n_entries and
 // n_pairs below are bounds and the stages read their counts from `totals`.
 hipError_t launch_depth_order(int64_t n, int64_t n_visible, const ss_frame& f, hipStream_t s,
