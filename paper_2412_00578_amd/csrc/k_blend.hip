@@ -77,6 +77,11 @@ __device__ __forceinline__ Rec load_rec(const float4* __restrict__ geom,
     return r;
 }
 
+typedef double d2v __attribute__((ext_vector_type(2)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) d2v lds_d2v;
+typedef __attribute__((address_space(3))) f4v lds_f4v;
+
 // The records of a tile's list staged in LDS, kBatch at a time.
 struct Stage {
     double2 uv[kBatch];     // (u, v)
@@ -161,13 +166,20 @@ __device__ __forceinline__ void blend_tile(const int tile, Stage& st,
         // pixel has finished
         const uint32_t nb8 = (nb + 7u) & ~7u;
         for (uint32_t k0 = 0; k0 < nb8; k0 += 8u) {
+            // the group's first staged record as one LDS address held in a
+            // vector register for its eight entries (each entry's four
+            // reads take it with an immediate offset)
+            uint32_t ga = (uint32_t)(uintptr_t)(const lds_d2v*)(s_uv + k0);
+            asm volatile("" : "+v"(ga));
+            const lds_d2v* __restrict__ g2 = (const lds_d2v*)(uintptr_t)ga;
+            const lds_f4v* __restrict__ g4 = (const lds_f4v*)(uintptr_t)ga;
 #pragma unroll
             for (uint32_t u = 0; u < 8u; ++u) {
                 const uint32_t k = k0 + u;
-                const double2 uv = s_uv[k];
-                const double2 ab = s_ab[k];
-                const double2 ct = s_ct[k];
-                const float4 c = s_col[k];
+                const d2v uv = g2[u];
+                const d2v ab = g2[kBatch + u];
+                const d2v ct = g2[2 * kBatch + u];
+                const f4v c = g4[3 * kBatch + u];
                 const double dx = fx - uv.x;
                 const double adx2 = (ab.x * dx) * dx;
                 const double b2dx = ab.y * dx;
