@@ -12,11 +12,12 @@
 //   k_emit      one lane per entry whose tile set the preprocess stage stored
 //               as a mask (tile rectangle within 8 x 8, so at most 64 tiles;
 //               the depth order left the sets in entry order, so these reads
-//               are coalesced): each
-//               lane expands its mask into its wave's LDS stage (1024 tile
-//               ids; entries past its end are handled as the others), then
-//               the wave copies the stage to the pair buffers with consecutive
-//               lanes on consecutive addresses.  Each workgroup lists its other entries
+//               are coalesced); the wave deals its entries' pairs out to its
+//               lanes (pair idx of the wave: owner by a binary search over
+//               the wave's prefix of counts, tile by selecting the owner's
+//               r-th mask bit), so consecutive lanes write consecutive
+//               addresses and no lane walks a long mask while the others
+//               wait.  Each workgroup lists its other entries
 //               in its own segment of the scratch (no atomics: thousands on one
 //               counter would serialise), and one workgroup turns the
 //               per-segment counts into offsets;
@@ -75,10 +76,26 @@ __device__ __forceinline__ void wave_lds_sync() {
 
 constexpr int kEmitBlock = 256;
 constexpr int kEmitWaves = kEmitBlock / 64;
-// Tile ids one wave can stage.  A wave's masked entries average a few tiles
-// each; entries past the stage's end go to the queue instead, which keeps
-// the kernel's LDS (and so its occupancy) small.
-constexpr int kStage = 1024;
+
+// The bit index of the r-th (from 0) set bit of the 64-bit mask hi:lo, by
+// halving: popcounts of the low half of the remaining window decide which
+// half holds it.
+__device__ __forceinline__ uint32_t select_bit64(uint32_t lo, uint32_t hi, uint32_t r) {
+    const uint32_t pl = (uint32_t)__popc(lo);
+    const bool up = r >= pl;
+    uint32_t x = up ? hi : lo;
+    uint32_t b = up ? 32u : 0u;
+    r = up ? r - pl : r;
+#pragma unroll
+    for (uint32_t half = 16; half >= 1; half >>= 1) {
+        const uint32_t c = (uint32_t)__popc(x & ((1u << half) - 1u));
+        const bool u = r >= c;
+        r = u ? r - c : r;
+        x = u ? x >> half : x;
+        b = u ? b + half : b;
+    }
+    return b;
+}
 
 __global__ __launch_bounds__(kEmitBlock) void k_emit(const Item* __restrict__ items,
                                                      BatchDims dims, uint32_t n_entries,
@@ -90,14 +107,16 @@ __global__ __launch_bounds__(kEmitBlock) void k_emit(const Item* __restrict__ it
                                                      uint32_t* __restrict__ values,
                                                      uint32_t* __restrict__ queue,
                                                      const uint64_t* __restrict__ totals) {
-    __shared__ uint32_t s_tile[kEmitWaves][kStage];
     // n_entries (the queue layout) and limit are bounds; the counts of this
     // frame may be smaller (device frame counts)
     const uint32_t n_valid = (uint32_t)frame_count(totals, 1, n_entries);
     limit = (uint32_t)frame_count(totals, 0, limit);
-    __shared__ uint32_t s_pre[kEmitWaves][64];    // exclusive prefix of the staged counts
+    __shared__ uint32_t s_pre[kEmitWaves][64];    // exclusive prefix of the masked counts
     __shared__ uint32_t s_pos[kEmitWaves][64];    // first pair position of each lane's entry
     __shared__ uint32_t s_gid[kEmitWaves][64];
+    __shared__ uint32_t s_mlo[kEmitWaves][64], s_mhi[kEmitWaves][64];   // the tile mask
+    __shared__ uint32_t s_base[kEmitWaves][64];   // tile id of the mask window's bit 0
+    __shared__ uint32_t s_txn[kEmitWaves][64];    // tiles per image row
     const int w = threadIdx.x >> 6;
     const int lane = (int)__lane_id();
     const int64_t j = (int64_t)blockIdx.x * kEmitBlock + threadIdx.x;   // depth-order entry
@@ -113,10 +132,7 @@ __global__ __launch_bounds__(kEmitBlock) void k_emit(const Item* __restrict__ it
     if (cnt) ts = tsets[j];                       // the tile sets in depth order
     const uint64_t mask = (uint64_t)ts.x | ((uint64_t)ts.y << 32);
     const bool masked = cnt && mask != 0ull;
-    // staged runs in lane order; the lanes whose run would pass the stage's
-    // end (a suffix of the masked lanes) join the queue
-    const bool fit = wave_incl_scan_u32(masked ? cnt : 0u) <= (uint32_t)kStage;
-    const bool big = cnt && !(masked && fit);
+    const bool big = cnt && !masked;
     {   // list the big entries in this workgroup's segment
         __shared__ uint32_t s_nbig[kEmitWaves];
         const uint64_t bigs = __ballot(big);
@@ -136,42 +152,41 @@ __global__ __launch_bounds__(kEmitBlock) void k_emit(const Item* __restrict__ it
         }
         if (threadIdx.x == 0) queue[nb * kEmitBlock + blockIdx.x] = all;
     }
-    const uint32_t small = big ? 0u : cnt;
+    const uint32_t small = masked ? cnt : 0u;
     const uint32_t incl = wave_incl_scan_u32(small);
     const uint32_t total = __shfl(incl, 63, 64);
     if (total == 0u) return;                      // wave-uniform; no workgroup barrier follows
-    const uint32_t pre = incl - small;
-    s_pre[w][lane] = pre;
+    s_pre[w][lane] = incl - small;
     s_pos[w][lane] = prev;
     s_gid[w][lane] = gid;
+    s_mlo[w][lane] = ts.x;
+    s_mhi[w][lane] = ts.y;
     if (small) {
         const Item& it = items[dims.n_items == 1 ? 0 : item_of_slot(items, dims.n_items, gid)];
-        const uint32_t tx_n = (uint32_t)it.tx_n, tile_off = (uint32_t)it.tile_off;
-        const uint32_t x0 = ts.z & 0xffffu, y0 = ts.z >> 16;
-        uint64_t m = mask;
-        uint32_t p = pre;
-        const uint32_t stop = pre + small;        // never past the lane's own share
-        while (m && p < stop) {
-            const uint32_t b = (uint32_t)__builtin_ctzll(m);
-            m &= m - 1ull;
-            s_tile[w][p++] = tile_off + (y0 + b / kSetSide) * tx_n + x0 + b % kSetSide;
-        }
+        const uint32_t tx_n = (uint32_t)it.tx_n;
+        s_base[w][lane] = (uint32_t)it.tile_off + (ts.z >> 16) * tx_n + (ts.z & 0xffffu);
+        s_txn[w][lane] = tx_n;
     }
     wave_lds_sync();
+    // the wave's pairs dealt out to its lanes: output idx belongs to the last
+    // lane whose run starts at or before it, and is that lane's r-th tile
     for (uint32_t idx = (uint32_t)lane; idx < total; idx += 128) {
-        // the last lanes whose staged runs start at or before idx, idx + 64
         const uint32_t idx2 = idx + 64;
         int a, a2;
         last_le64x2(s_pre[w], idx, idx2, a, a2);
-        const uint32_t pos = s_pos[w][a] + (idx - s_pre[w][a]);
+        const uint32_t r = idx - s_pre[w][a];
+        const uint32_t pos = s_pos[w][a] + r;
         if (pos < limit) {
-            keys[pos] = s_tile[w][idx];
+            const uint32_t b = select_bit64(s_mlo[w][a], s_mhi[w][a], r);
+            keys[pos] = s_base[w][a] + (b / kSetSide) * s_txn[w][a] + b % kSetSide;
             values[pos] = s_gid[w][a];
         }
         if (idx2 < total) {
-            const uint32_t pos2 = s_pos[w][a2] + (idx2 - s_pre[w][a2]);
+            const uint32_t r2 = idx2 - s_pre[w][a2];
+            const uint32_t pos2 = s_pos[w][a2] + r2;
             if (pos2 < limit) {
-                keys[pos2] = s_tile[w][idx2];
+                const uint32_t b2 = select_bit64(s_mlo[w][a2], s_mhi[w][a2], r2);
+                keys[pos2] = s_base[w][a2] + (b2 / kSetSide) * s_txn[w][a2] + b2 % kSetSide;
                 values[pos2] = s_gid[w][a2];
             }
         }
