@@ -236,6 +236,50 @@ def test_depth_order_random_keys(ss, gpu_device, n):
     assert np.array_equal(u32(f.emit_tmp[:4 * nv]).reshape(nv, 4), sets[want])
 
 
+@pytest.mark.parametrize("n", [1, 63, 64, 65, 4097, 200_003])
+def test_emit_random_masks(ss, gpu_device, n):
+    # Every entry's tile set as an 8 x 8 mask, from single bits (0 and 63) to
+    # the whole window: each entry's pair range must hold exactly its mask's
+    # tiles (in any order) with its Gaussian as value.
+    print(f"[case] emit masks n={n}", flush=True)
+    rng = np.random.default_rng(n + 13)
+    cam = scenegen.camera_c1()                      # 100 x 65 tiles
+    r = ss.Renderer(gpu_device)
+    # any scene of n Gaussians: the preprocess stage writes the frame's item table
+    g = ss.Gaussians.from_scene(scenegen.scene_c0(n=n, seed=n % 1000), gpu_device)
+    f = r.preprocess(g, cam, "accutile")
+    kind = rng.integers(0, 5, size=n)
+    m = (rng.integers(0, 2**32, size=n, dtype=np.uint64)
+         | (rng.integers(0, 2**32, size=n, dtype=np.uint64) << np.uint64(32)))
+    m = np.where(kind == 0, np.uint64(1), m)
+    m = np.where(kind == 1, np.uint64(1) << np.uint64(63), m)
+    m = np.where(kind == 2, np.uint64(0xFFFFFFFFFFFFFFFF), m)
+    m = np.where(kind == 3, m & (m >> np.uint64(3)) & (m >> np.uint64(7)), m)
+    m = np.where(m == 0, np.uint64(1) << np.uint64(5), m)
+    bits = np.unpackbits(m.view(np.uint8).reshape(n, 8), axis=1, bitorder="little")
+    cnt = bits.sum(1).astype(np.uint32)
+    x0 = rng.integers(0, cam.tiles_x - 7, size=n).astype(np.uint32)
+    y0 = rng.integers(0, cam.tiles_y - 7, size=n).astype(np.uint32)
+    order = rng.permutation(n).astype(np.uint32)
+    sets = np.stack([(m & np.uint64(0xFFFFFFFF)).astype(np.uint32),
+                     (m >> np.uint64(32)).astype(np.uint32), x0 | (y0 << 16), cnt], 1)
+    offs = np.cumsum(cnt, dtype=np.uint64).astype(np.uint32)
+    n_pairs = int(offs[-1])
+    f.order[:n].copy_(torch.from_numpy(order.view(np.int32)))
+    f.offsets[:n].copy_(torch.from_numpy(offs.view(np.int32)))
+    f.emit_tmp[:4 * n].copy_(torch.from_numpy(sets.reshape(-1).view(np.int32)))
+    pairs = r.emit(cam, f, "accutile", n, n_pairs)
+    torch.cuda.synchronize()
+    ent, b = np.nonzero(bits)                       # entry order, bits ascending
+    want_keys = (y0[ent] + b // 8) * cam.tiles_x + x0[ent] + b % 8
+    seg = np.repeat(np.arange(n), cnt)
+    keys = u32(pairs.keys[0][:n_pairs]).astype(np.int64)
+    got = keys[np.lexsort((keys, seg))]
+    want = want_keys.astype(np.int64)[np.lexsort((want_keys, seg))]
+    assert np.array_equal(got, want)
+    assert np.array_equal(u32(pairs.values[0][:n_pairs]), np.repeat(order, cnt))
+
+
 @pytest.mark.parametrize("n", [0, 1, 2, 4095, 4097, 70_001, 5_000_003])
 def test_sort_and_ranges_random_keys(ss, gpu_device, n):
     print(f"[case] sort n={n}", flush=True)
