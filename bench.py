@@ -603,6 +603,8 @@ def main():
                     help="skip the 150k-scene, differentiable-render and adjoint measurements")
     ap.add_argument("--serve-scale", type=float, default=1.0,
                     help="scale of the resident scenes of the serving measurement")
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="only measure the adjoint of the AccuTile frame (for profiling it)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device-to-device copy 5 times (the reference "
                          "kernel for scaling HBM traffic counters)")
@@ -632,6 +634,10 @@ def main():
     cams = scenegen.cameras_c1(8)
     g = ss.Gaussians.from_scene(scene, dev)
     log(f"scene: {scene.n} Gaussians, generated and uploaded in {time.perf_counter() - t0:.1f} s")
+    if args.adjoint_only:
+        res = backward_bench(ss, g, cams, args.steps, args.warmup)
+        print(json.dumps({"backward": res}), flush=True)
+        return
     r = ss.Renderer(dev)
     modes = [m for m in args.modes.split(",") if m]
     tiles = cams[0].tiles_x * cams[0].tiles_y
