@@ -39,6 +39,10 @@
  *   geom  [n,4] f32 = (u, v, depth, t)      t = 2 ln(255 sigma)  (Sec. 4.1)
  *   conic [n,4] f32 = (a, b, c, sigma)      Sigma_2D^{-1} = [[a, b], [b, c]]
  *   rgb   [n,4] f32 = (r, g, b, 0)          view-dependent SH colour
+ * geom and conic are interleaved in one [n,8] buffer: Gaussian i's geom is
+ * floats 8i .. 8i+3 of frame->geom and its conic floats 8i+4 .. 8i+7, with
+ * frame->conic == frame->geom + 4 (a record gather then touches 32
+ * contiguous bytes).
  * The geometry is evaluated in FP64 from the FP32 inputs and rounded once into
  * the record; every tile decision is then made in FP64 on the stored record, so
  * the tile counts of the preprocess stage equal the pairs the emit stage writes.
@@ -60,7 +64,7 @@
 extern "C" {
 #endif
 
-#define SS_ABI_VERSION 4
+#define SS_ABI_VERSION 5
 
 enum ss_status {
     SS_OK = 0,
@@ -107,8 +111,9 @@ typedef struct ss_gaussians {
 
 /* Per-frame buffers, sized by ss_frame_sizes(). */
 typedef struct ss_frame {
-    float *geom;            /* [n,4] */
-    float *conic;           /* [n,4] */
+    float *geom;            /* [n,8] (geom, conic) records, 16-byte aligned (32 keeps
+                               each record within one 64-byte line) */
+    float *conic;           /* geom + 4 (rejected otherwise) */
     float *rgb;             /* [n,4] */
     uint32_t *counts;       /* [n]   tiles per Gaussian */
     uint32_t *depth_keys;   /* [2n]  depth-order sort keys: the preprocess stage writes

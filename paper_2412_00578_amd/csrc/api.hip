@@ -115,6 +115,8 @@ int check_frame_records(const ss_frame* f, int64_t n) {
                   !f->tile_sets))
         return fail(SS_ERR_INVALID_ARG, "a per-Gaussian frame buffer is NULL");
     if (!f->totals) return fail(SS_ERR_INVALID_ARG, "frame totals is NULL");
+    if (n > 0 && f->conic != f->geom + 4)
+        return fail(SS_ERR_INVALID_ARG, "frame conic must be frame geom + 4 (interleaved records)");
     if (!aligned16(f->geom) || !aligned16(f->conic) || !aligned16(f->rgb) ||
         !aligned16(f->tile_sets) || !aligned16(f->emit_tmp))
         return fail(SS_ERR_INVALID_ARG, "frame records and emit_tmp must be 16-byte aligned");

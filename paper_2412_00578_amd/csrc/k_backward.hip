@@ -165,7 +165,7 @@ __global__ __launch_bounds__(64 * (4 / SPW)) void k_blend_bwd(
         const uint32_t cnt = hi - lo;
         if ((uint32_t)lane < cnt) {
             const uint32_t gi = values[start + lo + lane];
-            const float4 g = geom[gi], q = conic[gi], c = rgb[gi];
+            const float4 g = geom[kRec * (size_t)gi], q = conic[kRec * (size_t)gi], c = rgb[gi];
             s_uv[w][lane] = make_double2(g.x, g.y);
             s_ab[w][lane] = make_double2(q.x, 2.0 * (double)q.y);
             s_ct[w][lane] = make_double2(q.z, g.w);
@@ -341,7 +341,7 @@ __global__ __launch_bounds__(kPbBlock) void k_preprocess_bwd(ss_camera cam, BwdI
     const int nb = (in.sh_degree + 1) * (in.sh_degree + 1);
     const int need = 3 * nb, row = 3 * in.sh_stride;
     const bool real = i < n;
-    const float4 rec = real ? conic_rec[i] : make_float4(0.f, 0.f, 0.f, 0.f);
+    const float4 rec = real ? conic_rec[kRec * i] : make_float4(0.f, 0.f, 0.f, 0.f);
     const bool alive = rec.x != 0.0f || rec.y != 0.0f || rec.z != 0.0f;
     const float* G = g2d + (size_t)(real ? i : 0) * 12;
     const float4 col = real ? rgb_rec[i] : make_float4(0.f, 0.f, 0.f, 0.f);

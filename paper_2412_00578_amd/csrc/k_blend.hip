@@ -71,8 +71,8 @@ __device__ __forceinline__ Rec load_rec(const float4* __restrict__ geom,
                                         const float4* __restrict__ conic,
                                         const float4* __restrict__ rgb, uint32_t gi) {
     Rec r;
-    r.g = geom[gi];
-    r.q = conic[gi];
+    r.g = geom[kRec * (uint64_t)gi];
+    r.q = conic[kRec * (uint64_t)gi];
     r.c = rgb[gi];
     return r;
 }

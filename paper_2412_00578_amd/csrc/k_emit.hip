@@ -307,7 +307,8 @@ __global__ __launch_bounds__(kBigBlock) void k_emit_big(const Item* __restrict__
             tile_off = (uint32_t)it.tile_off;
             pos0 = j > 0 ? offsets[j - 1] : 0u;
             end = offsets[j];
-            ok = ellipse_setup(geom[i], conic[i], mode, tx_n, ty_n, by0, by1, e);
+            ok = ellipse_setup(geom[kRec * (uint64_t)i], conic[kRec * (uint64_t)i], mode, tx_n,
+                               ty_n, by0, by1, e);
         }
         const bool cols = ok && span_columns(e, mode);
         const uint32_t nmaj =

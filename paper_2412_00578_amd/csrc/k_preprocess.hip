@@ -247,7 +247,7 @@ __global__ __launch_bounds__(kPreBlock) void k_preprocess(const Item* __restrict
     auto record = [&]() -> uint32_t {
         const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
         if (i >= n) {  // padding slot between items
-            geom[o] = zero; conic[o] = zero; counts[o] = 0u;
+            geom[kRec * o] = zero; conic[kRec * o] = zero; counts[o] = 0u;
             dkeys[o] = kCulledKey;
             tsets[o] = make_uint4(0u, 0u, 0u, 0u);
             return 0u;
@@ -271,7 +271,7 @@ __global__ __launch_bounds__(kPreBlock) void k_preprocess(const Item* __restrict
         const double nn = ((qw * qw + qx * qx) + qy * qy) + qz * qz;
         ok = ok && (nn > 0.0);
         if (!ok) {
-            geom[o] = zero; conic[o] = zero; counts[o] = 0u;
+            geom[kRec * o] = zero; conic[kRec * o] = zero; counts[o] = 0u;
             dkeys[o] = kCulledKey;
             tsets[o] = make_uint4(0u, 0u, 0u, 0u);
             return 0u;
@@ -339,7 +339,7 @@ __global__ __launch_bounds__(kPreBlock) void k_preprocess(const Item* __restrict
         const float ca = (float)(C / D), cb = (float)(-B / D), cc = (float)(A / D);
         const float tt = (float)(2.0 * log(255.0 * (double)op));
         if (!(D > 0.0) || (mode != SS_TILE_3SIGMA && !(tt > 0.0f))) {
-            geom[o] = zero; conic[o] = zero; counts[o] = 0u;
+            geom[kRec * o] = zero; conic[kRec * o] = zero; counts[o] = 0u;
             dkeys[o] = kCulledKey;
             tsets[o] = make_uint4(0u, 0u, 0u, 0u);
             return 0u;
@@ -347,8 +347,8 @@ __global__ __launch_bounds__(kPreBlock) void k_preprocess(const Item* __restrict
 
         g4 = make_float4((float)u, (float)v, (float)z, tt);
         q4 = make_float4(ca, cb, cc, op);
-        geom[o] = g4;
-        conic[o] = q4;
+        geom[kRec * o] = g4;
+        conic[kRec * o] = q4;
         if (mode == SS_TILE_ACCUTILE) {   // tile set computed by the wave below
             defer = true;
             return 0u;

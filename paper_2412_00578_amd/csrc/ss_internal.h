@@ -21,6 +21,10 @@ constexpr float kAlphaMax = 0.99f;        // upper clamp of alpha
 constexpr float kTMin = 1e-4f;            // transmittance stop
 constexpr float kAlphaMin = 1.0f / 255.0f;  // inclusion cutoff, used as q <= t
 constexpr uint32_t kCulledKey = 0xffffffffu;  // depth-order key of a slot with no tiles
+// A Gaussian's record is geom (u, v, depth, t) followed by conic (a, b, c,
+// sigma): float4s kRec * i and kRec * i + 1 of frame.geom (frame.conic is
+// frame.geom + 4 floats), so a gather of both touches one 32-byte piece.
+constexpr int kRec = 2;
 
 // ---------------------------------------------------------------- tile geometry
 //

@@ -85,8 +85,9 @@ class Frame:
         self.info = info
         self.n, self.width, self.height = n, width, height
         dev = torch.device(device)
-        self.geom = torch.empty((n, 4), dtype=torch.float32, device=dev)
-        self.conic = torch.empty((n, 4), dtype=torch.float32, device=dev)
+        # geom and conic interleaved: one [n, 8] buffer, two [n, 4] views
+        self.records = torch.empty((n, 8), dtype=torch.float32, device=dev)
+        self.geom, self.conic = self.records[:, :4], self.records[:, 4:]
         self.rgb = torch.empty((n, 4), dtype=torch.float32, device=dev)
         self.counts = torch.empty(n, dtype=torch.int32, device=dev)
         self.depth_keys = torch.empty(2 * n, dtype=torch.int32, device=dev)
@@ -612,8 +613,8 @@ class BatchFrame:
         dev = torch.device(device)
         ns, npx = int(info.n_slots), int(info.n_pixels)
         self.info = info
-        self.geom = torch.empty((ns, 4), dtype=torch.float32, device=dev)
-        self.conic = torch.empty((ns, 4), dtype=torch.float32, device=dev)
+        self.records = torch.empty((ns, 8), dtype=torch.float32, device=dev)
+        self.geom, self.conic = self.records[:, :4], self.records[:, 4:]
         self.rgb = torch.empty((ns, 4), dtype=torch.float32, device=dev)
         self.counts = torch.empty(ns, dtype=torch.int32, device=dev)
         self.depth_keys = torch.empty(2 * ns, dtype=torch.int32, device=dev)

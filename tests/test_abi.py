@@ -40,7 +40,7 @@ def test_every_declared_symbol_is_exported_and_bound(L):
 def test_constants_match_independent_values(L):
     from paper_2412_00578_amd import _lib
     c = _lib.constants()
-    assert c.abi_version == 4 and c.tile == 16
+    assert c.abi_version == 5 and c.tile == 16
     assert c.alpha_min == pytest.approx(1 / 255, rel=1e-7)
     assert c.alpha_max == pytest.approx(0.99, rel=1e-7)
     assert c.t_min == pytest.approx(1e-4, rel=1e-7)
