@@ -101,6 +101,27 @@ def test_invalid_arguments_rejected_before_launch(L):
     assert L.ss_preprocess(ctypes.byref(camf), ctypes.byref(g), 2, ctypes.byref(f), None) == bad
 
 
+def test_records_must_be_interleaved(L):
+    # frame.conic must be frame.geom + 4 floats (one [n, 8] record buffer); a
+    # frame with separate arrays is rejected before anything is launched
+    import numpy as np
+    from paper_2412_00578_amd import _lib
+    n = 10
+    host = np.zeros(1 << 16, dtype=np.uint8)
+    base = (host.ctypes.data + 255) // 256 * 256
+    g = _lib.SSGaussians()
+    g.n, g.sh_degree, g.sh_stride = n, 0, 1
+    for k, name in enumerate(("means", "scales", "quats", "opacity", "sh")):
+        setattr(g, name, base + 1024 * k)
+    f = _lib.SSFrame()
+    for k, (name, _) in enumerate(_lib.SSFrame._fields_):
+        setattr(f, name, base + 8192 + 1024 * k)
+    f.conic = f.geom + 4 * n * 4          # a separate [n, 4] array after geom
+    assert L.ss_preprocess(ctypes.byref(_cam()), ctypes.byref(g), 2, ctypes.byref(f),
+                           None) == _lib.SS_ERR_INVALID_ARG
+    assert b"interleaved" in L.ss_last_error()
+
+
 def test_workspace_and_overflow_checks(L):
     from paper_2412_00578_amd import _lib
     p = _lib.SSPairs()
