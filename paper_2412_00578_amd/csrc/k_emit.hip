@@ -21,9 +21,11 @@
 //               in its own segment of the scratch (no atomics: thousands on one
 //               counter would serialise), and one workgroup turns the
 //               per-segment counts into offsets;
-//   k_emit_big  each wave takes 64 queued entries at a time and re-walks the
-//               FP64 tile spans of their records: the spans (rows, or columns
-//               for AccuTile on tall extents) of all 64 are dealt out to the
+//   k_emit_big  each wave takes 64 work items at a time, an item being a
+//               run of a queued entry's bands (an entry of thousands of tiles
+//               is split over up to 16 waves), and re-walks the FP64 tile
+//               spans of their records: the spans (rows, or columns for
+//               AccuTile on tall extents) of all 64 are dealt out to the
 //               lanes, a wave prefix sum places them, and the wave writes the
 //               keys with consecutive lanes on consecutive addresses.
 #include "ss_internal.h"
@@ -33,13 +35,18 @@ namespace {
 
 constexpr int kBigBlock = 256;
 constexpr int kBigGrid = 1024;
+constexpr uint32_t kBigPartTiles = 512;   // tiles per part of a queued entry (at least)
+constexpr int kBigParts = 16;             // parts of one queued entry at most
 
 // Scratch layout for n entries, nb = ceil(n / 256) workgroups: segments of
 // queued entries [0, 256 nb), their counts [256 nb, 257 nb), exclusive segment
-// offsets with the total last [257 nb, 258 nb + 1), and a coarse index
-// [258 nb + 1, 262 nb + 2): entry g names the segment holding queued entry
-// 64 g.
+// offsets with the total last [257 nb, 258 nb + 1), a coarse index
+// [258 nb + 1, 262 nb + 2): word g names the segment holding queued entry
+// 64 g, and per queued entry of more than one part a counter of the tiles
+// its parts have placed [262 nb + 2, 518 nb + 2), at the entry's position in
+// the queue.
 __host__ __device__ __forceinline__ int64_t queue_blocks(int64_t n) { return (n + 255) / 256; }
+__host__ __device__ __forceinline__ int64_t claim_offset(int64_t nb) { return 262 * nb + 2; }
 
 __device__ __forceinline__ uint32_t wave_incl_scan_u32(uint32_t x) {
     const int lane = (int)__lane_id();
@@ -148,7 +155,10 @@ __global__ __launch_bounds__(kEmitBlock) void k_emit(const Item* __restrict__ it
         if (big) {
             const uint32_t below = __builtin_amdgcn_mbcnt_hi(
                 (uint32_t)(bigs >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bigs, 0u));
-            queue[(int64_t)blockIdx.x * kEmitBlock + before + below] = (uint32_t)j;
+            const int64_t slot = (int64_t)blockIdx.x * kEmitBlock + before + below;
+            queue[slot] = (uint32_t)j;
+            // the counter of an entry of more than one part starts at 0
+            if (cnt > kBigPartTiles) queue[claim_offset(nb) + slot] = 0u;
         }
         if (threadIdx.x == 0) queue[nb * kEmitBlock + blockIdx.x] = all;
     }
@@ -201,40 +211,61 @@ __global__ __launch_bounds__(1024) void k_emit_offsets(uint32_t* __restrict__ qu
                                                        int64_t nb) {
     __shared__ uint32_t s_w[16];
     __shared__ uint32_t s_carry;
-    const uint32_t* cnt = queue + nb * kEmitBlock;
-    uint32_t* off = queue + nb * kEmitBlock + nb;
-    uint32_t* coarse = queue + nb * kEmitBlock + 2 * nb + 1;
-    if (threadIdx.x == 0) s_carry = 0u;
-    __syncthreads();
-    for (int64_t base = 0; base < nb; base += 1024 * kOffPer) {
-        const int64_t b0 = base + (int64_t)threadIdx.x * kOffPer;
-        uint32_t x[kOffPer], sum = 0;
-#pragma unroll
-        for (int k = 0; k < kOffPer; ++k) {
-            x[k] = b0 + k < nb ? cnt[b0 + k] : 0u;
-            sum += x[k];
-        }
-        const uint32_t inc = wave_incl_scan_u32(sum);
-        const int w = threadIdx.x >> 6;
-        if ((threadIdx.x & 63) == 63) s_w[w] = inc;
+    {
+        uint32_t* base = queue;
+        const uint32_t* cnt = base + nb * kEmitBlock;
+        uint32_t* off = base + nb * kEmitBlock + nb;
+        uint32_t* coarse = base + nb * kEmitBlock + 2 * nb + 1;
+        if (threadIdx.x == 0) s_carry = 0u;
         __syncthreads();
-        uint32_t before = s_carry;
-        for (int k = 0; k < w; ++k) before += s_w[k];
-        uint32_t o = before + inc - sum;
+        for (int64_t b = 0; b < nb; b += 1024 * kOffPer) {
+            const int64_t b0 = b + (int64_t)threadIdx.x * kOffPer;
+            uint32_t x[kOffPer], sum = 0;
 #pragma unroll
-        for (int k = 0; k < kOffPer; ++k) {
-            if (b0 + k < nb) {
-                off[b0 + k] = o;
-                for (uint32_t m = (o + 63u) & ~63u; m < o + x[k]; m += 64u)
-                    coarse[m >> 6] = (uint32_t)(b0 + k);
+            for (int k = 0; k < kOffPer; ++k) {
+                x[k] = b0 + k < nb ? cnt[b0 + k] : 0u;
+                sum += x[k];
             }
-            o += x[k];
+            const uint32_t inc = wave_incl_scan_u32(sum);
+            const int w = threadIdx.x >> 6;
+            if ((threadIdx.x & 63) == 63) s_w[w] = inc;
+            __syncthreads();
+            uint32_t before = s_carry;
+            for (int k = 0; k < w; ++k) before += s_w[k];
+            uint32_t o = before + inc - sum;
+#pragma unroll
+            for (int k = 0; k < kOffPer; ++k) {
+                if (b0 + k < nb) {
+                    off[b0 + k] = o;
+                    for (uint32_t m = (o + 63u) & ~63u; m < o + x[k]; m += 64u)
+                        coarse[m >> 6] = (uint32_t)(b0 + k);
+                }
+                o += x[k];
+            }
+            __syncthreads();
+            if (threadIdx.x == 1023) s_carry = before + inc;
+            __syncthreads();
         }
-        __syncthreads();
-        if (threadIdx.x == 1023) s_carry = before + inc;
-        __syncthreads();
+        if (threadIdx.x == 0) off[nb] = s_carry;
     }
-    if (threadIdx.x == 0) off[nb] = s_carry;
+}
+
+// The depth-order entry at queue position q (< the total): the segment
+// holding it is the last with offset <= q, between the segments holding
+// positions 64 g and 64 (g + 1).  *at receives its index in the queue.
+__device__ __forceinline__ uint32_t queue_entry(const uint32_t* __restrict__ base, int64_t nb,
+                                                uint32_t q, uint32_t total, uint32_t* at) {
+    const uint32_t* seg_off = base + nb * kEmitBlock + nb;
+    const uint32_t* coarse = base + nb * kEmitBlock + 2 * nb + 1;
+    const uint32_t g = q >> 6;
+    int64_t lo = coarse[g];
+    int64_t hi = (uint64_t)(g + 1) * 64u < total ? (int64_t)coarse[g + 1] : nb - 1;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi + 1) >> 1;
+        if (seg_off[mid] <= q) lo = mid; else hi = mid - 1;
+    }
+    *at = (uint32_t)(lo * kEmitBlock + (q - seg_off[lo]));
+    return base[*at];
 }
 
 __global__ __launch_bounds__(kBigBlock) void k_emit_big(const Item* __restrict__ items,
@@ -246,7 +277,7 @@ __global__ __launch_bounds__(kBigBlock) void k_emit_big(const Item* __restrict__
                                                         const uint32_t* __restrict__ offsets,
                                                         uint32_t* __restrict__ keys,
                                                         uint32_t* __restrict__ values,
-                                                        const uint32_t* __restrict__ queue,
+                                                        uint32_t* __restrict__ queue,
                                                         const uint64_t* __restrict__ totals) {
     constexpr int kW = kBigBlock / 64;
     // per band of the current chunk: start of its tiles in the chunk, tile id of
@@ -258,61 +289,72 @@ __global__ __launch_bounds__(kBigBlock) void k_emit_big(const Item* __restrict__
     __shared__ uint32_t s_pos[kW][64];
     __shared__ uint32_t s_end[kW][64];
     __shared__ uint32_t s_gid[kW][64];
-    __shared__ uint32_t s_done[kW][64];      // tiles placed so far, per entry of the round
+    __shared__ uint32_t s_done[kW][64];      // tiles placed so far, per item of the round
     limit = (uint32_t)frame_count(totals, 0, limit);
     const int w = threadIdx.x >> 6;
     const int lane = (int)__lane_id();
-    const uint32_t* seg_off = queue + nb * kEmitBlock + nb;
-    const uint32_t* coarse = queue + nb * kEmitBlock + 2 * nb + 1;
-    const uint32_t nq = seg_off[nb];
+    uint32_t* claim = queue + claim_offset(nb);
+    const uint32_t nq = queue[nb * kEmitBlock + nb + nb];             // queued entries
+    // Work item q is part q / nq_odd of queued entry q mod nq_odd (nq_odd: nq
+    // rounded up to odd, so that one entry's parts land on different waves
+    // whatever nq is).  An entry with c tiles over m bands has
+    // p = min(ceil(c / kBigPartTiles), kBigParts) parts, part k taking bands
+    // [k ceil(m / p), (k + 1) ceil(m / p)), so no wave walks all the bands of
+    // a Gaussian that covers thousands of tiles; items past an entry's part
+    // count do nothing.  Each round, lane l of the wave looks up item
+    // wave0 + (64 r + l) waves, so that the chains of dependent loads
+    // (segment search, entry, Gaussian, record) of 64 items overlap.  The
+    // bands (tile rows, or columns for AccuTile on tall extents) of the
+    // round's items are then dealt out to the lanes 64 at a time, each band's
+    // span evaluated on its own as the preprocess stage counted it, and the
+    // chunk's tiles written with consecutive lanes on consecutive pair
+    // positions.  A band takes its place in its entry's pair range with an
+    // add that returns the tiles placed before it (in LDS for an entry of one
+    // part, else on the entry's counter in the scratch, which k_emit zeroed):
+    // the order of one Gaussian's own pairs does not matter.
+    const uint32_t nq_odd = nq | 1u;
+    const uint64_t n_items = nq ? (uint64_t)nq_odd * kBigParts : 0u;
     const uint32_t wave0 = blockIdx.x * kW + w;
     const uint32_t waves = gridDim.x * kW;
-    // Each round, lane l of the wave looks up queued entry wave0 + (64 r + l)
-    // waves, so that the chains of dependent loads (segment search, entry,
-    // Gaussian, record) of 64 entries overlap.  The bands (tile rows, or
-    // columns for AccuTile on tall extents) of the round's entries are then
-    // dealt out to the lanes 64 at a time, each band's span evaluated on its
-    // own as the preprocess stage counted it, and the chunk's tiles written
-    // with consecutive lanes on consecutive pair positions.  A band takes its
-    // place in its entry's pair range with an LDS add: the order of one
-    // Gaussian's own pairs does not matter.
-    for (uint32_t r0 = 0; wave0 + (uint64_t)r0 * waves < nq; r0 += 64) {
-        const uint64_t bq = wave0 + (uint64_t)(r0 + lane) * waves;
-        const bool have = bq < nq;
-        const uint32_t b = have ? (uint32_t)bq : 0u;
+    for (uint32_t r0 = 0; wave0 + (uint64_t)r0 * waves < n_items; r0 += 64) {
+        const uint64_t iq = wave0 + (uint64_t)(r0 + lane) * waves;
+        const uint32_t b = iq < n_items ? (uint32_t)(iq % nq_odd) : nq;
+        const uint32_t part = iq < n_items ? (uint32_t)(iq / nq_odd) : 0u;
         Ellipse e;
         e.u = e.v = e.a = e.b = e.c = e.t = e.det = e.hx = e.hy = 0.0;
         e.x0 = e.x1 = e.y0 = e.y1 = 0;
         e.cols = false;
         bool ok = false;
-        uint32_t i = 0, pos0 = 0, end = 0, tile_off = 0;
+        uint32_t i = 0, pos0 = 0, end = 0, tile_off = 0, np = 0, slot = 0, j = 0;
         int tx_n = 0, ty_n = 0, by0 = 0, by1 = 0;
+        const bool have = b < nq;
+        if (have) j = queue_entry(queue, nb, b, nq, &slot);           // depth-order entry
         if (have) {
-            // the segment holding queued entry b: the last with offset <= b,
-            // between the segments holding entries 64 g and 64 (g + 1)
-            const uint32_t g = b >> 6;
-            int64_t lo = coarse[g];
-            int64_t hi = (uint64_t)(g + 1) * 64u < nq ? (int64_t)coarse[g + 1] : nb - 1;
-            while (lo < hi) {
-                const int64_t mid = (lo + hi + 1) >> 1;
-                if (seg_off[mid] <= b) lo = mid; else hi = mid - 1;
-            }
-            const uint32_t j = queue[lo * kEmitBlock + (b - seg_off[lo])];   // depth-order entry
-            i = order[j];
-            const Item& it = items[dims.n_items == 1 ? 0 : item_of_slot(items, dims.n_items, i)];
-            tx_n = it.tx_n;
-            ty_n = it.ty_n;
-            by0 = it.by0;
-            by1 = it.by1;
-            tile_off = (uint32_t)it.tile_off;
             pos0 = j > 0 ? offsets[j - 1] : 0u;
             end = offsets[j];
-            ok = ellipse_setup(geom[kRec * (uint64_t)i], conic[kRec * (uint64_t)i], mode, tx_n,
-                               ty_n, by0, by1, e);
+            const uint32_t np0 = (end - pos0 + kBigPartTiles - 1) / kBigPartTiles;
+            np = np0 < (uint32_t)kBigParts ? np0 : (uint32_t)kBigParts;
+            if (part < np) {
+                i = order[j];
+                const Item& it =
+                    items[dims.n_items == 1 ? 0 : item_of_slot(items, dims.n_items, i)];
+                tx_n = it.tx_n;
+                ty_n = it.ty_n;
+                by0 = it.by0;
+                by1 = it.by1;
+                tile_off = (uint32_t)it.tile_off;
+                ok = ellipse_setup(geom[kRec * (uint64_t)i], conic[kRec * (uint64_t)i], mode,
+                                   tx_n, ty_n, by0, by1, e);
+            }
         }
         const bool cols = ok && span_columns(e, mode);
-        const uint32_t nmaj =
+        const uint32_t m_all =
             ok ? (uint32_t)(cols ? e.x1 - e.x0 + 1 : e.y1 - e.y0 + 1) : 0u;
+        // this item's bands [kb0, kb0 + nmaj) of the entry's m_all
+        const uint32_t per = np ? (m_all + np - 1) / np : 0u;
+        const uint32_t kb0 = part * per < m_all ? part * per : m_all;
+        const uint32_t kb1 = kb0 + per < m_all ? kb0 + per : m_all;
+        const uint32_t nmaj = kb1 - kb0;
         const uint32_t incl = wave_incl_scan_u32(nmaj);
         const uint32_t n_bands = __shfl(incl, 63, 64);
         s_done[w][lane] = 0u;
@@ -328,7 +370,8 @@ __global__ __launch_bounds__(kBigBlock) void k_emit_big(const Item* __restrict__
             }
             L = L > 63 ? 63 : L;
             const int k = (int)(jb - ((uint32_t)__shfl((int)incl, L, 64) -
-                                      (uint32_t)__shfl((int)nmaj, L, 64)));
+                                      (uint32_t)__shfl((int)nmaj, L, 64))) +
+                          __shfl((int)kb0, L, 64);
             Ellipse el;
             el.u = __shfl(e.u, L, 64); el.v = __shfl(e.v, L, 64);
             el.a = __shfl(e.a, L, 64); el.b = __shfl(e.b, L, 64); el.c = __shfl(e.c, L, 64);
@@ -342,6 +385,7 @@ __global__ __launch_bounds__(kBigBlock) void k_emit_big(const Item* __restrict__
             const int txn = __shfl(tx_n, L, 64), tyn = __shfl(ty_n, L, 64);
             const uint32_t gi = __shfl(i, L, 64), p0 = __shfl(pos0, L, 64);
             const uint32_t pend = __shfl(end, L, 64), toff = __shfl(tile_off, L, 64);
+            const uint32_t pnp = __shfl(np, L, 64), pslot = __shfl(slot, L, 64);
             int lo = 0, hi = -1;
             if (jb < n_bands) {
                 if (mode == SS_TILE_ACCUTILE) {
@@ -352,7 +396,8 @@ __global__ __launch_bounds__(kBigBlock) void k_emit_big(const Item* __restrict__
                 }
             }
             const uint32_t len = hi >= lo ? (uint32_t)(hi - lo + 1) : 0u;
-            const uint32_t start = len ? atomicAdd(&s_done[w][L], len) : 0u;
+            uint32_t start = 0u;
+            if (len) start = pnp > 1u ? atomicAdd(claim + pslot, len) : atomicAdd(&s_done[w][L], len);
             const int major = (cl ? el.x0 : el.y0) + k;
             // tile id of the band's minor index m: rows toff + (major - row0) txn + m,
             // columns toff + (m - row0) txn + major
@@ -393,7 +438,7 @@ __global__ __launch_bounds__(kBigBlock) void k_emit_big(const Item* __restrict__
 int64_t emit_tmp_words(int64_t n) {
     const int64_t nb = queue_blocks(n);
     // the depth-ordered tile sets (4 words per entry), then the queue
-    const int64_t q = 4 * n + nb * kEmitBlock + 6 * nb + 2;
+    const int64_t q = 4 * n + claim_offset(nb) + nb * kEmitBlock;
     const int64_t pre = 2 * ((n + 63) / 64);     // the preprocess stage's partial counts
     return q > pre ? q : pre;
 }

@@ -239,12 +239,12 @@ class GpuBackend:
         px = int(r.cam.width) * int(r.cam.height)
         est = self.pairs_per.get(self._key(r), 4 * n)
         # records 48, counts 4, tile sets 16, depth keys 8, order 8, counts in
-        # depth order 4, offsets 4, emit scratch 20 (tile sets in depth order and
-        # the queue): 112 B per slot; image and
+        # depth order 4, offsets 4, emit scratch 24 (tile sets in depth order,
+        # the queue and its part counters): 116 B per slot; image and
         # per-pixel state 20 B per pixel (budgeted at 32 with the per-tile
         # ranges and order); 16 B per pair (two buffers) with the 1.25 growth;
         # sort scratch
-        return int(112 * n + 32 * px + 16 * 1.25 * est + (3 << 20))
+        return int(116 * n + 32 * px + 16 * 1.25 * est + (3 << 20))
 
     def peak_device_bytes(self) -> int:
         """Device memory the batches held at the peak of the run, beyond what
