@@ -73,6 +73,25 @@ def test_partial_edge_tiles(ss, gpu_device, mode):
     assert_pipeline_equal(gpu, oracle.render(sc, cam, mode))
 
 
+@pytest.mark.parametrize("mode", ["3sigma", "accutile"])
+def test_gaussians_over_thousands_of_tiles(ss, gpu_device, mode):
+    # The camera inside a scene with scales up to e^1.5 at 2560x1440 (14400
+    # tiles): hundreds of Gaussians of more than 512 tiles, whose emission is
+    # split over several waves, and some covering every tile (more than
+    # 16 x 512, the most runs one Gaussian is split into).  Stages only: the
+    # image of 13.6M 3-sigma pairs at this size is beyond the oracle's budget
+    # here, and the blend's inputs are the sorted pairs and ranges compared.
+    sc = scenegen.scene_blobs(30_000, 31, log_s=(-3.0, 1.5))
+    cam = scenegen.cameras_c1(8)[1].with_size(2560, 1440)
+    gpu = _run(ss, gpu_device, sc, cam, mode)
+    fr = oracle.render(sc, cam, mode, blend_tiles=None)
+    counts = fr.records.counts.astype(np.int64)
+    print(f"[case] pairs {fr.n_pairs}, over 512 tiles {(counts > 512).sum()}, "
+          f"over 8192 {(counts > 8192).sum()}", flush=True)
+    assert (counts > 8192).sum() > 0
+    assert_pipeline_equal(gpu, fr)
+
+
 def test_odd_sizes_and_sh_degrees(ss, gpu_device):
     # Ragged Gaussian count, tiny odd image, SH degree 1 and 2 stored with stride 16.
     cam = scenegen.Camera(200, 70, 180.0, 180.0, 100.0, 35.0, np.eye(3), np.zeros(3))
