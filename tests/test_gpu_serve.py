@@ -64,6 +64,24 @@ def test_batch_item_matches_oracle(ss, gpu_device, scenes):
         assert np.abs(img.cpu().numpy() - fr.image)[:, ok].max() <= 1e-4
 
 
+@pytest.mark.parametrize("mode", ["3sigma", "accutile"])
+def test_batch_with_gaussians_over_thousands_of_tiles(ss, gpu_device, scenes, mode):
+    # A camera inside a scene of large Gaussians at 2560x1440 (some cover all
+    # 14400 tiles, so their emission is split over several waves) batched with
+    # the same scene at 1600x1040 and another scene: every image bit-identical
+    # to the request rendered alone.
+    _, gs = scenes
+    big = ss.Gaussians.from_scene(scenegen.scene_blobs(30_000, 31, log_s=(-3.0, 1.5)),
+                                  gpu_device)
+    cam = scenegen.cameras_c1(8)[1]
+    reqs = [(gs[2], _cams(17, 1)[0]), (big, cam.with_size(2560, 1440)), (big, cam)]
+    print(f"[case] batch with large Gaussians mode={mode}", flush=True)
+    outs = ss.BatchRenderer(gpu_device).render(reqs, mode)
+    torch.cuda.synchronize()
+    for (g, c), img in zip(reqs, outs):
+        assert torch.equal(img, _alone(ss, gpu_device, g, c, mode))
+
+
 def test_batch_with_empty_and_tiny_scenes(ss, gpu_device, scenes):
     _, gs = scenes
     empty = scenegen.fixture_scene(np.zeros((0, 3)), np.zeros((0, 3)), np.zeros((0, 4)),
