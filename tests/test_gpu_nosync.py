@@ -32,12 +32,17 @@ def _same(a, b, p):
 
 
 @pytest.mark.parametrize("mode", MODES)
-@pytest.mark.parametrize("which", ["c0", "c1", "edge"])
+@pytest.mark.parametrize("which", ["c0", "c1", "edge", "large"])
 def test_nosync_equals_render(ss, gpu_device, mode, which):
     if which == "c0":
         sc, cam = scenegen.scene_c0(), scenegen.camera_c0()
     elif which == "c1":
         sc, cam = scenegen.scene_c1(), scenegen.camera_c1()
+    elif which == "large":
+        # Gaussians over thousands of the 14400 tiles: their emission split
+        # over several waves, from the counts on the device
+        sc = scenegen.scene_blobs(30_000, 31, log_s=(-3.0, 1.5))
+        cam = scenegen.cameras_c1(8)[1].with_size(2560, 1440)
     else:
         sc = scenegen.scene_blobs(60_000, 21, log_s=(-3.0, 1.0))
         cam = scenegen.cameras_c1(8)[1].with_size(1920, 1080)
