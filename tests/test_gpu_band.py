@@ -71,6 +71,33 @@ def test_band_matches_whole_frame(ss, gpu_device, mode, size, band):
     assert ok.mean() >= MIN_COMPARED
 
 
+@pytest.mark.parametrize("mode", ["3sigma", "accutile"])
+def test_band_of_large_gaussians(ss, gpu_device, mode):
+    # A band of a 2560x1440 view from inside a scene of large Gaussians (some
+    # cover every tile, so their emission in the band is split over several
+    # waves): pairs, counts and ranges as the oracle's frame restricted to the
+    # band, image rows bit-identical to the whole frame's (the oracle's image
+    # of this frame is beyond its budget here).
+    row0, rows = 40, 30
+    sc = scenegen.scene_blobs(30_000, 31, log_s=(-3.0, 1.5))
+    cam = scenegen.cameras_c1(8)[1].with_size(2560, 1440)
+    print(f"[case] band rows [{row0}, {row0 + rows}) of large Gaussians mode={mode}", flush=True)
+    g = ss.Gaussians.from_scene(sc, gpu_device)
+    out = ss.Renderer(gpu_device).render_band(g, cam, mode, row0, rows, full=True)
+    whole = ss.Renderer(gpu_device).render(g, cam, mode)
+    torch.cuda.synchronize()
+    fr = oracle.render(sc, cam, mode, blend_tiles=None)
+    keys, vals, ranges, counts = band_expectation(fr, cam, row0, rows)
+    p = out.n_pairs
+    assert p == len(keys)
+    assert np.array_equal(u32(out.frame.counts), counts)
+    assert np.array_equal(u32(out.pairs.keys[out.buf][:p]), keys)
+    assert np.array_equal(u32(out.pairs.values[out.buf][:p]), vals)
+    assert np.array_equal(u32(out.frame.ranges).reshape(-1, 2), ranges)
+    img = out.image.cpu().numpy()
+    assert np.array_equal(img, whole[:, 16 * row0:16 * (row0 + rows)].cpu().numpy())
+
+
 def test_bands_tile_the_frame(ss, gpu_device):
     """Eight bands of the 1.5M-Gaussian benchmark frame (AccuTile) together
     hold exactly the whole frame's pairs, and their images stack into the
