@@ -11,7 +11,7 @@
 // which moves about a third of the bytes of six passes over 12-byte pairs.
 //
 // Both are LSD radix sorts with digits of at most 8 bits, the key bits split
-// evenly over the passes (the tile sort's 13 bits as 7 + 6).  Each pass is
+// evenly over the passes (the tile sort's 13 bits as 6 + 7).  Each pass is
 // reduce-then-scan, so no workgroup ever waits on another:
 //   hist     workgroup b counts the digits of its contiguous key chunk
 //   dscan    256 workgroups, one per digit: exclusive scan of that digit's
@@ -383,15 +383,18 @@ hipError_t radix_sort(K* keys[2], uint32_t* vals[2], int cur, uint64_t n0, uint6
                       uint32_t* tmp, bool drop, bool identity, bool last_keys,
                       const uint4* gather, uint32_t* gather_out, uint4* sets_out, int* out_buf,
                       hipStream_t s, const uint64_t* totals = nullptr, int word = 0) {
-    // the bits are split as evenly as the passes allow (13 bits: 7 + 6), so
-    // no pass scatters into more buckets than it must: the fewer the buckets,
-    // the longer each sub-tile's runs of equal digits and its coalesced writes
+    // the bits are split as evenly as the passes allow, so no pass scatters
+    // into more buckets than it must: the fewer the buckets, the longer each
+    // sub-tile's runs of equal digits and its coalesced writes.  The wider
+    // digits go to the last passes (13 bits: 6 + 7): the top bits of a tile
+    // id take fewer values than their width allows (6500 tiles: 51 values of
+    // bits 7-12, 102 of bits 6-12), the low bits all of theirs
     const int passes = (bits + 7) / 8;
     int shift = 0;
     for (int pass = 0; pass < passes; ++pass) {
         const uint64_t m = pass == 0 ? n0 : n;       // pairs this pass reads
         const Plan plan = make_plan(m);
-        const int width = bits / passes + (pass < bits % passes ? 1 : 0);
+        const int width = bits / passes + (pass >= passes - bits % passes ? 1 : 0);
         const uint32_t dmask = (1u << width) - 1u;
         const bool last = pass + 1 == passes;
         const bool dr = pass == 0 && drop;
